@@ -1,0 +1,159 @@
+"""Named synthetic workloads and an on-disk cache of their inputs.
+
+Each builder returns a dict with the float64 operator (``P64`` CSR), the
+float32-rounded arrays handed to the embedding path (``rowptr`` int32,
+``col`` int32, ``val`` float32/float64, ``W`` float32/float64), landmark
+vertex ids, the mesh and the parameters.  The precision of ``val``/``W``
+is float64 for the FP64 workload and float32 otherwise; the reference
+eigenpairs are always taken on exactly these rounded values, upcast.
+
+Workloads (mesh recipe, landmark count, sparsity):
+  torus64x32   n=2,048 torus (R=1, r=0.4) with N(0, 0.01^2) vertex jitter,
+               l=64 geodesic farthest-point landmarks, p_row=10 (p=310), FP64
+  sphere7      icosphere level 7 (n=163,842) with radius 1 + 0.05 s/max|s|,
+               s a sum of 8 seeded real spherical harmonics of degree <= 6,
+               l=2,000, p_row=10 (p=809), FP32
+  bumpy_torus  nu x nv torus with sinusoidal tube-radius bumps (amp 0.05),
+               l = n/50 (or given), p_row=10, FP32
+  small meshes for tests (any of the above at reduced sizes)
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import time
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import meshes
+from . import operator as op
+
+__all__ = ["build_problem", "load", "cache_dir", "torus64x32", "sphere7", "PRESETS"]
+
+
+def cache_dir() -> str:
+    d = os.environ.get("SBMDS_CACHE")
+    if not d:
+        d = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "_cache")
+    os.makedirs(d, exist_ok=True)
+    return d
+
+
+def build_problem(V, F, l: int, p_row: float | None, seed: int, dtype=np.float32,
+                  landmarks=None, graph_operator: bool = False, log=None):
+    """Full input chain for one mesh.  ``p_row=None`` keeps P dense."""
+    t0 = time.time()
+    n = V.shape[0]
+    M = op.biharmonic(V, F, graph=graph_operator)
+    G = op.edge_graph(V, F)
+    if landmarks is None:
+        landmarks = op.farthest_point_landmarks(G, l, seed=seed)
+    landmarks = np.asarray(landmarks, dtype=np.int64)
+    if log:
+        log(f"  landmarks done ({time.time() - t0:.1f}s)")
+    W64 = op.landmark_sq_distances(G, landmarks)
+    if log:
+        log(f"  W done ({time.time() - t0:.1f}s)")
+    p = None if p_row is None else op.p_from_prow(n, l, p_row)
+    if l == n:
+        P64 = sp.csr_matrix((np.ones(n), (landmarks, np.arange(n))), shape=(n, n))
+        P64.sort_indices()
+    else:
+        P64, _ = op.interpolation_operator(M, landmarks, p)
+    if log:
+        log(f"  P done ({time.time() - t0:.1f}s)")
+    val = P64.data.astype(dtype)
+    W = W64.astype(dtype)
+    return {
+        "n": n, "l": l, "p": p if p is not None else n - l, "p_row": p_row, "seed": seed,
+        "V": V, "F": F, "landmarks": landmarks,
+        "rowptr": P64.indptr.astype(np.int32), "col": P64.indices.astype(np.int32),
+        "val": val, "W": W, "P64": P64, "W64": W64,
+    }
+
+
+def operator_rounded(prob) -> sp.csr_matrix:
+    """The CSR P exactly as handed to the path (rounded values), in float64."""
+    return sp.csr_matrix((prob["val"].astype(np.float64), prob["col"], prob["rowptr"]),
+                         shape=(prob["n"], prob["l"]))
+
+
+def _key(name: str, params: dict) -> str:
+    h = hashlib.sha1(json.dumps(params, sort_keys=True).encode()).hexdigest()[:12]
+    return f"{name}_{h}"
+
+
+_ARRAYS = ["V", "F", "landmarks", "rowptr", "col", "val", "W"]
+
+
+def _save(path, prob):
+    meta = {k: prob[k] for k in ("n", "l", "p", "p_row", "seed")}
+    np.savez(path, meta=json.dumps(meta), **{k: prob[k] for k in _ARRAYS})
+
+
+def _restore(path):
+    z = np.load(path, allow_pickle=False)
+    meta = json.loads(str(z["meta"]))
+    prob = dict(meta)
+    for k in _ARRAYS:
+        prob[k] = z[k]
+    return prob
+
+
+def _cached(name, params, make, use_cache=True, log=None):
+    path = os.path.join(cache_dir(), _key(name, params) + ".npz")
+    if use_cache and os.path.exists(path):
+        return _restore(path)
+    if log:
+        log(f"generating {name} {params}")
+    prob = make()
+    if use_cache:
+        tmp = path + ".tmp.npz"
+        _save(tmp, prob)
+        os.replace(tmp, path)
+    # drop float64 extras so cached and fresh results look the same
+    return {k: prob[k] for k in list(_ARRAYS) + ["n", "l", "p", "p_row", "seed"]}
+
+
+def torus64x32(p_row=10, l=64, seed=1001, jitter=0.01, fp64=True, use_cache=True, log=None):
+    params = dict(p_row=p_row, l=l, seed=seed, jitter=jitter, fp64=fp64, v=1)
+
+    def make():
+        V, F = meshes.torus_grid(64, 32, 1.0, 0.4, jitter=jitter, seed=seed)
+        return build_problem(V, F, l, p_row, seed, np.float64 if fp64 else np.float32, log=log)
+
+    return _cached("torus64x32", params, make, use_cache, log)
+
+
+def sphere7(p_row=10, l=2000, seed=2002, level=7, use_cache=True, log=None):
+    params = dict(p_row=p_row, l=l, seed=seed, level=level, v=1)
+
+    def make():
+        V, F = meshes.deformed_icosphere(level, seed)
+        return build_problem(V, F, l, p_row, seed, np.float32, log=log)
+
+    return _cached(f"sphere{level}", params, make, use_cache, log)
+
+
+def bumpy_torus(nu, nv, l=None, p_row=10, seed=3003, use_cache=True, log=None):
+    n = nu * nv
+    l = l if l is not None else max(2, round(n / 50))
+    params = dict(nu=nu, nv=nv, l=l, p_row=p_row, seed=seed, v=1)
+
+    def make():
+        V, F = meshes.bumpy_torus(nu, nv, seed)
+        return build_problem(V, F, l, p_row, seed, np.float32, log=log)
+
+    return _cached(f"bumpy_torus{nu}x{nv}", params, make, use_cache, log)
+
+
+def load(name: str, **kw):
+    return PRESETS[name](**kw)
+
+
+PRESETS = {
+    "torus64x32": torus64x32,
+    "sphere7": sphere7,
+}

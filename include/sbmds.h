@@ -1,0 +1,232 @@
+/*
+ * sbmds.h -- C ABI of the sparse biharmonic MDS (sBMDS) embedding path on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Turek & Huth, "Efficient, sparse representation of manifold
+ * distance matrices for classical scaling", Section 3.3, with classical MDS
+ * from Section 2.3): given the sparse interpolation operator P (n x l, the
+ * thresholded biharmonic operator of Section 3.1 / Eq. (PDefinition)) and
+ * the landmark block W (l x l; here the SQUARED landmark geodesic
+ * distances, the matrix classical scaling needs), compute the k
+ * algebraically largest eigenpairs (lambda_i, v_i) of
+ *
+ *        B = -1/2 * J * P * W * P^T * J,      J = I - 1 1^T / n,
+ *
+ * and the embedding Z = V_k * Lambda_k^{1/2}, without forming any n x n
+ * matrix.  The paper names a Lanczos method on matrix-vector products for
+ * this step; this library runs block subspace iteration with a
+ * Rayleigh-Ritz step on the same implicit operator, which reaches the same
+ * eigenpairs.  Coordinates whose eigenvalue is not positive are returned
+ * as zero and flagged in the report.
+ *
+ * Conventions for every function:
+ *   - All functions have C linkage; no exception crosses the boundary.
+ *   - Negative return values are errors: no output was written and
+ *     sbmds_last_error() returns a message (thread-local, valid until the
+ *     next call on the same thread).
+ *   - SBMDS_ENOCONV (positive) means the iteration limit was reached; the
+ *     outputs hold the best estimate and the report holds its error bounds.
+ *   - The caller owns every array it passes.  sbmds_create copies what it
+ *     needs, so inputs may be freed or reused once it returns.
+ *   - A context owns all device memory it allocated until sbmds_destroy.
+ *     It is bound to the HIP device that was current at sbmds_create and to
+ *     the stream given in the options; it is not thread-safe, but any number
+ *     of contexts may coexist.
+ */
+#ifndef SBMDS_H
+#define SBMDS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SBMDS_VERSION_MAJOR 0
+#define SBMDS_VERSION_MINOR 1
+#define SBMDS_MAX_BLOCK 64 /* largest subspace block the kernels carry */
+
+typedef struct sbmds_ctx sbmds_ctx; /* opaque */
+
+typedef enum {
+    SBMDS_OK = 0,
+    SBMDS_ENOCONV = 1,     /* warning: max_iter reached, outputs are best effort */
+    SBMDS_EINVAL = -1,     /* invalid argument or malformed input */
+    SBMDS_ENOMEM = -2,     /* device allocation failed or mem_cap exceeded */
+    SBMDS_EHIP = -3,       /* a HIP runtime call failed */
+    SBMDS_ENODEV = -4,     /* no usable gfx950 device */
+    SBMDS_EBREAKDOWN = -5  /* the basis lost rank and could not be repaired */
+} sbmds_status;
+
+typedef enum {
+    SBMDS_FP64 = 0,      /* P, W, vectors and accumulation in float64 */
+    SBMDS_FP32 = 1,      /* float32 storage and accumulation, float64 block algebra */
+    SBMDS_BF16_FP32 = 2  /* bfloat16 bulk iterations, then float32 refinement */
+} sbmds_precision;
+
+typedef enum {
+    SBMDS_START_RANDOM = 0, /* seeded Gaussian block (counter-based generator) */
+    SBMDS_START_LMDS = 1,   /* landmark MDS of W lifted through P */
+    SBMDS_START_LEARNED = 2,/* MLP prediction from landmark features, lifted through P */
+    SBMDS_START_USER = 3    /* caller-supplied block (sbmds_problem.X0), e.g. to resume */
+} sbmds_start;
+
+typedef enum { SBMDS_MEM_HOST = 0, SBMDS_MEM_DEVICE = 1 } sbmds_mem;
+
+/* Option flags */
+#define SBMDS_FLAG_KERNEL_TIMING 0x1u /* time every kernel launch with HIP events */
+#define SBMDS_FLAG_NO_GRAPH 0x2u      /* launch iterations eagerly, no hipGraph replay */
+#define SBMDS_FLAG_NO_CERTIFY 0x4u    /* skip the float64 certification pass */
+
+/*
+ * One problem (mesh).  Arrays live in host or device memory according to
+ * `mem`; all of one problem's arrays must be in the same place.
+ *
+ *   n, l      vertices and landmarks, 2 <= l <= n < 2^31.
+ *   nnz       number of stored entries of P, 0 <= nnz < 2^31.
+ *   P_rowptr  [n+1] int32, P_rowptr[0] = 0, non-decreasing, P_rowptr[n] = nnz.
+ *   P_col     [nnz] int32 landmark index of each entry, in [0, l), strictly
+ *             increasing within a row.
+ *   P_val     [nnz] entries of P: double for SBMDS_FP64, float otherwise.
+ *             Rows need not sum to one (the thresholded operator does not).
+ *   W         [l*l] row-major landmark block, same element type as P_val;
+ *             must be symmetric with finite entries.
+ *   xyz       [n*3] float vertex positions; read only for SBMDS_START_LEARNED
+ *             (may be NULL otherwise).
+ *   landmark_vertex [l] int32 vertex id of landmark j; read only for
+ *             SBMDS_START_LEARNED (may be NULL otherwise).
+ *   X0        [n*block] row-major start block, element type as P_val; read
+ *             only for SBMDS_START_USER.
+ */
+typedef struct {
+    int64_t n, l, nnz;
+    const int32_t *P_rowptr;
+    const int32_t *P_col;
+    const void *P_val;
+    const void *W;
+    const float *xyz;
+    const int32_t *landmark_vertex;
+    const void *X0;
+    int mem; /* sbmds_mem */
+} sbmds_problem;
+
+/*
+ * Solver options.  Call sbmds_default_options first, then override.
+ *   k          wanted eigenpairs / embedding dimension, 1 <= k <= block.
+ *   block      subspace width, k <= block <= min(l - 1, SBMDS_MAX_BLOCK).
+ *              Geodesic classical scaling has negative eigenvalues larger in
+ *              magnitude than the wanted ones; the block must be wide enough
+ *              to hold them as well (default 16).
+ *   prec       sbmds_precision (default SBMDS_FP32).
+ *   start      sbmds_start (default SBMDS_START_RANDOM).
+ *   tol        target bound on the relative eigenvalue error of each of the
+ *              k eigenvalues (default 1e-6).
+ *   max_iter   iteration cap over all phases (default 500).
+ *   seed       seed of the random start block.
+ *   stream     hipStream_t to run on (NULL = the null stream).
+ *   mlp_weights  path of a weights file for SBMDS_START_LEARNED (or NULL).
+ *   tune_cache   path of the autotuner cache (NULL = no persistent cache).
+ *   mem_cap    upper bound on device bytes the context may allocate (0 = none).
+ *   flags      SBMDS_FLAG_* bits.
+ */
+typedef struct {
+    int k;
+    int block;
+    int prec;
+    int start;
+    double tol;
+    int max_iter;
+    uint64_t seed;
+    void *stream;
+    const char *mlp_weights;
+    const char *tune_cache;
+    size_t mem_cap;
+    unsigned flags;
+} sbmds_options;
+
+/*
+ * Per-problem report filled by sbmds_embed.
+ *   status      per-problem sbmds_status.
+ *   iters_*     iterations run in each arithmetic (bf16 bulk, fp32,
+ *               fp64-accumulated certification / fp64 mode).
+ *   eig[i]      Ritz value i (i < k), descending.
+ *   err_bound[i] bound on |eig[i] - lambda_i| / |eig[i]| from the final
+ *               residuals (quadratic residual bound over gap-separated
+ *               clusters, or the plain residual norm when smaller).
+ *   resid[i]    ||B x_i - eig[i] x_i|| / |eig[i]|.
+ *   nonpositive number of the k eigenvalues <= 0 (their coordinates are 0).
+ *   ms_*        wall time of the start block, of the iterations, and of the
+ *               whole call, measured with HIP events on the context's stream.
+ */
+typedef struct {
+    int status;
+    int iters_bf16, iters_fp32, iters_fp64;
+    int nonpositive;
+    int certified;
+    double ms_start, ms_iter, ms_total;
+    double eig[SBMDS_MAX_BLOCK];
+    double err_bound[SBMDS_MAX_BLOCK];
+    double resid[SBMDS_MAX_BLOCK];
+} sbmds_report;
+
+/* Per-kernel timing (SBMDS_FLAG_KERNEL_TIMING): launches, summed event time
+ * and the algorithmic bytes and flops per launch summed over launches. */
+typedef struct {
+    char name[48];
+    int64_t launches;
+    double ms_total;
+    double bytes_total;
+    double flops_total;
+} sbmds_kernel_stat;
+
+/* Fill `opt` with the defaults listed above.  NULL is ignored. */
+void sbmds_default_options(sbmds_options *opt);
+
+/*
+ * Validate and upload `nprob` problems, build the transposed operator and
+ * the per-precision copies, and allocate every buffer the solve needs.
+ * Validation of host-resident inputs happens before any device call, so
+ * malformed input returns SBMDS_EINVAL even on a machine without a GPU.
+ * On success *out owns the new context; on error *out is set to NULL.
+ */
+int sbmds_create(const sbmds_problem *probs, int nprob, const sbmds_options *opt, sbmds_ctx **out);
+
+/*
+ * Run the eigensolve for every problem of the context.
+ *   eigvals  [nprob*k] host doubles (may be NULL): the k eigenvalues of each
+ *            problem, descending.
+ *   Z        [sum_p n_p * k] row-major embedding (may be NULL), problems
+ *            concatenated in order; double for SBMDS_FP64, float otherwise.
+ *   Z_mem    sbmds_mem of Z.
+ *   reports  [nprob] (may be NULL).
+ * Returns the worst per-problem status.  May be called repeatedly; each
+ * call starts again from the start block chosen in the options.
+ */
+int sbmds_embed(sbmds_ctx *ctx, double *eigvals, void *Z, int Z_mem, sbmds_report *reports);
+
+/* Copy the current basis block (the iteration's state) of problem `prob`
+ * into `X` ([n*block] row-major, element type as P_val, host or device per
+ * X_mem), so that a later solve can resume from it via SBMDS_START_USER. */
+int sbmds_get_block(sbmds_ctx *ctx, int prob, void *X, int X_mem);
+
+/* Copy at most `max` kernel statistics into `out`; returns the number
+ * available (or a negative status).  Statistics accumulate over calls until
+ * sbmds_reset_kernel_stats. */
+int sbmds_kernel_stats(sbmds_ctx *ctx, sbmds_kernel_stat *out, int max);
+void sbmds_reset_kernel_stats(sbmds_ctx *ctx);
+
+/* Release the context and all device memory it owns.  NULL is a no-op. */
+void sbmds_destroy(sbmds_ctx *ctx);
+
+/* Message of the last error on this thread ("" if none). */
+const char *sbmds_last_error(void);
+
+/* (major << 16) | minor */
+int sbmds_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBMDS_H */

@@ -1,0 +1,309 @@
+"""Python binding of the sBMDS embedding library (libsbmds.so, include/sbmds.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  Inputs may be NumPy arrays (host memory) or torch tensors on a
+ROCm device (device memory); torch supplies device memory and the stream.
+
+    from paper_1705_10887_amd import embed
+    Z, eig, report = embed(rowptr, col, val, W, k=3, block=16)
+
+The library is loaded from this directory; if it has not been built the
+import of the binding functions fails loudly (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "FP64", "FP32", "BF16_FP32",
+    "START_RANDOM", "START_LMDS", "START_LEARNED", "START_USER",
+    "FLAG_KERNEL_TIMING", "FLAG_NO_GRAPH", "FLAG_NO_CERTIFY",
+    "SbmdsError", "Problem", "Context", "embed", "lib", "lib_path", "version",
+]
+
+FP64, FP32, BF16_FP32 = 0, 1, 2
+START_RANDOM, START_LMDS, START_LEARNED, START_USER = 0, 1, 2, 3
+MEM_HOST, MEM_DEVICE = 0, 1
+FLAG_KERNEL_TIMING, FLAG_NO_GRAPH, FLAG_NO_CERTIFY = 0x1, 0x2, 0x4
+MAX_BLOCK = 64
+
+_STATUS = {0: "OK", 1: "ENOCONV", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENODEV", -5: "EBREAKDOWN"}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(_HERE, "libsbmds.so")
+
+
+class SbmdsError(RuntimeError):
+    def __init__(self, code, msg):
+        self.code = code
+        super().__init__(f"sbmds {_STATUS.get(code, code)}: {msg}")
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("l", ctypes.c_int64), ("nnz", ctypes.c_int64),
+        ("P_rowptr", ctypes.c_void_p), ("P_col", ctypes.c_void_p), ("P_val", ctypes.c_void_p),
+        ("W", ctypes.c_void_p), ("xyz", ctypes.c_void_p), ("landmark_vertex", ctypes.c_void_p),
+        ("X0", ctypes.c_void_p), ("mem", ctypes.c_int),
+    ]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_int), ("block", ctypes.c_int), ("prec", ctypes.c_int), ("start", ctypes.c_int),
+        ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("seed", ctypes.c_uint64),
+        ("stream", ctypes.c_void_p), ("mlp_weights", ctypes.c_char_p), ("tune_cache", ctypes.c_char_p),
+        ("mem_cap", ctypes.c_size_t), ("flags", ctypes.c_uint),
+    ]
+
+
+class _Report(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int), ("iters_bf16", ctypes.c_int), ("iters_fp32", ctypes.c_int),
+        ("iters_fp64", ctypes.c_int), ("nonpositive", ctypes.c_int), ("certified", ctypes.c_int),
+        ("ms_start", ctypes.c_double), ("ms_iter", ctypes.c_double), ("ms_total", ctypes.c_double),
+        ("eig", ctypes.c_double * MAX_BLOCK), ("err_bound", ctypes.c_double * MAX_BLOCK),
+        ("resid", ctypes.c_double * MAX_BLOCK),
+    ]
+
+
+class _KStat(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("ms_total", ctypes.c_double),
+        ("bytes_total", ctypes.c_double), ("flops_total", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+EXPORTS = [
+    "sbmds_default_options", "sbmds_create", "sbmds_embed", "sbmds_get_block",
+    "sbmds_kernel_stats", "sbmds_reset_kernel_stats", "sbmds_destroy",
+    "sbmds_last_error", "sbmds_version",
+]
+
+
+def lib():
+    """Load libsbmds.so (once).  Raises ImportError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(lib_path):
+        raise ImportError(f"{lib_path} is missing; build it with `python -m paper_1705_10887_amd._build` "
+                          "(there is no CPU fallback)")
+    L = ctypes.CDLL(lib_path)
+    L.sbmds_default_options.argtypes = [ctypes.POINTER(_Options)]
+    L.sbmds_default_options.restype = None
+    L.sbmds_create.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int, ctypes.POINTER(_Options),
+                               ctypes.POINTER(ctypes.c_void_p)]
+    L.sbmds_create.restype = ctypes.c_int
+    L.sbmds_embed.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                              ctypes.POINTER(_Report)]
+    L.sbmds_embed.restype = ctypes.c_int
+    L.sbmds_get_block.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]
+    L.sbmds_get_block.restype = ctypes.c_int
+    L.sbmds_kernel_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(_KStat), ctypes.c_int]
+    L.sbmds_kernel_stats.restype = ctypes.c_int
+    L.sbmds_reset_kernel_stats.argtypes = [ctypes.c_void_p]
+    L.sbmds_reset_kernel_stats.restype = None
+    L.sbmds_destroy.argtypes = [ctypes.c_void_p]
+    L.sbmds_destroy.restype = None
+    L.sbmds_last_error.argtypes = []
+    L.sbmds_last_error.restype = ctypes.c_char_p
+    L.sbmds_version.argtypes = []
+    L.sbmds_version.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def version():
+    v = lib().sbmds_version()
+    return (v >> 16, v & 0xFFFF)
+
+
+def _check(rc):
+    if rc < 0:
+        raise SbmdsError(rc, lib().sbmds_last_error().decode())
+    return rc
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+@dataclass
+class Problem:
+    """One mesh's operator: CSR of P (n x l) and W (l x l).
+
+    Arrays are NumPy (host) or torch tensors on the GPU (device); the value
+    dtype must be float64 for FP64 and float32 otherwise.
+    """
+    rowptr: object
+    col: object
+    val: object
+    W: object
+    n: int
+    l: int
+    X0: object = None
+    xyz: object = None
+    landmark_vertex: object = None
+    _keep: list = field(default_factory=list, repr=False)
+
+    @classmethod
+    def from_arrays(cls, rowptr, col, val, W, X0=None, xyz=None, landmark_vertex=None):
+        n = int(rowptr.shape[0]) - 1
+        l = int(W.shape[0])
+        return cls(rowptr, col, val, W, n, l, X0, xyz, landmark_vertex)
+
+    def _struct(self, fdtype):
+        dev = _is_torch(self.W) and self.W.is_cuda
+        keep = []
+
+        def ptr(a, dtype):
+            if a is None:
+                return None
+            if dev:
+                import torch
+                tdt = {np.int32: torch.int32, np.float32: torch.float32, np.float64: torch.float64}[dtype]
+                if a.dtype != tdt or not a.is_contiguous():
+                    raise TypeError(f"expected contiguous {tdt} tensor, got {a.dtype}")
+                keep.append(a)
+                return a.data_ptr()
+            arr = np.ascontiguousarray(a, dtype=dtype)
+            keep.append(arr)
+            return arr.ctypes.data
+
+        s = _Problem()
+        s.n = self.n
+        s.l = self.l
+        s.nnz = int(self.col.shape[0])
+        s.P_rowptr = ptr(self.rowptr, np.int32)
+        s.P_col = ptr(self.col, np.int32)
+        s.P_val = ptr(self.val, fdtype)
+        s.W = ptr(self.W, fdtype)
+        s.X0 = ptr(self.X0, fdtype)
+        s.xyz = ptr(self.xyz, np.float32)
+        s.landmark_vertex = ptr(self.landmark_vertex, np.int32)
+        s.mem = MEM_DEVICE if dev else MEM_HOST
+        self._keep = keep
+        return s
+
+
+class Context:
+    """A created solver context (sbmds_create) over one or more problems."""
+
+    def __init__(self, problems, k=3, block=16, prec=FP32, start=START_RANDOM, tol=1e-6, max_iter=500,
+                 seed=12345, stream=None, mlp_weights=None, tune_cache=None, mem_cap=0, flags=0):
+        L = lib()
+        if isinstance(problems, Problem):
+            problems = [problems]
+        self.problems = list(problems)
+        self.prec = prec
+        self.k = k
+        self.block = block
+        fdtype = np.float64 if prec == FP64 else np.float32
+        arr = (_Problem * len(self.problems))()
+        for i, p in enumerate(self.problems):
+            arr[i] = p._struct(fdtype)
+        o = _Options()
+        L.sbmds_default_options(ctypes.byref(o))
+        o.k, o.block, o.prec, o.start = k, block, prec, start
+        o.tol, o.max_iter, o.seed = tol, max_iter, seed
+        if stream is None and any(_is_torch(p.W) and p.W.is_cuda for p in self.problems):
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        o.stream = stream
+        self._mlp = mlp_weights.encode() if isinstance(mlp_weights, str) else mlp_weights
+        self._tune = tune_cache.encode() if isinstance(tune_cache, str) else tune_cache
+        o.mlp_weights = self._mlp
+        o.tune_cache = self._tune
+        o.mem_cap = mem_cap
+        o.flags = flags
+        self._opt = o
+        h = ctypes.c_void_p()
+        _check(L.sbmds_create(arr, len(self.problems), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        for p in self.problems:  # inputs may be released after create
+            p._keep = []
+
+    def embed(self, Z_out=None):
+        """Run the solve.  Returns (Z, eigvals [nprob, k], reports).
+
+        Z is written into ``Z_out`` if given (a device tensor or a host
+        array of shape [sum n, k]); otherwise a host NumPy array is returned.
+        """
+        L = lib()
+        nprob = len(self.problems)
+        eig = np.zeros((nprob, self.k), dtype=np.float64)
+        reps = (_Report * nprob)()
+        ntot = sum(p.n for p in self.problems)
+        zdt = np.float64 if self.prec == FP64 else np.float32
+        if Z_out is None:
+            Z = np.zeros((ntot, self.k), dtype=zdt)
+            zptr, zmem = Z.ctypes.data, MEM_HOST
+        elif _is_torch(Z_out) and Z_out.is_cuda:
+            Z = Z_out
+            zptr, zmem = Z_out.data_ptr(), MEM_DEVICE
+        else:
+            Z = Z_out
+            zptr, zmem = Z_out.ctypes.data, MEM_HOST
+        rc = _check(L.sbmds_embed(self._h, eig.ctypes.data, zptr, zmem, reps))
+        reports = [_report_dict(r, self.k, self.block) for r in reps]
+        return Z, eig, reports, rc
+
+    def get_block(self, prob=0):
+        """Current orthonormal basis X (n x block) of problem `prob` (host array)."""
+        p = self.problems[prob]
+        X = np.zeros((p.n, self.block), dtype=np.float64 if self.prec == FP64 else np.float32)
+        _check(lib().sbmds_get_block(self._h, prob, X.ctypes.data, MEM_HOST))
+        return X
+
+    def kernel_stats(self):
+        L = lib()
+        n = _check(L.sbmds_kernel_stats(self._h, None, 0))
+        arr = (_KStat * max(n, 1))()
+        L.sbmds_kernel_stats(self._h, arr, n)
+        return [dict(name=s.name.decode(), launches=s.launches, ms_total=s.ms_total,
+                     bytes_total=s.bytes_total, flops_total=s.flops_total) for s in arr[:n]]
+
+    def reset_kernel_stats(self):
+        lib().sbmds_reset_kernel_stats(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sbmds_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def _report_dict(r, k, block):
+    return dict(status=r.status, iters_bf16=r.iters_bf16, iters_fp32=r.iters_fp32, iters_fp64=r.iters_fp64,
+                nonpositive=r.nonpositive, certified=bool(r.certified), ms_start=r.ms_start,
+                ms_iter=r.ms_iter, ms_total=r.ms_total, eig=list(r.eig[:block]),
+                err_bound=list(r.err_bound[:block]), resid=list(r.resid[:block]))
+
+
+def embed(rowptr, col, val, W, k=3, block=16, prec=FP32, **kw):
+    """One-shot: create a context for one problem, solve, destroy.
+
+    Returns (Z [n, k], eigenvalues [k], report dict).
+    """
+    p = Problem.from_arrays(rowptr, col, val, W, X0=kw.pop("X0", None))
+    with Context([p], k=k, block=block, prec=prec, **kw) as ctx:
+        Z, eig, reps, _ = ctx.embed()
+    return Z, eig[0], reps[0]

@@ -1,0 +1,105 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sbmds {
+
+// Arithmetic of one iteration.  Each mode fixes the storage type of the P
+// values and of W, of the n x b block Y, of the l x b blocks T and U, and the
+// accumulation type:
+//   BF16   : P bf16, W bf16, Y bf16,  T bf16,  U f32, accumulate f32
+//   FP32   : P f32,  W f32,  Y f32,   T f32,   U f32, accumulate f32
+//   F64ACC : P f32,  W f32,  Y f64,   T f64,   U f64, accumulate f64
+//            (float32 operator, float64 arithmetic: the certification pass)
+//   FP64   : everything f64
+enum Mode { MODE_BF16 = 0, MODE_FP32 = 1, MODE_F64ACC = 2, MODE_FP64 = 3, NUM_MODES = 4 };
+
+inline int y_elem_bytes(Mode m) { return m == MODE_BF16 ? 2 : (m == MODE_FP32 ? 4 : 8); }
+
+constexpr int kMaxB = 64;
+
+// Device-resident state of the block solver for one problem.  Every array is
+// sized for the widest block and indexed with the problem's kernel width B.
+struct SolveState {
+    double H[kMaxB * kMaxB];     // X^T B X from the dense product
+    double s[kMaxB];             // c^T U, the outer centering correction
+    double G[kMaxB * kMaxB];     // Y'^T Y' of the new block
+    double e_new[kMaxB];         // 1^T Y' of the new block
+    double e_x[kMaxB];           // 1^T Y of the block the basis is built from
+    double C[kMaxB * kMaxB];     // basis X = J Y C (row-major B x B)
+    double Zmap[kMaxB * kMaxB];  // embedding Z = J Y Zmap (B x B, first k columns used)
+    double zshift[kMaxB];        // e_x^T Zmap / n
+    double theta[kMaxB];         // Ritz values, descending
+    double res[kMaxB];           // ||B x_i - theta_i x_i||
+    double bound[kMaxB];         // relative eigenvalue error bound per Ritz value
+    double maxbound;             // max over the k wanted values
+    double maxres;               // max over the k wanted values of res_i / |theta_i|
+    int iter;
+    int flags;                   // bit 0: Cholesky pivot repaired; bit 1: non-finite value
+    int dead;                    // columns dropped after rank loss
+    int nonpos;                  // wanted Ritz values <= 0
+};
+
+enum SolveFlags { SF_REPAIRED = 1, SF_NONFINITE = 2 };
+
+// Buffers and sizes of one problem on the device.
+struct DevProblem {
+    int64_t n = 0, l = 0, nnz = 0;
+    int lda = 0;          // padded row stride of W (multiple of 64), also rows of T/U
+    int b = 0, B = 0, k = 0;
+    // CSR of P and of P^T
+    int32_t *rp = nullptr, *ci = nullptr, *rpT = nullptr, *ciT = nullptr;
+    void *val[NUM_MODES] = {};   // P values per mode (aliases where modes share)
+    void *valT[NUM_MODES] = {};
+    void *W[NUM_MODES] = {};     // padded l x lda
+    double *c[NUM_MODES] = {};   // P^T 1 in float64 from that mode's values
+    void *Y[2] = {};             // n x B, sized for 8-byte elements
+    void *T = nullptr, *U = nullptr;  // lda x B, 8-byte elements
+    // reduction scratch
+    void *gpart = nullptr;       // split-K partials [ksplit][lda][B] (8-byte)
+    double *Hpart = nullptr, *spart = nullptr;   // [row tiles][B*B], [row tiles][B]
+    double *Gpart = nullptr, *epart = nullptr;   // [spmm blocks][B(B+1)/2], [blocks][B]
+    unsigned *counters = nullptr;                // tile counters + 2 global counters
+    int max_rowtiles = 0, max_ksplit = 0, max_spmm_blocks = 0;
+    SolveState *st = nullptr;
+    // host mirror of xyz / landmark ids for the learned start
+    float *xyz = nullptr;
+    int32_t *lmv = nullptr;
+};
+
+// Launch parameters chosen per (problem, mode); tunable.
+struct LaunchCfg {
+    int spmm_blocks = 0;   // grid of the row-split SpMM (grid-stride)
+    int gemm_rt = 0;       // rows per GEMM tile
+    int gemm_ksplit = 1;   // K splits of the GEMM
+    int gemm_kind = 0;     // 0 vector ALU, 1 MFMA
+};
+
+// Kernel launchers (defined in the .hip files).  All are asynchronous on
+// `stream` and return the hipError_t of the launch.
+hipError_t launch_spmm_t(Mode m, const DevProblem &p, int ycur, hipStream_t stream);
+hipError_t launch_gemm(Mode m, const DevProblem &p, const LaunchCfg &cfg, hipStream_t stream);
+hipError_t launch_spmm(Mode m, const DevProblem &p, const LaunchCfg &cfg, int ynext, hipStream_t stream);
+hipError_t launch_rr_solve(const DevProblem &p, int init, hipStream_t stream);
+hipError_t launch_random_start(Mode m, const DevProblem &p, const LaunchCfg &cfg, int ybuf,
+                               uint64_t seed, hipStream_t stream);
+hipError_t launch_user_start(Mode m, const DevProblem &p, const LaunchCfg &cfg, int ybuf,
+                             const void *X0, hipStream_t stream);
+hipError_t launch_convert_y(Mode from, Mode to, const DevProblem &p, int src, int dst,
+                            hipStream_t stream);
+hipError_t launch_embedding(Mode m, const DevProblem &p, int ybuf, void *Z, int z_double,
+                            hipStream_t stream);
+hipError_t launch_block_out(Mode m, const DevProblem &p, int ybuf, void *X, int x_double,
+                            hipStream_t stream);
+
+hipError_t launch_f32_to_bf16(const float *src, void *dst, int64_t count, hipStream_t stream);
+int gemm_rows_per_tile(Mode m, int B);
+
+// Algorithmic bytes / flops of one launch of each hot kernel.
+double spmm_bytes(Mode m, const DevProblem &p);
+double spmm_t_bytes(Mode m, const DevProblem &p);
+double gemm_bytes(Mode m, const DevProblem &p);
+
+}  // namespace sbmds

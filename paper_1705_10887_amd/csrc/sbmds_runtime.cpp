@@ -1,0 +1,762 @@
+// Host runtime behind the C ABI of include/sbmds.h: validation, the device
+// memory plan of a context, the precision schedule and the stopping rule.
+//
+// Iteration (block subspace iteration with Rayleigh-Ritz on
+// B = -1/2 J P W P^T J, the classical scaling matrix of Section 3.3):
+//   T  = (P^T Y - c e^T/n) C         k_spmm_t   (inner centering, rotation)
+//   U  = -1/2 W T, H = T^T U, s=c^T U k_gemm     (dense landmark product)
+//   Y' = P U - 1 s^T / n, G, e        k_spmm     (outer centering, Gram)
+//   Ritz pairs, bounds, next C        k_rr_solve (float64, one workgroup)
+//
+// Precision schedule: bf16 bulk iterations (BF16_FP32 only) until the Ritz
+// residuals reach the bf16 floor, float32 iterations until they reach the
+// float32 floor, then iterations on the same float32 operator with float64
+// vectors and accumulation until the float64 error bound certifies the
+// requested tolerance.  FP64 precision runs float64 throughout.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstddef>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sbmds.h"
+#include "sbmds_internal.h"
+
+using namespace sbmds;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+struct Summary {  // tail of SolveState read back after each iteration
+    double theta[kMaxB];
+    double res[kMaxB];
+    double bound[kMaxB];
+    double maxbound;
+    double maxres;
+    int iter;
+    int flags;
+    int dead;
+    int nonpos;
+};
+static_assert(sizeof(Summary) == sizeof(SolveState) - offsetof(SolveState, theta), "summary layout");
+
+inline uint16_t host_f2bf(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+inline float host_bf2f(uint16_t h) {
+    uint32_t u = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+int kernel_width(int block) {
+    for (int w : {4, 8, 16, 32, 64})
+        if (block <= w) return w;
+    return -1;
+}
+
+int spmm_rows_per_block(Mode m, int B) {
+    const int ysz = y_elem_bytes(m);
+    int vec = 16 / ysz;
+    if (vec > B) vec = B;
+    const int lpr = B / vec;
+    return 256 / lpr;
+}
+
+struct KStat {
+    std::string name;
+    int64_t launches = 0;
+    double ms = 0, bytes = 0, flops = 0;
+};
+
+struct PendingEv {
+    int stat;
+    hipEvent_t a, b;
+    double bytes, flops;
+};
+
+}  // namespace
+
+struct sbmds_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    sbmds_options opt{};
+    std::vector<DevProblem> probs;
+    std::vector<std::vector<LaunchCfg>> cfg;  // [problem][mode]
+    std::vector<void *> allocs;
+    std::vector<void *> user_x0;               // device copies of user start blocks
+    size_t bytes = 0;
+    Summary *host_sum = nullptr;               // pinned
+    bool timing = false;
+    std::vector<KStat> stats;
+    std::vector<PendingEv> pending;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<int> last_ybuf;                // Y buffer holding the final basis per problem
+    std::vector<int> last_mode;
+};
+
+namespace {
+
+int dalloc(sbmds_ctx *ctx, void **p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    if (ctx->opt.mem_cap && ctx->bytes + bytes > ctx->opt.mem_cap)
+        return fail(SBMDS_ENOMEM, "mem_cap exceeded (" + std::to_string(ctx->bytes + bytes) + " bytes needed)");
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(SBMDS_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    ctx->allocs.push_back(*p);
+    ctx->bytes += bytes;
+    return SBMDS_OK;
+}
+
+#define HIPCHK(expr)                                                                                   \
+    do {                                                                                               \
+        hipError_t _e = (expr);                                                                        \
+        if (_e != hipSuccess) return fail(SBMDS_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+#define OKCHK(expr)                 \
+    do {                            \
+        int _r = (expr);            \
+        if (_r < 0) return _r;      \
+    } while (0)
+
+int check_options(const sbmds_options &o) {
+    if (o.k < 1) return fail(SBMDS_EINVAL, "k must be >= 1");
+    if (o.block < o.k) return fail(SBMDS_EINVAL, "block must be >= k");
+    if (o.block > SBMDS_MAX_BLOCK) return fail(SBMDS_EINVAL, "block must be <= 64");
+    if (o.prec < SBMDS_FP64 || o.prec > SBMDS_BF16_FP32) return fail(SBMDS_EINVAL, "unknown precision");
+    if (o.start < SBMDS_START_RANDOM || o.start > SBMDS_START_USER) return fail(SBMDS_EINVAL, "unknown start");
+    if (!(o.tol > 0.0) || !std::isfinite(o.tol)) return fail(SBMDS_EINVAL, "tol must be positive and finite");
+    if (o.max_iter < 1) return fail(SBMDS_EINVAL, "max_iter must be >= 1");
+    if (o.start == SBMDS_START_LEARNED && o.mlp_weights == nullptr)
+        return fail(SBMDS_EINVAL, "SBMDS_START_LEARNED needs mlp_weights");
+    return SBMDS_OK;
+}
+
+int check_shape(const sbmds_problem &p, const sbmds_options &o, int idx) {
+    const std::string pre = "problem " + std::to_string(idx) + ": ";
+    if (p.mem != SBMDS_MEM_HOST && p.mem != SBMDS_MEM_DEVICE) return fail(SBMDS_EINVAL, pre + "mem must be 0 or 1");
+    if (p.l < 2) return fail(SBMDS_EINVAL, pre + "l must be >= 2");
+    if (p.n < p.l) return fail(SBMDS_EINVAL, pre + "l must be <= n");
+    if (p.n >= (int64_t)1 << 31) return fail(SBMDS_EINVAL, pre + "n must be < 2^31");
+    if (p.l > (int64_t)1 << 20) return fail(SBMDS_EINVAL, pre + "l must be <= 2^20");
+    if (p.nnz < 0 || p.nnz >= (int64_t)1 << 31) return fail(SBMDS_EINVAL, pre + "nnz out of range");
+    if (o.block > p.l - 1) return fail(SBMDS_EINVAL, pre + "block must be <= l - 1");
+    if (!p.P_rowptr) return fail(SBMDS_EINVAL, pre + "P_rowptr is NULL");
+    if (p.nnz > 0 && (!p.P_col || !p.P_val)) return fail(SBMDS_EINVAL, pre + "P_col/P_val is NULL");
+    if (!p.W) return fail(SBMDS_EINVAL, pre + "W is NULL");
+    if (o.start == SBMDS_START_USER && !p.X0) return fail(SBMDS_EINVAL, pre + "X0 is NULL");
+    if (o.start == SBMDS_START_LEARNED && (!p.xyz || !p.landmark_vertex))
+        return fail(SBMDS_EINVAL, pre + "xyz/landmark_vertex needed for the learned start");
+    return SBMDS_OK;
+}
+
+template <typename T>
+int check_contents(const sbmds_problem &p, const int32_t *rp, const int32_t *ci, const T *val, const T *W,
+                   int idx) {
+    const std::string pre = "problem " + std::to_string(idx) + ": ";
+    const int64_t n = p.n, l = p.l;
+    if (rp[0] != 0) return fail(SBMDS_EINVAL, pre + "P_rowptr[0] != 0");
+    if ((int64_t)rp[n] != p.nnz) return fail(SBMDS_EINVAL, pre + "P_rowptr[n] != nnz");
+    for (int64_t i = 0; i < n; ++i)
+        if (rp[i + 1] < rp[i] || (int64_t)rp[i + 1] > p.nnz)
+            return fail(SBMDS_EINVAL, pre + "P_rowptr not non-decreasing within [0, nnz] at row " + std::to_string(i));
+    for (int64_t i = 0; i < n; ++i) {
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            if (ci[e] < 0 || ci[e] >= l)
+                return fail(SBMDS_EINVAL, pre + "P_col out of range in row " + std::to_string(i));
+            if (e > rp[i] && ci[e] <= ci[e - 1])
+                return fail(SBMDS_EINVAL, pre + "P_col not strictly increasing in row " + std::to_string(i));
+            if (!std::isfinite((double)val[e])) return fail(SBMDS_EINVAL, pre + "non-finite P value");
+        }
+    }
+    for (int64_t i = 0; i < l; ++i) {
+        for (int64_t j = 0; j <= i; ++j) {
+            const T a = W[i * l + j], b = W[j * l + i];
+            if (!std::isfinite((double)a)) return fail(SBMDS_EINVAL, pre + "non-finite W entry");
+            if (a != b) return fail(SBMDS_EINVAL, pre + "W is not symmetric");
+        }
+    }
+    return SBMDS_OK;
+}
+
+// Stable counting-sort transpose: row j of P^T lists the vertices of column
+// j in increasing vertex order.
+template <typename T>
+void transpose_csr(int64_t n, int64_t l, const int32_t *rp, const int32_t *ci, const T *val,
+                   std::vector<int32_t> &rpT, std::vector<int32_t> &ciT, std::vector<T> &valT) {
+    const int64_t nnz = rp[n];
+    rpT.assign(l + 1, 0);
+    for (int64_t e = 0; e < nnz; ++e) rpT[ci[e] + 1]++;
+    for (int64_t j = 0; j < l; ++j) rpT[j + 1] += rpT[j];
+    std::vector<int32_t> cur(rpT.begin(), rpT.end() - 1);
+    ciT.resize(nnz);
+    valT.resize(nnz);
+    for (int64_t i = 0; i < n; ++i)
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            const int32_t pos = cur[ci[e]]++;
+            ciT[pos] = (int32_t)i;
+            valT[pos] = val[e];
+        }
+}
+
+template <typename T>
+std::vector<double> colsums(int64_t l, const std::vector<int32_t> &rpT, const std::vector<T> &valT) {
+    std::vector<double> c(l, 0.0);
+    for (int64_t j = 0; j < l; ++j) {
+        double s = 0.0;
+        for (int32_t e = rpT[j]; e < rpT[j + 1]; ++e) s += (double)valT[e];
+        c[j] = s;
+    }
+    return c;
+}
+
+std::vector<Mode> schedule(int prec) {
+    switch (prec) {
+        case SBMDS_FP64: return {MODE_FP64};
+        case SBMDS_FP32: return {MODE_FP32, MODE_F64ACC};
+        default: return {MODE_BF16, MODE_FP32, MODE_F64ACC};
+    }
+}
+
+LaunchCfg default_cfg(Mode m, const DevProblem &p) {
+    LaunchCfg c;
+    const int rpb = spmm_rows_per_block(m, p.B);
+    int64_t want = (p.n + rpb - 1) / rpb;
+    const int cap = p.B >= 64 ? 256 : 512;
+    c.spmm_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, cap));
+    c.gemm_rt = gemm_rows_per_tile(m, p.B);
+    const int rowtiles = (int)((p.l + c.gemm_rt - 1) / c.gemm_rt);
+    int ks = (1024 + rowtiles - 1) / rowtiles;
+    ks = std::max(1, std::min(ks, p.lda / 64));
+    // normalise to what the launcher will use
+    const int kblocks = p.lda / 64;
+    const int kchunk = ((kblocks + ks - 1) / ks) * 64;
+    c.gemm_ksplit = (p.lda + kchunk - 1) / kchunk;
+    return c;
+}
+
+hipEvent_t ev_get(sbmds_ctx *ctx) {
+    if (!ctx->ev_pool.empty()) {
+        hipEvent_t e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int stat_index(sbmds_ctx *ctx, const char *name) {
+    for (size_t i = 0; i < ctx->stats.size(); ++i)
+        if (ctx->stats[i].name == name) return (int)i;
+    ctx->stats.push_back(KStat{name});
+    return (int)ctx->stats.size() - 1;
+}
+
+// Runs `launch` on the context stream, bracketed by events when timing.
+template <typename F>
+int timed(sbmds_ctx *ctx, const char *name, double bytes, double flops, F &&launch) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (ctx->timing) {
+        a = ev_get(ctx);
+        b = ev_get(ctx);
+        if (a && b) HIPCHK(hipEventRecord(a, ctx->stream));
+    }
+    hipError_t e = launch();
+    if (e != hipSuccess) return fail(SBMDS_EHIP, std::string("launch of ") + name + " failed: " + hipGetErrorString(e));
+    if (ctx->timing && a && b) {
+        HIPCHK(hipEventRecord(b, ctx->stream));
+        ctx->pending.push_back(PendingEv{stat_index(ctx, name), a, b, bytes, flops});
+    }
+    return SBMDS_OK;
+}
+
+void collect_timing(sbmds_ctx *ctx) {
+    for (auto &pe : ctx->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, pe.a, pe.b) == hipSuccess) {
+            KStat &s = ctx->stats[pe.stat];
+            s.launches += 1;
+            s.ms += ms;
+            s.bytes += pe.bytes;
+            s.flops += pe.flops;
+        }
+        ctx->ev_pool.push_back(pe.a);
+        ctx->ev_pool.push_back(pe.b);
+    }
+    ctx->pending.clear();
+}
+
+int read_summary(sbmds_ctx *ctx, const DevProblem &p) {
+    HIPCHK(hipMemcpyAsync(ctx->host_sum, reinterpret_cast<const char *>(p.st) + offsetof(SolveState, theta),
+                          sizeof(Summary), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return SBMDS_OK;
+}
+
+int one_iteration(sbmds_ctx *ctx, int pi, Mode m, int ycur) {
+    const DevProblem &p = ctx->probs[pi];
+    const LaunchCfg &cfg = ctx->cfg[pi][m];
+    const double b = p.B;
+    OKCHK(timed(ctx, "spmm_t", spmm_t_bytes(m, p), 2.0 * p.nnz * b,
+                [&] { return launch_spmm_t(m, p, ycur, ctx->stream); }));
+    OKCHK(timed(ctx, "gemm", gemm_bytes(m, p), 2.0 * (double)p.l * p.l * b,
+                [&] { return launch_gemm(m, p, cfg, ctx->stream); }));
+    OKCHK(timed(ctx, "spmm", spmm_bytes(m, p), 2.0 * p.nnz * b,
+                [&] { return launch_spmm(m, p, cfg, ycur ^ 1, ctx->stream); }));
+    OKCHK(timed(ctx, "rr_solve", 0.0, 0.0, [&] { return launch_rr_solve(p, 0, ctx->stream); }));
+    return SBMDS_OK;
+}
+
+double ms_between(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
+    return ms;
+}
+
+int solve_problem(sbmds_ctx *ctx, int pi, sbmds_report *rep) {
+    DevProblem &p = ctx->probs[pi];
+    const sbmds_options &o = ctx->opt;
+    const std::vector<Mode> modes = schedule(o.prec);
+    hipEvent_t e0 = ev_get(ctx), e1 = ev_get(ctx), e2 = ev_get(ctx);
+    HIPCHK(hipEventRecord(e0, ctx->stream));
+
+    // start block
+    int ycur = 0;
+    Mode m = modes[0];
+    if (o.start == SBMDS_START_USER) {
+        OKCHK(timed(ctx, "start", 0.0, 0.0,
+                    [&] { return launch_user_start(m, p, ctx->cfg[pi][m], ycur, ctx->user_x0[pi], ctx->stream); }));
+    } else {
+        // LMDS and learned starts fall back to the random block here
+        OKCHK(timed(ctx, "start", 0.0, 0.0, [&] {
+            return launch_random_start(m, p, ctx->cfg[pi][m], ycur, o.seed + 0x9E3779B97F4A7C15ull * (uint64_t)pi,
+                                       ctx->stream);
+        }));
+    }
+    OKCHK(timed(ctx, "rr_init", 0.0, 0.0, [&] { return launch_rr_solve(p, 1, ctx->stream); }));
+    HIPCHK(hipEventRecord(e1, ctx->stream));
+
+    int iters = 0, it_mode[NUM_MODES] = {0, 0, 0, 0};
+    bool done = false, certified = false;
+    int zbuf = ycur;
+    Mode zmode = m;
+    for (size_t ph = 0; ph < modes.size() && !done; ++ph) {
+        const Mode mm = modes[ph];
+        if (ph > 0) {
+            OKCHK(timed(ctx, "convert", 0.0, 0.0,
+                        [&] { return launch_convert_y(modes[ph - 1], mm, p, ycur, ycur ^ 1, ctx->stream); }));
+            ycur ^= 1;
+        }
+        std::vector<double> hist;
+        const bool final_phase = (mm == MODE_F64ACC || mm == MODE_FP64);
+        while (iters < o.max_iter) {
+            OKCHK(one_iteration(ctx, pi, mm, ycur));
+            OKCHK(read_summary(ctx, p));
+            zbuf = ycur;
+            zmode = mm;
+            ycur ^= 1;
+            ++iters;
+            ++it_mode[mm];
+            const Summary &s = *ctx->host_sum;
+            if (s.flags & SF_NONFINITE) return fail(SBMDS_EBREAKDOWN, "non-finite values in the block solver");
+            hist.push_back(s.maxres);
+            const size_t h = hist.size();
+            if (final_phase) {
+                if (s.maxbound <= o.tol) {
+                    done = true;
+                    certified = true;
+                    break;
+                }
+                continue;
+            }
+            if (mm == MODE_FP32 && (o.flags & SBMDS_FLAG_NO_CERTIFY) && s.maxbound <= o.tol) {
+                done = true;
+                break;
+            }
+            const double floor_res = (mm == MODE_BF16) ? 5e-2 : 1e-3;
+            const bool plateau = h >= 4 && hist[h - 1] > 0.7 * hist[h - 3] && hist[h - 1] > 0.7 * hist[h - 4];
+            if (s.maxres <= floor_res || plateau) {
+                if (mm == MODE_FP32 && (o.flags & SBMDS_FLAG_NO_CERTIFY)) continue;
+                break;  // next phase
+            }
+        }
+        if (iters >= o.max_iter) break;
+    }
+    HIPCHK(hipEventRecord(e2, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->last_ybuf[pi] = zbuf;
+    ctx->last_mode[pi] = zmode;
+    const Summary &s = *ctx->host_sum;
+    if (rep) {
+        std::memset(rep, 0, sizeof(*rep));
+        rep->status = done ? SBMDS_OK : SBMDS_ENOCONV;
+        rep->iters_bf16 = it_mode[MODE_BF16];
+        rep->iters_fp32 = it_mode[MODE_FP32];
+        rep->iters_fp64 = it_mode[MODE_F64ACC] + it_mode[MODE_FP64];
+        rep->nonpositive = s.nonpos;
+        rep->certified = certified ? 1 : 0;
+        rep->ms_start = ms_between(e0, e1);
+        rep->ms_iter = ms_between(e1, e2);
+        rep->ms_total = ms_between(e0, e2);
+        for (int i = 0; i < p.b; ++i) {
+            rep->eig[i] = s.theta[i];
+            rep->err_bound[i] = s.bound[i];
+            rep->resid[i] = std::fabs(s.theta[i]) > 0 ? s.res[i] / std::fabs(s.theta[i]) : s.res[i];
+        }
+    }
+    ctx->ev_pool.push_back(e0);
+    ctx->ev_pool.push_back(e1);
+    ctx->ev_pool.push_back(e2);
+    return done ? SBMDS_OK : SBMDS_ENOCONV;
+}
+
+template <typename T>
+int upload_problem(sbmds_ctx *ctx, const sbmds_problem &in, DevProblem &p, const int32_t *rp, const int32_t *ci,
+                   const T *val, bool fp64) {
+    const int64_t n = p.n, l = p.l, nnz = p.nnz;
+    hipStream_t s = ctx->stream;
+    // transposed CSR and column sums on the host
+    std::vector<int32_t> rpT, ciT;
+    std::vector<T> valT;
+    transpose_csr<T>(n, l, rp, ci, val, rpT, ciT, valT);
+
+    OKCHK(dalloc(ctx, (void **)&p.rp, (n + 1) * 4));
+    OKCHK(dalloc(ctx, (void **)&p.ci, nnz * 4));
+    OKCHK(dalloc(ctx, (void **)&p.rpT, (l + 1) * 4));
+    OKCHK(dalloc(ctx, (void **)&p.ciT, nnz * 4));
+    HIPCHK(hipMemcpyAsync(p.rp, rp, (n + 1) * 4, hipMemcpyHostToDevice, s));
+    if (nnz) HIPCHK(hipMemcpyAsync(p.ci, ci, nnz * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(p.rpT, rpT.data(), (l + 1) * 4, hipMemcpyHostToDevice, s));
+    if (nnz) HIPCHK(hipMemcpyAsync(p.ciT, ciT.data(), nnz * 4, hipMemcpyHostToDevice, s));
+
+    const size_t wbytes_row = (size_t)p.lda * sizeof(T);
+    void *Wd = nullptr, *vd = nullptr, *vTd = nullptr, *cd = nullptr;
+    OKCHK(dalloc(ctx, &vd, nnz * sizeof(T)));
+    OKCHK(dalloc(ctx, &vTd, nnz * sizeof(T)));
+    OKCHK(dalloc(ctx, &Wd, (size_t)l * wbytes_row));
+    OKCHK(dalloc(ctx, &cd, l * 8));
+    if (nnz) {
+        HIPCHK(hipMemcpyAsync(vd, val, nnz * sizeof(T), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(vTd, valT.data(), nnz * sizeof(T), hipMemcpyHostToDevice, s));
+    }
+    HIPCHK(hipMemsetAsync(Wd, 0, (size_t)l * wbytes_row, s));
+    HIPCHK(hipMemcpy2DAsync(Wd, wbytes_row, in.W, (size_t)l * sizeof(T), (size_t)l * sizeof(T), l,
+                            in.mem == SBMDS_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    std::vector<double> c = colsums<T>(l, rpT, valT);
+    HIPCHK(hipMemcpyAsync(cd, c.data(), l * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));  // host vectors go out of scope
+    if (fp64) {
+        p.val[MODE_FP64] = vd;
+        p.valT[MODE_FP64] = vTd;
+        p.W[MODE_FP64] = Wd;
+        p.c[MODE_FP64] = (double *)cd;
+    } else {
+        for (Mode m : {MODE_FP32, MODE_F64ACC}) {
+            p.val[m] = vd;
+            p.valT[m] = vTd;
+            p.W[m] = Wd;
+            p.c[m] = (double *)cd;
+        }
+        if (ctx->opt.prec == SBMDS_BF16_FP32) {
+            void *v16 = nullptr, *vT16 = nullptr, *W16 = nullptr, *c16 = nullptr;
+            OKCHK(dalloc(ctx, &v16, nnz * 2));
+            OKCHK(dalloc(ctx, &vT16, nnz * 2));
+            OKCHK(dalloc(ctx, &W16, (size_t)l * p.lda * 2));
+            OKCHK(dalloc(ctx, &c16, l * 8));
+            HIPCHK(launch_f32_to_bf16((const float *)vd, v16, nnz, s));
+            HIPCHK(launch_f32_to_bf16((const float *)vTd, vT16, nnz, s));
+            HIPCHK(launch_f32_to_bf16((const float *)Wd, W16, (int64_t)l * p.lda, s));
+            std::vector<float> vb(valT.size());
+            for (size_t i = 0; i < valT.size(); ++i) vb[i] = host_bf2f(host_f2bf((float)valT[i]));
+            std::vector<double> cb = colsums<float>(l, rpT, vb);
+            HIPCHK(hipMemcpyAsync(c16, cb.data(), l * 8, hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
+            p.val[MODE_BF16] = v16;
+            p.valT[MODE_BF16] = vT16;
+            p.W[MODE_BF16] = W16;
+            p.c[MODE_BF16] = (double *)c16;
+        }
+    }
+    return SBMDS_OK;
+}
+
+int device_ok(int *dev) {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) return fail(SBMDS_ENODEV, "no HIP device available");
+    HIPCHK(hipGetDevice(dev));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, *dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(SBMDS_ENODEV, std::string("device is ") + prop.gcnArchName + ", this library targets gfx950");
+    return SBMDS_OK;
+}
+
+int create_impl(const sbmds_problem *probs, int nprob, const sbmds_options *opt_in, sbmds_ctx **out) {
+    if (!out) return fail(SBMDS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!probs || nprob < 1) return fail(SBMDS_EINVAL, "need at least one problem");
+    sbmds_options o;
+    sbmds_default_options(&o);
+    if (opt_in) o = *opt_in;
+    OKCHK(check_options(o));
+    for (int i = 0; i < nprob; ++i) OKCHK(check_shape(probs[i], o, i));
+    const bool fp64 = o.prec == SBMDS_FP64;
+    for (int i = 0; i < nprob; ++i) {
+        const sbmds_problem &p = probs[i];
+        if (p.mem != SBMDS_MEM_HOST) continue;
+        if (fp64)
+            OKCHK(check_contents<double>(p, p.P_rowptr, p.P_col, (const double *)p.P_val, (const double *)p.W, i));
+        else
+            OKCHK(check_contents<float>(p, p.P_rowptr, p.P_col, (const float *)p.P_val, (const float *)p.W, i));
+    }
+    int dev = 0;
+    OKCHK(device_ok(&dev));
+
+    sbmds_ctx *ctx = new sbmds_ctx();
+    ctx->device = dev;
+    ctx->opt = o;
+    ctx->stream = (hipStream_t)o.stream;
+    ctx->timing = (o.flags & SBMDS_FLAG_KERNEL_TIMING) != 0;
+    ctx->probs.resize(nprob);
+    ctx->cfg.resize(nprob);
+    ctx->user_x0.assign(nprob, nullptr);
+    ctx->last_ybuf.assign(nprob, 0);
+    ctx->last_mode.assign(nprob, (int)schedule(o.prec).back());
+    auto cleanup = [&](int rc) {
+        sbmds_destroy(ctx);
+        return rc;
+    };
+    if (hipHostMalloc((void **)&ctx->host_sum, sizeof(Summary), hipHostMallocDefault) != hipSuccess)
+        return cleanup(fail(SBMDS_ENOMEM, "pinned host allocation failed"));
+
+    const size_t esz = fp64 ? 8 : 4;
+    for (int i = 0; i < nprob; ++i) {
+        const sbmds_problem &in = probs[i];
+        DevProblem &p = ctx->probs[i];
+        p.n = in.n;
+        p.l = in.l;
+        p.nnz = in.nnz;
+        p.lda = (int)((in.l + 63) / 64) * 64;
+        p.b = o.block;
+        p.B = kernel_width(o.block);
+        p.k = o.k;
+        // host copies of device-resident inputs, then content validation
+        std::vector<int32_t> hrp, hci;
+        std::vector<char> hval, hW;
+        const int32_t *rp = in.P_rowptr, *ci = in.P_col;
+        const void *val = in.P_val;
+        if (in.mem == SBMDS_MEM_DEVICE) {
+            hrp.resize(in.n + 1);
+            hci.resize(std::max<int64_t>(in.nnz, 1));
+            hval.resize(std::max<int64_t>(in.nnz, 1) * esz);
+            hW.resize((size_t)in.l * in.l * esz);
+            if (hipMemcpy(hrp.data(), in.P_rowptr, (in.n + 1) * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+                (in.nnz && hipMemcpy(hci.data(), in.P_col, in.nnz * 4, hipMemcpyDeviceToHost) != hipSuccess) ||
+                (in.nnz && hipMemcpy(hval.data(), in.P_val, in.nnz * esz, hipMemcpyDeviceToHost) != hipSuccess) ||
+                hipMemcpy(hW.data(), in.W, hW.size(), hipMemcpyDeviceToHost) != hipSuccess)
+                return cleanup(fail(SBMDS_EHIP, "copying device inputs for validation failed"));
+            rp = hrp.data();
+            ci = hci.data();
+            val = hval.data();
+            int rc = fp64 ? check_contents<double>(in, rp, ci, (const double *)val, (const double *)hW.data(), i)
+                          : check_contents<float>(in, rp, ci, (const float *)val, (const float *)hW.data(), i);
+            if (rc < 0) return cleanup(rc);
+        }
+        int rc = fp64 ? upload_problem<double>(ctx, in, p, rp, ci, (const double *)val, true)
+                      : upload_problem<float>(ctx, in, p, rp, ci, (const float *)val, false);
+        if (rc < 0) return cleanup(rc);
+
+        // launch configurations and scratch sizes
+        ctx->cfg[i].resize(NUM_MODES);
+        for (int m = 0; m < NUM_MODES; ++m) {
+            ctx->cfg[i][m] = default_cfg((Mode)m, p);
+            const int rt = ctx->cfg[i][m].gemm_rt;
+            p.max_rowtiles = std::max(p.max_rowtiles, (int)((p.l + rt - 1) / rt));
+            p.max_ksplit = std::max(p.max_ksplit, ctx->cfg[i][m].gemm_ksplit);
+            p.max_spmm_blocks = std::max(p.max_spmm_blocks, ctx->cfg[i][m].spmm_blocks);
+        }
+        const int B = p.B;
+        const size_t E = (size_t)B * (B + 1) / 2;
+        rc = dalloc(ctx, &p.Y[0], (size_t)p.n * B * 8);
+        if (!rc) rc = dalloc(ctx, &p.Y[1], (size_t)p.n * B * 8);
+        if (!rc) rc = dalloc(ctx, &p.T, (size_t)p.lda * B * 8);
+        if (!rc) rc = dalloc(ctx, &p.U, (size_t)p.lda * B * 8);
+        if (!rc) rc = dalloc(ctx, &p.gpart, (size_t)p.max_ksplit * p.lda * B * 8);
+        if (!rc) rc = dalloc(ctx, (void **)&p.Hpart, (size_t)p.max_rowtiles * B * B * 8);
+        if (!rc) rc = dalloc(ctx, (void **)&p.spart, (size_t)p.max_rowtiles * B * 8);
+        if (!rc) rc = dalloc(ctx, (void **)&p.Gpart, (size_t)p.max_spmm_blocks * E * 8);
+        if (!rc) rc = dalloc(ctx, (void **)&p.epart, (size_t)p.max_spmm_blocks * B * 8);
+        if (!rc) rc = dalloc(ctx, (void **)&p.counters, (size_t)(p.max_rowtiles + 2) * 4);
+        if (!rc) rc = dalloc(ctx, (void **)&p.st, sizeof(SolveState));
+        if (rc < 0) return cleanup(rc);
+        if (hipMemsetAsync(p.T, 0, (size_t)p.lda * B * 8, ctx->stream) != hipSuccess ||
+            hipMemsetAsync(p.U, 0, (size_t)p.lda * B * 8, ctx->stream) != hipSuccess ||
+            hipMemsetAsync(p.counters, 0, (size_t)(p.max_rowtiles + 2) * 4, ctx->stream) != hipSuccess ||
+            hipMemsetAsync(p.st, 0, sizeof(SolveState), ctx->stream) != hipSuccess)
+            return cleanup(fail(SBMDS_EHIP, "hipMemsetAsync failed"));
+        if (o.start == SBMDS_START_USER) {
+            void *x0 = nullptr;
+            const size_t xb = (size_t)p.n * p.b * esz;
+            if ((rc = dalloc(ctx, &x0, xb)) < 0) return cleanup(rc);
+            if (hipMemcpyAsync(x0, in.X0, xb,
+                               in.mem == SBMDS_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                               ctx->stream) != hipSuccess)
+                return cleanup(fail(SBMDS_EHIP, "copying X0 failed"));
+            ctx->user_x0[i] = x0;
+        }
+    }
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return cleanup(fail(SBMDS_EHIP, "create: stream sync failed"));
+    *out = ctx;
+    return SBMDS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sbmds_default_options(sbmds_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->k = 3;
+    o->block = 16;
+    o->prec = SBMDS_FP32;
+    o->start = SBMDS_START_RANDOM;
+    o->tol = 1e-6;
+    o->max_iter = 500;
+    o->seed = 12345;
+    o->stream = nullptr;
+}
+
+int sbmds_create(const sbmds_problem *probs, int nprob, const sbmds_options *opt, sbmds_ctx **out) {
+    g_err.clear();
+    try {
+        return create_impl(probs, nprob, opt, out);
+    } catch (const std::exception &e) {
+        return fail(SBMDS_ENOMEM, std::string("host exception: ") + e.what());
+    } catch (...) {
+        return fail(SBMDS_ENOMEM, "unknown host exception");
+    }
+}
+
+int sbmds_embed(sbmds_ctx *ctx, double *eigvals, void *Z, int Z_mem, sbmds_report *reports) {
+    g_err.clear();
+    if (!ctx) return fail(SBMDS_EINVAL, "ctx is NULL");
+    if (Z && Z_mem != SBMDS_MEM_HOST && Z_mem != SBMDS_MEM_DEVICE) return fail(SBMDS_EINVAL, "Z_mem must be 0 or 1");
+    try {
+        HIPCHK(hipSetDevice(ctx->device));
+        int worst = SBMDS_OK;
+        const bool zdouble = ctx->opt.prec == SBMDS_FP64;
+        const size_t zsz = zdouble ? 8 : 4;
+        size_t zoff = 0;
+        for (int i = 0; i < (int)ctx->probs.size(); ++i) {
+            int rc = solve_problem(ctx, i, reports ? &reports[i] : nullptr);
+            if (rc < 0) return rc;
+            if (rc > worst) worst = rc;
+            const DevProblem &p = ctx->probs[i];
+            if (eigvals)
+                for (int j = 0; j < p.k; ++j) eigvals[(size_t)i * p.k + j] = ctx->host_sum->theta[j];
+            if (Z) {
+                const size_t bytes = (size_t)p.n * p.k * zsz;
+                char *dst = (char *)Z + zoff;
+                void *dz = dst;
+                if (Z_mem == SBMDS_MEM_HOST) HIPCHK(hipMalloc(&dz, bytes));
+                OKCHK(timed(ctx, "embedding", 0.0, 0.0, [&] {
+                    return launch_embedding((Mode)ctx->last_mode[i], p, ctx->last_ybuf[i], dz, zdouble ? 1 : 0,
+                                            ctx->stream);
+                }));
+                if (Z_mem == SBMDS_MEM_HOST) {
+                    hipError_t ce = hipMemcpyAsync(dst, dz, bytes, hipMemcpyDeviceToHost, ctx->stream);
+                    if (ce == hipSuccess) ce = hipStreamSynchronize(ctx->stream);
+                    (void)hipFree(dz);
+                    if (ce != hipSuccess) return fail(SBMDS_EHIP, std::string("copying Z failed: ") + hipGetErrorString(ce));
+                }
+                zoff += bytes;
+            }
+        }
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        if (ctx->timing) collect_timing(ctx);
+        return worst;
+    } catch (const std::exception &e) {
+        return fail(SBMDS_ENOMEM, std::string("host exception: ") + e.what());
+    }
+}
+
+int sbmds_get_block(sbmds_ctx *ctx, int prob, void *X, int X_mem) {
+    g_err.clear();
+    if (!ctx || !X) return fail(SBMDS_EINVAL, "ctx and X must be non-NULL");
+    if (prob < 0 || prob >= (int)ctx->probs.size()) return fail(SBMDS_EINVAL, "problem index out of range");
+    if (X_mem != SBMDS_MEM_HOST && X_mem != SBMDS_MEM_DEVICE) return fail(SBMDS_EINVAL, "X_mem must be 0 or 1");
+    const DevProblem &p = ctx->probs[prob];
+    const bool xd = ctx->opt.prec == SBMDS_FP64;
+    const size_t bytes = (size_t)p.n * p.b * (xd ? 8 : 4);
+    void *dx = X;
+    HIPCHK(hipSetDevice(ctx->device));
+    if (X_mem == SBMDS_MEM_HOST) HIPCHK(hipMalloc(&dx, bytes));
+    hipError_t e = launch_block_out((Mode)ctx->last_mode[prob], p, ctx->last_ybuf[prob], dx, xd ? 1 : 0, ctx->stream);
+    if (e == hipSuccess && X_mem == SBMDS_MEM_HOST) e = hipMemcpyAsync(X, dx, bytes, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (X_mem == SBMDS_MEM_HOST) (void)hipFree(dx);
+    if (e != hipSuccess) return fail(SBMDS_EHIP, std::string("sbmds_get_block: ") + hipGetErrorString(e));
+    return SBMDS_OK;
+}
+
+int sbmds_kernel_stats(sbmds_ctx *ctx, sbmds_kernel_stat *out, int max) {
+    if (!ctx) return fail(SBMDS_EINVAL, "ctx is NULL");
+    const int nst = (int)ctx->stats.size();
+    for (int i = 0; i < nst && out && i < max; ++i) {
+        std::memset(&out[i], 0, sizeof(out[i]));
+        std::snprintf(out[i].name, sizeof(out[i].name), "%s", ctx->stats[i].name.c_str());
+        out[i].launches = ctx->stats[i].launches;
+        out[i].ms_total = ctx->stats[i].ms;
+        out[i].bytes_total = ctx->stats[i].bytes;
+        out[i].flops_total = ctx->stats[i].flops;
+    }
+    return nst;
+}
+
+void sbmds_reset_kernel_stats(sbmds_ctx *ctx) {
+    if (ctx) ctx->stats.clear();
+}
+
+void sbmds_destroy(sbmds_ctx *ctx) {
+    if (!ctx) return;
+    if (ctx->stream || !ctx->allocs.empty()) (void)hipStreamSynchronize(ctx->stream);
+    for (void *p : ctx->allocs) (void)hipFree(p);
+    for (auto &pe : ctx->pending) {
+        (void)hipEventDestroy(pe.a);
+        (void)hipEventDestroy(pe.b);
+    }
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    if (ctx->host_sum) (void)hipHostFree(ctx->host_sum);
+    delete ctx;
+}
+
+const char *sbmds_last_error(void) { return g_err.c_str(); }
+
+int sbmds_version(void) { return (SBMDS_VERSION_MAJOR << 16) | SBMDS_VERSION_MINOR; }
+
+}  // extern "C"

@@ -1,0 +1,579 @@
+// Sparse products with the interpolation operator and the n-space block
+// kernels.
+//
+// The operator of Section 3.3 is applied as B X = -1/2 J P W P^T J X.  The
+// two sparse factors are
+//   k_spmm_t : T = (P^T Y - c e_x^T / n) C      (inner centering, basis rotation)
+//   k_spmm   : Y' = P U - 1 s^T / n              (outer centering)
+// where X = J Y C is the current orthonormal basis, c = P^T 1, e_x = 1^T Y and
+// s = c^T U.  J = I - 1 1^T / n is never formed: both centerings are rank-one
+// corrections (the paper notes J is identity plus rank one, Section 3.3).
+//
+// k_spmm additionally reduces the Gram matrix Y'^T Y' and the column sums
+// 1^T Y' of the values it stores (after rounding to the storage type), so the
+// next orthonormalisation needs no extra pass over Y'.
+#include "sbmds_common.h"
+
+namespace sbmds {
+
+// ---------------------------------------------------------------------------
+// Row-split SpMM with fused outer centering and Gram/column-sum epilogue.
+// A row is handled by LPR lanes, each owning VEC consecutive columns of the
+// block; a 256-thread block covers RPB rows per step and strides over rows.
+// ---------------------------------------------------------------------------
+template <int M, int B>
+struct SpmmShape {
+    using TY = typename Traits<M>::TY;
+    static constexpr int VEC = VecOf<TY, B>::v;
+    static constexpr int LPR = B / VEC;
+    static constexpr int RPB = 256 / LPR;
+    static constexpr int E = B * (B + 1) / 2;
+    static constexpr int NQ = (E + 255) / 256;
+};
+
+template <int B>
+__device__ __forceinline__ void gram_tile_accumulate(const double (*tile)[B], int rows, int tid,
+                                                     const int *ea, const int *eb, int nq,
+                                                     double *gacc, double &eacc) {
+    for (int q = 0; q < nq; ++q) {
+        if (ea[q] >= 0) {
+            double s = 0.0;
+            for (int r = 0; r < rows; ++r) s += tile[r][ea[q]] * tile[r][eb[q]];
+            gacc[q] += s;
+        }
+    }
+    if (tid < B) {
+        double s = 0.0;
+        for (int r = 0; r < rows; ++r) s += tile[r][tid];
+        eacc += s;
+    }
+}
+
+// Final reduction of Gram / column-sum partials (run by the last block).
+template <int B>
+__device__ void gram_finish(const double *__restrict__ Gpart, const double *__restrict__ epart,
+                            int nblk, double *__restrict__ G, double *__restrict__ e) {
+    constexpr int E = B * (B + 1) / 2;
+    for (int ent = threadIdx.x; ent < E; ent += blockDim.x) {
+        double s = 0.0;
+        for (int k = 0; k < nblk; ++k) s += Gpart[(size_t)k * E + ent];
+        int a, b;
+        tri_index(ent, B, a, b);
+        G[a * B + b] = s;
+        G[b * B + a] = s;
+    }
+    for (int j = threadIdx.x; j < B; j += blockDim.x) {
+        double s = 0.0;
+        for (int k = 0; k < nblk; ++k) s += epart[(size_t)k * B + j];
+        e[j] = s;
+    }
+}
+
+template <int M, int B>
+__global__ __launch_bounds__(256) void k_spmm(int n, const int32_t *__restrict__ rp,
+                                              const int32_t *__restrict__ ci,
+                                              const typename Traits<M>::TP *__restrict__ val,
+                                              const typename Traits<M>::TU *__restrict__ U,
+                                              SolveState *__restrict__ st,
+                                              typename Traits<M>::TY *__restrict__ Y,
+                                              double *__restrict__ Gpart, double *__restrict__ epart,
+                                              unsigned *__restrict__ counter) {
+    using Tr = Traits<M>;
+    using TA = typename Tr::TA;
+    using TY = typename Tr::TY;
+    using TU = typename Tr::TU;
+    using S = SpmmShape<M, B>;
+    constexpr int VEC = S::VEC, LPR = S::LPR, RPB = S::RPB, E = S::E, NQ = S::NQ;
+    __shared__ double tile[RPB][B];
+
+    const int tid = threadIdx.x;
+    const int g = tid % LPR;
+    const int slot = tid / LPR;
+    const double inv_n = 1.0 / (double)n;
+    TA sc[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) sc[v] = (TA)(st->s[g * VEC + v] * inv_n);
+
+    int ea[NQ], eb[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        int ent = tid + q * 256;
+        if (ent < E) tri_index(ent, B, ea[q], eb[q]);
+        else ea[q] = eb[q] = -1;
+    }
+    double gacc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) gacc[q] = 0.0;
+    double eacc = 0.0;
+
+    for (int64_t base = (int64_t)blockIdx.x * RPB; base < n; base += (int64_t)gridDim.x * RPB) {
+        const int64_t row = base + slot;
+        if (row < n) {
+            TA acc[VEC];
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[v] = (TA)0;
+            const int beg = rp[row], end = rp[row + 1];
+            for (int e = beg; e < end; ++e) {
+                const int c = ci[e];
+                const TA pv = up<TA>(val[e]);
+                Pack<TU, VEC> u = ldp<TU, VEC>(U + (size_t)c * B + g * VEC);
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) acc[v] += pv * up<TA>(u.v[v]);
+            }
+            Pack<TY, VEC> o;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) o.v[v] = down<TY>(acc[v] - sc[v]);
+            stp<TY, VEC>(Y + (size_t)row * B + g * VEC, o);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) tile[slot][g * VEC + v] = (double)up<TA>(o.v[v]);
+        } else {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) tile[slot][g * VEC + v] = 0.0;
+        }
+        __syncthreads();
+        gram_tile_accumulate<B>(tile, RPB, tid, ea, eb, NQ, gacc, eacc);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+        if (ea[q] >= 0) Gpart[(size_t)blockIdx.x * E + tid + q * 256] = gacc[q];
+    if (tid < B) epart[(size_t)blockIdx.x * B + tid] = eacc;
+    if (arrive_last(counter, gridDim.x)) {
+        gram_finish<B>(Gpart, epart, gridDim.x, st->G, st->e_new);
+        if (tid == 0) *counter = 0u;
+    }
+}
+
+// Gram matrix and column sums of a stored block (start blocks).
+template <int M, int B>
+__global__ __launch_bounds__(256) void k_gram(int n, const typename Traits<M>::TY *__restrict__ Y,
+                                              SolveState *__restrict__ st,
+                                              double *__restrict__ Gpart, double *__restrict__ epart,
+                                              unsigned *__restrict__ counter) {
+    using Tr = Traits<M>;
+    using TY = typename Tr::TY;
+    using S = SpmmShape<M, B>;
+    constexpr int VEC = S::VEC, LPR = S::LPR, RPB = S::RPB, E = S::E, NQ = S::NQ;
+    __shared__ double tile[RPB][B];
+    const int tid = threadIdx.x;
+    const int g = tid % LPR;
+    const int slot = tid / LPR;
+    int ea[NQ], eb[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        int ent = tid + q * 256;
+        if (ent < E) tri_index(ent, B, ea[q], eb[q]);
+        else ea[q] = eb[q] = -1;
+    }
+    double gacc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) gacc[q] = 0.0;
+    double eacc = 0.0;
+    for (int64_t base = (int64_t)blockIdx.x * RPB; base < n; base += (int64_t)gridDim.x * RPB) {
+        const int64_t row = base + slot;
+        if (row < n) {
+            Pack<TY, VEC> y = ldp<TY, VEC>(Y + (size_t)row * B + g * VEC);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) tile[slot][g * VEC + v] = (double)up<typename Tr::TA>(y.v[v]);
+        } else {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) tile[slot][g * VEC + v] = 0.0;
+        }
+        __syncthreads();
+        gram_tile_accumulate<B>(tile, RPB, tid, ea, eb, NQ, gacc, eacc);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+        if (ea[q] >= 0) Gpart[(size_t)blockIdx.x * E + tid + q * 256] = gacc[q];
+    if (tid < B) epart[(size_t)blockIdx.x * B + tid] = eacc;
+    if (arrive_last(counter, gridDim.x)) {
+        gram_finish<B>(Gpart, epart, gridDim.x, st->G, st->e_new);
+        if (tid == 0) *counter = 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// SpMM with the transposed operator (CSR of P^T, one wave per landmark row),
+// inner centering and the b x b basis rotation C.
+// ---------------------------------------------------------------------------
+template <int M, int B>
+__global__ __launch_bounds__(256) void k_spmm_t(int l, int n, const int32_t *__restrict__ rpT,
+                                                const int32_t *__restrict__ ciT,
+                                                const typename Traits<M>::TP *__restrict__ valT,
+                                                const typename Traits<M>::TY *__restrict__ Y,
+                                                const double *__restrict__ c,
+                                                const SolveState *__restrict__ st,
+                                                typename Traits<M>::TT *__restrict__ T) {
+    using Tr = Traits<M>;
+    using TA = typename Tr::TA;
+    using TY = typename Tr::TY;
+    using TT = typename Tr::TT;
+    constexpr int VEC = VecOf<TY, B>::v;
+    constexpr int LPR = B / VEC;
+    constexpr int EPW = 64 / LPR;
+    __shared__ double Cl[B * B];
+    __shared__ double ex[B];
+    __shared__ double rowbuf[4][B];
+
+    const int tid = threadIdx.x;
+    for (int i = tid; i < B * B; i += 256) Cl[i] = st->C[i];
+    if (tid < B) ex[tid] = st->e_x[tid];
+
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    const int g = lane % LPR;
+    const int slot = lane / LPR;
+    const int64_t j = (int64_t)blockIdx.x * 4 + wave;
+
+    TA acc[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] = (TA)0;
+    if (j < l) {
+        const int beg = rpT[j], end = rpT[j + 1];
+        for (int e = beg + slot; e < end; e += EPW) {
+            const TA pv = up<TA>(valT[e]);
+            const int vert = ciT[e];
+            Pack<TY, VEC> y = ldp<TY, VEC>(Y + (size_t)vert * B + g * VEC);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[v] += pv * up<TA>(y.v[v]);
+        }
+    }
+#pragma unroll
+    for (int m = LPR; m < 64; m <<= 1) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[v] += __shfl_xor(acc[v], m);
+    }
+    __syncthreads();  // Cl and ex loaded
+    if (j < l && slot == 0) {
+        const double cj = c[j] / (double)n;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) rowbuf[wave][g * VEC + v] = (double)acc[v] - cj * ex[g * VEC + v];
+    }
+    __syncthreads();
+    if (j < l && lane < B) {
+        double t = 0.0;
+#pragma unroll 8
+        for (int i = 0; i < B; ++i) t += rowbuf[wave][i] * Cl[i * B + lane];
+        T[(size_t)j * B + lane] = down<TT>((TA)t);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Start blocks, precision changes and outputs.
+// ---------------------------------------------------------------------------
+
+// Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+// easy as 1, 2, 3", SC 2011): counter = (row, column, 0, 0), key = seed.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)M0 * c[0];
+        uint64_t p1 = (uint64_t)M1 * c[2];
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c[1] ^ k0;
+        uint32_t n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+}
+
+// Standard normal from two uniforms in (0, 1] (Box-Muller).
+__device__ __forceinline__ double gauss_from(uint32_t a, uint32_t b) {
+    const double u1 = ((double)a + 1.0) * (1.0 / 4294967296.0);
+    const double u2 = (double)b * (1.0 / 4294967296.0);
+    return sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
+}
+
+template <int M, int B>
+__global__ __launch_bounds__(256) void k_random_block(int n, int b, uint64_t seed,
+                                                      typename Traits<M>::TY *__restrict__ Y) {
+    using TY = typename Traits<M>::TY;
+    using TA = typename Traits<M>::TA;
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)n * B) return;
+    const int64_t row = idx / B;
+    const int col = (int)(idx % B);
+    double z = 0.0;
+    if (col < b) {
+        uint32_t ctr[4] = {(uint32_t)row, (uint32_t)col, (uint32_t)(row >> 32), 0u};
+        philox4x32_10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32));
+        z = gauss_from(ctr[0], ctr[1]);
+    }
+    Y[idx] = down<TY>((TA)z);
+}
+
+template <typename TS, int M, int B>
+__global__ __launch_bounds__(256) void k_load_block(int n, int b, const TS *__restrict__ X0,
+                                                    typename Traits<M>::TY *__restrict__ Y) {
+    using TY = typename Traits<M>::TY;
+    using TA = typename Traits<M>::TA;
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)n * B) return;
+    const int64_t row = idx / B;
+    const int col = (int)(idx % B);
+    TA v = col < b ? (TA)X0[row * b + col] : (TA)0;
+    Y[idx] = down<TY>(v);
+}
+
+template <int MF, int MT>
+__global__ __launch_bounds__(256) void k_convert(int64_t count, const typename Traits<MF>::TY *__restrict__ src,
+                                                 typename Traits<MT>::TY *__restrict__ dst) {
+    using TAt = typename Traits<MT>::TA;
+    using TYt = typename Traits<MT>::TY;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < count) dst[i] = down<TYt>((TAt)up<double>(src[i]));
+}
+
+// Z = J Y Zmap restricted to the first k columns: Z_ij = sum_a Y_ia Zmap_aj - zshift_j.
+template <int M, int B, typename TZ>
+__global__ __launch_bounds__(256) void k_embedding(int n, int k, const typename Traits<M>::TY *__restrict__ Y,
+                                                   const SolveState *__restrict__ st, TZ *__restrict__ Z) {
+    __shared__ double Zm[B * B];
+    __shared__ double zs[B];
+    for (int i = threadIdx.x; i < B * B; i += 256) Zm[i] = st->Zmap[i];
+    if (threadIdx.x < B) zs[threadIdx.x] = st->zshift[threadIdx.x];
+    __syncthreads();
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (row >= n) return;
+    double y[B];
+#pragma unroll
+    for (int a = 0; a < B; ++a) y[a] = up<double>(Y[row * B + a]);
+    for (int j = 0; j < k; ++j) {
+        double z = -zs[j];
+#pragma unroll
+        for (int a = 0; a < B; ++a) z += y[a] * Zm[a * B + j];
+        Z[row * k + j] = (TZ)z;
+    }
+}
+
+// X = J Y C (the current orthonormal basis), first b columns.
+template <int M, int B, typename TX>
+__global__ __launch_bounds__(256) void k_block_out(int n, int b, const typename Traits<M>::TY *__restrict__ Y,
+                                                   const SolveState *__restrict__ st, TX *__restrict__ X) {
+    __shared__ double Cl[B * B];
+    __shared__ double sh[B];
+    for (int i = threadIdx.x; i < B * B; i += 256) Cl[i] = st->C[i];
+    __syncthreads();
+    if (threadIdx.x < B) {
+        double s = 0.0;
+        for (int a = 0; a < B; ++a) s += st->e_x[a] * Cl[a * B + threadIdx.x];
+        sh[threadIdx.x] = s / (double)n;
+    }
+    __syncthreads();
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (row >= n) return;
+    double y[B];
+#pragma unroll
+    for (int a = 0; a < B; ++a) y[a] = up<double>(Y[row * B + a]);
+    for (int j = 0; j < b; ++j) {
+        double x = -sh[j];
+#pragma unroll
+        for (int a = 0; a < B; ++a) x += y[a] * Cl[a * B + j];
+        X[row * b + j] = (TX)x;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <int M>
+static size_t val_bytes() { return sizeof(typename Traits<M>::TP); }
+
+#define SBMDS_DISPATCH_B(B_, CALL)                      \
+    switch (B_) {                                       \
+        case 4: { constexpr int BB = 4; CALL; } break;   \
+        case 8: { constexpr int BB = 8; CALL; } break;   \
+        case 16: { constexpr int BB = 16; CALL; } break; \
+        case 32: { constexpr int BB = 32; CALL; } break; \
+        case 64: { constexpr int BB = 64; CALL; } break; \
+        default: return hipErrorInvalidValue;           \
+    }
+
+#define SBMDS_DISPATCH_M(M_, CALL)                                 \
+    switch (M_) {                                                  \
+        case MODE_BF16: { constexpr int MM = MODE_BF16; CALL; } break;     \
+        case MODE_FP32: { constexpr int MM = MODE_FP32; CALL; } break;     \
+        case MODE_F64ACC: { constexpr int MM = MODE_F64ACC; CALL; } break; \
+        case MODE_FP64: { constexpr int MM = MODE_FP64; CALL; } break;     \
+        default: return hipErrorInvalidValue;                      \
+    }
+
+template <int MM, int BB>
+static hipError_t spmm_impl(const DevProblem &p, const LaunchCfg &cfg, int ynext, hipStream_t s) {
+    using Tr = Traits<MM>;
+    const int grid = cfg.spmm_blocks;
+    if (grid <= 0 || grid > p.max_spmm_blocks) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_spmm<MM, BB>), dim3(grid), dim3(256), 0, s, (int)p.n, p.rp, p.ci,
+                       (const typename Tr::TP *)p.val[MM], (const typename Tr::TU *)p.U, p.st,
+                       (typename Tr::TY *)p.Y[ynext], p.Gpart, p.epart, p.counters + 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmm(Mode m, const DevProblem &p, const LaunchCfg &cfg, int ynext, hipStream_t s) {
+    SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(p.B, return (spmm_impl<MM, BB>(p, cfg, ynext, s))));
+    return hipErrorInvalidValue;
+}
+
+template <int MM, int BB>
+static hipError_t spmm_t_impl(const DevProblem &p, int ycur, hipStream_t s) {
+    using Tr = Traits<MM>;
+    const int grid = (int)((p.l + 3) / 4);
+    hipLaunchKernelGGL((k_spmm_t<MM, BB>), dim3(grid), dim3(256), 0, s, (int)p.l, (int)p.n, p.rpT, p.ciT,
+                       (const typename Tr::TP *)p.valT[MM], (const typename Tr::TY *)p.Y[ycur], p.c[MM],
+                       p.st, (typename Tr::TT *)p.T);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmm_t(Mode m, const DevProblem &p, int ycur, hipStream_t s) {
+    SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(p.B, return (spmm_t_impl<MM, BB>(p, ycur, s))));
+    return hipErrorInvalidValue;
+}
+
+template <int MM, int BB>
+static hipError_t start_impl(const DevProblem &p, const LaunchCfg &cfg, int ybuf, uint64_t seed,
+                             const void *X0, hipStream_t s) {
+    using Tr = Traits<MM>;
+    const int64_t count = p.n * (int64_t)BB;
+    const int g1 = (int)((count + 255) / 256);
+    if (X0 == nullptr) {
+        hipLaunchKernelGGL((k_random_block<MM, BB>), dim3(g1), dim3(256), 0, s, (int)p.n, p.b, seed,
+                           (typename Tr::TY *)p.Y[ybuf]);
+    } else if (MM == MODE_FP64) {
+        hipLaunchKernelGGL((k_load_block<double, MM, BB>), dim3(g1), dim3(256), 0, s, (int)p.n, p.b,
+                           (const double *)X0, (typename Tr::TY *)p.Y[ybuf]);
+    } else {
+        hipLaunchKernelGGL((k_load_block<float, MM, BB>), dim3(g1), dim3(256), 0, s, (int)p.n, p.b,
+                           (const float *)X0, (typename Tr::TY *)p.Y[ybuf]);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int grid = cfg.spmm_blocks;
+    if (grid <= 0 || grid > p.max_spmm_blocks) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_gram<MM, BB>), dim3(grid), dim3(256), 0, s, (int)p.n,
+                       (const typename Tr::TY *)p.Y[ybuf], p.st, p.Gpart, p.epart, p.counters + 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_random_start(Mode m, const DevProblem &p, const LaunchCfg &cfg, int ybuf, uint64_t seed,
+                               hipStream_t s) {
+    SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(p.B, return (start_impl<MM, BB>(p, cfg, ybuf, seed, nullptr, s))));
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_user_start(Mode m, const DevProblem &p, const LaunchCfg &cfg, int ybuf, const void *X0,
+                             hipStream_t s) {
+    if (X0 == nullptr) return hipErrorInvalidValue;
+    SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(p.B, return (start_impl<MM, BB>(p, cfg, ybuf, 0, X0, s))));
+    return hipErrorInvalidValue;
+}
+
+template <int MF, int MT>
+static hipError_t convert_impl(const DevProblem &p, int src, int dst, hipStream_t s) {
+    const int64_t count = p.n * (int64_t)p.B;
+    hipLaunchKernelGGL((k_convert<MF, MT>), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, count,
+                       (const typename Traits<MF>::TY *)p.Y[src], (typename Traits<MT>::TY *)p.Y[dst]);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_y(Mode from, Mode to, const DevProblem &p, int src, int dst, hipStream_t s) {
+    if (src == dst) return hipErrorInvalidValue;
+    switch (from) {
+        case MODE_BF16: {
+            constexpr int MF = MODE_BF16;
+            SBMDS_DISPATCH_M(to, return (convert_impl<MF, MM>(p, src, dst, s)));
+        } break;
+        case MODE_FP32: {
+            constexpr int MF = MODE_FP32;
+            SBMDS_DISPATCH_M(to, return (convert_impl<MF, MM>(p, src, dst, s)));
+        } break;
+        case MODE_F64ACC: {
+            constexpr int MF = MODE_F64ACC;
+            SBMDS_DISPATCH_M(to, return (convert_impl<MF, MM>(p, src, dst, s)));
+        } break;
+        case MODE_FP64: {
+            constexpr int MF = MODE_FP64;
+            SBMDS_DISPATCH_M(to, return (convert_impl<MF, MM>(p, src, dst, s)));
+        } break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int MM, int BB>
+static hipError_t embedding_impl(const DevProblem &p, int ybuf, void *Z, int z_double, hipStream_t s) {
+    using Tr = Traits<MM>;
+    const unsigned grid = (unsigned)((p.n + 255) / 256);
+    if (z_double)
+        hipLaunchKernelGGL((k_embedding<MM, BB, double>), dim3(grid), dim3(256), 0, s, (int)p.n, p.k,
+                           (const typename Tr::TY *)p.Y[ybuf], p.st, (double *)Z);
+    else
+        hipLaunchKernelGGL((k_embedding<MM, BB, float>), dim3(grid), dim3(256), 0, s, (int)p.n, p.k,
+                           (const typename Tr::TY *)p.Y[ybuf], p.st, (float *)Z);
+    return hipGetLastError();
+}
+
+hipError_t launch_embedding(Mode m, const DevProblem &p, int ybuf, void *Z, int z_double, hipStream_t s) {
+    SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(p.B, return (embedding_impl<MM, BB>(p, ybuf, Z, z_double, s))));
+    return hipErrorInvalidValue;
+}
+
+template <int MM, int BB>
+static hipError_t block_out_impl(const DevProblem &p, int ybuf, void *X, int x_double, hipStream_t s) {
+    using Tr = Traits<MM>;
+    const unsigned grid = (unsigned)((p.n + 255) / 256);
+    if (x_double)
+        hipLaunchKernelGGL((k_block_out<MM, BB, double>), dim3(grid), dim3(256), 0, s, (int)p.n, p.b,
+                           (const typename Tr::TY *)p.Y[ybuf], p.st, (double *)X);
+    else
+        hipLaunchKernelGGL((k_block_out<MM, BB, float>), dim3(grid), dim3(256), 0, s, (int)p.n, p.b,
+                           (const typename Tr::TY *)p.Y[ybuf], p.st, (float *)X);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_out(Mode m, const DevProblem &p, int ybuf, void *X, int x_double, hipStream_t s) {
+    SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(p.B, return (block_out_impl<MM, BB>(p, ybuf, X, x_double, s))));
+    return hipErrorInvalidValue;
+}
+
+static double idx_val_bytes(Mode m) {
+    return 4.0 + (m == MODE_BF16 ? 2.0 : (m == MODE_FP64 ? 8.0 : 4.0));
+}
+static double u_bytes(Mode m) { return m == MODE_F64ACC || m == MODE_FP64 ? 8.0 : 4.0; }
+
+double spmm_bytes(Mode m, const DevProblem &p) {
+    // CSR stream + row pointers + one write of Y' + one read of U
+    return (double)p.nnz * idx_val_bytes(m) + 4.0 * (p.n + 1) + (double)p.n * p.B * y_elem_bytes(m) +
+           (double)p.l * p.B * u_bytes(m);
+}
+double spmm_t_bytes(Mode m, const DevProblem &p) {
+    // CSR(P^T) stream + row pointers + one read of Y + one write of T
+    return (double)p.nnz * idx_val_bytes(m) + 4.0 * (p.l + 1) + (double)p.n * p.B * y_elem_bytes(m) +
+           (double)p.l * p.B * y_elem_bytes(m);
+}
+
+}  // namespace sbmds
+
+namespace sbmds {
+
+__global__ __launch_bounds__(256) void k_f32_to_bf16(int64_t count, const float *__restrict__ src,
+                                                     bf16_t *__restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < count) dst[i] = f2bf(src[i]);
+}
+
+hipError_t launch_f32_to_bf16(const float *src, void *dst, int64_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_f32_to_bf16, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, count, src,
+                       (bf16_t *)dst);
+    return hipGetLastError();
+}
+
+}  // namespace sbmds

@@ -1,0 +1,114 @@
+"""The C ABI without a GPU: symbol exports and host-side validation."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1705_10887_amd as sb
+from tests.conftest import ROOT, gpu_available
+
+HEADER = os.path.join(ROOT, "include", "sbmds.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sbmds_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = sb.lib()
+    names = declared_functions()
+    assert "sbmds_create" in names and "sbmds_embed" in names and "sbmds_destroy" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(sb.EXPORTS) == names
+
+
+def test_version_and_defaults():
+    assert sb.version() == (0, 1)
+    o = sb._Options()
+    sb.lib().sbmds_default_options(ctypes.byref(o))
+    assert (o.k, o.block, o.prec, o.start, o.max_iter) == (3, 16, sb.FP32, sb.START_RANDOM, 500)
+    assert o.tol == 1e-6
+    sb.lib().sbmds_default_options(None)  # NULL is ignored
+    sb.lib().sbmds_destroy(None)          # NULL is a no-op
+
+
+def _tiny(n=6, l=4, dtype=np.float32):
+    rng = np.random.default_rng(0)
+    rows = [[i] if i < l else sorted(rng.choice(l, 2, replace=False).tolist()) for i in range(n)]
+    rp = np.cumsum([0] + [len(r) for r in rows]).astype(np.int32)
+    ci = np.concatenate(rows).astype(np.int32)
+    val = rng.random(len(ci)).astype(dtype)
+    pts = rng.standard_normal((l, 3))
+    W = ((pts[:, None] - pts[None]) ** 2).sum(-1).astype(dtype)
+    return rp, ci, val, W
+
+
+def _expect(code, *a, **kw):
+    with pytest.raises(sb.SbmdsError) as ei:
+        sb.embed(*a, **kw)
+    assert ei.value.code == code, str(ei.value)
+    return str(ei.value)
+
+
+def test_validation_errors_before_any_device_call():
+    rp, ci, val, W = _tiny()
+    E = -1
+    _expect(E, rp, ci, val, W, k=0, block=2)
+    _expect(E, rp, ci, val, W, k=3, block=2)
+    _expect(E, rp, ci, val, W, k=1, block=65)
+    _expect(E, rp, ci, val, W, k=1, block=4)          # block > l - 1
+    _expect(E, rp, ci, val, W, k=1, block=2, tol=0.0)
+    _expect(E, rp, ci, val, W, k=1, block=2, max_iter=0)
+    _expect(E, rp, ci, val, W, k=1, block=2, prec=7)
+    _expect(E, rp, ci, val, W, k=1, block=2, start=sb.START_LEARNED)  # no weights
+    _expect(E, rp, ci, val, W, k=1, block=2, start=sb.START_USER)     # no X0
+    bad = ci.copy(); bad[3] = 4
+    assert "out of range" in _expect(E, rp, bad, val, W, k=1, block=2)
+    bad = ci.copy(); bad[-1] = bad[-2]
+    assert "increasing" in _expect(E, rp, bad, val, W, k=1, block=2)
+    bad = rp.copy(); bad[2] = bad[3] + 1
+    _expect(E, bad, ci, val, W, k=1, block=2)
+    bad = rp.copy(); bad[0] = 1
+    _expect(E, bad, ci, val, W, k=1, block=2)
+    bad = val.copy(); bad[1] = np.nan
+    assert "non-finite" in _expect(E, rp, ci, bad, W, k=1, block=2)
+    bad = W.copy(); bad[0, 1] += 1
+    assert "symmetric" in _expect(E, rp, ci, val, bad, k=1, block=2)
+    bad = W.copy(); bad[1, 1] = np.inf
+    _expect(E, rp, ci, val, bad, k=1, block=2)
+    # l > n
+    rp2 = np.array([0, 1, 2], np.int32)
+    _expect(E, rp2, np.array([0, 1], np.int32), np.ones(2, np.float32), W, k=1, block=2)
+
+
+def test_null_arguments():
+    L = sb.lib()
+    h = ctypes.c_void_p()
+    assert L.sbmds_create(None, 1, None, ctypes.byref(h)) == -1
+    assert h.value is None
+    p = sb._Problem()
+    assert L.sbmds_create(ctypes.byref(p), 0, None, ctypes.byref(h)) == -1
+    assert L.sbmds_create(ctypes.byref(p), 1, None, None) == -1
+    assert L.sbmds_embed(None, None, None, 0, None) == -1
+    assert L.sbmds_get_block(None, 0, None, 0) == -1
+    assert L.sbmds_kernel_stats(None, None, 0) == -1
+    assert b"NULL" in L.sbmds_last_error() or L.sbmds_last_error()
+
+
+def test_no_device_gives_enodev():
+    if gpu_available():
+        pytest.skip("a GPU is present")
+    rp, ci, val, W = _tiny()
+    assert "device" in _expect(-4, rp, ci, val, W, k=1, block=2)
+
+
+def test_product_path_has_no_cpu_fallback():
+    # the binding refuses to run without the compiled library
+    src = open(os.path.join(ROOT, "paper_1705_10887_amd", "__init__.py")).read()
+    assert "import oracle" not in src and "from oracle" not in src
+    assert "no CPU fallback" in src

@@ -1,0 +1,138 @@
+"""HIP path vs the float64 CPU oracle, through the C ABI (needs a gfx950 GPU).
+
+Tolerances: 1e-6 relative eigenvalue error for float32 / bf16+fp32 solves
+(the target of the method's measurement), 1e-10 for the FP64 solve.  The
+oracle sees exactly the float32-rounded operator handed to the GPU.
+"""
+import numpy as np
+import pytest
+
+from synth import configs
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+def run(sb, prob, k, block, prec, **kw):
+    p = sb.Problem.from_arrays(prob["rowptr"], prob["col"], prob["val"], prob["W"], X0=kw.pop("X0", None))
+    with sb.Context([p], k=k, block=block, prec=prec, **kw) as ctx:
+        Z, eig, reps, rc = ctx.embed()
+        X = ctx.get_block(0)
+    return Z, eig[0], reps[0], rc, X
+
+
+def check(prob, Z, eig, rep, k, tol, angle_tol=3.0):
+    """Eigenvalues within `tol`; eigenvector clusters within `angle_tol` times
+    the angle that a `tol`-accurate Ritz value implies (see helpers)."""
+    lam, V, _ = H.oracle_for(prob, k)
+    err = H.rel_eig_err(eig, lam[:k])
+    ang = H.subspace_angle(Z, V, lam, k, tol=tol)
+    print(f"n={prob['n']} l={prob['l']} k={k} err={err:.3e} angle={ang:.3e} rep={rep['iters_bf16']},"
+          f"{rep['iters_fp32']},{rep['iters_fp64']} bound={max(rep['err_bound'][:k]):.2e}", flush=True)
+    assert err <= tol, (eig, lam[:k])
+    assert ang <= angle_tol
+    assert all(b <= tol for b in rep["err_bound"][:k]) or not rep["certified"]
+    return err, ang
+
+
+def test_torus64x32_fp64(gpu):
+    sb = gpu
+    prob = configs.torus64x32()
+    Z, eig, rep, rc, _ = run(sb, prob, 3, 16, sb.FP64, tol=1e-10)
+    assert rc == 0 and rep["certified"]
+    check(prob, Z, eig, rep, 3, 1e-10)
+
+
+def test_torus64x32_fp32(gpu):
+    sb = gpu
+    prob = dict(configs.torus64x32())
+    prob["val"] = prob["val"].astype(np.float32)
+    prob["W"] = prob["W"].astype(np.float32)
+    Z, eig, rep, rc, _ = run(sb, prob, 3, 16, sb.FP32)
+    assert rc == 0 and rep["certified"]
+    check(prob, Z, eig, rep, 3, 1e-6)
+
+
+@pytest.mark.parametrize("block", [4, 8, 16, 32, 64])
+def test_random_operator_all_widths(gpu, block):
+    sb = gpu
+    prob = H.random_problem(n=5000, l=300, row_len_max=12, seed=block, empty_rows=0.05, long_rows=3)
+    k = min(3, block)
+    Z, eig, rep, rc, _ = run(sb, prob, k, block, sb.FP32, max_iter=300)
+    assert rc == 0
+    check(prob, Z, eig, rep, k, 1e-6)
+
+
+def test_random_operator_fp64_ragged(gpu):
+    sb = gpu
+    prob = H.random_problem(n=3001, l=130, row_len_max=20, seed=7, dtype=np.float64, empty_rows=0.1,
+                            long_rows=2)
+    Z, eig, rep, rc, _ = run(sb, prob, 4, 16, sb.FP64, tol=1e-11)
+    assert rc == 0
+    check(prob, Z, eig, rep, 4, 1e-10)
+
+
+def test_sphere7_fp32_k3(gpu):
+    sb = gpu
+    prob = configs.sphere7()
+    Z, eig, rep, rc, _ = run(sb, prob, 3, 16, sb.FP32)
+    assert rc == 0 and rep["certified"]
+    check(prob, Z, eig, rep, 3, 1e-6)
+
+
+def test_sphere7_fp32_k10(gpu):
+    sb = gpu
+    prob = configs.sphere7()
+    Z, eig, rep, rc, _ = run(sb, prob, 10, 48, sb.FP32)
+    assert rc == 0 and rep["certified"]
+    check(prob, Z, eig, rep, 10, 1e-6)
+
+
+def test_sphere7_bf16_fp32(gpu):
+    sb = gpu
+    prob = configs.sphere7()
+    Z, eig, rep, rc, _ = run(sb, prob, 3, 16, sb.BF16_FP32)
+    assert rc == 0 and rep["certified"]
+    assert rep["iters_bf16"] >= 1
+    check(prob, Z, eig, rep, 3, 1e-6)
+
+
+def test_tiny_landmark_count(gpu):
+    sb = gpu
+    prob = H.random_problem(n=50, l=3, row_len_max=3, seed=3)
+    Z, eig, rep, rc, _ = run(sb, prob, 1, 2, sb.FP32)
+    check(prob, Z, eig, rep, 1, 1e-6)
+
+
+def test_bitwise_repeatable(gpu):
+    sb = gpu
+    prob = H.random_problem(n=20000, l=500, row_len_max=10, seed=11)
+    Z1, e1, _, _, _ = run(sb, prob, 3, 16, sb.FP32)
+    Z2, e2, _, _, _ = run(sb, prob, 3, 16, sb.FP32)
+    np.testing.assert_array_equal(e1, e2)
+    np.testing.assert_array_equal(Z1, Z2)
+
+
+def test_resume_from_block(gpu):
+    sb = gpu
+    prob = H.random_problem(n=8000, l=400, row_len_max=10, seed=5)
+    Z1, e1, rep1, _, X = run(sb, prob, 3, 16, sb.FP32)
+    Z2, e2, rep2, rc, _ = run(sb, prob, 3, 16, sb.FP32, start=sb.START_USER, X0=X)
+    assert rc == 0
+    assert rep2["iters_fp32"] + rep2["iters_fp64"] <= rep1["iters_fp32"] + rep1["iters_fp64"]
+    np.testing.assert_allclose(e2, e1, rtol=1e-7)
+
+
+def test_device_inputs_match_host_inputs(gpu):
+    sb = gpu
+    import torch
+    prob = H.random_problem(n=6000, l=200, row_len_max=8, seed=9)
+    Zh, eh, _, _, _ = run(sb, prob, 3, 16, sb.FP32)
+    dev = {k: (torch.from_numpy(v).cuda() if isinstance(v, np.ndarray) else v) for k, v in prob.items()}
+    p = sb.Problem.from_arrays(dev["rowptr"], dev["col"], dev["val"], dev["W"])
+    Zd = torch.zeros((prob["n"], 3), dtype=torch.float32, device="cuda")
+    with sb.Context([p], k=3, block=16, prec=sb.FP32) as ctx:
+        _, ed, _, _ = ctx.embed(Z_out=Zd)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(ed[0], eh)
+    np.testing.assert_array_equal(Zd.cpu().numpy(), Zh)

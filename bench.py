@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Benchmark: time to a k-embedding at 1e-6 relative eigenvalue error.
+
+Workload: sparse biharmonic classical scaling of a radially deformed
+icosphere (subdivision level 7, n = 163,842 vertices, 8 seeded spherical
+harmonics of degree <= 6, amplitude 5%), l = 2,000 geodesic farthest-point
+landmarks, P thresholded to p_row = 10 (p = 809, nnz = 1.62M), W = squared
+Dijkstra landmark distances, k = 3, block 16.  Inputs are synthetic and
+generated from fixed seeds (cached on disk after the first run).
+
+A step is one sbmds_embed call on device-resident inputs: start block,
+all iterations of the precision schedule up to the certified 1e-6 bound,
+and the embedding Z (left on the device).  Two forms are timed on the same
+GPU: the chosen form (bf16 bulk iterations, fp32 refinement, float64
+certification) and the plain fp32 form (fp32 iterations, same certification).
+
+Prints one JSON line.  Only one GPU is used; --gpus above 1 is refused.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def time_form(sb, torch, prob, prec, steps, warmup, k, block, flags=0, start=None):
+    p = sb.Problem.from_arrays(*(torch.from_numpy(prob[x]).cuda() for x in ("rowptr", "col", "val", "W")))
+    kw = {}
+    if start is not None:
+        kw["start"] = start
+    ctx = sb.Context([p], k=k, block=block, prec=prec, flags=flags, **kw)
+    Z = torch.empty((prob["n"], k), dtype=torch.float32, device="cuda")
+    for _ in range(warmup):
+        ctx.embed(Z_out=Z)
+    ctx.reset_kernel_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = None
+    for _ in range(steps):
+        _, eig, reps, rc = ctx.embed(Z_out=Z)
+        if rc != 0:
+            raise RuntimeError(f"solve did not certify (status {rc})")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    stats = ctx.kernel_stats()
+    ctx.close()
+    return ms, eig[0], reps[0], stats
+
+
+def cpu_baseline(prob, k, budget_s=20.0):
+    """The float64 oracle (l x l reduction route) on the host cores."""
+    import numpy as np
+
+    from oracle import eig as oeig
+    from synth import configs
+
+    threads = int(os.environ.get("OPENBLAS_NUM_THREADS", os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    P = configs.operator_rounded(prob)
+    W = prob["W"].astype(np.float64)
+    times = []
+    t_start = time.perf_counter()
+    lam = None
+    while time.perf_counter() - t_start < budget_s and len(times) < 10:
+        t0 = time.perf_counter()
+        lam, _, _ = oeig.top_k(P, W, k, route="reduction")
+        times.append(time.perf_counter() - t0)
+    times.sort()
+    return {"value": round(times[len(times) // 2] * 1e3, 1), "unit": "ms", "cores": threads, "kind": "oracle",
+            "sample": f"full solve (float64 l x l reduction route, k={k}), median of {len(times)} runs"}, lam
+
+
+def traffic_from_profiles(kernel):
+    """HBM bytes per launch from committed rocprofv3 counter summaries."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_sphere7_traffic.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("traffic_bytes_per_launch:"):
+            try:
+                return float(line.split(":", 1)[1])
+            except ValueError:
+                return None
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--k", type=int, default=3)
+    ap.add_argument("--block", type=int, default=16)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build runs the solve on a single MI355X); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    from synth import configs
+
+    log("loading inputs")
+    prob = configs.sphere7(log=log)
+    import numpy as np
+    import torch
+
+    import paper_1705_10887_amd as sb
+
+    torch.cuda.set_device(0)
+    k, block = args.k, args.block
+    log("timing plain fp32")
+    ms_fp32, eig32, rep32, _ = time_form(sb, torch, prob, sb.FP32, args.steps, args.warmup, k, block)
+    log(f"plain fp32 {ms_fp32:.3f} ms  iters {rep32['iters_fp32']}+{rep32['iters_fp64']}")
+    log("timing chosen (bf16 -> fp32 -> fp64 certify)")
+    ms_ch, eigc, repc, _ = time_form(sb, torch, prob, sb.BF16_FP32, args.steps, args.warmup, k, block)
+    log(f"chosen {ms_ch:.3f} ms  iters {repc['iters_bf16']}+{repc['iters_fp32']}+{repc['iters_fp64']}")
+    chosen_prec = sb.BF16_FP32
+    value = ms_ch
+    if ms_fp32 < ms_ch:
+        # the schedule that certifies fastest is the chosen one
+        chosen_prec, value, eigc, repc = sb.FP32, ms_fp32, eig32, rep32
+    log("kernel timing pass")
+    _, _, _, stats = time_form(sb, torch, prob, chosen_prec, args.steps, 1, k, block, flags=sb.FLAG_KERNEL_TIMING)
+    per = {s["name"]: s for s in stats}
+    dom = max((s for s in stats if s["bytes_total"] > 0), key=lambda s: s["ms_total"])
+    avg_ms = dom["ms_total"] / dom["launches"]
+    bytes_per = dom["bytes_total"] / dom["launches"]
+    achieved = bytes_per / (avg_ms * 1e-3) / 1e9
+    spmm = per.get("spmm")
+    spmm_gbs = spmm["bytes_total"] / (spmm["ms_total"] * 1e-3) / 1e9 if spmm else None
+    traffic = traffic_from_profiles(dom["name"])
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        cpu, lam_cpu = cpu_baseline(prob, k)
+        err = float(np.max(np.abs(eigc - lam_cpu[:k]) / np.abs(lam_cpu[:k])))
+        log(f"chosen vs oracle rel eig err {err:.2e}")
+        if err > 1e-6:
+            raise RuntimeError(f"eigenvalues off the oracle by {err:.2e}")
+
+    out = {
+        "metric": "ms to k-embedding at 1e-6 rel eig err (chosen vs plain FP32); SpMM % HBM peak",
+        "value": round(value, 4),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(value, 4),
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "bf16+f32" if chosen_prec == sb.BF16_FP32 else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "sphere7: icosphere level 7 (n=163842) deformed by 8 seeded spherical harmonics, "
+                        "l=2000 FPS landmarks, p_row=10 (nnz=1620000), W=D^2_ll float32",
+            "n": int(prob["n"]), "l": int(prob["l"]), "nnz": int(len(prob["col"])), "k": k, "block": block,
+            "chosen": "bf16->fp32->f64 certify" if chosen_prec == sb.BF16_FP32 else "fp32->f64 certify",
+        },
+        "plain_fp32_ms": round(ms_fp32, 4),
+        "chosen_over_plain": round(ms_fp32 / value, 3),
+        "iters": {"bf16": repc["iters_bf16"], "fp32": repc["iters_fp32"], "fp64": repc["iters_fp64"]},
+        "err_bound": max(repc["err_bound"][:k]),
+        "spmm_hbm_frac": round(spmm_gbs / HBM_PEAK_GBS, 4) if spmm_gbs else None,
+        "kernels": {s["name"]: {"avg_us": round(1e3 * s["ms_total"] / max(s["launches"], 1), 2),
+                                "launches_per_step": round(s["launches"] / args.steps, 2)} for s in stats},
+        "roofline": {
+            "kernel": dom["name"],
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "bytes_per_launch": bytes_per,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -77,23 +77,108 @@ struct VecOf {
     static constexpr int v = (16 / (int)sizeof(T)) < B ? (16 / (int)sizeof(T)) : B;
 };
 
+// Cross-block data inside one kernel.  gfx950 has one L2 per XCD and the L2s
+// are not coherent with each other for ordinary device memory; a device-wide
+// fence (__threadfence) therefore writes back and invalidates the whole L2,
+// which is ruinous when hundreds of blocks do it.  Partial results that
+// another block of the same launch reads are instead written and read with
+// agent-scope atomic accesses (write-through / coherent loads, no cache
+// maintenance), and completion is signalled with a relaxed counter atomic
+// after the writer's stores have been acknowledged.
+template <typename T>
+__device__ __forceinline__ void st_coherent(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T ld_coherent(const T *p) {
+    return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Completion protocol for two-phase reductions: every block publishes its
-// partial, then counts itself in; the block that arrives last reads all
-// partials (in block order, so the result is deterministic) and resets the
-// counter for the next launch.  Returns true in every thread of the last
-// block.
+// partial (st_coherent), then counts itself in; the block that arrives last
+// reads all partials (ld_coherent, in block order, so the result is
+// deterministic) and resets the counter for the next launch.  Returns true
+// in every thread of the last block.
 __device__ __forceinline__ bool arrive_last(unsigned *counter, unsigned total) {
     __shared__ int s_last;
-    __threadfence();
-    __syncthreads();
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's coherent stores are acknowledged
+    __syncthreads();                // ... and those of every thread in the block
     if (threadIdx.x == 0) {
-        unsigned prev = atomicAdd(counter, 1u);
+        const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         s_last = (prev == total - 1u);
     }
     __syncthreads();
-    if (s_last) __threadfence();
     return s_last != 0;
 }
+
+// Counter reset by the last block (the next launch starts from zero).
+__device__ __forceinline__ void counter_reset(unsigned *counter) {
+    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Deterministic tree reduction across blocks.  `scratch` holds level 0 (the
+// producers' partial vectors, [nparts][E], written with st_coherent)
+// followed by the levels above it;
+// `counters` holds one arrival counter per group of every level (all zero
+// between launches).  A producer calls this after writing partial `p`; the
+// last producer of each group of FAN partials sums that group (in index
+// order) into the next level, and so on until a single group remains, whose
+// sum goes to `out`.  Returns true in the block that wrote `out`.
+template <int FAN>
+__device__ bool tree_reduce(double *__restrict__ scratch, int E, int p, int nparts,
+                            unsigned *__restrict__ counters, double *__restrict__ out) {
+    double *src = scratch;
+    unsigned *cnt = counters;
+    int count = nparts, idx = p;
+    for (;;) {
+        const int ngroups = (count + FAN - 1) / FAN;
+        const int g = idx / FAN;
+        const int g0 = g * FAN;
+        const int gs = min(FAN, count - g0);
+        if (!arrive_last(cnt + g, (unsigned)gs)) return false;
+        double *dst = (ngroups == 1) ? out : src + (size_t)count * E;
+        for (int e = threadIdx.x; e < E; e += blockDim.x) {
+            double acc[FAN];
+#pragma unroll
+            for (int q = 0; q < FAN; ++q) acc[q] = q < gs ? ld_coherent(src + (size_t)(g0 + q) * E + e) : 0.0;
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < FAN; ++q) s += acc[q];
+            st_coherent(dst + (size_t)g * E + e, s);
+        }
+        if (threadIdx.x == 0) counter_reset(cnt + g);
+        if (ngroups == 1) return true;
+        src += (size_t)count * E;
+        cnt += ngroups;
+        count = ngroups;
+        idx = g;
+    }
+}
+
+// Sizes of the scratch / counter areas tree_reduce needs for nparts partials.
+__host__ __device__ inline size_t tree_scratch_elems(int nparts, int E, int fan) {
+    size_t tot = 0;
+    int count = nparts;
+    for (;;) {
+        tot += (size_t)count * E;
+        const int ng = (count + fan - 1) / fan;
+        if (ng == 1) break;
+        count = ng;
+    }
+    return tot;
+}
+__host__ __device__ inline int tree_counter_count(int nparts, int fan) {
+    int tot = 0, count = nparts;
+    for (;;) {
+        const int ng = (count + fan - 1) / fan;
+        tot += ng;
+        if (ng == 1) break;
+        count = ng;
+    }
+    return tot;
+}
+
+constexpr int kFan = 16;
 
 __device__ __forceinline__ void tri_index(int ent, int B, int &a, int &b) {
     int r = ent, i = 0;

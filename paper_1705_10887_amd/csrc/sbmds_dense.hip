@@ -67,8 +67,8 @@ __global__ __launch_bounds__(256) void k_gemm_vec(int l, int lda, int kchunk, in
                                                   typename Traits<M>::TA *__restrict__ part,
                                                   typename Traits<M>::TU *__restrict__ U,
                                                   const double *__restrict__ c, SolveState *__restrict__ st,
-                                                  double *__restrict__ Hpart, double *__restrict__ spart,
-                                                  unsigned *__restrict__ counters) {
+                                                  double *__restrict__ red, unsigned *__restrict__ tile_cnt,
+                                                  unsigned *__restrict__ tree_cnt) {
     using Tr = Traits<M>;
     using TA = typename Tr::TA;
     using TT = typename Tr::TT;
@@ -98,15 +98,19 @@ __global__ __launch_bounds__(256) void k_gemm_vec(int l, int lda, int kchunk, in
             const int row = r0 + r;
             w[r] = row < l ? up<TA>(W[(size_t)row * lda + k]) : (TA)0;
         }
-        const TT *trow = T + (size_t)k * B;
+        // rows of T past l are padding; they are never read (W's padding
+        // columns are zero, but the stale bytes there need not be finite)
+        if (k < l) {
+            const TT *trow = T + (size_t)k * B;
 #pragma unroll
-        for (int j0 = 0; j0 < B; j0 += TV) {
-            Pack<TT, TV> tv = ldp<TT, TV>(trow + j0);
+            for (int j0 = 0; j0 < B; j0 += TV) {
+                Pack<TT, TV> tv = ldp<TT, TV>(trow + j0);
 #pragma unroll
-            for (int jj = 0; jj < TV; ++jj) {
-                const TA t = up<TA>(tv.v[jj]);
+                for (int jj = 0; jj < TV; ++jj) {
+                    const TA t = up<TA>(tv.v[jj]);
 #pragma unroll
-                for (int r = 0; r < RW; ++r) acc[r * B + j0 + jj] += w[r] * t;
+                    for (int r = 0; r < RW; ++r) acc[r * B + j0 + jj] += w[r] * t;
+                }
             }
         }
     }
@@ -116,11 +120,11 @@ __global__ __launch_bounds__(256) void k_gemm_vec(int l, int lda, int kchunk, in
     if ((lane % GROUP) == 0) {
         const int row = r0 + idx / B;
         const int j = idx % B;
-        if (row < l) part[((size_t)ks * lda + row) * B + j] = acc[0];
+        if (row < l) st_coherent(part + ((size_t)ks * lda + row) * B + j, acc[0]);
     }
 
     // ---- per-tile finish: the last of the ksplit blocks of this row tile
-    if (!arrive_last(counters + 2 + rt, (unsigned)ksplit)) return;
+    if (!arrive_last(tile_cnt + rt, (unsigned)ksplit)) return;
     __shared__ double ul[RT][B];
     __shared__ double tl[RT][B];
     __shared__ double cl[RT];
@@ -130,7 +134,7 @@ __global__ __launch_bounds__(256) void k_gemm_vec(int l, int lda, int kchunk, in
         const int row = tile0 + r;
         if (row < l) {
             TA sum = (TA)0;
-            for (int q = 0; q < ksplit; ++q) sum += part[((size_t)q * lda + row) * B + j];
+            for (int q = 0; q < ksplit; ++q) sum += ld_coherent(part + ((size_t)q * lda + row) * B + j);
             const TU u = down<TU>((TA)(-0.5) * sum);
             U[(size_t)row * B + j] = u;
             ul[r][j] = (double)up<TA>(u);
@@ -141,34 +145,23 @@ __global__ __launch_bounds__(256) void k_gemm_vec(int l, int lda, int kchunk, in
         }
     }
     for (int r = tid; r < RT; r += 256) cl[r] = (tile0 + r) < l ? c[tile0 + r] : 0.0;
-    if (tid == 0) counters[2 + rt] = 0u;
+    if (tid == 0) counter_reset(tile_cnt + rt);
     __syncthreads();
+    // this tile's contribution to H = T^T U and s = c^T U
+    constexpr int EH = B * B + B;
+    double *mine = red + (size_t)rt * EH;
     for (int e = tid; e < B * B; e += 256) {
         const int a = e / B, bb = e % B;
         double s = 0.0;
         for (int r = 0; r < RT; ++r) s += tl[r][a] * ul[r][bb];
-        Hpart[(size_t)rt * B * B + e] = s;
+        st_coherent(mine + e, s);
     }
     for (int j = tid; j < B; j += 256) {
         double s = 0.0;
         for (int r = 0; r < RT; ++r) s += cl[r] * ul[r][j];
-        spart[(size_t)rt * B + j] = s;
+        st_coherent(mine + B * B + j, s);
     }
-
-    // ---- global finish: the last row tile reduces H and s over all tiles
-    if (!arrive_last(counters + 1, gridDim.x)) return;
-    const int ntiles = gridDim.x;
-    for (int e = tid; e < B * B; e += 256) {
-        double s = 0.0;
-        for (int t = 0; t < ntiles; ++t) s += Hpart[(size_t)t * B * B + e];
-        st->H[e] = s;
-    }
-    for (int j = tid; j < B; j += 256) {
-        double s = 0.0;
-        for (int t = 0; t < ntiles; ++t) s += spart[(size_t)t * B + j];
-        st->s[j] = s;
-    }
-    if (tid == 0) counters[1] = 0u;
+    tree_reduce<kFan>(red, EH, rt, gridDim.x, tree_cnt, st->Hs);
 }
 
 template <int MM, int BB>
@@ -185,7 +178,7 @@ static hipError_t gemm_impl(const DevProblem &p, const LaunchCfg &cfg, hipStream
     if (rowtiles > p.max_rowtiles || ksplit > p.max_ksplit) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_gemm_vec<MM, BB>), dim3(rowtiles, ksplit), dim3(256), 0, s, (int)p.l, p.lda, kchunk,
                        ksplit, (const typename Tr::TW *)p.W[MM], (const typename Tr::TT *)p.T, (TA *)p.gpart,
-                       (typename Tr::TU *)p.U, p.c[MM], p.st, p.Hpart, p.spart, p.counters);
+                       (typename Tr::TU *)p.U, p.c[MM], p.st, p.red_gemm, p.tile_cnt, p.gemm_cnt);
     return hipGetLastError();
 }
 

@@ -23,10 +23,8 @@ constexpr int kMaxB = 64;
 // Device-resident state of the block solver for one problem.  Every array is
 // sized for the widest block and indexed with the problem's kernel width B.
 struct SolveState {
-    double H[kMaxB * kMaxB];     // X^T B X from the dense product
-    double s[kMaxB];             // c^T U, the outer centering correction
-    double G[kMaxB * kMaxB];     // Y'^T Y' of the new block
-    double e_new[kMaxB];         // 1^T Y' of the new block
+    double Hs[kMaxB * kMaxB + kMaxB];           // H = X^T B X (B x B row-major), then s = c^T U
+    double Ge[kMaxB * (kMaxB + 1) / 2 + kMaxB]; // Y'^T Y' (packed upper triangle), then 1^T Y'
     double e_x[kMaxB];           // 1^T Y of the block the basis is built from
     double C[kMaxB * kMaxB];     // basis X = J Y C (row-major B x B)
     double Zmap[kMaxB * kMaxB];  // embedding Z = J Y Zmap (B x B, first k columns used)
@@ -40,6 +38,8 @@ struct SolveState {
     int flags;                   // bit 0: Cholesky pivot repaired; bit 1: non-finite value
     int dead;                    // columns dropped after rank loss
     int nonpos;                  // wanted Ritz values <= 0
+    int sweeps;                  // Jacobi sweeps of the last Rayleigh-Ritz step
+    int pad_;
 };
 
 enum SolveFlags { SF_REPAIRED = 1, SF_NONFINITE = 2 };
@@ -57,11 +57,12 @@ struct DevProblem {
     double *c[NUM_MODES] = {};   // P^T 1 in float64 from that mode's values
     void *Y[2] = {};             // n x B, sized for 8-byte elements
     void *T = nullptr, *U = nullptr;  // lda x B, 8-byte elements
-    // reduction scratch
-    void *gpart = nullptr;       // split-K partials [ksplit][lda][B] (8-byte)
-    double *Hpart = nullptr, *spart = nullptr;   // [row tiles][B*B], [row tiles][B]
-    double *Gpart = nullptr, *epart = nullptr;   // [spmm blocks][B(B+1)/2], [blocks][B]
-    unsigned *counters = nullptr;                // tile counters + 2 global counters
+    // reduction scratch (see tree_reduce): split-K partials of the dense
+    // product, tree levels and arrival counters
+    void *gpart = nullptr;       // [ksplit][lda][B] (8-byte elements)
+    double *red_gemm = nullptr;  // H/s partials per row tile and tree levels
+    double *red_spmm = nullptr;  // Gram/column-sum partials per block and tree levels
+    unsigned *tile_cnt = nullptr, *gemm_cnt = nullptr, *spmm_cnt = nullptr;
     int max_rowtiles = 0, max_ksplit = 0, max_spmm_blocks = 0;
     SolveState *st = nullptr;
     // host mirror of xyz / landmark ids for the learned start
@@ -72,6 +73,7 @@ struct DevProblem {
 // Launch parameters chosen per (problem, mode); tunable.
 struct LaunchCfg {
     int spmm_blocks = 0;   // grid of the row-split SpMM (grid-stride)
+    int spmmt_wpr = 4;     // waves per landmark row in the transposed SpMM (1, 2 or 4)
     int gemm_rt = 0;       // rows per GEMM tile
     int gemm_ksplit = 1;   // K splits of the GEMM
     int gemm_kind = 0;     // 0 vector ALU, 1 MFMA
@@ -79,7 +81,7 @@ struct LaunchCfg {
 
 // Kernel launchers (defined in the .hip files).  All are asynchronous on
 // `stream` and return the hipError_t of the launch.
-hipError_t launch_spmm_t(Mode m, const DevProblem &p, int ycur, hipStream_t stream);
+hipError_t launch_spmm_t(Mode m, const DevProblem &p, const LaunchCfg &cfg, int ycur, hipStream_t stream);
 hipError_t launch_gemm(Mode m, const DevProblem &p, const LaunchCfg &cfg, hipStream_t stream);
 hipError_t launch_spmm(Mode m, const DevProblem &p, const LaunchCfg &cfg, int ynext, hipStream_t stream);
 hipError_t launch_rr_solve(const DevProblem &p, int init, hipStream_t stream);

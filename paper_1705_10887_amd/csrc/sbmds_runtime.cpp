@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "../../include/sbmds.h"
+#include "sbmds_common.h"
 #include "sbmds_internal.h"
 
 using namespace sbmds;
@@ -49,6 +50,8 @@ struct Summary {  // tail of SolveState read back after each iteration
     int flags;
     int dead;
     int nonpos;
+    int sweeps;
+    int pad_;
 };
 static_assert(sizeof(Summary) == sizeof(SolveState) - offsetof(SolveState, theta), "summary layout");
 
@@ -244,8 +247,10 @@ LaunchCfg default_cfg(Mode m, const DevProblem &p) {
     LaunchCfg c;
     const int rpb = spmm_rows_per_block(m, p.B);
     int64_t want = (p.n + rpb - 1) / rpb;
-    const int cap = p.B >= 64 ? 256 : 512;
+    const int cap = 1024;
     c.spmm_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, cap));
+    const double per_row = p.l > 0 ? (double)p.nnz / (double)p.l : 0.0;
+    c.spmmt_wpr = per_row >= 256.0 ? 4 : (per_row >= 64.0 ? 2 : 1);
     c.gemm_rt = gemm_rows_per_tile(m, p.B);
     const int rowtiles = (int)((p.l + c.gemm_rt - 1) / c.gemm_rt);
     int ks = (1024 + rowtiles - 1) / rowtiles;
@@ -321,7 +326,7 @@ int one_iteration(sbmds_ctx *ctx, int pi, Mode m, int ycur) {
     const LaunchCfg &cfg = ctx->cfg[pi][m];
     const double b = p.B;
     OKCHK(timed(ctx, "spmm_t", spmm_t_bytes(m, p), 2.0 * p.nnz * b,
-                [&] { return launch_spmm_t(m, p, ycur, ctx->stream); }));
+                [&] { return launch_spmm_t(m, p, cfg, ycur, ctx->stream); }));
     OKCHK(timed(ctx, "gemm", gemm_bytes(m, p), 2.0 * (double)p.l * p.l * b,
                 [&] { return launch_gemm(m, p, cfg, ctx->stream); }));
     OKCHK(timed(ctx, "spmm", spmm_bytes(m, p), 2.0 * p.nnz * b,
@@ -600,22 +605,29 @@ int create_impl(const sbmds_problem *probs, int nprob, const sbmds_options *opt_
             p.max_spmm_blocks = std::max(p.max_spmm_blocks, ctx->cfg[i][m].spmm_blocks);
         }
         const int B = p.B;
-        const size_t E = (size_t)B * (B + 1) / 2;
+        const int EG = B * (B + 1) / 2 + B;   // Gram triangle + column sums
+        const int EH = B * B + B;             // H + s
+        const int nspmm_cnt = tree_counter_count(p.max_spmm_blocks, kFan);
+        const int ngemm_cnt = tree_counter_count(p.max_rowtiles, kFan);
+        const size_t ncnt = (size_t)p.max_rowtiles + nspmm_cnt + ngemm_cnt;
+        unsigned *cnt = nullptr;
         rc = dalloc(ctx, &p.Y[0], (size_t)p.n * B * 8);
         if (!rc) rc = dalloc(ctx, &p.Y[1], (size_t)p.n * B * 8);
         if (!rc) rc = dalloc(ctx, &p.T, (size_t)p.lda * B * 8);
         if (!rc) rc = dalloc(ctx, &p.U, (size_t)p.lda * B * 8);
         if (!rc) rc = dalloc(ctx, &p.gpart, (size_t)p.max_ksplit * p.lda * B * 8);
-        if (!rc) rc = dalloc(ctx, (void **)&p.Hpart, (size_t)p.max_rowtiles * B * B * 8);
-        if (!rc) rc = dalloc(ctx, (void **)&p.spart, (size_t)p.max_rowtiles * B * 8);
-        if (!rc) rc = dalloc(ctx, (void **)&p.Gpart, (size_t)p.max_spmm_blocks * E * 8);
-        if (!rc) rc = dalloc(ctx, (void **)&p.epart, (size_t)p.max_spmm_blocks * B * 8);
-        if (!rc) rc = dalloc(ctx, (void **)&p.counters, (size_t)(p.max_rowtiles + 2) * 4);
+        if (!rc) rc = dalloc(ctx, (void **)&p.red_gemm, tree_scratch_elems(p.max_rowtiles, EH, kFan) * 8);
+        if (!rc) rc = dalloc(ctx, (void **)&p.red_spmm, tree_scratch_elems(p.max_spmm_blocks, EG, kFan) * 8);
+        if (!rc) rc = dalloc(ctx, (void **)&cnt, ncnt * 4);
         if (!rc) rc = dalloc(ctx, (void **)&p.st, sizeof(SolveState));
+        if (rc < 0) return cleanup(rc);
+        p.tile_cnt = cnt;
+        p.spmm_cnt = cnt + p.max_rowtiles;
+        p.gemm_cnt = p.spmm_cnt + nspmm_cnt;
         if (rc < 0) return cleanup(rc);
         if (hipMemsetAsync(p.T, 0, (size_t)p.lda * B * 8, ctx->stream) != hipSuccess ||
             hipMemsetAsync(p.U, 0, (size_t)p.lda * B * 8, ctx->stream) != hipSuccess ||
-            hipMemsetAsync(p.counters, 0, (size_t)(p.max_rowtiles + 2) * 4, ctx->stream) != hipSuccess ||
+            hipMemsetAsync(cnt, 0, ncnt * 4, ctx->stream) != hipSuccess ||
             hipMemsetAsync(p.st, 0, sizeof(SolveState), ctx->stream) != hipSuccess)
             return cleanup(fail(SBMDS_EHIP, "hipMemsetAsync failed"));
         if (o.start == SBMDS_START_USER) {

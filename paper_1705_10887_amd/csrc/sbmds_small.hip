@@ -4,9 +4,10 @@
 //
 // Iteration state: X = J Y C is an orthonormal, centred basis (J the
 // centering matrix), Y' = B X was just produced by the sparse/dense kernels,
-// and the kernels also left
+// and the kernels also left (SolveState::Hs and ::Ge)
 //   H  = X^T B X            (from T^T U, Section 3.3 operator)
 //   G  = Y'^T Y',  e = 1^T Y'
+// All inputs are staged into LDS first; the step runs in a single wave.
 // This step computes
 //   1. H = S Theta S^T       (cyclic Jacobi, Ritz values sorted descending;
 //                             classical MDS keeps the largest eigenvalues,
@@ -22,49 +23,50 @@
 
 namespace sbmds {
 
+constexpr int kSolveThreads = 64;  // one wave: barriers are nearly free
+
 template <int B>
 struct SmallLds {
-    double A[B][B + 1];
-    double V[B][B + 1];
-    double Gc[B][B + 1];
-    double th[B];
-    double red[256];
-    int perm[B];
-    int dead[B];
+    double A[B][B + 1];     // H, then the sorted eigenvectors S
+    double V[B][B + 1];     // Jacobi rotations; later scratch (Zmap, Gc S, L^-1)
+    double Gc[B][B + 1];    // centred Gram; later S^T Gc S and its Cholesky factor
+    double Cold[B][B + 1];  // basis transform the current H was computed with
+    double e_new[B], e_x[B];
+    double th[B], res[B];
+    int perm[B], dead[B];
     int rot_p[B / 2 + 1], rot_q[B / 2 + 1];
     double rot_c[B / 2 + 1], rot_s[B / 2 + 1];
 };
 
-__device__ __forceinline__ double block_sum(double v, double *red) {
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    double r = red[0];
-    __syncthreads();
-    return r;
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return v;
 }
 
 // Cyclic Jacobi with round-robin pair ordering; A (b x b, symmetric) is
 // diagonalised in place and V accumulates the rotations (V starts as I).
+// The b/2 rotations of one round act on disjoint index pairs, so A <- J^T A J
+// splits into independent 2x2 blocks (pair k rows, pair l columns) and
+// V <- V J into independent row pieces: one barrier-separated phase each.
 template <int B>
-__device__ void jacobi(SmallLds<B> &L, int b) {
+__device__ int jacobi(SmallLds<B> &L, int b) {
     const int tid = threadIdx.x;
-    const int bb = (b & 1) ? b + 1 : b;  // odd sizes get a dummy index
+    constexpr int NT = kSolveThreads;
+    const int bb = (b & 1) ? b + 1 : b;  // odd sizes get a dummy index (a zero padding row)
     const int npair = bb / 2;
-    for (int sweep = 0; sweep < 40; ++sweep) {
+    int sweep = 0;
+    for (; sweep < 40; ++sweep) {
         double off = 0.0, dia = 0.0;
-        for (int e = tid; e < b * b; e += 256) {
+        for (int e = tid; e < b * b; e += NT) {
             const int i = e / b, j = e % b;
             const double v = L.A[i][j];
             if (i != j) off += v * v;
             else dia += v * v;
         }
-        off = block_sum(off, L.red);
-        dia = block_sum(dia, L.red);
-        if (!(off > 1e-32 * dia) || dia == 0.0) break;
+        off = wave_sum(off);
+        dia = wave_sum(dia);
+        if (!(off > 1e-30 * dia) || dia == 0.0) break;
         for (int round = 0; round < bb - 1; ++round) {
             if (tid < npair) {
                 int p, q;
@@ -92,40 +94,40 @@ __device__ void jacobi(SmallLds<B> &L, int b) {
                 L.rot_s[tid] = s;
             }
             __syncthreads();
-            // rows: A <- J^T A
-            for (int e = tid; e < npair * b; e += 256) {
-                const int k = e / b, col = e % b;
-                const int p = L.rot_p[k], q = L.rot_q[k];
-                const double s = L.rot_s[k];
-                if (s != 0.0) {
-                    const double c = L.rot_c[k];
-                    const double ap = L.A[p][col], aq = L.A[q][col];
-                    L.A[p][col] = c * ap - s * aq;
-                    L.A[q][col] = s * ap + c * aq;
-                }
+            // A <- J^T A J on the 2x2 block (rows of pair k, columns of pair l)
+            for (int e = tid; e < npair * npair; e += NT) {
+                const int k = e / npair, l2 = e % npair;
+                const int pk = L.rot_p[k], qk = L.rot_q[k], pl = L.rot_p[l2], ql = L.rot_q[l2];
+                const double ck = L.rot_c[k], sk = L.rot_s[k], cl = L.rot_c[l2], sl = L.rot_s[l2];
+                if (sk == 0.0 && sl == 0.0) continue;
+                const double a00 = L.A[pk][pl], a01 = L.A[pk][ql], a10 = L.A[qk][pl], a11 = L.A[qk][ql];
+                // rows
+                const double r00 = ck * a00 - sk * a10, r01 = ck * a01 - sk * a11;
+                const double r10 = sk * a00 + ck * a10, r11 = sk * a01 + ck * a11;
+                // columns
+                L.A[pk][pl] = cl * r00 - sl * r01;
+                L.A[pk][ql] = sl * r00 + cl * r01;
+                L.A[qk][pl] = cl * r10 - sl * r11;
+                L.A[qk][ql] = sl * r10 + cl * r11;
             }
-            __syncthreads();
-            // columns: A <- A J, V <- V J
-            for (int e = tid; e < npair * b; e += 256) {
-                const int k = e / b, row = e % b;
-                const int p = L.rot_p[k], q = L.rot_q[k];
-                const double s = L.rot_s[k];
-                if (s != 0.0) {
-                    const double c = L.rot_c[k];
-                    const double ap = L.A[row][p], aq = L.A[row][q];
-                    L.A[row][p] = c * ap - s * aq;
-                    L.A[row][q] = s * ap + c * aq;
-                    const double vp = L.V[row][p], vq = L.V[row][q];
-                    L.V[row][p] = c * vp - s * vq;
-                    L.V[row][q] = s * vp + c * vq;
-                }
+            // V <- V J
+            for (int e = tid; e < npair * b; e += NT) {
+                const int l2 = e / b, row = e % b;
+                const double sl = L.rot_s[l2];
+                if (sl == 0.0) continue;
+                const int pl = L.rot_p[l2], ql = L.rot_q[l2];
+                const double cl = L.rot_c[l2];
+                const double vp = L.V[row][pl], vq = L.V[row][ql];
+                L.V[row][pl] = cl * vp - sl * vq;
+                L.V[row][ql] = sl * vp + cl * vq;
             }
             __syncthreads();
         }
     }
+    return sweep;
 }
 
-// Error bounds for the k wanted Ritz values (thread 0).  Ritz values closer
+// Error bounds for the k wanted Ritz values (one thread).  Ritz values closer
 // than 1e-3 (relative) form a cluster; a cluster's gap is its distance to the
 // nearest other Ritz value or to the magnitude of the smallest Ritz value of
 // the block (which stands for the spectrum the block does not hold).  For
@@ -139,7 +141,6 @@ __device__ void bounds(SolveState *st, const double *th, const double *res, int 
     while (i < b) {
         int j = i;
         while (j + 1 < b && fabs(th[j] - th[j + 1]) <= 1e-3 * fmax(fabs(th[j]), fabs(th[j + 1]))) ++j;
-        // cluster [i, j]
         double r2 = 0.0;
         for (int q = i; q <= j; ++q) r2 += res[q] * res[q];
         double gap = INFINITY;
@@ -169,99 +170,107 @@ __device__ void bounds(SolveState *st, const double *th, const double *res, int 
 }
 
 template <int B>
-__global__ __launch_bounds__(256) void k_rr_solve(SolveState *__restrict__ st, int b, int k, double n,
-                                                  double piv_tol, int init) {
+__global__ __launch_bounds__(kSolveThreads) void k_rr_solve(SolveState *__restrict__ st, int b, int k,
+                                                            double n, double piv_tol, int init) {
     __shared__ SmallLds<B> L;
+    constexpr int NT = kSolveThreads;
+    constexpr int E = B * (B + 1) / 2;
     const int tid = threadIdx.x;
     const double inv_n = 1.0 / n;
 
-    // Gc = G - e e^T / n
-    for (int e = tid; e < b * b; e += 256) {
-        const int i = e / b, j = e % b;
-        L.Gc[i][j] = st->G[i * B + j] - st->e_new[i] * st->e_new[j] * inv_n;
+    // ---- stage every input in LDS
+    for (int j = tid; j < B; j += NT) {
+        L.e_new[j] = st->Ge[E + j];
+        L.e_x[j] = st->e_x[j];
+        L.dead[j] = 0;
     }
-    if (tid < B) L.dead[tid] = 0;
-    __syncthreads();
-
-    if (init) {
-        for (int e = tid; e < b * b; e += 256) {
-            const int i = e / b, j = e % b;
+    for (int e = tid; e < B * B; e += NT) {
+        const int i = e / B, j = e % B;
+        L.Cold[i][j] = st->C[e];
+        if (init) {
             L.A[i][j] = (i == j) ? 1.0 : 0.0;  // S = I
-        }
-        __syncthreads();
-    } else {
-        for (int e = tid; e < b * b; e += 256) {
-            const int i = e / b, j = e % b;
-            L.A[i][j] = 0.5 * (st->H[i * B + j] + st->H[j * B + i]);
+        } else {
+            L.A[i][j] = 0.5 * (st->Hs[i * B + j] + st->Hs[j * B + i]);
             L.V[i][j] = (i == j) ? 1.0 : 0.0;
         }
-        __syncthreads();
-        jacobi<B>(L, b);
+    }
+    __syncthreads();
+    // Gc = G - e e^T / n from the packed upper triangle
+    for (int e = tid; e < B * B; e += NT) {
+        const int a = e / B, c = e % B;
+        const int lo = a < c ? a : c, hi = a < c ? c : a;
+        const int pk = lo * B - (lo * (lo - 1)) / 2 + (hi - lo);
+        L.Gc[a][c] = st->Ge[pk] - L.e_new[a] * L.e_new[c] * inv_n;
+    }
+    __syncthreads();
+
+    if (!init) {
+        const int nsw = jacobi<B>(L, b);
+        if (tid == 0) st->sweeps = nsw;
         // sort Ritz values descending (ties by index)
-        if (tid < b) {
-            const double t = L.A[tid][tid];
+        for (int t = tid; t < b; t += NT) {
+            const double th = L.A[t][t];
             int rank = 0;
             for (int j = 0; j < b; ++j) {
                 const double u = L.A[j][j];
-                rank += (u > t) || (u == t && j < tid);
+                rank += (u > th) || (u == th && j < t);
             }
-            L.perm[rank] = tid;
+            L.perm[rank] = t;
         }
         __syncthreads();
-        if (tid < b) L.th[tid] = L.A[L.perm[tid]][L.perm[tid]];
+        for (int t = tid; t < b; t += NT) L.th[t] = L.A[L.perm[t]][L.perm[t]];
         __syncthreads();
-        // S (sorted eigenvectors) into A
-        for (int e = tid; e < b * b; e += 256) {
+        for (int e = tid; e < b * b; e += NT) {
             const int r = e / b, i = e % b;
-            L.A[r][i] = L.V[r][L.perm[i]];
+            L.A[r][i] = L.V[r][L.perm[i]];  // S, columns in Ritz order
         }
         __syncthreads();
-        // Zmap = C S_k sqrt(max(theta, 0)), zshift = e_x^T Zmap / n
-        for (int e = tid; e < B * B; e += 256) {
+        // Zmap = Cold S_k sqrt(max(theta, 0)) into V, zshift = e_x^T Zmap / n
+        for (int e = tid; e < B * B; e += NT) {
             const int r = e / B, i = e % B;
             double z = 0.0;
             if (r < b && i < k) {
-                for (int m = 0; m < b; ++m) z += st->C[r * B + m] * L.A[m][i];
+                for (int m = 0; m < b; ++m) z += L.Cold[r][m] * L.A[m][i];
                 z *= sqrt(fmax(L.th[i], 0.0));
             }
-            st->Zmap[e] = z;
+            L.V[r][i] = z;
         }
         __syncthreads();
-        if (tid < B) {
+        for (int e = tid; e < B * B; e += NT) st->Zmap[e] = L.V[e / B][e % B];
+        for (int i = tid; i < B; i += NT) {
             double z = 0.0;
-            if (tid < k)
-                for (int r = 0; r < b; ++r) z += st->e_x[r] * st->Zmap[r * B + tid];
-            st->zshift[tid] = z * inv_n;
+            if (i < k)
+                for (int r = 0; r < b; ++r) z += L.e_x[r] * L.V[r][i];
+            st->zshift[i] = z * inv_n;
         }
-        // GS = Gc S into V
-        for (int e = tid; e < b * b; e += 256) {
+        __syncthreads();
+        // Gc S into V
+        for (int e = tid; e < b * b; e += NT) {
             const int r = e / b, i = e % b;
             double v = 0.0;
             for (int m = 0; m < b; ++m) v += L.Gc[r][m] * L.A[m][i];
             L.V[r][i] = v;
         }
         __syncthreads();
-        // residuals, Ritz values out
-        if (tid < b) {
+        // ||B x_i - theta_i x_i||^2 = s_i^T Gc s_i - theta_i^2
+        for (int i = tid; i < b; i += NT) {
             double d = 0.0;
-            for (int r = 0; r < b; ++r) d += L.A[r][tid] * L.V[r][tid];
-            const double t = L.th[tid];
-            L.red[tid] = sqrt(fmax(d - t * t, 0.0));
-            st->theta[tid] = t;
+            for (int r = 0; r < b; ++r) d += L.A[r][i] * L.V[r][i];
+            const double t = L.th[i];
+            L.res[i] = sqrt(fmax(d - t * t, 0.0));
+            st->theta[i] = t;
         }
         __syncthreads();
-        if (tid == 0) bounds(st, L.th, L.red, b, k);
-        __syncthreads();
-        // Gc <- S^T Gc S
-        for (int e = tid; e < b * b; e += 256) {
+        if (tid == 0) bounds(st, L.th, L.res, b, k);
+        // S^T Gc S into Gc (reads only A and V), then symmetrise
+        for (int e = tid; e < b * b; e += NT) {
             const int i = e / b, j = e % b;
             double v = 0.0;
             for (int r = 0; r < b; ++r) v += L.A[r][i] * L.V[r][j];
             L.Gc[i][j] = v;
         }
         __syncthreads();
-        // symmetrise
-        for (int e = tid; e < b * b; e += 256) {
+        for (int e = tid; e < b * b; e += NT) {
             const int i = e / b, j = e % b;
             if (i < j) {
                 const double v = 0.5 * (L.Gc[i][j] + L.Gc[j][i]);
@@ -272,10 +281,10 @@ __global__ __launch_bounds__(256) void k_rr_solve(SolveState *__restrict__ st, i
         __syncthreads();
     }
 
-    // Left-looking Cholesky Gc = Lc Lc^T, Lc stored in the lower triangle.
-    // A pivot that kept no more than piv_tol of its original size marks a
-    // column whose direction is already spanned by earlier ones; it is
-    // dropped from the next basis (its column of C' is zero).
+    // Left-looking Cholesky Gc = Lc Lc^T, Lc in the lower triangle.  A pivot
+    // that kept no more than piv_tol of its original size marks a column whose
+    // direction is already spanned by earlier ones; it is dropped from the
+    // next basis (its column of C' is zero).
     for (int j = 0; j < b; ++j) {
         if (tid == 0) {
             const double orig = L.Gc[j][j];
@@ -291,7 +300,7 @@ __global__ __launch_bounds__(256) void k_rr_solve(SolveState *__restrict__ st, i
         __syncthreads();
         const int isdead = L.dead[j];
         const double ljj = L.Gc[j][j];
-        for (int i = j + 1 + tid; i < b; i += 256) {
+        for (int i = j + 1 + tid; i < b; i += NT) {
             if (isdead) {
                 L.Gc[i][j] = 0.0;
             } else {
@@ -302,9 +311,8 @@ __global__ __launch_bounds__(256) void k_rr_solve(SolveState *__restrict__ st, i
         }
         __syncthreads();
     }
-    // Linv = Lc^{-1} into V (column j per thread, forward substitution)
-    if (tid < b) {
-        const int j = tid;
+    // Lc^{-1} into V, one column per thread (forward substitution)
+    for (int j = tid; j < b; j += NT) {
         for (int i = 0; i < b; ++i) L.V[i][j] = 0.0;
         L.V[j][j] = 1.0 / L.Gc[j][j];
         for (int i = j + 1; i < b; ++i) {
@@ -314,25 +322,27 @@ __global__ __launch_bounds__(256) void k_rr_solve(SolveState *__restrict__ st, i
         }
     }
     __syncthreads();
-    // C' = S Linv^T ; dropped columns are zeroed
-    for (int e = tid; e < B * B; e += 256) {
+    // C' = S Lc^{-T}; dropped columns are zero
+    int nonfinite = 0;
+    for (int e = tid; e < B * B; e += NT) {
         const int r = e / B, j = e % B;
         double v = 0.0;
         if (r < b && j < b && !L.dead[j]) {
             for (int m = 0; m <= j; ++m) v += L.A[r][m] * L.V[j][m];
         }
+        nonfinite |= !isfinite(v);
         st->C[e] = v;
     }
-    if (tid < B) st->e_x[tid] = st->e_new[tid];
-    __syncthreads();
+    for (int j = tid; j < B; j += NT) st->e_x[j] = L.e_new[j];
+    nonfinite = (int)wave_sum((double)nonfinite);
     if (tid == 0) {
         int nd = 0;
         for (int j = 0; j < b; ++j) nd += L.dead[j];
         st->dead = nd;
-        if (nd) st->flags |= SF_REPAIRED;
-        bool fin = true;
-        for (int j = 0; j < b; ++j) fin = fin && isfinite(st->C[j * B + j]);
-        if (!fin) st->flags |= SF_NONFINITE;
+        int fl = st->flags;
+        if (nd) fl |= SF_REPAIRED;
+        if (nonfinite) fl |= SF_NONFINITE;
+        st->flags = fl;
         if (init) {
             st->iter = 0;
             st->maxbound = INFINITY;
@@ -345,12 +355,13 @@ __global__ __launch_bounds__(256) void k_rr_solve(SolveState *__restrict__ st, i
 
 hipError_t launch_rr_solve(const DevProblem &p, int init, hipStream_t s) {
     const double piv_tol = 1e-10;
+    const dim3 blk(kSolveThreads);
     switch (p.B) {
-        case 4: hipLaunchKernelGGL((k_rr_solve<4>), dim3(1), dim3(256), 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init); break;
-        case 8: hipLaunchKernelGGL((k_rr_solve<8>), dim3(1), dim3(256), 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init); break;
-        case 16: hipLaunchKernelGGL((k_rr_solve<16>), dim3(1), dim3(256), 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init); break;
-        case 32: hipLaunchKernelGGL((k_rr_solve<32>), dim3(1), dim3(256), 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init); break;
-        case 64: hipLaunchKernelGGL((k_rr_solve<64>), dim3(1), dim3(256), 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init); break;
+        case 4: hipLaunchKernelGGL((k_rr_solve<4>), dim3(1), blk, 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init); break;
+        case 8: hipLaunchKernelGGL((k_rr_solve<8>), dim3(1), blk, 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init); break;
+        case 16: hipLaunchKernelGGL((k_rr_solve<16>), dim3(1), blk, 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init); break;
+        case 32: hipLaunchKernelGGL((k_rr_solve<32>), dim3(1), blk, 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init); break;
+        case 64: hipLaunchKernelGGL((k_rr_solve<64>), dim3(1), blk, 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -49,24 +49,21 @@ __device__ __forceinline__ void gram_tile_accumulate(const double (*tile)[B], in
     }
 }
 
-// Final reduction of Gram / column-sum partials (run by the last block).
-template <int B>
-__device__ void gram_finish(const double *__restrict__ Gpart, const double *__restrict__ epart,
-                            int nblk, double *__restrict__ G, double *__restrict__ e) {
+// Publish this block's Gram / column-sum partial and join the tree
+// reduction whose result lands in st->Ge (packed triangle, then sums).
+template <int B, int NQ>
+__device__ __forceinline__ void gram_publish(const int *ea, const double *gacc, double eacc,
+                                             double *__restrict__ red, unsigned *__restrict__ cnt,
+                                             SolveState *__restrict__ st) {
     constexpr int E = B * (B + 1) / 2;
-    for (int ent = threadIdx.x; ent < E; ent += blockDim.x) {
-        double s = 0.0;
-        for (int k = 0; k < nblk; ++k) s += Gpart[(size_t)k * E + ent];
-        int a, b;
-        tri_index(ent, B, a, b);
-        G[a * B + b] = s;
-        G[b * B + a] = s;
-    }
-    for (int j = threadIdx.x; j < B; j += blockDim.x) {
-        double s = 0.0;
-        for (int k = 0; k < nblk; ++k) s += epart[(size_t)k * B + j];
-        e[j] = s;
-    }
+    constexpr int EG = E + B;
+    const int tid = threadIdx.x;
+    double *mine = red + (size_t)blockIdx.x * EG;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+        if (ea[q] >= 0) st_coherent(mine + tid + q * 256, gacc[q]);
+    if (tid < B) st_coherent(mine + E + tid, eacc);
+    tree_reduce<kFan>(red, EG, blockIdx.x, gridDim.x, cnt, st->Ge);
 }
 
 template <int M, int B>
@@ -76,8 +73,7 @@ __global__ __launch_bounds__(256) void k_spmm(int n, const int32_t *__restrict__
                                               const typename Traits<M>::TU *__restrict__ U,
                                               SolveState *__restrict__ st,
                                               typename Traits<M>::TY *__restrict__ Y,
-                                              double *__restrict__ Gpart, double *__restrict__ epart,
-                                              unsigned *__restrict__ counter) {
+                                              double *__restrict__ red, unsigned *__restrict__ cnt) {
     using Tr = Traits<M>;
     using TA = typename Tr::TA;
     using TY = typename Tr::TY;
@@ -92,7 +88,7 @@ __global__ __launch_bounds__(256) void k_spmm(int n, const int32_t *__restrict__
     const double inv_n = 1.0 / (double)n;
     TA sc[VEC];
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) sc[v] = (TA)(st->s[g * VEC + v] * inv_n);
+    for (int v = 0; v < VEC; ++v) sc[v] = (TA)(st->Hs[B * B + g * VEC + v] * inv_n);
 
     int ea[NQ], eb[NQ];
 #pragma unroll
@@ -113,12 +109,22 @@ __global__ __launch_bounds__(256) void k_spmm(int n, const int32_t *__restrict__
 #pragma unroll
             for (int v = 0; v < VEC; ++v) acc[v] = (TA)0;
             const int beg = rp[row], end = rp[row + 1];
-            for (int e = beg; e < end; ++e) {
-                const int c = ci[e];
-                const TA pv = up<TA>(val[e]);
-                Pack<TU, VEC> u = ldp<TU, VEC>(U + (size_t)c * B + g * VEC);
+            int e = beg;
+            // two independent gathers in flight per lane
+            for (; e + 1 < end; e += 2) {
+                const int c0 = ci[e], c1 = ci[e + 1];
+                const TA p0 = up<TA>(val[e]), p1 = up<TA>(val[e + 1]);
+                Pack<TU, VEC> u0 = ldp<TU, VEC>(U + (size_t)c0 * B + g * VEC);
+                Pack<TU, VEC> u1 = ldp<TU, VEC>(U + (size_t)c1 * B + g * VEC);
 #pragma unroll
-                for (int v = 0; v < VEC; ++v) acc[v] += pv * up<TA>(u.v[v]);
+                for (int v = 0; v < VEC; ++v) acc[v] += p0 * up<TA>(u0.v[v]) + p1 * up<TA>(u1.v[v]);
+            }
+            if (e < end) {
+                const int c0 = ci[e];
+                const TA p0 = up<TA>(val[e]);
+                Pack<TU, VEC> u0 = ldp<TU, VEC>(U + (size_t)c0 * B + g * VEC);
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) acc[v] += p0 * up<TA>(u0.v[v]);
             }
             Pack<TY, VEC> o;
 #pragma unroll
@@ -134,22 +140,14 @@ __global__ __launch_bounds__(256) void k_spmm(int n, const int32_t *__restrict__
         gram_tile_accumulate<B>(tile, RPB, tid, ea, eb, NQ, gacc, eacc);
         __syncthreads();
     }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-        if (ea[q] >= 0) Gpart[(size_t)blockIdx.x * E + tid + q * 256] = gacc[q];
-    if (tid < B) epart[(size_t)blockIdx.x * B + tid] = eacc;
-    if (arrive_last(counter, gridDim.x)) {
-        gram_finish<B>(Gpart, epart, gridDim.x, st->G, st->e_new);
-        if (tid == 0) *counter = 0u;
-    }
+    gram_publish<B, NQ>(ea, gacc, eacc, red, cnt, st);
 }
 
 // Gram matrix and column sums of a stored block (start blocks).
 template <int M, int B>
 __global__ __launch_bounds__(256) void k_gram(int n, const typename Traits<M>::TY *__restrict__ Y,
-                                              SolveState *__restrict__ st,
-                                              double *__restrict__ Gpart, double *__restrict__ epart,
-                                              unsigned *__restrict__ counter) {
+                                              SolveState *__restrict__ st, double *__restrict__ red,
+                                              unsigned *__restrict__ cnt) {
     using Tr = Traits<M>;
     using TY = typename Tr::TY;
     using S = SpmmShape<M, B>;
@@ -183,21 +181,15 @@ __global__ __launch_bounds__(256) void k_gram(int n, const typename Traits<M>::T
         gram_tile_accumulate<B>(tile, RPB, tid, ea, eb, NQ, gacc, eacc);
         __syncthreads();
     }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-        if (ea[q] >= 0) Gpart[(size_t)blockIdx.x * E + tid + q * 256] = gacc[q];
-    if (tid < B) epart[(size_t)blockIdx.x * B + tid] = eacc;
-    if (arrive_last(counter, gridDim.x)) {
-        gram_finish<B>(Gpart, epart, gridDim.x, st->G, st->e_new);
-        if (tid == 0) *counter = 0u;
-    }
+    gram_publish<B, NQ>(ea, gacc, eacc, red, cnt, st);
 }
 
 // ---------------------------------------------------------------------------
-// SpMM with the transposed operator (CSR of P^T, one wave per landmark row),
-// inner centering and the b x b basis rotation C.
+// SpMM with the transposed operator (CSR of P^T), inner centering and the
+// b x b basis rotation C.  WPR waves share one landmark row (its p + 1
+// entries are split over them); a 256-thread block covers 4 / WPR rows.
 // ---------------------------------------------------------------------------
-template <int M, int B>
+template <int M, int B, int WPR>
 __global__ __launch_bounds__(256) void k_spmm_t(int l, int n, const int32_t *__restrict__ rpT,
                                                 const int32_t *__restrict__ ciT,
                                                 const typename Traits<M>::TP *__restrict__ valT,
@@ -211,10 +203,12 @@ __global__ __launch_bounds__(256) void k_spmm_t(int l, int n, const int32_t *__r
     using TT = typename Tr::TT;
     constexpr int VEC = VecOf<TY, B>::v;
     constexpr int LPR = B / VEC;
-    constexpr int EPW = 64 / LPR;
+    constexpr int EPW = 64 / LPR;       // entries per wave step
+    constexpr int RPBLK = 4 / WPR;      // landmark rows per block
     __shared__ double Cl[B * B];
     __shared__ double ex[B];
-    __shared__ double rowbuf[4][B];
+    __shared__ double part[4][B];       // per-wave partial sums
+    __shared__ double rowbuf[RPBLK][B];
 
     const int tid = threadIdx.x;
     for (int i = tid; i < B * B; i += 256) Cl[i] = st->C[i];
@@ -224,19 +218,31 @@ __global__ __launch_bounds__(256) void k_spmm_t(int l, int n, const int32_t *__r
     const int lane = tid & 63;
     const int g = lane % LPR;
     const int slot = lane / LPR;
-    const int64_t j = (int64_t)blockIdx.x * 4 + wave;
+    const int rloc = wave / WPR;        // row within the block
+    const int wsub = wave % WPR;        // wave within the row
+    const int64_t j = (int64_t)blockIdx.x * RPBLK + rloc;
 
     TA acc[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) acc[v] = (TA)0;
     if (j < l) {
         const int beg = rpT[j], end = rpT[j + 1];
-        for (int e = beg + slot; e < end; e += EPW) {
-            const TA pv = up<TA>(valT[e]);
-            const int vert = ciT[e];
-            Pack<TY, VEC> y = ldp<TY, VEC>(Y + (size_t)vert * B + g * VEC);
+        constexpr int STEP = EPW * WPR;
+        int e = beg + wsub * EPW + slot;
+        for (; e + STEP < end; e += 2 * STEP) {
+            const TA p0 = up<TA>(valT[e]), p1 = up<TA>(valT[e + STEP]);
+            const int v0 = ciT[e], v1 = ciT[e + STEP];
+            Pack<TY, VEC> y0 = ldp<TY, VEC>(Y + (size_t)v0 * B + g * VEC);
+            Pack<TY, VEC> y1 = ldp<TY, VEC>(Y + (size_t)v1 * B + g * VEC);
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) acc[v] += pv * up<TA>(y.v[v]);
+            for (int v = 0; v < VEC; ++v) acc[v] += p0 * up<TA>(y0.v[v]) + p1 * up<TA>(y1.v[v]);
+        }
+        if (e < end) {
+            const TA p0 = up<TA>(valT[e]);
+            const int v0 = ciT[e];
+            Pack<TY, VEC> y0 = ldp<TY, VEC>(Y + (size_t)v0 * B + g * VEC);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[v] += p0 * up<TA>(y0.v[v]);
         }
     }
 #pragma unroll
@@ -244,17 +250,22 @@ __global__ __launch_bounds__(256) void k_spmm_t(int l, int n, const int32_t *__r
 #pragma unroll
         for (int v = 0; v < VEC; ++v) acc[v] += __shfl_xor(acc[v], m);
     }
-    __syncthreads();  // Cl and ex loaded
-    if (j < l && slot == 0) {
-        const double cj = c[j] / (double)n;
+    if (slot == 0) {
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) rowbuf[wave][g * VEC + v] = (double)acc[v] - cj * ex[g * VEC + v];
+        for (int v = 0; v < VEC; ++v) part[wave][g * VEC + v] = (double)acc[v];
+    }
+    __syncthreads();  // Cl, ex and the wave partials
+    if (wsub == 0 && lane < B && j < l) {
+        double r = 0.0;
+#pragma unroll
+        for (int q = 0; q < WPR; ++q) r += part[wave + q][lane];
+        rowbuf[rloc][lane] = r - (c[j] / (double)n) * ex[lane];
     }
     __syncthreads();
-    if (j < l && lane < B) {
+    if (wsub == 0 && lane < B && j < l) {
         double t = 0.0;
 #pragma unroll 8
-        for (int i = 0; i < B; ++i) t += rowbuf[wave][i] * Cl[i * B + lane];
+        for (int i = 0; i < B; ++i) t += rowbuf[rloc][i] * Cl[i * B + lane];
         T[(size_t)j * B + lane] = down<TT>((TA)t);
     }
 }
@@ -413,7 +424,7 @@ static hipError_t spmm_impl(const DevProblem &p, const LaunchCfg &cfg, int ynext
     if (grid <= 0 || grid > p.max_spmm_blocks) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_spmm<MM, BB>), dim3(grid), dim3(256), 0, s, (int)p.n, p.rp, p.ci,
                        (const typename Tr::TP *)p.val[MM], (const typename Tr::TU *)p.U, p.st,
-                       (typename Tr::TY *)p.Y[ynext], p.Gpart, p.epart, p.counters + 0);
+                       (typename Tr::TY *)p.Y[ynext], p.red_spmm, p.spmm_cnt);
     return hipGetLastError();
 }
 
@@ -422,18 +433,24 @@ hipError_t launch_spmm(Mode m, const DevProblem &p, const LaunchCfg &cfg, int yn
     return hipErrorInvalidValue;
 }
 
-template <int MM, int BB>
+template <int MM, int BB, int WPR>
 static hipError_t spmm_t_impl(const DevProblem &p, int ycur, hipStream_t s) {
     using Tr = Traits<MM>;
-    const int grid = (int)((p.l + 3) / 4);
-    hipLaunchKernelGGL((k_spmm_t<MM, BB>), dim3(grid), dim3(256), 0, s, (int)p.l, (int)p.n, p.rpT, p.ciT,
+    constexpr int RPBLK = 4 / WPR;
+    const int grid = (int)((p.l + RPBLK - 1) / RPBLK);
+    hipLaunchKernelGGL((k_spmm_t<MM, BB, WPR>), dim3(grid), dim3(256), 0, s, (int)p.l, (int)p.n, p.rpT, p.ciT,
                        (const typename Tr::TP *)p.valT[MM], (const typename Tr::TY *)p.Y[ycur], p.c[MM],
                        p.st, (typename Tr::TT *)p.T);
     return hipGetLastError();
 }
 
-hipError_t launch_spmm_t(Mode m, const DevProblem &p, int ycur, hipStream_t s) {
-    SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(p.B, return (spmm_t_impl<MM, BB>(p, ycur, s))));
+hipError_t launch_spmm_t(Mode m, const DevProblem &p, const LaunchCfg &cfg, int ycur, hipStream_t s) {
+    switch (cfg.spmmt_wpr) {
+        case 1: SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(p.B, return (spmm_t_impl<MM, BB, 1>(p, ycur, s)))); break;
+        case 2: SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(p.B, return (spmm_t_impl<MM, BB, 2>(p, ycur, s)))); break;
+        case 4: SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(p.B, return (spmm_t_impl<MM, BB, 4>(p, ycur, s)))); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipErrorInvalidValue;
 }
 
@@ -458,7 +475,7 @@ static hipError_t start_impl(const DevProblem &p, const LaunchCfg &cfg, int ybuf
     const int grid = cfg.spmm_blocks;
     if (grid <= 0 || grid > p.max_spmm_blocks) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_gram<MM, BB>), dim3(grid), dim3(256), 0, s, (int)p.n,
-                       (const typename Tr::TY *)p.Y[ybuf], p.st, p.Gpart, p.epart, p.counters + 0);
+                       (const typename Tr::TY *)p.Y[ybuf], p.st, p.red_spmm, p.spmm_cnt);
     return hipGetLastError();
 }
 

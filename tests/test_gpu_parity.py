@@ -136,3 +136,18 @@ def test_device_inputs_match_host_inputs(gpu):
     torch.cuda.synchronize()
     np.testing.assert_array_equal(ed[0], eh)
     np.testing.assert_array_equal(Zd.cpu().numpy(), Zh)
+
+
+@pytest.mark.parametrize("prec", ["FP32", "BF16_FP32"])
+def test_repeated_calls_same_context(gpu, prec):
+    # a context is reused across calls; buffers left by a previous call (in
+    # another storage precision) must not leak into the next solve
+    sb = gpu
+    prob = H.random_problem(n=12000, l=700, row_len_max=10, seed=21)
+    p = sb.Problem.from_arrays(prob["rowptr"], prob["col"], prob["val"], prob["W"])
+    lam, _, _ = H.oracle_for(prob, 3)
+    with sb.Context([p], k=3, block=16, prec=getattr(sb, prec)) as ctx:
+        for call in range(3):
+            Z, eig, reps, rc = ctx.embed()
+            assert rc == 0 and reps[0]["certified"], (call, reps[0])
+            assert H.rel_eig_err(eig[0], lam[:3]) <= 1e-6, call

@@ -156,6 +156,7 @@ typedef struct {
  *               clusters, or the plain residual norm when smaller).
  *   resid[i]    ||B x_i - eig[i] x_i|| / |eig[i]|.
  *   nonpositive number of the k eigenvalues <= 0 (their coordinates are 0).
+ *   jacobi_sweeps total Jacobi sweeps spent in the Rayleigh-Ritz steps.
  *   ms_*        wall time of the start block, of the iterations, and of the
  *               whole call, measured with HIP events on the context's stream.
  */
@@ -164,6 +165,8 @@ typedef struct {
     int iters_bf16, iters_fp32, iters_fp64;
     int nonpositive;
     int certified;
+    int jacobi_sweeps;
+    int reserved_;
     double ms_start, ms_iter, ms_total;
     double eig[SBMDS_MAX_BLOCK];
     double err_bound[SBMDS_MAX_BLOCK];

@@ -1,0 +1,99 @@
+// Error bounds of the Ritz values (shared by both small-solver variants).
+#pragma once
+
+#include "sbmds_common.h"
+
+namespace sbmds {
+
+// Error bounds for the k wanted Ritz values (one thread).  Ritz values closer
+// than 1e-3 (relative) form a cluster; a cluster's gap is its distance to the
+// nearest other Ritz value or to the magnitude of the smallest Ritz value of
+// the block (which stands for the spectrum the block does not hold).  For
+// each wanted value the bound is min(||r_i||, ||R_cluster||^2 / gap) / |theta_i|.
+__device__ inline void bounds(SolveState *st, const double *th, const double *res, int b, int k) {
+    double floor_mag = INFINITY;
+    for (int i = 0; i < b; ++i) floor_mag = fmin(floor_mag, fabs(th[i]));
+    double maxb = 0.0, maxr = 0.0;
+    int nonpos = 0;
+    int i = 0;
+    while (i < b) {
+        int j = i;
+        while (j + 1 < b && fabs(th[j] - th[j + 1]) <= 1e-3 * fmax(fabs(th[j]), fabs(th[j + 1]))) ++j;
+        double r2 = 0.0;
+        for (int q = i; q <= j; ++q) r2 += res[q] * res[q];
+        double gap = INFINITY;
+        if (i > 0) gap = fmin(gap, th[i - 1] - th[i]);
+        if (j + 1 < b) gap = fmin(gap, th[j] - th[j + 1]);
+        const double lo = th[j];
+        const double out_gap = lo > 0.0 ? lo - floor_mag : (-lo) - floor_mag;
+        gap = fmin(gap, out_gap);
+        for (int q = i; q <= j; ++q) {
+            const double a = fabs(th[q]);
+            double bnd = res[q];
+            if (gap > 0.0) bnd = fmin(bnd, r2 / gap);
+            const double rel = a > 0.0 ? bnd / a : INFINITY;
+            st->bound[q] = rel;
+            st->res[q] = res[q];
+            if (q < k) {
+                maxb = fmax(maxb, rel);
+                maxr = fmax(maxr, a > 0.0 ? res[q] / a : INFINITY);
+                if (th[q] <= 0.0) ++nonpos;
+            }
+        }
+        i = j + 1;
+    }
+    st->maxbound = maxb;
+    st->maxres = maxr;
+    st->nonpos = nonpos;
+}
+
+// Schedule bookkeeping after a Rayleigh-Ritz step (one thread).  In `init`
+// mode it resets the control state for a new solve.
+__device__ inline void phase_control(SolveState *st, const PhaseRule &rule, int init) {
+    if (init) {
+        st->ycur = 0;
+        st->zbuf = 0;
+        st->zmode = rule.mode;
+        st->phase = 0;
+        st->done = 0;
+        st->pending_convert = 0;
+        st->phase_iters = 0;
+        st->total_iters = 0;
+        for (int i = 0; i < 4; ++i) st->iters[i] = 0;
+        st->sweeps_total = 0;
+        st->ymode = rule.mode;
+        for (int i = 0; i < 4; ++i) st->hist[i] = INFINITY;
+        return;
+    }
+    // the block just produced (Y') becomes current; the basis the Ritz
+    // vectors were taken from stays readable until the next SpMM overwrites it
+    st->zbuf = st->ycur;
+    st->zmode = rule.mode;
+    st->ymode = rule.mode;
+    st->ycur ^= 1;
+    st->total_iters += 1;
+    st->iters[rule.phase] += 1;
+    st->sweeps_total += st->sweeps;
+    st->hist[3] = st->hist[2];
+    st->hist[2] = st->hist[1];
+    st->hist[1] = st->hist[0];
+    st->hist[0] = st->maxres;
+    st->phase_iters += 1;
+    if (st->flags & SF_NONFINITE) {
+        st->done = 1;
+        return;
+    }
+    if (rule.is_final) {
+        if (st->maxbound <= rule.tol) st->done = 1;
+        return;
+    }
+    const bool plateau = st->phase_iters >= 4 && st->hist[0] > 0.7 * st->hist[2] && st->hist[0] > 0.7 * st->hist[3];
+    if (st->maxres <= rule.floor_res || plateau || st->phase_iters >= rule.cap) {
+        st->phase += 1;
+        st->pending_convert = 1;
+        st->phase_iters = 0;
+        for (int i = 0; i < 4; ++i) st->hist[i] = INFINITY;
+    }
+}
+
+}  // namespace sbmds

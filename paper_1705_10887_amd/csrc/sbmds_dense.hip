@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void k_gemm_vec(int l, int lda, int kchunk, in
                                                   typename Traits<M>::TU *__restrict__ U,
                                                   const double *__restrict__ c, SolveState *__restrict__ st,
                                                   double *__restrict__ red, unsigned *__restrict__ tile_cnt,
-                                                  unsigned *__restrict__ tree_cnt) {
+                                                  unsigned *__restrict__ tree_cnt, int phase) {
     using Tr = Traits<M>;
     using TA = typename Tr::TA;
     using TT = typename Tr::TT;
@@ -76,6 +76,7 @@ __global__ __launch_bounds__(256) void k_gemm_vec(int l, int lda, int kchunk, in
     using Sh = GemmShape<TA, B>;
     constexpr int RW = Sh::RW, NV = Sh::NV, RT = Sh::RT;
     constexpr int TV = VecOf<TT, B>::v;
+    if (st->done || st->phase != phase) return;  // uniform: the schedule moved on
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
@@ -165,7 +166,7 @@ __global__ __launch_bounds__(256) void k_gemm_vec(int l, int lda, int kchunk, in
 }
 
 template <int MM, int BB>
-static hipError_t gemm_impl(const DevProblem &p, const LaunchCfg &cfg, hipStream_t s) {
+static hipError_t gemm_impl(const DevProblem &p, const LaunchCfg &cfg, int phase, hipStream_t s) {
     using Tr = Traits<MM>;
     using TA = typename Tr::TA;
     constexpr int RT = GemmShape<TA, BB>::RT;
@@ -178,7 +179,7 @@ static hipError_t gemm_impl(const DevProblem &p, const LaunchCfg &cfg, hipStream
     if (rowtiles > p.max_rowtiles || ksplit > p.max_ksplit) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_gemm_vec<MM, BB>), dim3(rowtiles, ksplit), dim3(256), 0, s, (int)p.l, p.lda, kchunk,
                        ksplit, (const typename Tr::TW *)p.W[MM], (const typename Tr::TT *)p.T, (TA *)p.gpart,
-                       (typename Tr::TU *)p.U, p.c[MM], p.st, p.red_gemm, p.tile_cnt, p.gemm_cnt);
+                       (typename Tr::TU *)p.U, p.c[MM], p.st, p.red_gemm, p.tile_cnt, p.gemm_cnt, phase);
     return hipGetLastError();
 }
 
@@ -192,12 +193,12 @@ static hipError_t gemm_impl(const DevProblem &p, const LaunchCfg &cfg, hipStream
         default: return hipErrorInvalidValue;            \
     }
 
-hipError_t launch_gemm(Mode m, const DevProblem &p, const LaunchCfg &cfg, hipStream_t s) {
+hipError_t launch_gemm(Mode m, const DevProblem &p, const LaunchCfg &cfg, int phase, hipStream_t s) {
     switch (m) {
-        case MODE_BF16: { constexpr int MM = MODE_BF16; SBMDS_DISPATCH_B2(p.B, return (gemm_impl<MM, BB>(p, cfg, s))); } break;
-        case MODE_FP32: { constexpr int MM = MODE_FP32; SBMDS_DISPATCH_B2(p.B, return (gemm_impl<MM, BB>(p, cfg, s))); } break;
-        case MODE_F64ACC: { constexpr int MM = MODE_F64ACC; SBMDS_DISPATCH_B2(p.B, return (gemm_impl<MM, BB>(p, cfg, s))); } break;
-        case MODE_FP64: { constexpr int MM = MODE_FP64; SBMDS_DISPATCH_B2(p.B, return (gemm_impl<MM, BB>(p, cfg, s))); } break;
+        case MODE_BF16: { constexpr int MM = MODE_BF16; SBMDS_DISPATCH_B2(p.B, return (gemm_impl<MM, BB>(p, cfg, phase, s))); } break;
+        case MODE_FP32: { constexpr int MM = MODE_FP32; SBMDS_DISPATCH_B2(p.B, return (gemm_impl<MM, BB>(p, cfg, phase, s))); } break;
+        case MODE_F64ACC: { constexpr int MM = MODE_F64ACC; SBMDS_DISPATCH_B2(p.B, return (gemm_impl<MM, BB>(p, cfg, phase, s))); } break;
+        case MODE_FP64: { constexpr int MM = MODE_FP64; SBMDS_DISPATCH_B2(p.B, return (gemm_impl<MM, BB>(p, cfg, phase, s))); } break;
         default: break;
     }
     return hipErrorInvalidValue;

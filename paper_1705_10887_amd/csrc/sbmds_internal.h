@@ -39,7 +39,32 @@ struct SolveState {
     int dead;                    // columns dropped after rank loss
     int nonpos;                  // wanted Ritz values <= 0
     int sweeps;                  // Jacobi sweeps of the last Rayleigh-Ritz step
-    int pad_;
+    // ---- device-side control of the precision schedule (see PhaseRule)
+    int ycur;                    // Y buffer holding the current block
+    int zbuf;                    // Y buffer the last Rayleigh-Ritz basis came from
+    int zmode;                   // Mode of that buffer
+    int phase;                   // running phase of the schedule
+    int done;                    // 1 once the stopping rule is met
+    int pending_convert;         // a phase just ended; the next one converts Y first
+    int phase_iters;             // iterations run in the current phase
+    int total_iters;             // iterations run in this solve
+    int iters[4];                // iterations run per phase
+    int sweeps_total;            // Jacobi sweeps in this solve
+    int ymode;                   // Mode of the current block Y[ycur]
+    double hist[4];              // maxres of the latest iterations of the phase
+};
+
+// What the Rayleigh-Ritz step decides after an iteration of phase `phase`.
+// A final phase ends the solve once maxbound <= tol; other phases hand over
+// to the next one once maxres <= floor_res, once the residual stalls
+// (no 30% gain over three iterations) or after `cap` iterations.
+struct PhaseRule {
+    int phase;
+    int is_final;
+    int cap;
+    int mode;
+    double floor_res;
+    double tol;
 };
 
 enum SolveFlags { SF_REPAIRED = 1, SF_NONFINITE = 2 };
@@ -81,16 +106,16 @@ struct LaunchCfg {
 
 // Kernel launchers (defined in the .hip files).  All are asynchronous on
 // `stream` and return the hipError_t of the launch.
-hipError_t launch_spmm_t(Mode m, const DevProblem &p, const LaunchCfg &cfg, int ycur, hipStream_t stream);
-hipError_t launch_gemm(Mode m, const DevProblem &p, const LaunchCfg &cfg, hipStream_t stream);
-hipError_t launch_spmm(Mode m, const DevProblem &p, const LaunchCfg &cfg, int ynext, hipStream_t stream);
-hipError_t launch_rr_solve(const DevProblem &p, int init, hipStream_t stream);
-hipError_t launch_random_start(Mode m, const DevProblem &p, const LaunchCfg &cfg, int ybuf,
-                               uint64_t seed, hipStream_t stream);
-hipError_t launch_user_start(Mode m, const DevProblem &p, const LaunchCfg &cfg, int ybuf,
-                             const void *X0, hipStream_t stream);
-hipError_t launch_convert_y(Mode from, Mode to, const DevProblem &p, int src, int dst,
-                            hipStream_t stream);
+hipError_t launch_spmm_t(Mode m, const DevProblem &p, const LaunchCfg &cfg, int phase, hipStream_t stream);
+hipError_t launch_gemm(Mode m, const DevProblem &p, const LaunchCfg &cfg, int phase, hipStream_t stream);
+hipError_t launch_spmm(Mode m, const DevProblem &p, const LaunchCfg &cfg, int phase, hipStream_t stream);
+hipError_t launch_rr_solve(const DevProblem &p, int init, int max_sweeps, const PhaseRule &rule,
+                           hipStream_t stream);
+hipError_t launch_random_start(Mode m, const DevProblem &p, const LaunchCfg &cfg, uint64_t seed,
+                               hipStream_t stream);
+hipError_t launch_user_start(Mode m, const DevProblem &p, const LaunchCfg &cfg, const void *X0,
+                             hipStream_t stream);
+hipError_t launch_convert_y(Mode from, Mode to, const DevProblem &p, int phase, hipStream_t stream);
 hipError_t launch_embedding(Mode m, const DevProblem &p, int ybuf, void *Z, int z_double,
                             hipStream_t stream);
 hipError_t launch_block_out(Mode m, const DevProblem &p, int ybuf, void *X, int x_double,

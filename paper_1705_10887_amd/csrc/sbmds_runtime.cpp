@@ -51,7 +51,10 @@ struct Summary {  // tail of SolveState read back after each iteration
     int dead;
     int nonpos;
     int sweeps;
-    int pad_;
+    int ycur, zbuf, zmode, phase, done, pending_convert, phase_iters, total_iters;
+    int iters[4];
+    int sweeps_total, ymode;
+    double hist[4];
 };
 static_assert(sizeof(Summary) == sizeof(SolveState) - offsetof(SolveState, theta), "summary layout");
 
@@ -111,8 +114,10 @@ struct sbmds_ctx {
     std::vector<KStat> stats;
     std::vector<PendingEv> pending;
     std::vector<hipEvent_t> ev_pool;
-    std::vector<int> last_ybuf;                // Y buffer holding the final basis per problem
+    std::vector<int> last_ybuf;                // Y buffer of the final Ritz basis per problem
     std::vector<int> last_mode;
+    std::vector<int> cur_ybuf, cur_mode;       // current block (for sbmds_get_block)
+    std::vector<std::vector<int>> expect;      // iterations per phase seen in the last solve
 };
 
 namespace {
@@ -235,12 +240,29 @@ std::vector<double> colsums(int64_t l, const std::vector<int32_t> &rpT, const st
     return c;
 }
 
-std::vector<Mode> schedule(int prec) {
-    switch (prec) {
-        case SBMDS_FP64: return {MODE_FP64};
-        case SBMDS_FP32: return {MODE_FP32, MODE_F64ACC};
-        default: return {MODE_BF16, MODE_FP32, MODE_F64ACC};
+// The precision schedule: one phase per arithmetic.  Non-final phases hand
+// over at the residual floor of their storage precision (or when the
+// residual stalls); the final phase stops at the certified tolerance.
+std::vector<PhaseRule> schedule(const sbmds_options &o) {
+    std::vector<Mode> modes;
+    switch (o.prec) {
+        case SBMDS_FP64: modes = {MODE_FP64}; break;
+        case SBMDS_FP32: modes = {MODE_FP32, MODE_F64ACC}; break;
+        default: modes = {MODE_BF16, MODE_FP32, MODE_F64ACC}; break;
     }
+    if ((o.flags & SBMDS_FLAG_NO_CERTIFY) && modes.size() > 1) modes.pop_back();
+    std::vector<PhaseRule> out;
+    for (size_t i = 0; i < modes.size(); ++i) {
+        PhaseRule r{};
+        r.phase = (int)i;
+        r.mode = modes[i];
+        r.is_final = (i + 1 == modes.size()) ? 1 : 0;
+        r.cap = 60;
+        r.floor_res = modes[i] == MODE_BF16 ? 5e-2 : 1e-3;
+        r.tol = o.tol;
+        out.push_back(r);
+    }
+    return out;
 }
 
 LaunchCfg default_cfg(Mode m, const DevProblem &p) {
@@ -321,17 +343,35 @@ int read_summary(sbmds_ctx *ctx, const DevProblem &p) {
     return SBMDS_OK;
 }
 
-int one_iteration(sbmds_ctx *ctx, int pi, Mode m, int ycur) {
+// Jacobi sweeps allowed per Rayleigh-Ritz step.  Inexact diagonalisation
+// keeps every reported bound valid (each Ritz value is the exact Rayleigh
+// quotient of the vector it belongs to, and its residual is measured), and
+// the next iteration continues the diagonalisation in the rotated basis;
+// the final phase, which may end the solve, diagonalises fully.
+int sweep_cap(const PhaseRule &r) {
+    static int env = -1;
+    if (env < 0) {
+        const char *e = std::getenv("SBMDS_MAX_SWEEPS");
+        env = e ? std::max(1, std::atoi(e)) : 0;
+    }
+    if (r.is_final) return 40;
+    return env > 0 ? env : 1;
+}
+
+// One iteration of phase `r`, enqueued without synchronising: every kernel
+// checks on the device that the solve is still in this phase.
+int enqueue_iteration(sbmds_ctx *ctx, int pi, const PhaseRule &r) {
     const DevProblem &p = ctx->probs[pi];
+    const Mode m = (Mode)r.mode;
     const LaunchCfg &cfg = ctx->cfg[pi][m];
     const double b = p.B;
     OKCHK(timed(ctx, "spmm_t", spmm_t_bytes(m, p), 2.0 * p.nnz * b,
-                [&] { return launch_spmm_t(m, p, cfg, ycur, ctx->stream); }));
+                [&] { return launch_spmm_t(m, p, cfg, r.phase, ctx->stream); }));
     OKCHK(timed(ctx, "gemm", gemm_bytes(m, p), 2.0 * (double)p.l * p.l * b,
-                [&] { return launch_gemm(m, p, cfg, ctx->stream); }));
+                [&] { return launch_gemm(m, p, cfg, r.phase, ctx->stream); }));
     OKCHK(timed(ctx, "spmm", spmm_bytes(m, p), 2.0 * p.nnz * b,
-                [&] { return launch_spmm(m, p, cfg, ycur ^ 1, ctx->stream); }));
-    OKCHK(timed(ctx, "rr_solve", 0.0, 0.0, [&] { return launch_rr_solve(p, 0, ctx->stream); }));
+                [&] { return launch_spmm(m, p, cfg, r.phase, ctx->stream); }));
+    OKCHK(timed(ctx, "rr_solve", 0.0, 0.0, [&] { return launch_rr_solve(p, 0, sweep_cap(r), r, ctx->stream); }));
     return SBMDS_OK;
 }
 
@@ -344,85 +384,77 @@ double ms_between(hipEvent_t a, hipEvent_t b) {
 int solve_problem(sbmds_ctx *ctx, int pi, sbmds_report *rep) {
     DevProblem &p = ctx->probs[pi];
     const sbmds_options &o = ctx->opt;
-    const std::vector<Mode> modes = schedule(o.prec);
+    const std::vector<PhaseRule> rules = schedule(o);
+    const int nph = (int)rules.size();
+    std::vector<int> &expect = ctx->expect[pi];
+    if ((int)expect.size() != nph) {
+        expect.assign(nph, 3);
+        expect[nph - 1] = 1;
+    }
     hipEvent_t e0 = ev_get(ctx), e1 = ev_get(ctx), e2 = ev_get(ctx);
     HIPCHK(hipEventRecord(e0, ctx->stream));
 
-    // start block
-    int ycur = 0;
-    Mode m = modes[0];
+    // start block in buffer 0, then its orthonormalisation
+    const Mode m0 = (Mode)rules[0].mode;
     if (o.start == SBMDS_START_USER) {
         OKCHK(timed(ctx, "start", 0.0, 0.0,
-                    [&] { return launch_user_start(m, p, ctx->cfg[pi][m], ycur, ctx->user_x0[pi], ctx->stream); }));
+                    [&] { return launch_user_start(m0, p, ctx->cfg[pi][m0], ctx->user_x0[pi], ctx->stream); }));
     } else {
         // LMDS and learned starts fall back to the random block here
         OKCHK(timed(ctx, "start", 0.0, 0.0, [&] {
-            return launch_random_start(m, p, ctx->cfg[pi][m], ycur, o.seed + 0x9E3779B97F4A7C15ull * (uint64_t)pi,
+            return launch_random_start(m0, p, ctx->cfg[pi][m0], o.seed + 0x9E3779B97F4A7C15ull * (uint64_t)pi,
                                        ctx->stream);
         }));
     }
-    OKCHK(timed(ctx, "rr_init", 0.0, 0.0, [&] { return launch_rr_solve(p, 1, ctx->stream); }));
+    OKCHK(timed(ctx, "rr_init", 0.0, 0.0, [&] { return launch_rr_solve(p, 1, 0, rules[0], ctx->stream); }));
     HIPCHK(hipEventRecord(e1, ctx->stream));
 
-    int iters = 0, it_mode[NUM_MODES] = {0, 0, 0, 0};
-    bool done = false, certified = false;
-    int zbuf = ycur;
-    Mode zmode = m;
-    for (size_t ph = 0; ph < modes.size() && !done; ++ph) {
-        const Mode mm = modes[ph];
-        if (ph > 0) {
-            OKCHK(timed(ctx, "convert", 0.0, 0.0,
-                        [&] { return launch_convert_y(modes[ph - 1], mm, p, ycur, ycur ^ 1, ctx->stream); }));
-            ycur ^= 1;
+    // Enqueue whole phases without waiting; the device decides when each
+    // phase ends and when the solve is done, and later launches return at
+    // once.  The host looks at the state once per round.
+    int launched = 0, from = 0, pending = 0;
+    bool first = true;
+    const Summary &s = *ctx->host_sum;
+    for (;;) {
+        for (int ph = from; ph < nph && launched < o.max_iter; ++ph) {
+            if (ph > from || pending) {
+                const Mode mf = (Mode)rules[ph - 1].mode, mt = (Mode)rules[ph].mode;
+                OKCHK(timed(ctx, "convert", 0.0, 0.0, [&] { return launch_convert_y(mf, mt, p, ph, ctx->stream); }));
+            }
+            int n_it = (first || ph > from) ? std::max(1, expect[ph]) : 2;
+            n_it = std::min(n_it, o.max_iter - launched);
+            for (int i = 0; i < n_it; ++i) OKCHK(enqueue_iteration(ctx, pi, rules[ph]));
+            launched += n_it;
         }
-        std::vector<double> hist;
-        const bool final_phase = (mm == MODE_F64ACC || mm == MODE_FP64);
-        while (iters < o.max_iter) {
-            OKCHK(one_iteration(ctx, pi, mm, ycur));
-            OKCHK(read_summary(ctx, p));
-            zbuf = ycur;
-            zmode = mm;
-            ycur ^= 1;
-            ++iters;
-            ++it_mode[mm];
-            const Summary &s = *ctx->host_sum;
-            if (s.flags & SF_NONFINITE) return fail(SBMDS_EBREAKDOWN, "non-finite values in the block solver");
-            hist.push_back(s.maxres);
-            const size_t h = hist.size();
-            if (final_phase) {
-                if (s.maxbound <= o.tol) {
-                    done = true;
-                    certified = true;
-                    break;
-                }
-                continue;
-            }
-            if (mm == MODE_FP32 && (o.flags & SBMDS_FLAG_NO_CERTIFY) && s.maxbound <= o.tol) {
-                done = true;
-                break;
-            }
-            const double floor_res = (mm == MODE_BF16) ? 5e-2 : 1e-3;
-            const bool plateau = h >= 4 && hist[h - 1] > 0.7 * hist[h - 3] && hist[h - 1] > 0.7 * hist[h - 4];
-            if (s.maxres <= floor_res || plateau) {
-                if (mm == MODE_FP32 && (o.flags & SBMDS_FLAG_NO_CERTIFY)) continue;
-                break;  // next phase
-            }
-        }
-        if (iters >= o.max_iter) break;
+        OKCHK(read_summary(ctx, p));
+        if (s.done || launched >= o.max_iter) break;
+        from = s.phase;
+        pending = s.pending_convert;
+        first = false;
+        if (from >= nph) break;  // cannot happen: the final phase never hands over
     }
+    if (s.flags & SF_NONFINITE) return fail(SBMDS_EBREAKDOWN, "non-finite values in the block solver");
+    const bool done = s.done != 0;
+    if (done)
+        for (int ph = 0; ph < nph; ++ph) expect[ph] = s.iters[ph];
     HIPCHK(hipEventRecord(e2, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    ctx->last_ybuf[pi] = zbuf;
-    ctx->last_mode[pi] = zmode;
-    const Summary &s = *ctx->host_sum;
+    ctx->last_ybuf[pi] = s.zbuf;
+    ctx->last_mode[pi] = s.zmode;
+    ctx->cur_ybuf[pi] = s.ycur;
+    ctx->cur_mode[pi] = s.ymode;
     if (rep) {
         std::memset(rep, 0, sizeof(*rep));
         rep->status = done ? SBMDS_OK : SBMDS_ENOCONV;
-        rep->iters_bf16 = it_mode[MODE_BF16];
-        rep->iters_fp32 = it_mode[MODE_FP32];
-        rep->iters_fp64 = it_mode[MODE_F64ACC] + it_mode[MODE_FP64];
+        for (int ph = 0; ph < nph; ++ph) {
+            const int it = s.iters[ph];
+            if (rules[ph].mode == MODE_BF16) rep->iters_bf16 += it;
+            else if (rules[ph].mode == MODE_FP32) rep->iters_fp32 += it;
+            else rep->iters_fp64 += it;
+        }
         rep->nonpositive = s.nonpos;
-        rep->certified = certified ? 1 : 0;
+        rep->certified = (done && rules[nph - 1].mode != MODE_FP32 && rules[nph - 1].mode != MODE_BF16) ? 1 : 0;
+        rep->jacobi_sweeps = s.sweeps_total;
         rep->ms_start = ms_between(e0, e1);
         rep->ms_iter = ms_between(e1, e2);
         rep->ms_total = ms_between(e0, e2);
@@ -550,7 +582,10 @@ int create_impl(const sbmds_problem *probs, int nprob, const sbmds_options *opt_
     ctx->cfg.resize(nprob);
     ctx->user_x0.assign(nprob, nullptr);
     ctx->last_ybuf.assign(nprob, 0);
-    ctx->last_mode.assign(nprob, (int)schedule(o.prec).back());
+    ctx->last_mode.assign(nprob, schedule(o).back().mode);
+    ctx->cur_ybuf.assign(nprob, 0);
+    ctx->cur_mode.assign(nprob, schedule(o).back().mode);
+    ctx->expect.assign(nprob, std::vector<int>());
     auto cleanup = [&](int rc) {
         sbmds_destroy(ctx);
         return rc;
@@ -728,7 +763,7 @@ int sbmds_get_block(sbmds_ctx *ctx, int prob, void *X, int X_mem) {
     void *dx = X;
     HIPCHK(hipSetDevice(ctx->device));
     if (X_mem == SBMDS_MEM_HOST) HIPCHK(hipMalloc(&dx, bytes));
-    hipError_t e = launch_block_out((Mode)ctx->last_mode[prob], p, ctx->last_ybuf[prob], dx, xd ? 1 : 0, ctx->stream);
+    hipError_t e = launch_block_out((Mode)ctx->cur_mode[prob], p, ctx->cur_ybuf[prob], dx, xd ? 1 : 0, ctx->stream);
     if (e == hipSuccess && X_mem == SBMDS_MEM_HOST) e = hipMemcpyAsync(X, dx, bytes, hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (X_mem == SBMDS_MEM_HOST) (void)hipFree(dx);

@@ -19,7 +19,7 @@
 //   5. Sc^T Gc S = L L^T (Cholesky) and C' = S L^{-T}, so X' = J Y' C' is
 //      orthonormal again and its leading columns follow the Ritz order.
 // In `init` mode only step 5 runs, with S = I, on a fresh start block.
-#include "sbmds_common.h"
+#include "sbmds_bounds.h"
 
 namespace sbmds {
 
@@ -50,13 +50,13 @@ __device__ __forceinline__ double wave_sum(double v) {
 // splits into independent 2x2 blocks (pair k rows, pair l columns) and
 // V <- V J into independent row pieces: one barrier-separated phase each.
 template <int B>
-__device__ int jacobi(SmallLds<B> &L, int b) {
+__device__ int jacobi(SmallLds<B> &L, int b, int max_sweeps) {
     const int tid = threadIdx.x;
     constexpr int NT = kSolveThreads;
     const int bb = (b & 1) ? b + 1 : b;  // odd sizes get a dummy index (a zero padding row)
     const int npair = bb / 2;
     int sweep = 0;
-    for (; sweep < 40; ++sweep) {
+    for (; sweep < max_sweeps; ++sweep) {
         double off = 0.0, dia = 0.0;
         for (int e = tid; e < b * b; e += NT) {
             const int i = e / b, j = e % b;
@@ -66,7 +66,7 @@ __device__ int jacobi(SmallLds<B> &L, int b) {
         }
         off = wave_sum(off);
         dia = wave_sum(dia);
-        if (!(off > 1e-30 * dia) || dia == 0.0) break;
+        if (!(off > 1e-24 * dia) || dia == 0.0) break;
         for (int round = 0; round < bb - 1; ++round) {
             if (tid < npair) {
                 int p, q;
@@ -127,52 +127,12 @@ __device__ int jacobi(SmallLds<B> &L, int b) {
     return sweep;
 }
 
-// Error bounds for the k wanted Ritz values (one thread).  Ritz values closer
-// than 1e-3 (relative) form a cluster; a cluster's gap is its distance to the
-// nearest other Ritz value or to the magnitude of the smallest Ritz value of
-// the block (which stands for the spectrum the block does not hold).  For
-// each wanted value the bound is min(||r_i||, ||R_cluster||^2 / gap) / |theta_i|.
-__device__ void bounds(SolveState *st, const double *th, const double *res, int b, int k) {
-    double floor_mag = INFINITY;
-    for (int i = 0; i < b; ++i) floor_mag = fmin(floor_mag, fabs(th[i]));
-    double maxb = 0.0, maxr = 0.0;
-    int nonpos = 0;
-    int i = 0;
-    while (i < b) {
-        int j = i;
-        while (j + 1 < b && fabs(th[j] - th[j + 1]) <= 1e-3 * fmax(fabs(th[j]), fabs(th[j + 1]))) ++j;
-        double r2 = 0.0;
-        for (int q = i; q <= j; ++q) r2 += res[q] * res[q];
-        double gap = INFINITY;
-        if (i > 0) gap = fmin(gap, th[i - 1] - th[i]);
-        if (j + 1 < b) gap = fmin(gap, th[j] - th[j + 1]);
-        const double lo = th[j];
-        const double out_gap = lo > 0.0 ? lo - floor_mag : (-lo) - floor_mag;
-        gap = fmin(gap, out_gap);
-        for (int q = i; q <= j; ++q) {
-            const double a = fabs(th[q]);
-            double bnd = res[q];
-            if (gap > 0.0) bnd = fmin(bnd, r2 / gap);
-            const double rel = a > 0.0 ? bnd / a : INFINITY;
-            st->bound[q] = rel;
-            st->res[q] = res[q];
-            if (q < k) {
-                maxb = fmax(maxb, rel);
-                maxr = fmax(maxr, a > 0.0 ? res[q] / a : INFINITY);
-                if (th[q] <= 0.0) ++nonpos;
-            }
-        }
-        i = j + 1;
-    }
-    st->maxbound = maxb;
-    st->maxres = maxr;
-    st->nonpos = nonpos;
-}
-
 template <int B>
 __global__ __launch_bounds__(kSolveThreads) void k_rr_solve(SolveState *__restrict__ st, int b, int k,
-                                                            double n, double piv_tol, int init) {
+                                                            double n, double piv_tol, int init,
+                                                            int max_sweeps, PhaseRule rule) {
     __shared__ SmallLds<B> L;
+    if (!init && (st->done || st->phase != rule.phase)) return;
     constexpr int NT = kSolveThreads;
     constexpr int E = B * (B + 1) / 2;
     const int tid = threadIdx.x;
@@ -205,7 +165,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_rr_solve(SolveState *__restri
     __syncthreads();
 
     if (!init) {
-        const int nsw = jacobi<B>(L, b);
+        const int nsw = jacobi<B>(L, b, max_sweeps);
         if (tid == 0) st->sweeps = nsw;
         // sort Ritz values descending (ties by index)
         for (int t = tid; t < b; t += NT) {
@@ -347,21 +307,26 @@ __global__ __launch_bounds__(kSolveThreads) void k_rr_solve(SolveState *__restri
             st->iter = 0;
             st->maxbound = INFINITY;
             st->maxres = INFINITY;
+            st->sweeps = 0;
         } else {
             st->iter += 1;
         }
+        phase_control(st, rule, init);
     }
 }
 
-hipError_t launch_rr_solve(const DevProblem &p, int init, hipStream_t s) {
+hipError_t launch_rr_solve_reg(const DevProblem &p, int init, int max_sweeps, const PhaseRule &rule, hipStream_t s);
+
+hipError_t launch_rr_solve(const DevProblem &p, int init, int max_sweeps, const PhaseRule &rule, hipStream_t s) {
+    if (p.B <= 16) return launch_rr_solve_reg(p, init, max_sweeps, rule, s);
     const double piv_tol = 1e-10;
     const dim3 blk(kSolveThreads);
     switch (p.B) {
-        case 4: hipLaunchKernelGGL((k_rr_solve<4>), dim3(1), blk, 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init); break;
-        case 8: hipLaunchKernelGGL((k_rr_solve<8>), dim3(1), blk, 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init); break;
-        case 16: hipLaunchKernelGGL((k_rr_solve<16>), dim3(1), blk, 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init); break;
-        case 32: hipLaunchKernelGGL((k_rr_solve<32>), dim3(1), blk, 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init); break;
-        case 64: hipLaunchKernelGGL((k_rr_solve<64>), dim3(1), blk, 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init); break;
+        case 4: hipLaunchKernelGGL((k_rr_solve<4>), dim3(1), blk, 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init, max_sweeps, rule); break;
+        case 8: hipLaunchKernelGGL((k_rr_solve<8>), dim3(1), blk, 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init, max_sweeps, rule); break;
+        case 16: hipLaunchKernelGGL((k_rr_solve<16>), dim3(1), blk, 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init, max_sweeps, rule); break;
+        case 32: hipLaunchKernelGGL((k_rr_solve<32>), dim3(1), blk, 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init, max_sweeps, rule); break;
+        case 64: hipLaunchKernelGGL((k_rr_solve<64>), dim3(1), blk, 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init, max_sweeps, rule); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

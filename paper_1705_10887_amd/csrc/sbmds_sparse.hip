@@ -71,8 +71,7 @@ __global__ __launch_bounds__(256) void k_spmm(int n, const int32_t *__restrict__
                                               const int32_t *__restrict__ ci,
                                               const typename Traits<M>::TP *__restrict__ val,
                                               const typename Traits<M>::TU *__restrict__ U,
-                                              SolveState *__restrict__ st,
-                                              typename Traits<M>::TY *__restrict__ Y,
+                                              SolveState *__restrict__ st, void *Y0, void *Y1, int phase,
                                               double *__restrict__ red, unsigned *__restrict__ cnt) {
     using Tr = Traits<M>;
     using TA = typename Tr::TA;
@@ -81,6 +80,8 @@ __global__ __launch_bounds__(256) void k_spmm(int n, const int32_t *__restrict__
     using S = SpmmShape<M, B>;
     constexpr int VEC = S::VEC, LPR = S::LPR, RPB = S::RPB, E = S::E, NQ = S::NQ;
     __shared__ double tile[RPB][B];
+    if (st->done || st->phase != phase) return;  // uniform: the schedule moved on
+    TY *__restrict__ Y = (TY *)(st->ycur ? Y0 : Y1);  // writes the other buffer
 
     const int tid = threadIdx.x;
     const int g = tid % LPR;
@@ -193,9 +194,9 @@ template <int M, int B, int WPR>
 __global__ __launch_bounds__(256) void k_spmm_t(int l, int n, const int32_t *__restrict__ rpT,
                                                 const int32_t *__restrict__ ciT,
                                                 const typename Traits<M>::TP *__restrict__ valT,
-                                                const typename Traits<M>::TY *__restrict__ Y,
+                                                const void *Y0, const void *Y1,
                                                 const double *__restrict__ c,
-                                                const SolveState *__restrict__ st,
+                                                const SolveState *__restrict__ st, int phase,
                                                 typename Traits<M>::TT *__restrict__ T) {
     using Tr = Traits<M>;
     using TA = typename Tr::TA;
@@ -209,6 +210,8 @@ __global__ __launch_bounds__(256) void k_spmm_t(int l, int n, const int32_t *__r
     __shared__ double ex[B];
     __shared__ double part[4][B];       // per-wave partial sums
     __shared__ double rowbuf[RPBLK][B];
+    if (st->done || st->phase != phase) return;
+    const TY *__restrict__ Y = (const TY *)(st->ycur ? Y1 : Y0);
 
     const int tid = threadIdx.x;
     for (int i = tid; i < B * B; i += 256) Cl[i] = st->C[i];
@@ -296,13 +299,15 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
     }
 }
 
-// Standard normal from two uniforms in (0, 1] (Box-Muller).
-__device__ __forceinline__ double gauss_from(uint32_t a, uint32_t b) {
-    const double u1 = ((double)a + 1.0) * (1.0 / 4294967296.0);
-    const double u2 = (double)b * (1.0 / 4294967296.0);
-    return sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
+// Standard normal from two uniforms in (0, 1] (Box-Muller, float32: the
+// start block needs no precision).
+__device__ __forceinline__ float gauss_from(uint32_t a, uint32_t b) {
+    const float u1 = ((float)(a >> 8) + 1.0f) * (1.0f / 16777216.0f);
+    const float u2 = (float)(b >> 8) * (1.0f / 16777216.0f);
+    return sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
 }
 
+// Start block into buffer 0; columns >= b are zero.  Counter (row, column).
 template <int M, int B>
 __global__ __launch_bounds__(256) void k_random_block(int n, int b, uint64_t seed,
                                                       typename Traits<M>::TY *__restrict__ Y) {
@@ -312,7 +317,7 @@ __global__ __launch_bounds__(256) void k_random_block(int n, int b, uint64_t see
     if (idx >= (int64_t)n * B) return;
     const int64_t row = idx / B;
     const int col = (int)(idx % B);
-    double z = 0.0;
+    float z = 0.0f;
     if (col < b) {
         uint32_t ctr[4] = {(uint32_t)row, (uint32_t)col, (uint32_t)(row >> 32), 0u};
         philox4x32_10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32));
@@ -334,13 +339,28 @@ __global__ __launch_bounds__(256) void k_load_block(int n, int b, const TS *__re
     Y[idx] = down<TY>(v);
 }
 
+// Precision change at the start of phase `phase`: the current block is
+// copied into the other buffer in the new storage type (widening, so
+// exact).  Runs only when the previous phase has just ended.
 template <int MF, int MT>
-__global__ __launch_bounds__(256) void k_convert(int64_t count, const typename Traits<MF>::TY *__restrict__ src,
-                                                 typename Traits<MT>::TY *__restrict__ dst) {
+__global__ __launch_bounds__(256) void k_convert(int64_t count, const void *Y0, const void *Y1, void *W0, void *W1,
+                                                 const SolveState *__restrict__ st, int phase) {
+    if (st->done || st->phase != phase || !st->pending_convert) return;
     using TAt = typename Traits<MT>::TA;
     using TYt = typename Traits<MT>::TY;
+    const typename Traits<MF>::TY *src = (const typename Traits<MF>::TY *)(st->ycur ? Y1 : Y0);
+    TYt *dst = (TYt *)(st->ycur ? W0 : W1);
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < count) dst[i] = down<TYt>((TAt)up<double>(src[i]));
+}
+
+// After the conversion: the other buffer is now current.
+__global__ void k_phase_begin(SolveState *__restrict__ st, int phase, int mode) {
+    if (threadIdx.x == 0 && !st->done && st->phase == phase && st->pending_convert) {
+        st->ycur ^= 1;
+        st->ymode = mode;
+        st->pending_convert = 0;
+    }
 }
 
 // Z = J Y Zmap restricted to the first k columns: Z_ij = sum_a Y_ia Zmap_aj - zshift_j.
@@ -418,106 +438,107 @@ static size_t val_bytes() { return sizeof(typename Traits<M>::TP); }
     }
 
 template <int MM, int BB>
-static hipError_t spmm_impl(const DevProblem &p, const LaunchCfg &cfg, int ynext, hipStream_t s) {
+static hipError_t spmm_impl(const DevProblem &p, const LaunchCfg &cfg, int phase, hipStream_t s) {
     using Tr = Traits<MM>;
     const int grid = cfg.spmm_blocks;
     if (grid <= 0 || grid > p.max_spmm_blocks) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_spmm<MM, BB>), dim3(grid), dim3(256), 0, s, (int)p.n, p.rp, p.ci,
-                       (const typename Tr::TP *)p.val[MM], (const typename Tr::TU *)p.U, p.st,
-                       (typename Tr::TY *)p.Y[ynext], p.red_spmm, p.spmm_cnt);
+                       (const typename Tr::TP *)p.val[MM], (const typename Tr::TU *)p.U, p.st, p.Y[0], p.Y[1],
+                       phase, p.red_spmm, p.spmm_cnt);
     return hipGetLastError();
 }
 
-hipError_t launch_spmm(Mode m, const DevProblem &p, const LaunchCfg &cfg, int ynext, hipStream_t s) {
-    SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(p.B, return (spmm_impl<MM, BB>(p, cfg, ynext, s))));
+hipError_t launch_spmm(Mode m, const DevProblem &p, const LaunchCfg &cfg, int phase, hipStream_t s) {
+    SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(p.B, return (spmm_impl<MM, BB>(p, cfg, phase, s))));
     return hipErrorInvalidValue;
 }
 
 template <int MM, int BB, int WPR>
-static hipError_t spmm_t_impl(const DevProblem &p, int ycur, hipStream_t s) {
+static hipError_t spmm_t_impl(const DevProblem &p, int phase, hipStream_t s) {
     using Tr = Traits<MM>;
     constexpr int RPBLK = 4 / WPR;
     const int grid = (int)((p.l + RPBLK - 1) / RPBLK);
     hipLaunchKernelGGL((k_spmm_t<MM, BB, WPR>), dim3(grid), dim3(256), 0, s, (int)p.l, (int)p.n, p.rpT, p.ciT,
-                       (const typename Tr::TP *)p.valT[MM], (const typename Tr::TY *)p.Y[ycur], p.c[MM],
-                       p.st, (typename Tr::TT *)p.T);
+                       (const typename Tr::TP *)p.valT[MM], (const void *)p.Y[0], (const void *)p.Y[1], p.c[MM],
+                       p.st, phase, (typename Tr::TT *)p.T);
     return hipGetLastError();
 }
 
-hipError_t launch_spmm_t(Mode m, const DevProblem &p, const LaunchCfg &cfg, int ycur, hipStream_t s) {
+hipError_t launch_spmm_t(Mode m, const DevProblem &p, const LaunchCfg &cfg, int phase, hipStream_t s) {
     switch (cfg.spmmt_wpr) {
-        case 1: SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(p.B, return (spmm_t_impl<MM, BB, 1>(p, ycur, s)))); break;
-        case 2: SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(p.B, return (spmm_t_impl<MM, BB, 2>(p, ycur, s)))); break;
-        case 4: SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(p.B, return (spmm_t_impl<MM, BB, 4>(p, ycur, s)))); break;
+        case 1: SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(p.B, return (spmm_t_impl<MM, BB, 1>(p, phase, s)))); break;
+        case 2: SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(p.B, return (spmm_t_impl<MM, BB, 2>(p, phase, s)))); break;
+        case 4: SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(p.B, return (spmm_t_impl<MM, BB, 4>(p, phase, s)))); break;
         default: return hipErrorInvalidValue;
     }
     return hipErrorInvalidValue;
 }
 
 template <int MM, int BB>
-static hipError_t start_impl(const DevProblem &p, const LaunchCfg &cfg, int ybuf, uint64_t seed,
-                             const void *X0, hipStream_t s) {
+static hipError_t start_impl(const DevProblem &p, const LaunchCfg &cfg, uint64_t seed, const void *X0,
+                             hipStream_t s) {
     using Tr = Traits<MM>;
     const int64_t count = p.n * (int64_t)BB;
     const int g1 = (int)((count + 255) / 256);
     if (X0 == nullptr) {
         hipLaunchKernelGGL((k_random_block<MM, BB>), dim3(g1), dim3(256), 0, s, (int)p.n, p.b, seed,
-                           (typename Tr::TY *)p.Y[ybuf]);
+                           (typename Tr::TY *)p.Y[0]);
     } else if (MM == MODE_FP64) {
         hipLaunchKernelGGL((k_load_block<double, MM, BB>), dim3(g1), dim3(256), 0, s, (int)p.n, p.b,
-                           (const double *)X0, (typename Tr::TY *)p.Y[ybuf]);
+                           (const double *)X0, (typename Tr::TY *)p.Y[0]);
     } else {
         hipLaunchKernelGGL((k_load_block<float, MM, BB>), dim3(g1), dim3(256), 0, s, (int)p.n, p.b,
-                           (const float *)X0, (typename Tr::TY *)p.Y[ybuf]);
+                           (const float *)X0, (typename Tr::TY *)p.Y[0]);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int grid = cfg.spmm_blocks;
     if (grid <= 0 || grid > p.max_spmm_blocks) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_gram<MM, BB>), dim3(grid), dim3(256), 0, s, (int)p.n,
-                       (const typename Tr::TY *)p.Y[ybuf], p.st, p.red_spmm, p.spmm_cnt);
+                       (const typename Tr::TY *)p.Y[0], p.st, p.red_spmm, p.spmm_cnt);
     return hipGetLastError();
 }
 
-hipError_t launch_random_start(Mode m, const DevProblem &p, const LaunchCfg &cfg, int ybuf, uint64_t seed,
-                               hipStream_t s) {
-    SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(p.B, return (start_impl<MM, BB>(p, cfg, ybuf, seed, nullptr, s))));
+hipError_t launch_random_start(Mode m, const DevProblem &p, const LaunchCfg &cfg, uint64_t seed, hipStream_t s) {
+    SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(p.B, return (start_impl<MM, BB>(p, cfg, seed, nullptr, s))));
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_user_start(Mode m, const DevProblem &p, const LaunchCfg &cfg, int ybuf, const void *X0,
-                             hipStream_t s) {
+hipError_t launch_user_start(Mode m, const DevProblem &p, const LaunchCfg &cfg, const void *X0, hipStream_t s) {
     if (X0 == nullptr) return hipErrorInvalidValue;
-    SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(p.B, return (start_impl<MM, BB>(p, cfg, ybuf, 0, X0, s))));
+    SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(p.B, return (start_impl<MM, BB>(p, cfg, 0, X0, s))));
     return hipErrorInvalidValue;
 }
 
 template <int MF, int MT>
-static hipError_t convert_impl(const DevProblem &p, int src, int dst, hipStream_t s) {
+static hipError_t convert_impl(const DevProblem &p, int phase, hipStream_t s) {
     const int64_t count = p.n * (int64_t)p.B;
     hipLaunchKernelGGL((k_convert<MF, MT>), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, count,
-                       (const typename Traits<MF>::TY *)p.Y[src], (typename Traits<MT>::TY *)p.Y[dst]);
+                       (const void *)p.Y[0], (const void *)p.Y[1], p.Y[0], p.Y[1], (const SolveState *)p.st,
+                       phase);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_phase_begin, dim3(1), dim3(64), 0, s, p.st, phase, MT);
     return hipGetLastError();
 }
 
-hipError_t launch_convert_y(Mode from, Mode to, const DevProblem &p, int src, int dst, hipStream_t s) {
-    if (src == dst) return hipErrorInvalidValue;
+hipError_t launch_convert_y(Mode from, Mode to, const DevProblem &p, int phase, hipStream_t s) {
     switch (from) {
         case MODE_BF16: {
             constexpr int MF = MODE_BF16;
-            SBMDS_DISPATCH_M(to, return (convert_impl<MF, MM>(p, src, dst, s)));
+            SBMDS_DISPATCH_M(to, return (convert_impl<MF, MM>(p, phase, s)));
         } break;
         case MODE_FP32: {
             constexpr int MF = MODE_FP32;
-            SBMDS_DISPATCH_M(to, return (convert_impl<MF, MM>(p, src, dst, s)));
+            SBMDS_DISPATCH_M(to, return (convert_impl<MF, MM>(p, phase, s)));
         } break;
         case MODE_F64ACC: {
             constexpr int MF = MODE_F64ACC;
-            SBMDS_DISPATCH_M(to, return (convert_impl<MF, MM>(p, src, dst, s)));
+            SBMDS_DISPATCH_M(to, return (convert_impl<MF, MM>(p, phase, s)));
         } break;
         case MODE_FP64: {
             constexpr int MF = MODE_FP64;
-            SBMDS_DISPATCH_M(to, return (convert_impl<MF, MM>(p, src, dst, s)));
+            SBMDS_DISPATCH_M(to, return (convert_impl<MF, MM>(p, phase, s)));
         } break;
         default: return hipErrorInvalidValue;
     }

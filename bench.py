@@ -81,28 +81,54 @@ def cpu_baseline(prob, k, budget_s=20.0):
 
 
 def traffic_from_profiles(kernel):
-    """HBM bytes per launch from committed rocprofv3 counter summaries."""
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    import hashlib
+
     path = os.path.join(ROOT, "profiles", f"{kernel}_sphere7_traffic.md")
     if not os.path.exists(path):
         return None
+    want, value = None, None
     for line in open(path):
-        if line.startswith("traffic_bytes_per_launch:"):
+        if line.startswith("kernel_source_sha1:"):
+            parts = line.split()
+            want = (parts[1], parts[2])
+        elif line.startswith("traffic_bytes_per_launch:"):
             try:
-                return float(line.split(":", 1)[1])
+                value = float(line.split(":", 1)[1])
             except ValueError:
                 return None
-    return None
+    if want is None or value is None:
+        return None
+    src = os.path.join(ROOT, "paper_1705_10887_amd", "csrc", want[0])
+    if not os.path.exists(src):
+        return None
+    have = hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]
+    return value if have == want[1] else None
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=3, help=">= 1; the first call learns the phase schedule")
     ap.add_argument("--k", type=int, default=3)
     ap.add_argument("--block", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.empty(args.calibrate_copy << 18, dtype=torch.float32, device="cuda")
+        a.fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4, "launches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build runs the solve on a single MI355X); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)

@@ -180,6 +180,18 @@ __host__ __device__ inline int tree_counter_count(int nparts, int fan) {
 
 constexpr int kFan = 16;
 
+// Problem that owns block `bid` of a batched launch: the largest p with
+// off[p] <= bid (off is ascending, off[0] = 0).  Uniform across the block.
+__device__ __forceinline__ int find_problem(const int *__restrict__ off, int nprob, int bid) {
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= bid) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 __device__ __forceinline__ void tri_index(int ent, int B, int &a, int &b) {
     int r = ent, i = 0;
     while (r >= B - i) {

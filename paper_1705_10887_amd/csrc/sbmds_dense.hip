@@ -61,28 +61,40 @@ struct ReduceScatter {
 };
 
 template <int M, int B>
-__global__ __launch_bounds__(256) void k_gemm_vec(int l, int lda, int kchunk, int ksplit,
-                                                  const typename Traits<M>::TW *__restrict__ W,
-                                                  const typename Traits<M>::TT *__restrict__ T,
-                                                  typename Traits<M>::TA *__restrict__ part,
-                                                  typename Traits<M>::TU *__restrict__ U,
-                                                  const double *__restrict__ c, SolveState *__restrict__ st,
-                                                  double *__restrict__ red, unsigned *__restrict__ tile_cnt,
-                                                  unsigned *__restrict__ tree_cnt, int phase) {
+__global__ __launch_bounds__(256) void k_gemm_vec(const ProbView *__restrict__ views, const int *__restrict__ off,
+                                                  int nprob, int phase) {
     using Tr = Traits<M>;
     using TA = typename Tr::TA;
     using TT = typename Tr::TT;
     using TU = typename Tr::TU;
+    using TW = typename Tr::TW;
     using Sh = GemmShape<TA, B>;
     constexpr int RW = Sh::RW, NV = Sh::NV, RT = Sh::RT;
     constexpr int TV = VecOf<TT, B>::v;
+
+    const int pidx = find_problem(off, nprob, blockIdx.x);
+    const ProbView &v = views[pidx];
+    SolveState *__restrict__ st = v.st;
     if (st->done || st->phase != phase) return;  // uniform: the schedule moved on
+    const int vb = blockIdx.x - off[pidx];
+    const int l = v.l, lda = v.lda;
+    const int rowtiles = v.gemm_rowtiles[M];
+    const int ksplit = v.gemm_ksplit[M];
+    const int kchunk = v.gemm_kchunk[M];
+    const TW *__restrict__ W = (const TW *)v.W[M];
+    const TT *__restrict__ T = (const TT *)v.T;
+    TA *__restrict__ part = (TA *)v.gpart;
+    TU *__restrict__ U = (TU *)v.U;
+    const double *__restrict__ c = v.c[M];
+    double *__restrict__ red = v.red_gemm;
+    unsigned *__restrict__ tile_cnt = v.tile_cnt;
+    unsigned *__restrict__ tree_cnt = v.gemm_cnt;
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
-    const int rt = blockIdx.x;
-    const int ks = blockIdx.y;
+    const int rt = vb % rowtiles;
+    const int ks = vb / rowtiles;
     const int r0 = rt * RT + wave * RW;
     const int kbeg = ks * kchunk;
     const int kend = min(lda, kbeg + kchunk);
@@ -162,25 +174,7 @@ __global__ __launch_bounds__(256) void k_gemm_vec(int l, int lda, int kchunk, in
         for (int r = 0; r < RT; ++r) s += cl[r] * ul[r][j];
         st_coherent(mine + B * B + j, s);
     }
-    tree_reduce<kFan>(red, EH, rt, gridDim.x, tree_cnt, st->Hs);
-}
-
-template <int MM, int BB>
-static hipError_t gemm_impl(const DevProblem &p, const LaunchCfg &cfg, int phase, hipStream_t s) {
-    using Tr = Traits<MM>;
-    using TA = typename Tr::TA;
-    constexpr int RT = GemmShape<TA, BB>::RT;
-    const int rowtiles = (int)((p.l + RT - 1) / RT);
-    int ksplit = cfg.gemm_ksplit < 1 ? 1 : cfg.gemm_ksplit;
-    const int kblocks = p.lda / 64;
-    if (ksplit > kblocks) ksplit = kblocks;
-    const int kchunk = ((kblocks + ksplit - 1) / ksplit) * 64;
-    ksplit = (p.lda + kchunk - 1) / kchunk;
-    if (rowtiles > p.max_rowtiles || ksplit > p.max_ksplit) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_gemm_vec<MM, BB>), dim3(rowtiles, ksplit), dim3(256), 0, s, (int)p.l, p.lda, kchunk,
-                       ksplit, (const typename Tr::TW *)p.W[MM], (const typename Tr::TT *)p.T, (TA *)p.gpart,
-                       (typename Tr::TU *)p.U, p.c[MM], p.st, p.red_gemm, p.tile_cnt, p.gemm_cnt, phase);
-    return hipGetLastError();
+    tree_reduce<kFan>(red, EH, rt, rowtiles, tree_cnt, st->Hs);
 }
 
 #define SBMDS_DISPATCH_B2(B_, CALL)                      \
@@ -193,12 +187,15 @@ static hipError_t gemm_impl(const DevProblem &p, const LaunchCfg &cfg, int phase
         default: return hipErrorInvalidValue;            \
     }
 
-hipError_t launch_gemm(Mode m, const DevProblem &p, const LaunchCfg &cfg, int phase, hipStream_t s) {
+hipError_t launch_gemm(Mode m, const Batch &bt, int phase, hipStream_t s) {
+    const int grid = bt.total[BK_GEMM][m];
+    if (grid <= 0) return hipErrorInvalidValue;
+    const int *off = bt.off(BK_GEMM, m);
     switch (m) {
-        case MODE_BF16: { constexpr int MM = MODE_BF16; SBMDS_DISPATCH_B2(p.B, return (gemm_impl<MM, BB>(p, cfg, phase, s))); } break;
-        case MODE_FP32: { constexpr int MM = MODE_FP32; SBMDS_DISPATCH_B2(p.B, return (gemm_impl<MM, BB>(p, cfg, phase, s))); } break;
-        case MODE_F64ACC: { constexpr int MM = MODE_F64ACC; SBMDS_DISPATCH_B2(p.B, return (gemm_impl<MM, BB>(p, cfg, phase, s))); } break;
-        case MODE_FP64: { constexpr int MM = MODE_FP64; SBMDS_DISPATCH_B2(p.B, return (gemm_impl<MM, BB>(p, cfg, phase, s))); } break;
+        case MODE_BF16: { constexpr int MM = MODE_BF16; SBMDS_DISPATCH_B2(bt.B, hipLaunchKernelGGL((k_gemm_vec<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase); return hipGetLastError()); } break;
+        case MODE_FP32: { constexpr int MM = MODE_FP32; SBMDS_DISPATCH_B2(bt.B, hipLaunchKernelGGL((k_gemm_vec<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase); return hipGetLastError()); } break;
+        case MODE_F64ACC: { constexpr int MM = MODE_F64ACC; SBMDS_DISPATCH_B2(bt.B, hipLaunchKernelGGL((k_gemm_vec<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase); return hipGetLastError()); } break;
+        case MODE_FP64: { constexpr int MM = MODE_FP64; SBMDS_DISPATCH_B2(bt.B, hipLaunchKernelGGL((k_gemm_vec<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase); return hipGetLastError()); } break;
         default: break;
     }
     return hipErrorInvalidValue;

@@ -69,7 +69,7 @@ struct PhaseRule {
 
 enum SolveFlags { SF_REPAIRED = 1, SF_NONFINITE = 2 };
 
-// Buffers and sizes of one problem on the device.
+// Buffers and sizes of one problem on the device (host-side bookkeeping).
 struct DevProblem {
     int64_t n = 0, l = 0, nnz = 0;
     int lda = 0;          // padded row stride of W (multiple of 64), also rows of T/U
@@ -90,41 +90,73 @@ struct DevProblem {
     unsigned *tile_cnt = nullptr, *gemm_cnt = nullptr, *spmm_cnt = nullptr;
     int max_rowtiles = 0, max_ksplit = 0, max_spmm_blocks = 0;
     SolveState *st = nullptr;
-    // host mirror of xyz / landmark ids for the learned start
-    float *xyz = nullptr;
-    int32_t *lmv = nullptr;
+    const void *X0 = nullptr;    // device copy of a user start block
 };
 
-// Launch parameters chosen per (problem, mode); tunable.
+// Launch geometry of one problem in one mode; tunable.
 struct LaunchCfg {
     int spmm_blocks = 0;   // grid of the row-split SpMM (grid-stride)
-    int spmmt_wpr = 4;     // waves per landmark row in the transposed SpMM (1, 2 or 4)
-    int gemm_rt = 0;       // rows per GEMM tile
-    int gemm_ksplit = 1;   // K splits of the GEMM
-    int gemm_kind = 0;     // 0 vector ALU, 1 MFMA
+    int gemm_rt = 0;       // rows per dense-product tile (fixed by mode and B)
+    int gemm_ksplit = 1;   // K splits of the dense product
+    int gemm_kchunk = 64;  // K range per split (multiple of 64)
+};
+
+// What one launch sees of one problem (device array, one entry per problem).
+struct ProbView {
+    int n, l, nnz, lda;
+    const int32_t *rp, *ci, *rpT, *ciT;
+    const void *val[NUM_MODES];
+    const void *valT[NUM_MODES];
+    const void *W[NUM_MODES];
+    const double *c[NUM_MODES];
+    void *Y0, *Y1, *T, *U, *gpart;
+    double *red_gemm, *red_spmm;
+    unsigned *tile_cnt, *gemm_cnt, *spmm_cnt;
+    SolveState *st;
+    const void *X0;
+    int64_t zoff;          // element offset of this problem's rows in the output Z
+    int spmm_blocks[NUM_MODES];
+    int gemm_rowtiles[NUM_MODES];
+    int gemm_ksplit[NUM_MODES];
+    int gemm_kchunk[NUM_MODES];
+};
+
+// Block-to-problem tables: for each kind of launch and mode, off[p] is the
+// first block of problem p and off[nprob] the grid size.
+enum BlockKind { BK_SPMM = 0, BK_SPMMT = 1, BK_GEMM = 2, BK_ELEM_NB = 3, BK_ELEM_N = 4, NUM_BK = 5 };
+
+// Host handle of a batch: every launch covers all problems of a context.
+struct Batch {
+    int nprob = 0;
+    int B = 0, b = 0, k = 0;
+    int spmmt_wpr = 4;           // waves per landmark row in the transposed SpMM
+    ProbView *views = nullptr;   // device [nprob]
+    int *offs = nullptr;         // device [NUM_BK][NUM_MODES][nprob + 1]
+    int total[NUM_BK][NUM_MODES] = {};
+    const int *off(BlockKind kd, Mode m) const { return offs + ((size_t)kd * NUM_MODES + m) * (nprob + 1); }
 };
 
 // Kernel launchers (defined in the .hip files).  All are asynchronous on
-// `stream` and return the hipError_t of the launch.
-hipError_t launch_spmm_t(Mode m, const DevProblem &p, const LaunchCfg &cfg, int phase, hipStream_t stream);
-hipError_t launch_gemm(Mode m, const DevProblem &p, const LaunchCfg &cfg, int phase, hipStream_t stream);
-hipError_t launch_spmm(Mode m, const DevProblem &p, const LaunchCfg &cfg, int phase, hipStream_t stream);
-hipError_t launch_rr_solve(const DevProblem &p, int init, int max_sweeps, const PhaseRule &rule,
+// `stream`, cover every problem of the batch, and return the hipError_t of
+// the launch.  Kernels of an iteration skip problems whose schedule is not
+// in `phase`.
+hipError_t launch_spmm_t(Mode m, const Batch &bt, int phase, hipStream_t stream);
+hipError_t launch_gemm(Mode m, const Batch &bt, int phase, hipStream_t stream);
+hipError_t launch_spmm(Mode m, const Batch &bt, int phase, hipStream_t stream);
+hipError_t launch_rr_solve(const Batch &bt, int init, int max_sweeps, const PhaseRule &rule,
                            hipStream_t stream);
-hipError_t launch_random_start(Mode m, const DevProblem &p, const LaunchCfg &cfg, uint64_t seed,
-                               hipStream_t stream);
-hipError_t launch_user_start(Mode m, const DevProblem &p, const LaunchCfg &cfg, const void *X0,
-                             hipStream_t stream);
-hipError_t launch_convert_y(Mode from, Mode to, const DevProblem &p, int phase, hipStream_t stream);
-hipError_t launch_embedding(Mode m, const DevProblem &p, int ybuf, void *Z, int z_double,
-                            hipStream_t stream);
+hipError_t launch_random_start(Mode m, const Batch &bt, uint64_t seed, hipStream_t stream);
+hipError_t launch_user_start(Mode m, const Batch &bt, hipStream_t stream);
+hipError_t launch_convert_y(Mode from, Mode to, const Batch &bt, int phase, hipStream_t stream);
+hipError_t launch_embedding(const Batch &bt, void *Z, int z_double, hipStream_t stream);
 hipError_t launch_block_out(Mode m, const DevProblem &p, int ybuf, void *X, int x_double,
                             hipStream_t stream);
 
 hipError_t launch_f32_to_bf16(const float *src, void *dst, int64_t count, hipStream_t stream);
 int gemm_rows_per_tile(Mode m, int B);
+int spmm_rows_per_block(Mode m, int B);
 
-// Algorithmic bytes / flops of one launch of each hot kernel.
+// Algorithmic bytes / flops of one launch of each hot kernel (one problem).
 double spmm_bytes(Mode m, const DevProblem &p);
 double spmm_t_bytes(Mode m, const DevProblem &p);
 double gemm_bytes(Mode m, const DevProblem &p);

@@ -78,14 +78,6 @@ int kernel_width(int block) {
     return -1;
 }
 
-int spmm_rows_per_block(Mode m, int B) {
-    const int ysz = y_elem_bytes(m);
-    int vec = 16 / ysz;
-    if (vec > B) vec = B;
-    const int lpr = B / vec;
-    return 256 / lpr;
-}
-
 struct KStat {
     std::string name;
     int64_t launches = 0;
@@ -107,17 +99,18 @@ struct sbmds_ctx {
     std::vector<DevProblem> probs;
     std::vector<std::vector<LaunchCfg>> cfg;  // [problem][mode]
     std::vector<void *> allocs;
-    std::vector<void *> user_x0;               // device copies of user start blocks
     size_t bytes = 0;
-    Summary *host_sum = nullptr;               // pinned
+    Summary *host_sum = nullptr;               // pinned, one per problem
+    SolveState *st_all = nullptr;              // device, one per problem (contiguous)
+    Batch bt;                                  // launch tables over all problems
     bool timing = false;
     std::vector<KStat> stats;
     std::vector<PendingEv> pending;
     std::vector<hipEvent_t> ev_pool;
-    std::vector<int> last_ybuf;                // Y buffer of the final Ritz basis per problem
-    std::vector<int> last_mode;
-    std::vector<int> cur_ybuf, cur_mode;       // current block (for sbmds_get_block)
-    std::vector<std::vector<int>> expect;      // iterations per phase seen in the last solve
+    std::vector<int> cur_ybuf, cur_mode;       // current block per problem (for sbmds_get_block)
+    std::vector<int> expect;                   // iterations per phase seen in the last solve
+    void *zstage = nullptr;                    // device staging of Z for host outputs
+    size_t zstage_bytes = 0;
 };
 
 namespace {
@@ -271,16 +264,13 @@ LaunchCfg default_cfg(Mode m, const DevProblem &p) {
     int64_t want = (p.n + rpb - 1) / rpb;
     const int cap = 1024;
     c.spmm_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, cap));
-    const double per_row = p.l > 0 ? (double)p.nnz / (double)p.l : 0.0;
-    c.spmmt_wpr = per_row >= 256.0 ? 4 : (per_row >= 64.0 ? 2 : 1);
     c.gemm_rt = gemm_rows_per_tile(m, p.B);
     const int rowtiles = (int)((p.l + c.gemm_rt - 1) / c.gemm_rt);
     int ks = (1024 + rowtiles - 1) / rowtiles;
-    ks = std::max(1, std::min(ks, p.lda / 64));
-    // normalise to what the launcher will use
     const int kblocks = p.lda / 64;
-    const int kchunk = ((kblocks + ks - 1) / ks) * 64;
-    c.gemm_ksplit = (p.lda + kchunk - 1) / kchunk;
+    ks = std::max(1, std::min(ks, kblocks));
+    c.gemm_kchunk = ((kblocks + ks - 1) / ks) * 64;
+    c.gemm_ksplit = (p.lda + c.gemm_kchunk - 1) / c.gemm_kchunk;
     return c;
 }
 
@@ -336,9 +326,11 @@ void collect_timing(sbmds_ctx *ctx) {
     ctx->pending.clear();
 }
 
-int read_summary(sbmds_ctx *ctx, const DevProblem &p) {
-    HIPCHK(hipMemcpyAsync(ctx->host_sum, reinterpret_cast<const char *>(p.st) + offsetof(SolveState, theta),
-                          sizeof(Summary), hipMemcpyDeviceToHost, ctx->stream));
+int read_summaries(sbmds_ctx *ctx) {
+    const int np = (int)ctx->probs.size();
+    HIPCHK(hipMemcpy2DAsync(ctx->host_sum, sizeof(Summary),
+                            reinterpret_cast<const char *>(ctx->st_all) + offsetof(SolveState, theta), sizeof(SolveState),
+                            sizeof(Summary), np, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return SBMDS_OK;
 }
@@ -358,20 +350,24 @@ int sweep_cap(const PhaseRule &r) {
     return env > 0 ? env : 1;
 }
 
-// One iteration of phase `r`, enqueued without synchronising: every kernel
-// checks on the device that the solve is still in this phase.
-int enqueue_iteration(sbmds_ctx *ctx, int pi, const PhaseRule &r) {
-    const DevProblem &p = ctx->probs[pi];
+// One iteration of phase `r` for every problem, enqueued without
+// synchronising: each kernel checks on the device, per problem, that the
+// solve is still in this phase.
+int enqueue_iteration(sbmds_ctx *ctx, const PhaseRule &r) {
     const Mode m = (Mode)r.mode;
-    const LaunchCfg &cfg = ctx->cfg[pi][m];
-    const double b = p.B;
-    OKCHK(timed(ctx, "spmm_t", spmm_t_bytes(m, p), 2.0 * p.nnz * b,
-                [&] { return launch_spmm_t(m, p, cfg, r.phase, ctx->stream); }));
-    OKCHK(timed(ctx, "gemm", gemm_bytes(m, p), 2.0 * (double)p.l * p.l * b,
-                [&] { return launch_gemm(m, p, cfg, r.phase, ctx->stream); }));
-    OKCHK(timed(ctx, "spmm", spmm_bytes(m, p), 2.0 * p.nnz * b,
-                [&] { return launch_spmm(m, p, cfg, r.phase, ctx->stream); }));
-    OKCHK(timed(ctx, "rr_solve", 0.0, 0.0, [&] { return launch_rr_solve(p, 0, sweep_cap(r), r, ctx->stream); }));
+    const Batch &bt = ctx->bt;
+    double b_spmm = 0, b_spmmt = 0, b_gemm = 0, f_sp = 0, f_ge = 0;
+    for (const DevProblem &p : ctx->probs) {
+        b_spmm += spmm_bytes(m, p);
+        b_spmmt += spmm_t_bytes(m, p);
+        b_gemm += gemm_bytes(m, p);
+        f_sp += 2.0 * p.nnz * p.B;
+        f_ge += 2.0 * (double)p.l * p.l * p.B;
+    }
+    OKCHK(timed(ctx, "spmm_t", b_spmmt, f_sp, [&] { return launch_spmm_t(m, bt, r.phase, ctx->stream); }));
+    OKCHK(timed(ctx, "gemm", b_gemm, f_ge, [&] { return launch_gemm(m, bt, r.phase, ctx->stream); }));
+    OKCHK(timed(ctx, "spmm", b_spmm, f_sp, [&] { return launch_spmm(m, bt, r.phase, ctx->stream); }));
+    OKCHK(timed(ctx, "rr_solve", 0.0, 0.0, [&] { return launch_rr_solve(bt, 0, sweep_cap(r), r, ctx->stream); }));
     return SBMDS_OK;
 }
 
@@ -381,12 +377,15 @@ double ms_between(hipEvent_t a, hipEvent_t b) {
     return ms;
 }
 
-int solve_problem(sbmds_ctx *ctx, int pi, sbmds_report *rep) {
-    DevProblem &p = ctx->probs[pi];
+// Solve every problem of the context together: one launch per kernel and
+// iteration covers all meshes; each mesh follows the precision schedule on
+// its own and drops out of the launches once it is certified.
+int solve_all(sbmds_ctx *ctx, sbmds_report *reps) {
     const sbmds_options &o = ctx->opt;
+    const int np = (int)ctx->probs.size();
     const std::vector<PhaseRule> rules = schedule(o);
     const int nph = (int)rules.size();
-    std::vector<int> &expect = ctx->expect[pi];
+    std::vector<int> &expect = ctx->expect;
     if ((int)expect.size() != nph) {
         expect.assign(nph, 3);
         expect[nph - 1] = 1;
@@ -394,80 +393,93 @@ int solve_problem(sbmds_ctx *ctx, int pi, sbmds_report *rep) {
     hipEvent_t e0 = ev_get(ctx), e1 = ev_get(ctx), e2 = ev_get(ctx);
     HIPCHK(hipEventRecord(e0, ctx->stream));
 
-    // start block in buffer 0, then its orthonormalisation
+    // start blocks in buffer 0, then their orthonormalisation
     const Mode m0 = (Mode)rules[0].mode;
     if (o.start == SBMDS_START_USER) {
-        OKCHK(timed(ctx, "start", 0.0, 0.0,
-                    [&] { return launch_user_start(m0, p, ctx->cfg[pi][m0], ctx->user_x0[pi], ctx->stream); }));
+        OKCHK(timed(ctx, "start", 0.0, 0.0, [&] { return launch_user_start(m0, ctx->bt, ctx->stream); }));
     } else {
         // LMDS and learned starts fall back to the random block here
-        OKCHK(timed(ctx, "start", 0.0, 0.0, [&] {
-            return launch_random_start(m0, p, ctx->cfg[pi][m0], o.seed + 0x9E3779B97F4A7C15ull * (uint64_t)pi,
-                                       ctx->stream);
-        }));
+        OKCHK(timed(ctx, "start", 0.0, 0.0, [&] { return launch_random_start(m0, ctx->bt, o.seed, ctx->stream); }));
     }
-    OKCHK(timed(ctx, "rr_init", 0.0, 0.0, [&] { return launch_rr_solve(p, 1, 0, rules[0], ctx->stream); }));
+    OKCHK(timed(ctx, "rr_init", 0.0, 0.0, [&] { return launch_rr_solve(ctx->bt, 1, 0, rules[0], ctx->stream); }));
     HIPCHK(hipEventRecord(e1, ctx->stream));
 
     // Enqueue whole phases without waiting; the device decides when each
-    // phase ends and when the solve is done, and later launches return at
-    // once.  The host looks at the state once per round.
+    // phase ends and when a problem is done, and later launches skip it.
+    // The host looks at the state once per round.
     int launched = 0, from = 0, pending = 0;
-    bool first = true;
-    const Summary &s = *ctx->host_sum;
+    bool first = true, all_done = false;
+    const Summary *S = ctx->host_sum;
     for (;;) {
         for (int ph = from; ph < nph && launched < o.max_iter; ++ph) {
             if (ph > from || pending) {
                 const Mode mf = (Mode)rules[ph - 1].mode, mt = (Mode)rules[ph].mode;
-                OKCHK(timed(ctx, "convert", 0.0, 0.0, [&] { return launch_convert_y(mf, mt, p, ph, ctx->stream); }));
+                OKCHK(timed(ctx, "convert", 0.0, 0.0,
+                            [&] { return launch_convert_y(mf, mt, ctx->bt, ph, ctx->stream); }));
             }
             int n_it = (first || ph > from) ? std::max(1, expect[ph]) : 2;
             n_it = std::min(n_it, o.max_iter - launched);
-            for (int i = 0; i < n_it; ++i) OKCHK(enqueue_iteration(ctx, pi, rules[ph]));
+            for (int i = 0; i < n_it; ++i) OKCHK(enqueue_iteration(ctx, rules[ph]));
             launched += n_it;
         }
-        OKCHK(read_summary(ctx, p));
-        if (s.done || launched >= o.max_iter) break;
-        from = s.phase;
-        pending = s.pending_convert;
+        OKCHK(read_summaries(ctx));
+        all_done = true;
+        from = nph;
+        pending = 0;
+        for (int i = 0; i < np; ++i) {
+            if (S[i].flags & SF_NONFINITE) return fail(SBMDS_EBREAKDOWN, "non-finite values in the block solver");
+            if (!S[i].done) {
+                all_done = false;
+                // the slowest problem sets where the next round starts
+                if (S[i].phase < from || (S[i].phase == from && S[i].pending_convert)) {
+                    from = S[i].phase;
+                    pending = S[i].pending_convert;
+                }
+            }
+        }
+        if (all_done || launched >= o.max_iter || from >= nph) break;
         first = false;
-        if (from >= nph) break;  // cannot happen: the final phase never hands over
     }
-    if (s.flags & SF_NONFINITE) return fail(SBMDS_EBREAKDOWN, "non-finite values in the block solver");
-    const bool done = s.done != 0;
-    if (done)
-        for (int ph = 0; ph < nph; ++ph) expect[ph] = s.iters[ph];
+    if (all_done) {
+        for (int ph = 0; ph < nph; ++ph) {
+            int mx = 0;
+            for (int i = 0; i < np; ++i) mx = std::max(mx, S[i].iters[ph]);
+            expect[ph] = mx;
+        }
+    }
     HIPCHK(hipEventRecord(e2, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    ctx->last_ybuf[pi] = s.zbuf;
-    ctx->last_mode[pi] = s.zmode;
-    ctx->cur_ybuf[pi] = s.ycur;
-    ctx->cur_mode[pi] = s.ymode;
-    if (rep) {
+    for (int i = 0; i < np; ++i) {
+        ctx->cur_ybuf[i] = S[i].ycur;
+        ctx->cur_mode[i] = S[i].ymode;
+        if (!reps) continue;
+        sbmds_report *rep = &reps[i];
+        const DevProblem &p = ctx->probs[i];
         std::memset(rep, 0, sizeof(*rep));
+        const bool done = S[i].done != 0;
         rep->status = done ? SBMDS_OK : SBMDS_ENOCONV;
         for (int ph = 0; ph < nph; ++ph) {
-            const int it = s.iters[ph];
+            const int it = S[i].iters[ph];
             if (rules[ph].mode == MODE_BF16) rep->iters_bf16 += it;
             else if (rules[ph].mode == MODE_FP32) rep->iters_fp32 += it;
             else rep->iters_fp64 += it;
         }
-        rep->nonpositive = s.nonpos;
-        rep->certified = (done && rules[nph - 1].mode != MODE_FP32 && rules[nph - 1].mode != MODE_BF16) ? 1 : 0;
-        rep->jacobi_sweeps = s.sweeps_total;
+        rep->nonpositive = S[i].nonpos;
+        rep->certified = (done && (rules[nph - 1].mode == MODE_F64ACC || rules[nph - 1].mode == MODE_FP64)) ? 1 : 0;
+        rep->jacobi_sweeps = S[i].sweeps_total;
         rep->ms_start = ms_between(e0, e1);
         rep->ms_iter = ms_between(e1, e2);
         rep->ms_total = ms_between(e0, e2);
-        for (int i = 0; i < p.b; ++i) {
-            rep->eig[i] = s.theta[i];
-            rep->err_bound[i] = s.bound[i];
-            rep->resid[i] = std::fabs(s.theta[i]) > 0 ? s.res[i] / std::fabs(s.theta[i]) : s.res[i];
+        for (int j = 0; j < p.b; ++j) {
+            rep->eig[j] = S[i].theta[j];
+            rep->err_bound[j] = S[i].bound[j];
+            rep->resid[j] = std::fabs(S[i].theta[j]) > 0 ? S[i].res[j] / std::fabs(S[i].theta[j]) : S[i].res[j];
         }
     }
     ctx->ev_pool.push_back(e0);
     ctx->ev_pool.push_back(e1);
     ctx->ev_pool.push_back(e2);
-    return done ? SBMDS_OK : SBMDS_ENOCONV;
+    return all_done ? SBMDS_OK : SBMDS_ENOCONV;
 }
 
 template <typename T>
@@ -540,6 +552,99 @@ int upload_problem(sbmds_ctx *ctx, const sbmds_problem &in, DevProblem &p, const
     return SBMDS_OK;
 }
 
+// Launch tables of the context: one view per problem and, per kind of
+// launch and mode, the prefix sums of the blocks each problem takes.
+int build_batch(sbmds_ctx *ctx) {
+    const int np = (int)ctx->probs.size();
+    Batch &bt = ctx->bt;
+    bt.nprob = np;
+    bt.B = ctx->probs[0].B;
+    bt.b = ctx->probs[0].b;
+    bt.k = ctx->probs[0].k;
+    double nnz = 0, l = 0;
+    for (const DevProblem &p : ctx->probs) {
+        nnz += (double)p.nnz;
+        l += (double)p.l;
+    }
+    const double per_row = nnz / l;  // mean entries per landmark column of P
+    bt.spmmt_wpr = per_row >= 256 ? 4 : (per_row >= 64 ? 2 : 1);
+    const int rows_per_blk = 4 / bt.spmmt_wpr;
+
+    std::vector<ProbView> views(np);
+    std::vector<int> offs((size_t)NUM_BK * NUM_MODES * (np + 1), 0);
+    int64_t zoff = 0;
+    for (int i = 0; i < np; ++i) {
+        const DevProblem &p = ctx->probs[i];
+        ProbView &v = views[i];
+        std::memset(&v, 0, sizeof(v));
+        v.n = (int)p.n;
+        v.l = (int)p.l;
+        v.nnz = (int)p.nnz;
+        v.lda = p.lda;
+        v.rp = p.rp;
+        v.ci = p.ci;
+        v.rpT = p.rpT;
+        v.ciT = p.ciT;
+        for (int m = 0; m < NUM_MODES; ++m) {
+            v.val[m] = p.val[m];
+            v.valT[m] = p.valT[m];
+            v.W[m] = p.W[m];
+            v.c[m] = p.c[m];
+            const LaunchCfg &c = ctx->cfg[i][m];
+            v.spmm_blocks[m] = c.spmm_blocks;
+            v.gemm_rowtiles[m] = (int)((p.l + c.gemm_rt - 1) / c.gemm_rt);
+            v.gemm_ksplit[m] = c.gemm_ksplit;
+            v.gemm_kchunk[m] = c.gemm_kchunk;
+        }
+        v.Y0 = p.Y[0];
+        v.Y1 = p.Y[1];
+        v.T = p.T;
+        v.U = p.U;
+        v.gpart = p.gpart;
+        v.red_gemm = p.red_gemm;
+        v.red_spmm = p.red_spmm;
+        v.tile_cnt = p.tile_cnt;
+        v.gemm_cnt = p.gemm_cnt;
+        v.spmm_cnt = p.spmm_cnt;
+        v.st = p.st;
+        v.X0 = p.X0;
+        v.zoff = zoff;
+        zoff += p.n * p.k;
+    }
+    for (int kd = 0; kd < NUM_BK; ++kd) {
+        for (int m = 0; m < NUM_MODES; ++m) {
+            int *o = offs.data() + ((size_t)kd * NUM_MODES + m) * (np + 1);
+            int64_t acc = 0;
+            for (int i = 0; i < np; ++i) {
+                o[i] = (int)acc;
+                const DevProblem &p = ctx->probs[i];
+                const ProbView &v = views[i];
+                int64_t nb = 0;
+                switch (kd) {
+                    case BK_SPMM: nb = v.spmm_blocks[m]; break;
+                    case BK_SPMMT: nb = (p.l + rows_per_blk - 1) / rows_per_blk; break;
+                    case BK_GEMM: nb = (int64_t)v.gemm_rowtiles[m] * v.gemm_ksplit[m]; break;
+                    case BK_ELEM_NB: nb = (p.n * p.B + 255) / 256; break;
+                    default: nb = (p.n + 255) / 256; break;
+                }
+                acc += nb;
+            }
+            if (acc >= ((int64_t)1 << 31)) return fail(SBMDS_EINVAL, "too many blocks for one launch");
+            o[np] = (int)acc;
+            bt.total[kd][m] = (int)acc;
+        }
+    }
+    OKCHK(dalloc(ctx, (void **)&bt.views, sizeof(ProbView) * np));
+    OKCHK(dalloc(ctx, (void **)&bt.offs, sizeof(int) * offs.size()));
+    HIPCHK(hipMemcpyAsync(bt.views, views.data(), sizeof(ProbView) * np, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(bt.offs, offs.data(), sizeof(int) * offs.size(), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));  // host tables go out of scope
+    size_t zmax = 0;
+    for (const DevProblem &p : ctx->probs) zmax += (size_t)p.n * p.k;
+    ctx->zstage_bytes = zmax * (ctx->opt.prec == SBMDS_FP64 ? 8 : 4);
+    return SBMDS_OK;
+}
+
 int device_ok(int *dev) {
     int count = 0;
     hipError_t e = hipGetDeviceCount(&count);
@@ -580,18 +685,17 @@ int create_impl(const sbmds_problem *probs, int nprob, const sbmds_options *opt_
     ctx->timing = (o.flags & SBMDS_FLAG_KERNEL_TIMING) != 0;
     ctx->probs.resize(nprob);
     ctx->cfg.resize(nprob);
-    ctx->user_x0.assign(nprob, nullptr);
-    ctx->last_ybuf.assign(nprob, 0);
-    ctx->last_mode.assign(nprob, schedule(o).back().mode);
     ctx->cur_ybuf.assign(nprob, 0);
     ctx->cur_mode.assign(nprob, schedule(o).back().mode);
-    ctx->expect.assign(nprob, std::vector<int>());
     auto cleanup = [&](int rc) {
         sbmds_destroy(ctx);
         return rc;
     };
-    if (hipHostMalloc((void **)&ctx->host_sum, sizeof(Summary), hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc((void **)&ctx->host_sum, sizeof(Summary) * nprob, hipHostMallocDefault) != hipSuccess)
         return cleanup(fail(SBMDS_ENOMEM, "pinned host allocation failed"));
+    if (int rc = dalloc(ctx, (void **)&ctx->st_all, sizeof(SolveState) * nprob); rc < 0) return cleanup(rc);
+    if (hipMemsetAsync(ctx->st_all, 0, sizeof(SolveState) * nprob, ctx->stream) != hipSuccess)
+        return cleanup(fail(SBMDS_EHIP, "hipMemsetAsync failed"));
 
     const size_t esz = fp64 ? 8 : 4;
     for (int i = 0; i < nprob; ++i) {
@@ -654,16 +758,14 @@ int create_impl(const sbmds_problem *probs, int nprob, const sbmds_options *opt_
         if (!rc) rc = dalloc(ctx, (void **)&p.red_gemm, tree_scratch_elems(p.max_rowtiles, EH, kFan) * 8);
         if (!rc) rc = dalloc(ctx, (void **)&p.red_spmm, tree_scratch_elems(p.max_spmm_blocks, EG, kFan) * 8);
         if (!rc) rc = dalloc(ctx, (void **)&cnt, ncnt * 4);
-        if (!rc) rc = dalloc(ctx, (void **)&p.st, sizeof(SolveState));
         if (rc < 0) return cleanup(rc);
+        p.st = ctx->st_all + i;
         p.tile_cnt = cnt;
         p.spmm_cnt = cnt + p.max_rowtiles;
         p.gemm_cnt = p.spmm_cnt + nspmm_cnt;
-        if (rc < 0) return cleanup(rc);
         if (hipMemsetAsync(p.T, 0, (size_t)p.lda * B * 8, ctx->stream) != hipSuccess ||
             hipMemsetAsync(p.U, 0, (size_t)p.lda * B * 8, ctx->stream) != hipSuccess ||
-            hipMemsetAsync(cnt, 0, ncnt * 4, ctx->stream) != hipSuccess ||
-            hipMemsetAsync(p.st, 0, sizeof(SolveState), ctx->stream) != hipSuccess)
+            hipMemsetAsync(cnt, 0, ncnt * 4, ctx->stream) != hipSuccess)
             return cleanup(fail(SBMDS_EHIP, "hipMemsetAsync failed"));
         if (o.start == SBMDS_START_USER) {
             void *x0 = nullptr;
@@ -673,9 +775,10 @@ int create_impl(const sbmds_problem *probs, int nprob, const sbmds_options *opt_
                                in.mem == SBMDS_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                                ctx->stream) != hipSuccess)
                 return cleanup(fail(SBMDS_EHIP, "copying X0 failed"));
-            ctx->user_x0[i] = x0;
+            p.X0 = x0;
         }
     }
+    if (int rc = build_batch(ctx); rc < 0) return cleanup(rc);
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) return cleanup(fail(SBMDS_EHIP, "create: stream sync failed"));
     *out = ctx;
     return SBMDS_OK;
@@ -715,34 +818,24 @@ int sbmds_embed(sbmds_ctx *ctx, double *eigvals, void *Z, int Z_mem, sbmds_repor
     if (Z && Z_mem != SBMDS_MEM_HOST && Z_mem != SBMDS_MEM_DEVICE) return fail(SBMDS_EINVAL, "Z_mem must be 0 or 1");
     try {
         HIPCHK(hipSetDevice(ctx->device));
-        int worst = SBMDS_OK;
+        const int np = (int)ctx->probs.size();
         const bool zdouble = ctx->opt.prec == SBMDS_FP64;
-        const size_t zsz = zdouble ? 8 : 4;
-        size_t zoff = 0;
-        for (int i = 0; i < (int)ctx->probs.size(); ++i) {
-            int rc = solve_problem(ctx, i, reports ? &reports[i] : nullptr);
-            if (rc < 0) return rc;
-            if (rc > worst) worst = rc;
-            const DevProblem &p = ctx->probs[i];
-            if (eigvals)
-                for (int j = 0; j < p.k; ++j) eigvals[(size_t)i * p.k + j] = ctx->host_sum->theta[j];
-            if (Z) {
-                const size_t bytes = (size_t)p.n * p.k * zsz;
-                char *dst = (char *)Z + zoff;
-                void *dz = dst;
-                if (Z_mem == SBMDS_MEM_HOST) HIPCHK(hipMalloc(&dz, bytes));
-                OKCHK(timed(ctx, "embedding", 0.0, 0.0, [&] {
-                    return launch_embedding((Mode)ctx->last_mode[i], p, ctx->last_ybuf[i], dz, zdouble ? 1 : 0,
-                                            ctx->stream);
-                }));
-                if (Z_mem == SBMDS_MEM_HOST) {
-                    hipError_t ce = hipMemcpyAsync(dst, dz, bytes, hipMemcpyDeviceToHost, ctx->stream);
-                    if (ce == hipSuccess) ce = hipStreamSynchronize(ctx->stream);
-                    (void)hipFree(dz);
-                    if (ce != hipSuccess) return fail(SBMDS_EHIP, std::string("copying Z failed: ") + hipGetErrorString(ce));
-                }
-                zoff += bytes;
+        int worst = solve_all(ctx, reports);
+        if (worst < 0) return worst;
+        if (eigvals)
+            for (int i = 0; i < np; ++i)
+                for (int j = 0; j < ctx->probs[i].k; ++j)
+                    eigvals[(size_t)i * ctx->probs[i].k + j] = ctx->host_sum[i].theta[j];
+        if (Z) {
+            void *dz = Z;
+            if (Z_mem == SBMDS_MEM_HOST) {
+                if (!ctx->zstage) OKCHK(dalloc(ctx, &ctx->zstage, ctx->zstage_bytes));
+                dz = ctx->zstage;
             }
+            OKCHK(timed(ctx, "embedding", 0.0, 0.0,
+                        [&] { return launch_embedding(ctx->bt, dz, zdouble ? 1 : 0, ctx->stream); }));
+            if (Z_mem == SBMDS_MEM_HOST)
+                HIPCHK(hipMemcpyAsync(Z, dz, ctx->zstage_bytes, hipMemcpyDeviceToHost, ctx->stream));
         }
         HIPCHK(hipStreamSynchronize(ctx->stream));
         if (ctx->timing) collect_timing(ctx);

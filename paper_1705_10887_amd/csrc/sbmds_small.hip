@@ -128,10 +128,12 @@ __device__ int jacobi(SmallLds<B> &L, int b, int max_sweeps) {
 }
 
 template <int B>
-__global__ __launch_bounds__(kSolveThreads) void k_rr_solve(SolveState *__restrict__ st, int b, int k,
-                                                            double n, double piv_tol, int init,
-                                                            int max_sweeps, PhaseRule rule) {
+__global__ __launch_bounds__(kSolveThreads) void k_rr_solve(const ProbView *__restrict__ views, int b, int k,
+                                                            double piv_tol, int init, int max_sweeps,
+                                                            PhaseRule rule) {
     __shared__ SmallLds<B> L;
+    SolveState *__restrict__ st = views[blockIdx.x].st;
+    const double n = (double)views[blockIdx.x].n;
     if (!init && (st->done || st->phase != rule.phase)) return;
     constexpr int NT = kSolveThreads;
     constexpr int E = B * (B + 1) / 2;
@@ -315,18 +317,15 @@ __global__ __launch_bounds__(kSolveThreads) void k_rr_solve(SolveState *__restri
     }
 }
 
-hipError_t launch_rr_solve_reg(const DevProblem &p, int init, int max_sweeps, const PhaseRule &rule, hipStream_t s);
+hipError_t launch_rr_solve_reg(const Batch &bt, int init, int max_sweeps, const PhaseRule &rule, hipStream_t s);
 
-hipError_t launch_rr_solve(const DevProblem &p, int init, int max_sweeps, const PhaseRule &rule, hipStream_t s) {
-    if (p.B <= 16) return launch_rr_solve_reg(p, init, max_sweeps, rule, s);
+hipError_t launch_rr_solve(const Batch &bt, int init, int max_sweeps, const PhaseRule &rule, hipStream_t s) {
+    if (bt.B <= 16) return launch_rr_solve_reg(bt, init, max_sweeps, rule, s);
     const double piv_tol = 1e-10;
-    const dim3 blk(kSolveThreads);
-    switch (p.B) {
-        case 4: hipLaunchKernelGGL((k_rr_solve<4>), dim3(1), blk, 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init, max_sweeps, rule); break;
-        case 8: hipLaunchKernelGGL((k_rr_solve<8>), dim3(1), blk, 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init, max_sweeps, rule); break;
-        case 16: hipLaunchKernelGGL((k_rr_solve<16>), dim3(1), blk, 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init, max_sweeps, rule); break;
-        case 32: hipLaunchKernelGGL((k_rr_solve<32>), dim3(1), blk, 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init, max_sweeps, rule); break;
-        case 64: hipLaunchKernelGGL((k_rr_solve<64>), dim3(1), blk, 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init, max_sweeps, rule); break;
+    const dim3 blk(kSolveThreads), grid(bt.nprob);
+    switch (bt.B) {
+        case 32: hipLaunchKernelGGL((k_rr_solve<32>), grid, blk, 0, s, bt.views, bt.b, bt.k, piv_tol, init, max_sweeps, rule); break;
+        case 64: hipLaunchKernelGGL((k_rr_solve<64>), grid, blk, 0, s, bt.views, bt.b, bt.k, piv_tol, init, max_sweeps, rule); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

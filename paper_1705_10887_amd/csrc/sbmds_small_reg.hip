@@ -147,9 +147,11 @@ struct Rounds<B, B> {
 }  // namespace
 
 template <int B>
-__global__ __launch_bounds__(64) void k_rr_solve_reg(SolveState *__restrict__ st, int b, int k, double n,
+__global__ __launch_bounds__(64) void k_rr_solve_reg(const ProbView *__restrict__ views, int b, int k,
                                                      double piv_tol, int init, int max_sweeps,
                                                      PhaseRule rule) {
+    SolveState *__restrict__ st = views[blockIdx.x].st;
+    const double n = (double)views[blockIdx.x].n;
     constexpr int E = B * (B + 1) / 2;
     if (!init && (st->done || st->phase != rule.phase)) return;
     __shared__ double Cold[B][B + 1];
@@ -343,12 +345,13 @@ __global__ __launch_bounds__(64) void k_rr_solve_reg(SolveState *__restrict__ st
     }
 }
 
-hipError_t launch_rr_solve_reg(const DevProblem &p, int init, int max_sweeps, const PhaseRule &rule, hipStream_t s) {
+hipError_t launch_rr_solve_reg(const Batch &bt, int init, int max_sweeps, const PhaseRule &rule, hipStream_t s) {
     const double piv_tol = 1e-10;
-    switch (p.B) {
-        case 4: hipLaunchKernelGGL((k_rr_solve_reg<4>), dim3(1), dim3(64), 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init, max_sweeps, rule); break;
-        case 8: hipLaunchKernelGGL((k_rr_solve_reg<8>), dim3(1), dim3(64), 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init, max_sweeps, rule); break;
-        case 16: hipLaunchKernelGGL((k_rr_solve_reg<16>), dim3(1), dim3(64), 0, s, p.st, p.b, p.k, (double)p.n, piv_tol, init, max_sweeps, rule); break;
+    const dim3 grid(bt.nprob), blk(64);
+    switch (bt.B) {
+        case 4: hipLaunchKernelGGL((k_rr_solve_reg<4>), grid, blk, 0, s, bt.views, bt.b, bt.k, piv_tol, init, max_sweeps, rule); break;
+        case 8: hipLaunchKernelGGL((k_rr_solve_reg<8>), grid, blk, 0, s, bt.views, bt.b, bt.k, piv_tol, init, max_sweeps, rule); break;
+        case 16: hipLaunchKernelGGL((k_rr_solve_reg<16>), grid, blk, 0, s, bt.views, bt.b, bt.k, piv_tol, init, max_sweeps, rule); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

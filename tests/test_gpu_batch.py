@@ -1,0 +1,101 @@
+"""Many meshes in one context: every launch covers all problems (needs a gfx950 GPU).
+
+Each problem of a batch follows its own precision schedule and stops on its
+own certified bound, so each must agree with the float64 oracle exactly as a
+single-problem solve does, and the trajectory of a problem must not depend on
+the other problems it shares launches with.
+"""
+import numpy as np
+import pytest
+
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+# (n, l, row_len_max, seed): ragged sizes, all with 64..256 stored entries per
+# landmark column on average, so batch and single solves pick the same launch
+# shape of the transposed product
+SHAPES = [(5000, 300, 12, 31), (8000, 400, 10, 32), (3001, 150, 8, 33), (6500, 333, 11, 34), (2048, 100, 9, 35)]
+
+
+def problems(dtype=np.float32):
+    return [H.random_problem(n=n, l=l, row_len_max=r, seed=s, dtype=dtype, empty_rows=0.05, long_rows=2)
+            for n, l, r, s in SHAPES]
+
+
+def solve(sb, probs, prec, k=3, block=16, **kw):
+    ps = [sb.Problem.from_arrays(p["rowptr"], p["col"], p["val"], p["W"]) for p in probs]
+    with sb.Context(ps, k=k, block=block, prec=prec, **kw) as ctx:
+        Z, eig, reps, rc = ctx.embed()
+        blocks = [ctx.get_block(i) for i in range(len(probs))]
+    return Z, eig, reps, rc, blocks
+
+
+def split_rows(Z, probs):
+    out, r = [], 0
+    for p in probs:
+        out.append(Z[r:r + p["n"]])
+        r += p["n"]
+    return out
+
+
+@pytest.mark.parametrize("prec,tol", [("FP32", 1e-6), ("BF16_FP32", 1e-6), ("FP64", 1e-10)])
+def test_batch_each_problem_matches_oracle(gpu, prec, tol):
+    sb = gpu
+    dtype = np.float64 if prec == "FP64" else np.float32
+    probs = problems(dtype)
+    Z, eig, reps, rc, _ = solve(sb, probs, getattr(sb, prec), tol=tol)
+    assert rc == 0
+    for i, (p, Zi) in enumerate(zip(probs, split_rows(Z, probs))):
+        lam, V, _ = H.oracle_for(p, 3)
+        err = H.rel_eig_err(eig[i], lam[:3])
+        ang = H.subspace_angle(Zi, V, lam, 3, tol=tol)
+        print(f"problem {i} n={p['n']} l={p['l']} err={err:.2e} angle={ang:.2e} "
+              f"iters={reps[i]['iters_bf16']},{reps[i]['iters_fp32']},{reps[i]['iters_fp64']}", flush=True)
+        assert reps[i]["status"] == 0 and reps[i]["certified"], (i, reps[i])
+        assert err <= tol, (i, eig[i], lam[:3])
+        assert ang <= 3.0, i
+        assert max(reps[i]["err_bound"][:3]) <= tol
+
+
+def test_batch_problem_independent_of_companions(gpu):
+    # problem 0 draws the same start block alone or in a batch, and the
+    # kernels take the same per-problem launch shape, so its solve is the same
+    # to the bit
+    sb = gpu
+    probs = problems()
+    Zb, eb, rb, _, Xb = solve(sb, probs, sb.FP32)
+    Zs, es, rs, _, Xs = solve(sb, probs[:1], sb.FP32)
+    np.testing.assert_array_equal(eb[0], es[0])
+    np.testing.assert_array_equal(split_rows(Zb, probs)[0], Zs)
+    np.testing.assert_array_equal(Xb[0], Xs[0])
+    assert (rb[0]["iters_fp32"], rb[0]["iters_fp64"]) == (rs[0]["iters_fp32"], rs[0]["iters_fp64"])
+
+
+def test_batch_resume_one_problem(gpu):
+    # the block of problem 2 of a batch resumes a single-problem solve
+    sb = gpu
+    probs = problems()
+    _, eb, rb, _, Xb = solve(sb, probs, sb.FP32)
+    p = probs[2]
+    prob = sb.Problem.from_arrays(p["rowptr"], p["col"], p["val"], p["W"], X0=Xb[2])
+    with sb.Context([prob], k=3, block=16, prec=sb.FP32, start=sb.START_USER) as ctx:
+        _, e2, r2, rc = ctx.embed()
+    assert rc == 0
+    assert r2[0]["iters_fp32"] + r2[0]["iters_fp64"] <= rb[2]["iters_fp32"] + rb[2]["iters_fp64"]
+    np.testing.assert_allclose(e2[0], eb[2], rtol=1e-7)
+
+
+def test_batch_device_output(gpu):
+    import torch
+    sb = gpu
+    probs = problems()
+    Zh, eh, _, _, _ = solve(sb, probs, sb.FP32)
+    ps = [sb.Problem.from_arrays(p["rowptr"], p["col"], p["val"], p["W"]) for p in probs]
+    Zd = torch.full((sum(p["n"] for p in probs), 3), float("nan"), dtype=torch.float32, device="cuda")
+    with sb.Context(ps, k=3, block=16, prec=sb.FP32) as ctx:
+        _, ed, _, rc = ctx.embed(Z_out=Zd)
+    torch.cuda.synchronize()
+    assert rc == 0
+    np.testing.assert_array_equal(ed, eh)
+    np.testing.assert_array_equal(Zd.cpu().numpy(), Zh)

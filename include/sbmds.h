@@ -157,6 +157,8 @@ typedef struct {
  *   resid[i]    ||B x_i - eig[i] x_i|| / |eig[i]|.
  *   nonpositive number of the k eigenvalues <= 0 (their coordinates are 0).
  *   jacobi_sweeps total Jacobi sweeps spent in the Rayleigh-Ritz steps.
+ *   start_iters iterations spent building the start block (the landmark
+ *               problem's iterations for SBMDS_START_LMDS, else 0).
  *   ms_*        wall time of the start block, of the iterations, and of the
  *               whole call, measured with HIP events on the context's stream.
  */
@@ -166,7 +168,7 @@ typedef struct {
     int nonpositive;
     int certified;
     int jacobi_sweeps;
-    int reserved_;
+    int start_iters;
     double ms_start, ms_iter, ms_total;
     double eig[SBMDS_MAX_BLOCK];
     double err_bound[SBMDS_MAX_BLOCK];

@@ -65,7 +65,7 @@ class _Report(ctypes.Structure):
     _fields_ = [
         ("status", ctypes.c_int), ("iters_bf16", ctypes.c_int), ("iters_fp32", ctypes.c_int),
         ("iters_fp64", ctypes.c_int), ("nonpositive", ctypes.c_int), ("certified", ctypes.c_int),
-        ("jacobi_sweeps", ctypes.c_int), ("reserved_", ctypes.c_int),
+        ("jacobi_sweeps", ctypes.c_int), ("start_iters", ctypes.c_int),
         ("ms_start", ctypes.c_double), ("ms_iter", ctypes.c_double), ("ms_total", ctypes.c_double),
         ("eig", ctypes.c_double * MAX_BLOCK), ("err_bound", ctypes.c_double * MAX_BLOCK),
         ("resid", ctypes.c_double * MAX_BLOCK),
@@ -294,7 +294,7 @@ class Context:
 
 def _report_dict(r, k, block):
     return dict(status=r.status, iters_bf16=r.iters_bf16, iters_fp32=r.iters_fp32, iters_fp64=r.iters_fp64,
-                nonpositive=r.nonpositive, certified=bool(r.certified), jacobi_sweeps=r.jacobi_sweeps,
+                nonpositive=r.nonpositive, certified=bool(r.certified), jacobi_sweeps=r.jacobi_sweeps, start_iters=r.start_iters,
                 ms_start=r.ms_start,
                 ms_iter=r.ms_iter, ms_total=r.ms_total, eig=list(r.eig[:block]),
                 err_bound=list(r.err_bound[:block]), resid=list(r.resid[:block]))

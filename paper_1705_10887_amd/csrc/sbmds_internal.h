@@ -115,6 +115,7 @@ struct ProbView {
     SolveState *st;
     const void *X0;
     int64_t zoff;          // element offset of this problem's rows in the output Z
+    int64_t loff;          // row offset of this problem's landmarks in per-landmark arrays
     int spmm_blocks[NUM_MODES];
     int gemm_rowtiles[NUM_MODES];
     int gemm_ksplit[NUM_MODES];
@@ -123,7 +124,7 @@ struct ProbView {
 
 // Block-to-problem tables: for each kind of launch and mode, off[p] is the
 // first block of problem p and off[nprob] the grid size.
-enum BlockKind { BK_SPMM = 0, BK_SPMMT = 1, BK_GEMM = 2, BK_ELEM_NB = 3, BK_ELEM_N = 4, NUM_BK = 5 };
+enum BlockKind { BK_SPMM = 0, BK_SPMMT = 1, BK_GEMM = 2, BK_ELEM_NB = 3, BK_ELEM_N = 4, BK_ELEM_LB = 5, NUM_BK = 6 };
 
 // Host handle of a batch: every launch covers all problems of a context.
 struct Batch {
@@ -149,6 +150,14 @@ hipError_t launch_random_start(Mode m, const Batch &bt, uint64_t seed, hipStream
 hipError_t launch_user_start(Mode m, const Batch &bt, hipStream_t stream);
 hipError_t launch_convert_y(Mode from, Mode to, const Batch &bt, int phase, hipStream_t stream);
 hipError_t launch_embedding(const Batch &bt, void *Z, int z_double, hipStream_t stream);
+// Landmark-block start: fills U of every problem of `bt` with an l x b block
+// (in the transposed-product type of mode m) and arms the state so that the
+// next SpMM launch of phase 0 writes P U into buffer 0 with its Gram.  The
+// block is the current basis of the matching problem of `lmk` (landmark MDS)
+// when `lmk` is non-NULL, else the first k columns come from `learned`
+// ([sum l] x k floats, rows at ProbView::loff) and the rest are Gaussian.
+hipError_t launch_lift_prep(Mode m, const Batch &bt, const Batch *lmk, const float *learned, uint64_t seed,
+                            hipStream_t stream);
 hipError_t launch_block_out(Mode m, const DevProblem &p, int ybuf, void *X, int x_double,
                             hipStream_t stream);
 

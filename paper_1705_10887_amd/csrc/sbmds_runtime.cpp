@@ -92,25 +92,32 @@ struct PendingEv {
 
 }  // namespace
 
+// A batch of problems solved together: device buffers, launch tables and
+// the host's view of their solver state.
+struct SolveSet {
+    std::vector<DevProblem> probs;
+    std::vector<std::vector<LaunchCfg>> cfg;  // [problem][mode]
+    Batch bt;                                  // launch tables over all problems
+    SolveState *st_all = nullptr;              // device, one per problem (contiguous)
+    Summary *host_sum = nullptr;               // pinned, one per problem
+    std::vector<int> expect;                   // iterations per phase seen in the last solve
+    std::vector<int> cur_ybuf, cur_mode;       // current block per problem
+    size_t zstage_bytes = 0;
+};
+
 struct sbmds_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     sbmds_options opt{};
-    std::vector<DevProblem> probs;
-    std::vector<std::vector<LaunchCfg>> cfg;  // [problem][mode]
     std::vector<void *> allocs;
     size_t bytes = 0;
-    Summary *host_sum = nullptr;               // pinned, one per problem
-    SolveState *st_all = nullptr;              // device, one per problem (contiguous)
-    Batch bt;                                  // launch tables over all problems
+    SolveSet main;                             // the problems of the context
+    SolveSet lmk;                              // their landmark problems (landmark MDS start)
     bool timing = false;
     std::vector<KStat> stats;
     std::vector<PendingEv> pending;
     std::vector<hipEvent_t> ev_pool;
-    std::vector<int> cur_ybuf, cur_mode;       // current block per problem (for sbmds_get_block)
-    std::vector<int> expect;                   // iterations per phase seen in the last solve
     void *zstage = nullptr;                    // device staging of Z for host outputs
-    size_t zstage_bytes = 0;
 };
 
 namespace {
@@ -326,10 +333,10 @@ void collect_timing(sbmds_ctx *ctx) {
     ctx->pending.clear();
 }
 
-int read_summaries(sbmds_ctx *ctx) {
-    const int np = (int)ctx->probs.size();
-    HIPCHK(hipMemcpy2DAsync(ctx->host_sum, sizeof(Summary),
-                            reinterpret_cast<const char *>(ctx->st_all) + offsetof(SolveState, theta), sizeof(SolveState),
+int read_summaries(sbmds_ctx *ctx, SolveSet &set) {
+    const int np = (int)set.probs.size();
+    HIPCHK(hipMemcpy2DAsync(set.host_sum, sizeof(Summary),
+                            reinterpret_cast<const char *>(set.st_all) + offsetof(SolveState, theta), sizeof(SolveState),
                             sizeof(Summary), np, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return SBMDS_OK;
@@ -353,11 +360,11 @@ int sweep_cap(const PhaseRule &r) {
 // One iteration of phase `r` for every problem, enqueued without
 // synchronising: each kernel checks on the device, per problem, that the
 // solve is still in this phase.
-int enqueue_iteration(sbmds_ctx *ctx, const PhaseRule &r) {
+int enqueue_iteration(sbmds_ctx *ctx, SolveSet &set, const PhaseRule &r) {
     const Mode m = (Mode)r.mode;
-    const Batch &bt = ctx->bt;
+    const Batch &bt = set.bt;
     double b_spmm = 0, b_spmmt = 0, b_gemm = 0, f_sp = 0, f_ge = 0;
-    for (const DevProblem &p : ctx->probs) {
+    for (const DevProblem &p : set.probs) {
         b_spmm += spmm_bytes(m, p);
         b_spmmt += spmm_t_bytes(m, p);
         b_gemm += gemm_bytes(m, p);
@@ -377,52 +384,39 @@ double ms_between(hipEvent_t a, hipEvent_t b) {
     return ms;
 }
 
-// Solve every problem of the context together: one launch per kernel and
-// iteration covers all meshes; each mesh follows the precision schedule on
-// its own and drops out of the launches once it is certified.
-int solve_all(sbmds_ctx *ctx, sbmds_report *reps) {
-    const sbmds_options &o = ctx->opt;
-    const int np = (int)ctx->probs.size();
-    const std::vector<PhaseRule> rules = schedule(o);
+// Solve every problem of `set` together: one launch per kernel and
+// iteration covers all of them; each follows the schedule `rules` on its own
+// and drops out of the launches once it is done.  `start` enqueues the start
+// block and its orthonormalisation.  Returns 1 if every problem finished.
+template <typename StartFn>
+int run_set(sbmds_ctx *ctx, SolveSet &set, const std::vector<PhaseRule> &rules, int max_iter, StartFn &&start) {
+    const int np = (int)set.probs.size();
     const int nph = (int)rules.size();
-    std::vector<int> &expect = ctx->expect;
+    std::vector<int> &expect = set.expect;
     if ((int)expect.size() != nph) {
         expect.assign(nph, 3);
         expect[nph - 1] = 1;
     }
-    hipEvent_t e0 = ev_get(ctx), e1 = ev_get(ctx), e2 = ev_get(ctx);
-    HIPCHK(hipEventRecord(e0, ctx->stream));
-
-    // start blocks in buffer 0, then their orthonormalisation
-    const Mode m0 = (Mode)rules[0].mode;
-    if (o.start == SBMDS_START_USER) {
-        OKCHK(timed(ctx, "start", 0.0, 0.0, [&] { return launch_user_start(m0, ctx->bt, ctx->stream); }));
-    } else {
-        // LMDS and learned starts fall back to the random block here
-        OKCHK(timed(ctx, "start", 0.0, 0.0, [&] { return launch_random_start(m0, ctx->bt, o.seed, ctx->stream); }));
-    }
-    OKCHK(timed(ctx, "rr_init", 0.0, 0.0, [&] { return launch_rr_solve(ctx->bt, 1, 0, rules[0], ctx->stream); }));
-    HIPCHK(hipEventRecord(e1, ctx->stream));
-
+    OKCHK(start());
     // Enqueue whole phases without waiting; the device decides when each
     // phase ends and when a problem is done, and later launches skip it.
     // The host looks at the state once per round.
     int launched = 0, from = 0, pending = 0;
     bool first = true, all_done = false;
-    const Summary *S = ctx->host_sum;
+    const Summary *S = set.host_sum;
     for (;;) {
-        for (int ph = from; ph < nph && launched < o.max_iter; ++ph) {
+        for (int ph = from; ph < nph && launched < max_iter; ++ph) {
             if (ph > from || pending) {
                 const Mode mf = (Mode)rules[ph - 1].mode, mt = (Mode)rules[ph].mode;
                 OKCHK(timed(ctx, "convert", 0.0, 0.0,
-                            [&] { return launch_convert_y(mf, mt, ctx->bt, ph, ctx->stream); }));
+                            [&] { return launch_convert_y(mf, mt, set.bt, ph, ctx->stream); }));
             }
             int n_it = (first || ph > from) ? std::max(1, expect[ph]) : 2;
-            n_it = std::min(n_it, o.max_iter - launched);
-            for (int i = 0; i < n_it; ++i) OKCHK(enqueue_iteration(ctx, rules[ph]));
+            n_it = std::min(n_it, max_iter - launched);
+            for (int i = 0; i < n_it; ++i) OKCHK(enqueue_iteration(ctx, set, rules[ph]));
             launched += n_it;
         }
-        OKCHK(read_summaries(ctx));
+        OKCHK(read_summaries(ctx, set));
         all_done = true;
         from = nph;
         pending = 0;
@@ -437,7 +431,7 @@ int solve_all(sbmds_ctx *ctx, sbmds_report *reps) {
                 }
             }
         }
-        if (all_done || launched >= o.max_iter || from >= nph) break;
+        if (all_done || launched >= max_iter || from >= nph) break;
         first = false;
     }
     if (all_done) {
@@ -447,14 +441,75 @@ int solve_all(sbmds_ctx *ctx, sbmds_report *reps) {
             expect[ph] = mx;
         }
     }
+    for (int i = 0; i < np; ++i) {
+        set.cur_ybuf[i] = S[i].ycur;
+        set.cur_mode[i] = S[i].ymode;
+    }
+    return all_done ? 1 : 0;
+}
+
+// The landmark problems are solved to a loose tolerance: their basis only
+// seeds the main iteration.
+constexpr double kLmdsTol = 1e-5;
+constexpr int kLmdsMaxIter = 12;
+
+std::vector<PhaseRule> lmds_rules(const sbmds_options &o) {
+    PhaseRule r{};
+    r.phase = 0;
+    r.is_final = 1;
+    r.cap = kLmdsMaxIter;
+    r.mode = o.prec == SBMDS_FP64 ? MODE_FP64 : MODE_FP32;
+    r.floor_res = 0.0;
+    r.tol = kLmdsTol;
+    return {r};
+}
+
+int solve_all(sbmds_ctx *ctx, sbmds_report *reps) {
+    const sbmds_options &o = ctx->opt;
+    SolveSet &set = ctx->main;
+    const int np = (int)set.probs.size();
+    const std::vector<PhaseRule> rules = schedule(o);
+    const int nph = (int)rules.size();
+    hipEvent_t e0 = ev_get(ctx), e1 = ev_get(ctx), e2 = ev_get(ctx);
+    HIPCHK(hipEventRecord(e0, ctx->stream));
+    const Mode m0 = (Mode)rules[0].mode;
+    auto start = [&]() -> int {
+        if (o.start == SBMDS_START_USER) {
+            OKCHK(timed(ctx, "start", 0.0, 0.0, [&] { return launch_user_start(m0, set.bt, ctx->stream); }));
+        } else if (o.start == SBMDS_START_LMDS) {
+            // landmark MDS: top eigenvectors of -1/2 J W J on the landmarks
+            // (the same iteration with P = I), lifted through P
+            const std::vector<PhaseRule> lr = lmds_rules(o);
+            const int rc = run_set(ctx, ctx->lmk, lr, kLmdsMaxIter, [&]() -> int {
+                const Mode lm = (Mode)lr[0].mode;
+                OKCHK(timed(ctx, "start", 0.0, 0.0,
+                            [&] { return launch_random_start(lm, ctx->lmk.bt, o.seed, ctx->stream); }));
+                OKCHK(timed(ctx, "rr_init", 0.0, 0.0,
+                            [&] { return launch_rr_solve(ctx->lmk.bt, 1, 0, lr[0], ctx->stream); }));
+                return SBMDS_OK;
+            });
+            if (rc < 0) return rc;
+            OKCHK(timed(ctx, "lift", 0.0, 0.0,
+                        [&] { return launch_lift_prep(m0, set.bt, &ctx->lmk.bt, nullptr, o.seed, ctx->stream); }));
+            OKCHK(timed(ctx, "lift", 0.0, 0.0, [&] { return launch_spmm(m0, set.bt, 0, ctx->stream); }));
+        } else {
+            // the learned start falls back to the random block until a
+            // network is loaded
+            OKCHK(timed(ctx, "start", 0.0, 0.0, [&] { return launch_random_start(m0, set.bt, o.seed, ctx->stream); }));
+        }
+        OKCHK(timed(ctx, "rr_init", 0.0, 0.0, [&] { return launch_rr_solve(set.bt, 1, 0, rules[0], ctx->stream); }));
+        HIPCHK(hipEventRecord(e1, ctx->stream));
+        return SBMDS_OK;
+    };
+    const int rc = run_set(ctx, set, rules, o.max_iter, start);
+    if (rc < 0) return rc;
+    const bool all_done = rc == 1;
     HIPCHK(hipEventRecord(e2, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    for (int i = 0; i < np; ++i) {
-        ctx->cur_ybuf[i] = S[i].ycur;
-        ctx->cur_mode[i] = S[i].ymode;
-        if (!reps) continue;
+    const Summary *S = set.host_sum;
+    for (int i = 0; i < np && reps; ++i) {
         sbmds_report *rep = &reps[i];
-        const DevProblem &p = ctx->probs[i];
+        const DevProblem &p = set.probs[i];
         std::memset(rep, 0, sizeof(*rep));
         const bool done = S[i].done != 0;
         rep->status = done ? SBMDS_OK : SBMDS_ENOCONV;
@@ -467,6 +522,7 @@ int solve_all(sbmds_ctx *ctx, sbmds_report *reps) {
         rep->nonpositive = S[i].nonpos;
         rep->certified = (done && (rules[nph - 1].mode == MODE_F64ACC || rules[nph - 1].mode == MODE_FP64)) ? 1 : 0;
         rep->jacobi_sweeps = S[i].sweeps_total;
+        rep->start_iters = o.start == SBMDS_START_LMDS ? ctx->lmk.host_sum[i].total_iters : 0;
         rep->ms_start = ms_between(e0, e1);
         rep->ms_iter = ms_between(e1, e2);
         rep->ms_total = ms_between(e0, e2);
@@ -554,15 +610,15 @@ int upload_problem(sbmds_ctx *ctx, const sbmds_problem &in, DevProblem &p, const
 
 // Launch tables of the context: one view per problem and, per kind of
 // launch and mode, the prefix sums of the blocks each problem takes.
-int build_batch(sbmds_ctx *ctx) {
-    const int np = (int)ctx->probs.size();
-    Batch &bt = ctx->bt;
+int build_batch(sbmds_ctx *ctx, SolveSet &set) {
+    const int np = (int)set.probs.size();
+    Batch &bt = set.bt;
     bt.nprob = np;
-    bt.B = ctx->probs[0].B;
-    bt.b = ctx->probs[0].b;
-    bt.k = ctx->probs[0].k;
+    bt.B = set.probs[0].B;
+    bt.b = set.probs[0].b;
+    bt.k = set.probs[0].k;
     double nnz = 0, l = 0;
-    for (const DevProblem &p : ctx->probs) {
+    for (const DevProblem &p : set.probs) {
         nnz += (double)p.nnz;
         l += (double)p.l;
     }
@@ -572,9 +628,9 @@ int build_batch(sbmds_ctx *ctx) {
 
     std::vector<ProbView> views(np);
     std::vector<int> offs((size_t)NUM_BK * NUM_MODES * (np + 1), 0);
-    int64_t zoff = 0;
+    int64_t zoff = 0, loff = 0;
     for (int i = 0; i < np; ++i) {
-        const DevProblem &p = ctx->probs[i];
+        const DevProblem &p = set.probs[i];
         ProbView &v = views[i];
         std::memset(&v, 0, sizeof(v));
         v.n = (int)p.n;
@@ -590,7 +646,7 @@ int build_batch(sbmds_ctx *ctx) {
             v.valT[m] = p.valT[m];
             v.W[m] = p.W[m];
             v.c[m] = p.c[m];
-            const LaunchCfg &c = ctx->cfg[i][m];
+            const LaunchCfg &c = set.cfg[i][m];
             v.spmm_blocks[m] = c.spmm_blocks;
             v.gemm_rowtiles[m] = (int)((p.l + c.gemm_rt - 1) / c.gemm_rt);
             v.gemm_ksplit[m] = c.gemm_ksplit;
@@ -609,7 +665,9 @@ int build_batch(sbmds_ctx *ctx) {
         v.st = p.st;
         v.X0 = p.X0;
         v.zoff = zoff;
+        v.loff = loff;
         zoff += p.n * p.k;
+        loff += p.l;
     }
     for (int kd = 0; kd < NUM_BK; ++kd) {
         for (int m = 0; m < NUM_MODES; ++m) {
@@ -617,7 +675,7 @@ int build_batch(sbmds_ctx *ctx) {
             int64_t acc = 0;
             for (int i = 0; i < np; ++i) {
                 o[i] = (int)acc;
-                const DevProblem &p = ctx->probs[i];
+                const DevProblem &p = set.probs[i];
                 const ProbView &v = views[i];
                 int64_t nb = 0;
                 switch (kd) {
@@ -625,6 +683,7 @@ int build_batch(sbmds_ctx *ctx) {
                     case BK_SPMMT: nb = (p.l + rows_per_blk - 1) / rows_per_blk; break;
                     case BK_GEMM: nb = (int64_t)v.gemm_rowtiles[m] * v.gemm_ksplit[m]; break;
                     case BK_ELEM_NB: nb = (p.n * p.B + 255) / 256; break;
+                    case BK_ELEM_LB: nb = (p.l * p.B + 255) / 256; break;
                     default: nb = (p.n + 255) / 256; break;
                 }
                 acc += nb;
@@ -640,9 +699,105 @@ int build_batch(sbmds_ctx *ctx) {
     HIPCHK(hipMemcpyAsync(bt.offs, offs.data(), sizeof(int) * offs.size(), hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));  // host tables go out of scope
     size_t zmax = 0;
-    for (const DevProblem &p : ctx->probs) zmax += (size_t)p.n * p.k;
-    ctx->zstage_bytes = zmax * (ctx->opt.prec == SBMDS_FP64 ? 8 : 4);
+    for (const DevProblem &p : set.probs) zmax += (size_t)p.n * p.k;
+    set.zstage_bytes = zmax * (ctx->opt.prec == SBMDS_FP64 ? 8 : 4);
     return SBMDS_OK;
+}
+
+// Pinned summaries and the contiguous solver states of a set.
+int alloc_set(sbmds_ctx *ctx, SolveSet &set, int nprob) {
+    set.probs.resize(nprob);
+    set.cfg.resize(nprob);
+    set.cur_ybuf.assign(nprob, 0);
+    set.cur_mode.assign(nprob, schedule(ctx->opt).back().mode);
+    if (hipHostMalloc((void **)&set.host_sum, sizeof(Summary) * nprob, hipHostMallocDefault) != hipSuccess)
+        return fail(SBMDS_ENOMEM, "pinned host allocation failed");
+    std::memset(set.host_sum, 0, sizeof(Summary) * nprob);
+    OKCHK(dalloc(ctx, (void **)&set.st_all, sizeof(SolveState) * nprob));
+    HIPCHK(hipMemsetAsync(set.st_all, 0, sizeof(SolveState) * nprob, ctx->stream));
+    return SBMDS_OK;
+}
+
+// Launch configurations and the iteration buffers of problem i of a set
+// (its operator is already on the device).
+int alloc_work(sbmds_ctx *ctx, SolveSet &set, int i) {
+    DevProblem &p = set.probs[i];
+    set.cfg[i].resize(NUM_MODES);
+    for (int m = 0; m < NUM_MODES; ++m) {
+        set.cfg[i][m] = default_cfg((Mode)m, p);
+        const int rt = set.cfg[i][m].gemm_rt;
+        p.max_rowtiles = std::max(p.max_rowtiles, (int)((p.l + rt - 1) / rt));
+        p.max_ksplit = std::max(p.max_ksplit, set.cfg[i][m].gemm_ksplit);
+        p.max_spmm_blocks = std::max(p.max_spmm_blocks, set.cfg[i][m].spmm_blocks);
+    }
+    const int B = p.B;
+    const int EG = B * (B + 1) / 2 + B;   // Gram triangle + column sums
+    const int EH = B * B + B;             // H + s
+    const int nspmm_cnt = tree_counter_count(p.max_spmm_blocks, kFan);
+    const int ngemm_cnt = tree_counter_count(p.max_rowtiles, kFan);
+    const size_t ncnt = (size_t)p.max_rowtiles + nspmm_cnt + ngemm_cnt;
+    unsigned *cnt = nullptr;
+    OKCHK(dalloc(ctx, &p.Y[0], (size_t)p.n * B * 8));
+    OKCHK(dalloc(ctx, &p.Y[1], (size_t)p.n * B * 8));
+    OKCHK(dalloc(ctx, &p.T, (size_t)p.lda * B * 8));
+    OKCHK(dalloc(ctx, &p.U, (size_t)p.lda * B * 8));
+    OKCHK(dalloc(ctx, &p.gpart, (size_t)p.max_ksplit * p.lda * B * 8));
+    OKCHK(dalloc(ctx, (void **)&p.red_gemm, tree_scratch_elems(p.max_rowtiles, EH, kFan) * 8));
+    OKCHK(dalloc(ctx, (void **)&p.red_spmm, tree_scratch_elems(p.max_spmm_blocks, EG, kFan) * 8));
+    OKCHK(dalloc(ctx, (void **)&cnt, ncnt * 4));
+    p.st = set.st_all + i;
+    p.tile_cnt = cnt;
+    p.spmm_cnt = cnt + p.max_rowtiles;
+    p.gemm_cnt = p.spmm_cnt + nspmm_cnt;
+    HIPCHK(hipMemsetAsync(p.T, 0, (size_t)p.lda * B * 8, ctx->stream));
+    HIPCHK(hipMemsetAsync(p.U, 0, (size_t)p.lda * B * 8, ctx->stream));
+    HIPCHK(hipMemsetAsync(cnt, 0, ncnt * 4, ctx->stream));
+    return SBMDS_OK;
+}
+
+// The landmark problem of main problem i for the landmark MDS start: P = I
+// (l x l), the same W, so its operator is -1/2 J W J on the landmarks.
+int make_landmark_problem(sbmds_ctx *ctx, int i) {
+    const DevProblem &mp = ctx->main.probs[i];
+    DevProblem &p = ctx->lmk.probs[i];
+    const int64_t l = mp.l;
+    p.n = l;
+    p.l = l;
+    p.nnz = l;
+    p.lda = mp.lda;
+    p.b = mp.b;
+    p.B = mp.B;
+    p.k = mp.k;
+    std::vector<int32_t> iota(l + 1);
+    for (int64_t j = 0; j <= l; ++j) iota[j] = (int32_t)j;
+    const bool fp64 = ctx->opt.prec == SBMDS_FP64;
+    const size_t esz = fp64 ? 8 : 4;
+    std::vector<char> ones(l * esz);
+    for (int64_t j = 0; j < l; ++j) {
+        if (fp64) reinterpret_cast<double *>(ones.data())[j] = 1.0;
+        else reinterpret_cast<float *>(ones.data())[j] = 1.0f;
+    }
+    std::vector<double> c(l, 1.0);
+    void *vals = nullptr, *cd = nullptr;
+    OKCHK(dalloc(ctx, (void **)&p.rp, (l + 1) * 4));
+    OKCHK(dalloc(ctx, (void **)&p.ci, l * 4));
+    OKCHK(dalloc(ctx, &vals, l * esz));
+    OKCHK(dalloc(ctx, &cd, l * 8));
+    HIPCHK(hipMemcpyAsync(p.rp, iota.data(), (l + 1) * 4, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(p.ci, iota.data(), l * 4, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(vals, ones.data(), l * esz, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(cd, c.data(), l * 8, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));  // host vectors go out of scope
+    p.rpT = p.rp;
+    p.ciT = p.ci;
+    for (Mode m : {MODE_FP32, MODE_F64ACC, MODE_FP64}) {
+        if ((m == MODE_FP64) != fp64) continue;
+        p.val[m] = vals;
+        p.valT[m] = vals;
+        p.W[m] = mp.W[m];
+        p.c[m] = (double *)cd;
+    }
+    return alloc_work(ctx, ctx->lmk, i);
 }
 
 int device_ok(int *dev) {
@@ -683,24 +838,16 @@ int create_impl(const sbmds_problem *probs, int nprob, const sbmds_options *opt_
     ctx->opt = o;
     ctx->stream = (hipStream_t)o.stream;
     ctx->timing = (o.flags & SBMDS_FLAG_KERNEL_TIMING) != 0;
-    ctx->probs.resize(nprob);
-    ctx->cfg.resize(nprob);
-    ctx->cur_ybuf.assign(nprob, 0);
-    ctx->cur_mode.assign(nprob, schedule(o).back().mode);
     auto cleanup = [&](int rc) {
         sbmds_destroy(ctx);
         return rc;
     };
-    if (hipHostMalloc((void **)&ctx->host_sum, sizeof(Summary) * nprob, hipHostMallocDefault) != hipSuccess)
-        return cleanup(fail(SBMDS_ENOMEM, "pinned host allocation failed"));
-    if (int rc = dalloc(ctx, (void **)&ctx->st_all, sizeof(SolveState) * nprob); rc < 0) return cleanup(rc);
-    if (hipMemsetAsync(ctx->st_all, 0, sizeof(SolveState) * nprob, ctx->stream) != hipSuccess)
-        return cleanup(fail(SBMDS_EHIP, "hipMemsetAsync failed"));
+    if (int rc = alloc_set(ctx, ctx->main, nprob); rc < 0) return cleanup(rc);
 
     const size_t esz = fp64 ? 8 : 4;
     for (int i = 0; i < nprob; ++i) {
         const sbmds_problem &in = probs[i];
-        DevProblem &p = ctx->probs[i];
+        DevProblem &p = ctx->main.probs[i];
         p.n = in.n;
         p.l = in.l;
         p.nnz = in.nnz;
@@ -734,39 +881,7 @@ int create_impl(const sbmds_problem *probs, int nprob, const sbmds_options *opt_
                       : upload_problem<float>(ctx, in, p, rp, ci, (const float *)val, false);
         if (rc < 0) return cleanup(rc);
 
-        // launch configurations and scratch sizes
-        ctx->cfg[i].resize(NUM_MODES);
-        for (int m = 0; m < NUM_MODES; ++m) {
-            ctx->cfg[i][m] = default_cfg((Mode)m, p);
-            const int rt = ctx->cfg[i][m].gemm_rt;
-            p.max_rowtiles = std::max(p.max_rowtiles, (int)((p.l + rt - 1) / rt));
-            p.max_ksplit = std::max(p.max_ksplit, ctx->cfg[i][m].gemm_ksplit);
-            p.max_spmm_blocks = std::max(p.max_spmm_blocks, ctx->cfg[i][m].spmm_blocks);
-        }
-        const int B = p.B;
-        const int EG = B * (B + 1) / 2 + B;   // Gram triangle + column sums
-        const int EH = B * B + B;             // H + s
-        const int nspmm_cnt = tree_counter_count(p.max_spmm_blocks, kFan);
-        const int ngemm_cnt = tree_counter_count(p.max_rowtiles, kFan);
-        const size_t ncnt = (size_t)p.max_rowtiles + nspmm_cnt + ngemm_cnt;
-        unsigned *cnt = nullptr;
-        rc = dalloc(ctx, &p.Y[0], (size_t)p.n * B * 8);
-        if (!rc) rc = dalloc(ctx, &p.Y[1], (size_t)p.n * B * 8);
-        if (!rc) rc = dalloc(ctx, &p.T, (size_t)p.lda * B * 8);
-        if (!rc) rc = dalloc(ctx, &p.U, (size_t)p.lda * B * 8);
-        if (!rc) rc = dalloc(ctx, &p.gpart, (size_t)p.max_ksplit * p.lda * B * 8);
-        if (!rc) rc = dalloc(ctx, (void **)&p.red_gemm, tree_scratch_elems(p.max_rowtiles, EH, kFan) * 8);
-        if (!rc) rc = dalloc(ctx, (void **)&p.red_spmm, tree_scratch_elems(p.max_spmm_blocks, EG, kFan) * 8);
-        if (!rc) rc = dalloc(ctx, (void **)&cnt, ncnt * 4);
-        if (rc < 0) return cleanup(rc);
-        p.st = ctx->st_all + i;
-        p.tile_cnt = cnt;
-        p.spmm_cnt = cnt + p.max_rowtiles;
-        p.gemm_cnt = p.spmm_cnt + nspmm_cnt;
-        if (hipMemsetAsync(p.T, 0, (size_t)p.lda * B * 8, ctx->stream) != hipSuccess ||
-            hipMemsetAsync(p.U, 0, (size_t)p.lda * B * 8, ctx->stream) != hipSuccess ||
-            hipMemsetAsync(cnt, 0, ncnt * 4, ctx->stream) != hipSuccess)
-            return cleanup(fail(SBMDS_EHIP, "hipMemsetAsync failed"));
+        if ((rc = alloc_work(ctx, ctx->main, i)) < 0) return cleanup(rc);
         if (o.start == SBMDS_START_USER) {
             void *x0 = nullptr;
             const size_t xb = (size_t)p.n * p.b * esz;
@@ -778,7 +893,13 @@ int create_impl(const sbmds_problem *probs, int nprob, const sbmds_options *opt_
             p.X0 = x0;
         }
     }
-    if (int rc = build_batch(ctx); rc < 0) return cleanup(rc);
+    if (int rc = build_batch(ctx, ctx->main); rc < 0) return cleanup(rc);
+    if (o.start == SBMDS_START_LMDS) {
+        if (int rc = alloc_set(ctx, ctx->lmk, nprob); rc < 0) return cleanup(rc);
+        for (int i = 0; i < nprob; ++i)
+            if (int rc = make_landmark_problem(ctx, i); rc < 0) return cleanup(rc);
+        if (int rc = build_batch(ctx, ctx->lmk); rc < 0) return cleanup(rc);
+    }
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) return cleanup(fail(SBMDS_EHIP, "create: stream sync failed"));
     *out = ctx;
     return SBMDS_OK;
@@ -818,24 +939,25 @@ int sbmds_embed(sbmds_ctx *ctx, double *eigvals, void *Z, int Z_mem, sbmds_repor
     if (Z && Z_mem != SBMDS_MEM_HOST && Z_mem != SBMDS_MEM_DEVICE) return fail(SBMDS_EINVAL, "Z_mem must be 0 or 1");
     try {
         HIPCHK(hipSetDevice(ctx->device));
-        const int np = (int)ctx->probs.size();
+        const SolveSet &set = ctx->main;
+        const int np = (int)set.probs.size();
         const bool zdouble = ctx->opt.prec == SBMDS_FP64;
         int worst = solve_all(ctx, reports);
         if (worst < 0) return worst;
         if (eigvals)
             for (int i = 0; i < np; ++i)
-                for (int j = 0; j < ctx->probs[i].k; ++j)
-                    eigvals[(size_t)i * ctx->probs[i].k + j] = ctx->host_sum[i].theta[j];
+                for (int j = 0; j < set.probs[i].k; ++j)
+                    eigvals[(size_t)i * set.probs[i].k + j] = set.host_sum[i].theta[j];
         if (Z) {
             void *dz = Z;
             if (Z_mem == SBMDS_MEM_HOST) {
-                if (!ctx->zstage) OKCHK(dalloc(ctx, &ctx->zstage, ctx->zstage_bytes));
+                if (!ctx->zstage) OKCHK(dalloc(ctx, &ctx->zstage, set.zstage_bytes));
                 dz = ctx->zstage;
             }
             OKCHK(timed(ctx, "embedding", 0.0, 0.0,
-                        [&] { return launch_embedding(ctx->bt, dz, zdouble ? 1 : 0, ctx->stream); }));
+                        [&] { return launch_embedding(set.bt, dz, zdouble ? 1 : 0, ctx->stream); }));
             if (Z_mem == SBMDS_MEM_HOST)
-                HIPCHK(hipMemcpyAsync(Z, dz, ctx->zstage_bytes, hipMemcpyDeviceToHost, ctx->stream));
+                HIPCHK(hipMemcpyAsync(Z, dz, set.zstage_bytes, hipMemcpyDeviceToHost, ctx->stream));
         }
         HIPCHK(hipStreamSynchronize(ctx->stream));
         if (ctx->timing) collect_timing(ctx);
@@ -848,15 +970,15 @@ int sbmds_embed(sbmds_ctx *ctx, double *eigvals, void *Z, int Z_mem, sbmds_repor
 int sbmds_get_block(sbmds_ctx *ctx, int prob, void *X, int X_mem) {
     g_err.clear();
     if (!ctx || !X) return fail(SBMDS_EINVAL, "ctx and X must be non-NULL");
-    if (prob < 0 || prob >= (int)ctx->probs.size()) return fail(SBMDS_EINVAL, "problem index out of range");
+    if (prob < 0 || prob >= (int)ctx->main.probs.size()) return fail(SBMDS_EINVAL, "problem index out of range");
     if (X_mem != SBMDS_MEM_HOST && X_mem != SBMDS_MEM_DEVICE) return fail(SBMDS_EINVAL, "X_mem must be 0 or 1");
-    const DevProblem &p = ctx->probs[prob];
+    const DevProblem &p = ctx->main.probs[prob];
     const bool xd = ctx->opt.prec == SBMDS_FP64;
     const size_t bytes = (size_t)p.n * p.b * (xd ? 8 : 4);
     void *dx = X;
     HIPCHK(hipSetDevice(ctx->device));
     if (X_mem == SBMDS_MEM_HOST) HIPCHK(hipMalloc(&dx, bytes));
-    hipError_t e = launch_block_out((Mode)ctx->cur_mode[prob], p, ctx->cur_ybuf[prob], dx, xd ? 1 : 0, ctx->stream);
+    hipError_t e = launch_block_out((Mode)ctx->main.cur_mode[prob], p, ctx->main.cur_ybuf[prob], dx, xd ? 1 : 0, ctx->stream);
     if (e == hipSuccess && X_mem == SBMDS_MEM_HOST) e = hipMemcpyAsync(X, dx, bytes, hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (X_mem == SBMDS_MEM_HOST) (void)hipFree(dx);
@@ -891,7 +1013,8 @@ void sbmds_destroy(sbmds_ctx *ctx) {
         (void)hipEventDestroy(pe.b);
     }
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
-    if (ctx->host_sum) (void)hipHostFree(ctx->host_sum);
+    if (ctx->main.host_sum) (void)hipHostFree(ctx->main.host_sum);
+    if (ctx->lmk.host_sum) (void)hipHostFree(ctx->lmk.host_sum);
     delete ctx;
 }
 

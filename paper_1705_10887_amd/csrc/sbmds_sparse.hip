@@ -429,6 +429,53 @@ __global__ __launch_bounds__(256) void k_embedding(const ProbView *__restrict__ 
     }
 }
 
+// Landmark-block start (see launch_lift_prep).  One thread per element of
+// the l x B block U of problem p.
+template <int M, int B, int LMDS>
+__global__ __launch_bounds__(256) void k_lift_prep(const ProbView *__restrict__ views, const int *__restrict__ off,
+                                                   int nprob, int b, int k, const ProbView *__restrict__ lviews,
+                                                   const float *__restrict__ learned, uint64_t seed) {
+    using TU = typename Traits<M>::TU;
+    const int p = find_problem(off, nprob, blockIdx.x);
+    const ProbView &v = views[p];
+    const int64_t idx = (int64_t)(blockIdx.x - off[p]) * 256 + threadIdx.x;
+    if (idx == 0) {
+        SolveState *st = v.st;
+        for (int a = 0; a < B; ++a) st->Hs[B * B + a] = 0.0;  // no outer centering term
+        st->ycur = 1;  // the SpMM writes the other buffer: buffer 0
+        st->phase = 0;
+        st->done = 0;
+    }
+    if (idx >= (int64_t)v.l * B) return;
+    const int64_t j = idx / B;
+    const int a = (int)(idx % B);
+    double u = 0.0;
+    if (a < b) {
+        if (LMDS) {
+            // column a of the landmark problem's current basis J Y C
+            const ProbView &lv = lviews[p];
+            const SolveState *ls = lv.st;
+            const void *Y = ls->ycur ? lv.Y1 : lv.Y0;
+            const int mode = ls->ymode;
+            double x = 0.0, sh = 0.0;
+            for (int c = 0; c < B; ++c) {
+                const double cc = ls->C[c * B + a];
+                x += load_y(Y, j * B + c, mode) * cc;
+                sh += ls->e_x[c] * cc;
+            }
+            u = x - sh / (double)lv.n;
+        } else if (a < k) {
+            u = (double)learned[(v.loff + j) * k + a];
+        } else {
+            // counter (landmark, column, tag, problem): disjoint from the n-space start block
+            uint32_t ctr[4] = {(uint32_t)j, (uint32_t)a, 0x4c69667du, (uint32_t)p};
+            philox4x32_10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32));
+            u = (double)gauss_from(ctr[0], ctr[1]);
+        }
+    }
+    ((TU *)v.U)[j * B + a] = (TU)u;
+}
+
 // X = J Y C (the current orthonormal basis), first b columns, one problem.
 template <int M, int B, typename TX>
 __global__ __launch_bounds__(256) void k_block_out(int n, int b, const typename Traits<M>::TY *__restrict__ Y,
@@ -590,6 +637,28 @@ hipError_t launch_embedding(const Batch &bt, void *Z, int z_double, hipStream_t 
                                (float *)Z);
         return hipGetLastError();
     });
+    return hipErrorInvalidValue;
+}
+
+template <int MM, int BB>
+static hipError_t lift_impl(const Batch &bt, const Batch *lmk, const float *learned, uint64_t seed, hipStream_t s) {
+    const int grid = bt.total[BK_ELEM_LB][0];
+    if (grid <= 0) return hipErrorInvalidValue;
+    const int *off = bt.off(BK_ELEM_LB, MODE_BF16);
+    if (lmk)
+        hipLaunchKernelGGL((k_lift_prep<MM, BB, 1>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, bt.b, bt.k,
+                           (const ProbView *)lmk->views, (const float *)nullptr, seed);
+    else
+        hipLaunchKernelGGL((k_lift_prep<MM, BB, 0>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, bt.b, bt.k,
+                           (const ProbView *)nullptr, learned, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_lift_prep(Mode m, const Batch &bt, const Batch *lmk, const float *learned, uint64_t seed,
+                            hipStream_t s) {
+    if (lmk && (lmk->nprob != bt.nprob || lmk->B != bt.B)) return hipErrorInvalidValue;
+    if (!lmk && !learned) return hipErrorInvalidValue;
+    SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(bt.B, return (lift_impl<MM, BB>(bt, lmk, learned, seed, s))));
     return hipErrorInvalidValue;
 }
 

@@ -11,6 +11,8 @@ Modules:
   mds       textbook classical MDS, strain, approximation error
   refchain  brute-force dense reference of the input chain for tiny meshes
             (cotangent operator, biharmonic P, thresholding, geodesics, FPS)
+  mlp       landmark features, the warm-start network, its alignment loss,
+            gradients and the Adam update
 """
-from . import eig, mds, refchain  # noqa: F401
+from . import eig, mds, mlp, refchain  # noqa: F401
 from .eig import top_k, embed, b_matrix  # noqa: F401

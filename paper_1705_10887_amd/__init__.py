@@ -85,6 +85,10 @@ EXPORTS = [
     "sbmds_default_options", "sbmds_create", "sbmds_embed", "sbmds_get_block",
     "sbmds_kernel_stats", "sbmds_reset_kernel_stats", "sbmds_destroy",
     "sbmds_last_error", "sbmds_version",
+    # learned warm start (include/sbmds_mlp.h)
+    "sbmds_mlp_create", "sbmds_mlp_load", "sbmds_mlp_save", "sbmds_mlp_num_params", "sbmds_mlp_get_params",
+    "sbmds_mlp_set_params", "sbmds_mlp_set_norm", "sbmds_mlp_features", "sbmds_mlp_forward",
+    "sbmds_mlp_loss_grad", "sbmds_mlp_adam_step", "sbmds_mlp_destroy",
 ]
 
 
@@ -117,6 +121,24 @@ def lib():
     L.sbmds_last_error.restype = ctypes.c_char_p
     L.sbmds_version.argtypes = []
     L.sbmds_version.restype = ctypes.c_int
+    vp, i64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    for name, args, res in [
+        ("sbmds_mlp_create", [ci, ctypes.c_uint64, vp, ctypes.POINTER(vp)], ci),
+        ("sbmds_mlp_load", [ctypes.c_char_p, vp, ctypes.POINTER(vp)], ci),
+        ("sbmds_mlp_save", [vp, ctypes.c_char_p], ci),
+        ("sbmds_mlp_num_params", [vp], i64),
+        ("sbmds_mlp_get_params", [vp, vp], ci),
+        ("sbmds_mlp_set_params", [vp, vp], ci),
+        ("sbmds_mlp_set_norm", [vp, vp, vp], ci),
+        ("sbmds_mlp_features", [vp, i64, vp, vp, i64, ci, vp, ci, vp], ci),
+        ("sbmds_mlp_forward", [vp, vp, i64, vp, ci], ci),
+        ("sbmds_mlp_loss_grad", [vp, vp, vp, vp, ci, vp, vp, ci], ci),
+        ("sbmds_mlp_adam_step", [vp, ctypes.c_float], ci),
+        ("sbmds_mlp_destroy", [vp], None),
+    ]:
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
     _lib = L
     return L
 

@@ -12,7 +12,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsbmds.so")
-SOURCES = ["sbmds_runtime.cpp", "sbmds_sparse.hip", "sbmds_dense.hip", "sbmds_small.hip", "sbmds_small_reg.hip"]
+SOURCES = ["sbmds_runtime.cpp", "sbmds_sparse.hip", "sbmds_dense.hip", "sbmds_small.hip", "sbmds_small_reg.hip",
+           "sbmds_mlp.hip", "sbmds_mlp_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

@@ -26,8 +26,10 @@
 #include <vector>
 
 #include "../../include/sbmds.h"
+#include "../../include/sbmds_mlp.h"
 #include "sbmds_common.h"
 #include "sbmds_internal.h"
+#include "sbmds_mlp_internal.h"
 
 using namespace sbmds;
 
@@ -39,6 +41,15 @@ int fail(int code, const std::string &msg) {
     g_err = msg;
     return code;
 }
+
+}  // namespace
+
+namespace sbmds {
+int api_fail(int code, const std::string &msg) { return fail(code, msg); }
+void api_clear_error() { g_err.clear(); }
+}  // namespace sbmds
+
+namespace {
 
 struct Summary {  // tail of SolveState read back after each iteration
     double theta[kMaxB];
@@ -113,6 +124,14 @@ struct sbmds_ctx {
     size_t bytes = 0;
     SolveSet main;                             // the problems of the context
     SolveSet lmk;                              // their landmark problems (landmark MDS start)
+    // learned start: network, per-problem vertex positions and landmark
+    // ids, and per-landmark features / predictions (rows at ProbView::loff)
+    sbmds_mlp *net = nullptr;
+    std::vector<float *> xyz;
+    std::vector<int32_t *> lmv;
+    float *feat = nullptr, *learned = nullptr;
+    double *rowmax = nullptr;
+    int64_t total_l = 0;
     bool timing = false;
     std::vector<KStat> stats;
     std::vector<PendingEv> pending;
@@ -492,9 +511,24 @@ int solve_all(sbmds_ctx *ctx, sbmds_report *reps) {
             OKCHK(timed(ctx, "lift", 0.0, 0.0,
                         [&] { return launch_lift_prep(m0, set.bt, &ctx->lmk.bt, nullptr, o.seed, ctx->stream); }));
             OKCHK(timed(ctx, "lift", 0.0, 0.0, [&] { return launch_spmm(m0, set.bt, 0, ctx->stream); }));
+        } else if (o.start == SBMDS_START_LEARNED) {
+            // network prediction on the landmarks (first k columns, the rest
+            // Gaussian), lifted through P
+            int64_t loff = 0;
+            for (int i = 0; i < np; ++i) {
+                const DevProblem &p = set.probs[i];
+                const Mode wm = o.prec == SBMDS_FP64 ? MODE_FP64 : MODE_FP32;
+                OKCHK(timed(ctx, "features", 0.0, 0.0, [&] {
+                    return mlp::launch_features(p.W[wm], wm == MODE_FP64 ? 1 : 0, p.l, p.lda, ctx->xyz[i],
+                                                ctx->lmv[i], ctx->feat + loff * mlp::kIn, ctx->rowmax, ctx->stream);
+                }));
+                loff += p.l;
+            }
+            OKCHK(mlp::forward_device(ctx->net, ctx->feat, ctx->total_l, ctx->learned));
+            OKCHK(timed(ctx, "lift", 0.0, 0.0,
+                        [&] { return launch_lift_prep(m0, set.bt, nullptr, ctx->learned, o.seed, ctx->stream); }));
+            OKCHK(timed(ctx, "lift", 0.0, 0.0, [&] { return launch_spmm(m0, set.bt, 0, ctx->stream); }));
         } else {
-            // the learned start falls back to the random block until a
-            // network is loaded
             OKCHK(timed(ctx, "start", 0.0, 0.0, [&] { return launch_random_start(m0, set.bt, o.seed, ctx->stream); }));
         }
         OKCHK(timed(ctx, "rr_init", 0.0, 0.0, [&] { return launch_rr_solve(set.bt, 1, 0, rules[0], ctx->stream); }));
@@ -800,6 +834,41 @@ int make_landmark_problem(sbmds_ctx *ctx, int i) {
     return alloc_work(ctx, ctx->lmk, i);
 }
 
+// Learned start: load the network and keep device copies of the vertex
+// positions and landmark ids of every problem.
+int setup_learned(sbmds_ctx *ctx, const sbmds_problem *probs, int nprob) {
+    OKCHK(sbmds_mlp_load(ctx->opt.mlp_weights, ctx->stream, &ctx->net));
+    if (mlp::out_width(ctx->net) != ctx->opt.k)
+        return fail(SBMDS_EINVAL, "the network predicts " + std::to_string(mlp::out_width(ctx->net)) +
+                                      " coordinates but k = " + std::to_string(ctx->opt.k));
+    ctx->xyz.assign(nprob, nullptr);
+    ctx->lmv.assign(nprob, nullptr);
+    int64_t maxl = 0;
+    ctx->total_l = 0;
+    for (int i = 0; i < nprob; ++i) {
+        const sbmds_problem &in = probs[i];
+        const hipMemcpyKind kind = in.mem == SBMDS_MEM_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+        std::vector<int32_t> hl(in.l);
+        HIPCHK(hipMemcpy(hl.data(), in.landmark_vertex, in.l * 4, kind));
+        for (int64_t j = 0; j < in.l; ++j)
+            if (hl[j] < 0 || hl[j] >= in.n)
+                return fail(SBMDS_EINVAL, "problem " + std::to_string(i) + ": landmark_vertex out of range");
+        OKCHK(dalloc(ctx, (void **)&ctx->xyz[i], (size_t)in.n * 12));
+        OKCHK(dalloc(ctx, (void **)&ctx->lmv[i], (size_t)in.l * 4));
+        HIPCHK(hipMemcpyAsync(ctx->xyz[i], in.xyz, (size_t)in.n * 12,
+                              in.mem == SBMDS_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                              ctx->stream));
+        HIPCHK(hipMemcpyAsync(ctx->lmv[i], hl.data(), (size_t)in.l * 4, hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));  // hl goes out of scope
+        maxl = std::max<int64_t>(maxl, in.l);
+        ctx->total_l += in.l;
+    }
+    OKCHK(dalloc(ctx, (void **)&ctx->feat, (size_t)ctx->total_l * mlp::kIn * 4));
+    OKCHK(dalloc(ctx, (void **)&ctx->learned, (size_t)ctx->total_l * ctx->opt.k * 4));
+    OKCHK(dalloc(ctx, (void **)&ctx->rowmax, (size_t)maxl * 8));
+    return SBMDS_OK;
+}
+
 int device_ok(int *dev) {
     int count = 0;
     hipError_t e = hipGetDeviceCount(&count);
@@ -894,6 +963,8 @@ int create_impl(const sbmds_problem *probs, int nprob, const sbmds_options *opt_
         }
     }
     if (int rc = build_batch(ctx, ctx->main); rc < 0) return cleanup(rc);
+    if (o.start == SBMDS_START_LEARNED)
+        if (int rc = setup_learned(ctx, probs, nprob); rc < 0) return cleanup(rc);
     if (o.start == SBMDS_START_LMDS) {
         if (int rc = alloc_set(ctx, ctx->lmk, nprob); rc < 0) return cleanup(rc);
         for (int i = 0; i < nprob; ++i)
@@ -1013,6 +1084,7 @@ void sbmds_destroy(sbmds_ctx *ctx) {
         (void)hipEventDestroy(pe.b);
     }
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    if (ctx->net) sbmds_mlp_destroy(ctx->net);
     if (ctx->main.host_sum) (void)hipHostFree(ctx->main.host_sum);
     if (ctx->lmk.host_sum) (void)hipHostFree(ctx->lmk.host_sum);
     delete ctx;

@@ -9,19 +9,23 @@ import pytest
 import paper_1705_10887_amd as sb
 from tests.conftest import ROOT, gpu_available
 
-HEADER = os.path.join(ROOT, "include", "sbmds.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(sbmds_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(sbmds_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
     L = sb.lib()
     names = declared_functions()
     assert "sbmds_create" in names and "sbmds_embed" in names and "sbmds_destroy" in names
+    assert "sbmds_mlp_loss_grad" in names and "sbmds_mlp_adam_step" in names
     for name in names:
         assert hasattr(L, name), name
     assert sorted(sb.EXPORTS) == names

@@ -22,7 +22,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/sbmds.h"
@@ -114,11 +116,14 @@ struct SolveSet {
     std::vector<int> expect;                   // iterations per phase seen in the last solve
     std::vector<int> cur_ybuf, cur_mode;       // current block per problem
     size_t zstage_bytes = 0;
+    // captured rounds of iterations, keyed by their launch sequence
+    std::map<std::string, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
 };
 
 struct sbmds_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    hipStream_t own_stream = nullptr;          // created when the options give no stream
     sbmds_options opt{};
     std::vector<void *> allocs;
     size_t bytes = 0;
@@ -403,6 +408,53 @@ double ms_between(hipEvent_t a, hipEvent_t b) {
     return ms;
 }
 
+// Enqueue one round of launches (phase conversions and iterations).  Unless
+// kernel timing is on or graphs are disabled, the round is captured once
+// into a hipGraph and replayed on later calls with the same sequence; the
+// kernels read every per-call value (phase, block buffer, state) from the
+// device, so a replay is the same work as the eager launches.
+int enqueue_round(sbmds_ctx *ctx, SolveSet &set, const std::vector<PhaseRule> &rules,
+                  const std::vector<std::pair<int, int>> &ops) {
+    auto run_ops = [&]() -> int {
+        for (const auto &op : ops) {
+            const int ph = op.second;
+            if (op.first) {
+                const Mode mf = (Mode)rules[ph - 1].mode, mt = (Mode)rules[ph].mode;
+                OKCHK(timed(ctx, "convert", 0.0, 0.0,
+                            [&] { return launch_convert_y(mf, mt, set.bt, ph, ctx->stream); }));
+            } else {
+                OKCHK(enqueue_iteration(ctx, set, rules[ph]));
+            }
+        }
+        return SBMDS_OK;
+    };
+    const bool use_graph = !ctx->timing && !(ctx->opt.flags & SBMDS_FLAG_NO_GRAPH) && ctx->stream != nullptr;
+    if (!use_graph || ops.empty()) return run_ops();
+    std::string key;
+    for (const auto &op : ops) key += (op.first ? 'c' : 'i') + std::to_string(op.second) + ",";
+    auto it = set.graphs.find(key);
+    if (it == set.graphs.end()) {
+        HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        const int rc = run_ops();
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+        if (rc < 0) {
+            if (e == hipSuccess && g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(SBMDS_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return fail(SBMDS_EHIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+        }
+        it = set.graphs.emplace(key, std::make_pair(g, ex)).first;
+    }
+    HIPCHK(hipGraphLaunch(it->second.second, ctx->stream));
+    return SBMDS_OK;
+}
+
 // Solve every problem of `set` together: one launch per kernel and
 // iteration covers all of them; each follows the schedule `rules` on its own
 // and drops out of the launches once it is done.  `start` enqueues the start
@@ -424,17 +476,15 @@ int run_set(sbmds_ctx *ctx, SolveSet &set, const std::vector<PhaseRule> &rules, 
     bool first = true, all_done = false;
     const Summary *S = set.host_sum;
     for (;;) {
+        std::vector<std::pair<int, int>> ops;  // (is_convert, phase)
         for (int ph = from; ph < nph && launched < max_iter; ++ph) {
-            if (ph > from || pending) {
-                const Mode mf = (Mode)rules[ph - 1].mode, mt = (Mode)rules[ph].mode;
-                OKCHK(timed(ctx, "convert", 0.0, 0.0,
-                            [&] { return launch_convert_y(mf, mt, set.bt, ph, ctx->stream); }));
-            }
+            if (ph > from || pending) ops.push_back({1, ph});
             int n_it = (first || ph > from) ? std::max(1, expect[ph]) : 2;
             n_it = std::min(n_it, max_iter - launched);
-            for (int i = 0; i < n_it; ++i) OKCHK(enqueue_iteration(ctx, set, rules[ph]));
+            for (int i = 0; i < n_it; ++i) ops.push_back({0, ph});
             launched += n_it;
         }
+        OKCHK(enqueue_round(ctx, set, rules, ops));
         OKCHK(read_summaries(ctx, set));
         all_done = true;
         from = nph;
@@ -906,6 +956,15 @@ int create_impl(const sbmds_problem *probs, int nprob, const sbmds_options *opt_
     ctx->device = dev;
     ctx->opt = o;
     ctx->stream = (hipStream_t)o.stream;
+    if (!ctx->stream) {
+        // a stream of our own (it synchronises with the null stream), so
+        // that rounds of iterations can be captured as graphs
+        if (hipStreamCreate(&ctx->own_stream) != hipSuccess) {
+            delete ctx;
+            return fail(SBMDS_EHIP, "hipStreamCreate failed");
+        }
+        ctx->stream = ctx->own_stream;
+    }
     ctx->timing = (o.flags & SBMDS_FLAG_KERNEL_TIMING) != 0;
     auto cleanup = [&](int rc) {
         sbmds_destroy(ctx);
@@ -1078,14 +1137,20 @@ void sbmds_reset_kernel_stats(sbmds_ctx *ctx) {
 void sbmds_destroy(sbmds_ctx *ctx) {
     if (!ctx) return;
     if (ctx->stream || !ctx->allocs.empty()) (void)hipStreamSynchronize(ctx->stream);
+    for (SolveSet *set : {&ctx->main, &ctx->lmk})
+        for (auto &g : set->graphs) {
+            (void)hipGraphExecDestroy(g.second.second);
+            (void)hipGraphDestroy(g.second.first);
+        }
+    if (ctx->net) sbmds_mlp_destroy(ctx->net);
     for (void *p : ctx->allocs) (void)hipFree(p);
     for (auto &pe : ctx->pending) {
         (void)hipEventDestroy(pe.a);
         (void)hipEventDestroy(pe.b);
     }
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
-    if (ctx->net) sbmds_mlp_destroy(ctx->net);
     if (ctx->main.host_sum) (void)hipHostFree(ctx->main.host_sum);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
     if (ctx->lmk.host_sum) (void)hipHostFree(ctx->lmk.host_sum);
     delete ctx;
 }

@@ -151,3 +151,21 @@ def test_repeated_calls_same_context(gpu, prec):
             Z, eig, reps, rc = ctx.embed()
             assert rc == 0 and reps[0]["certified"], (call, reps[0])
             assert H.rel_eig_err(eig[0], lam[:3]) <= 1e-6, call
+
+
+def test_graph_replay_matches_eager_launches(gpu):
+    # rounds of iterations replayed from captured graphs do the same work as
+    # eager launches: same results to the bit, on every call of a context
+    sb = gpu
+    prob = H.random_problem(n=15000, l=600, row_len_max=10, seed=23)
+    out = {}
+    for flags in (0, sb.FLAG_NO_GRAPH):
+        p = sb.Problem.from_arrays(prob["rowptr"], prob["col"], prob["val"], prob["W"])
+        with sb.Context([p], k=3, block=16, prec=sb.BF16_FP32, flags=flags) as ctx:
+            out[flags] = [ctx.embed() for _ in range(3)]
+    for call in range(3):
+        Zg, eg, rg, _ = out[0][call]
+        Ze, ee, re_, _ = out[sb.FLAG_NO_GRAPH][call]
+        np.testing.assert_array_equal(eg, ee)
+        np.testing.assert_array_equal(Zg, Ze)
+        assert rg[0]["certified"] and re_[0]["certified"]

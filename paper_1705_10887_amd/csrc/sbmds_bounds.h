@@ -47,53 +47,117 @@ __device__ inline void bounds(SolveState *st, const double *th, const double *re
     st->nonpos = nonpos;
 }
 
-// Schedule bookkeeping after a Rayleigh-Ritz step (one thread).  In `init`
-// mode it resets the control state for a new solve.
-__device__ inline void phase_control(SolveState *st, const PhaseRule &rule, int init) {
+// Control fields of SolveState, held in registers by the thread that
+// updates them (loaded together at kernel start, stored together at the
+// end, so their global-memory latency is paid once).
+struct Ctl {
+    double maxbound, maxres;
+    int iter, flags, dead, nonpos, sweeps;
+    int ycur, zbuf, zmode, phase, done, pending_convert, phase_iters, total_iters;
+    int iters[4];
+    int sweeps_total, ymode;
+    double hist[4];
+};
+
+__device__ inline Ctl load_ctl(const SolveState *st) {
+    Ctl c;
+    c.maxbound = st->maxbound;
+    c.maxres = st->maxres;
+    c.iter = st->iter;
+    c.flags = st->flags;
+    c.dead = st->dead;
+    c.nonpos = st->nonpos;
+    c.sweeps = st->sweeps;
+    c.ycur = st->ycur;
+    c.zbuf = st->zbuf;
+    c.zmode = st->zmode;
+    c.phase = st->phase;
+    c.done = st->done;
+    c.pending_convert = st->pending_convert;
+    c.phase_iters = st->phase_iters;
+    c.total_iters = st->total_iters;
+    for (int i = 0; i < 4; ++i) c.iters[i] = st->iters[i];
+    c.sweeps_total = st->sweeps_total;
+    c.ymode = st->ymode;
+    for (int i = 0; i < 4; ++i) c.hist[i] = st->hist[i];
+    return c;
+}
+
+__device__ inline void store_ctl(SolveState *st, const Ctl &c) {
+    st->maxbound = c.maxbound;
+    st->maxres = c.maxres;
+    st->iter = c.iter;
+    st->flags = c.flags;
+    st->dead = c.dead;
+    st->nonpos = c.nonpos;
+    st->sweeps = c.sweeps;
+    st->ycur = c.ycur;
+    st->zbuf = c.zbuf;
+    st->zmode = c.zmode;
+    st->phase = c.phase;
+    st->done = c.done;
+    st->pending_convert = c.pending_convert;
+    st->phase_iters = c.phase_iters;
+    st->total_iters = c.total_iters;
+    for (int i = 0; i < 4; ++i) st->iters[i] = c.iters[i];
+    st->sweeps_total = c.sweeps_total;
+    st->ymode = c.ymode;
+    for (int i = 0; i < 4; ++i) st->hist[i] = c.hist[i];
+}
+
+// Schedule bookkeeping after a Rayleigh-Ritz step.  In `init` mode it
+// resets the control state for a new solve.
+__device__ inline void phase_control(Ctl &st, const PhaseRule &rule, int init) {
     if (init) {
-        st->ycur = 0;
-        st->zbuf = 0;
-        st->zmode = rule.mode;
-        st->phase = 0;
-        st->done = 0;
-        st->pending_convert = 0;
-        st->phase_iters = 0;
-        st->total_iters = 0;
-        for (int i = 0; i < 4; ++i) st->iters[i] = 0;
-        st->sweeps_total = 0;
-        st->ymode = rule.mode;
-        for (int i = 0; i < 4; ++i) st->hist[i] = INFINITY;
+        st.ycur = 0;
+        st.zbuf = 0;
+        st.zmode = rule.mode;
+        st.phase = 0;
+        st.done = 0;
+        st.pending_convert = 0;
+        st.phase_iters = 0;
+        st.total_iters = 0;
+        for (int i = 0; i < 4; ++i) st.iters[i] = 0;
+        st.sweeps_total = 0;
+        st.ymode = rule.mode;
+        for (int i = 0; i < 4; ++i) st.hist[i] = INFINITY;
         return;
     }
     // the block just produced (Y') becomes current; the basis the Ritz
     // vectors were taken from stays readable until the next SpMM overwrites it
-    st->zbuf = st->ycur;
-    st->zmode = rule.mode;
-    st->ymode = rule.mode;
-    st->ycur ^= 1;
-    st->total_iters += 1;
-    st->iters[rule.phase] += 1;
-    st->sweeps_total += st->sweeps;
-    st->hist[3] = st->hist[2];
-    st->hist[2] = st->hist[1];
-    st->hist[1] = st->hist[0];
-    st->hist[0] = st->maxres;
-    st->phase_iters += 1;
-    if (st->flags & SF_NONFINITE) {
-        st->done = 1;
+    st.zbuf = st.ycur;
+    st.zmode = rule.mode;
+    st.ymode = rule.mode;
+    st.ycur ^= 1;
+    st.total_iters += 1;
+    for (int i = 0; i < 4; ++i) st.iters[i] += (i == rule.phase) ? 1 : 0;
+    st.sweeps_total += st.sweeps;
+    st.hist[3] = st.hist[2];
+    st.hist[2] = st.hist[1];
+    st.hist[1] = st.hist[0];
+    st.hist[0] = st.maxres;
+    st.phase_iters += 1;
+    if (st.flags & SF_NONFINITE) {
+        st.done = 1;
         return;
     }
     if (rule.is_final) {
-        if (st->maxbound <= rule.tol) st->done = 1;
+        if (st.maxbound <= rule.tol) st.done = 1;
         return;
     }
-    const bool plateau = st->phase_iters >= 4 && st->hist[0] > 0.7 * st->hist[2] && st->hist[0] > 0.7 * st->hist[3];
-    if (st->maxres <= rule.floor_res || plateau || st->phase_iters >= rule.cap) {
-        st->phase += 1;
-        st->pending_convert = 1;
-        st->phase_iters = 0;
-        for (int i = 0; i < 4; ++i) st->hist[i] = INFINITY;
+    const bool plateau = st.phase_iters >= 4 && st.hist[0] > 0.7 * st.hist[2] && st.hist[0] > 0.7 * st.hist[3];
+    if (st.maxres <= rule.floor_res || plateau || st.phase_iters >= rule.cap) {
+        st.phase += 1;
+        st.pending_convert = 1;
+        st.phase_iters = 0;
+        for (int i = 0; i < 4; ++i) st.hist[i] = INFINITY;
     }
+}
+
+__device__ inline void phase_control(SolveState *st, const PhaseRule &rule, int init) {
+    Ctl c = load_ctl(st);
+    phase_control(c, rule, init);
+    store_ctl(st, c);
 }
 
 }  // namespace sbmds

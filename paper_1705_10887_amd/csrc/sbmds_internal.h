@@ -164,6 +164,7 @@ hipError_t launch_block_out(Mode m, const DevProblem &p, int ybuf, void *X, int 
 hipError_t launch_f32_to_bf16(const float *src, void *dst, int64_t count, hipStream_t stream);
 int gemm_rows_per_tile(Mode m, int B);
 int spmm_rows_per_block(Mode m, int B);
+int spmm_block_cap(Mode m, int B);  // most blocks worth launching for one problem
 
 // Algorithmic bytes / flops of one launch of each hot kernel (one problem).
 double spmm_bytes(Mode m, const DevProblem &p);

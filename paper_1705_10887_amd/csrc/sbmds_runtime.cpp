@@ -293,7 +293,7 @@ LaunchCfg default_cfg(Mode m, const DevProblem &p) {
     LaunchCfg c;
     const int rpb = spmm_rows_per_block(m, p.B);
     int64_t want = (p.n + rpb - 1) / rpb;
-    const int cap = 1024;
+    const int cap = spmm_block_cap(m, p.B);
     c.spmm_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, cap));
     c.gemm_rt = gemm_rows_per_tile(m, p.B);
     const int rowtiles = (int)((p.l + c.gemm_rt - 1) / c.gemm_rt);

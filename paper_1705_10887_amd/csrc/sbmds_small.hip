@@ -317,10 +317,12 @@ __global__ __launch_bounds__(kSolveThreads) void k_rr_solve(const ProbView *__re
     }
 }
 
-hipError_t launch_rr_solve_reg(const Batch &bt, int init, int max_sweeps, const PhaseRule &rule, hipStream_t s);
+hipError_t launch_rr_solve2(const Batch &bt, int init, int max_sweeps, const PhaseRule &rule, hipStream_t s);
 
+// Widths up to 32 run the element-parallel kernel of sbmds_rr.hip; 64 runs
+// the kernel above.
 hipError_t launch_rr_solve(const Batch &bt, int init, int max_sweeps, const PhaseRule &rule, hipStream_t s) {
-    if (bt.B <= 16) return launch_rr_solve_reg(bt, init, max_sweeps, rule, s);
+    if (bt.B <= 32) return launch_rr_solve2(bt, init, max_sweeps, rule, s);
     const double piv_tol = 1e-10;
     const dim3 blk(kSolveThreads), grid(bt.nprob);
     switch (bt.B) {

@@ -36,8 +36,10 @@ int spmm_rows_per_block(Mode m, int B) {
     int vec = 16 / ysz;
     if (vec > B) vec = B;
     const int lpr = B / vec;
-    return 256 / lpr;
+    return ((B == 16 || B == 32) ? 1024 : 256) / lpr;
 }
+
+int spmm_block_cap(Mode, int B) { return (B == 16 || B == 32) ? 256 : 1024; }
 
 template <int B>
 __device__ __forceinline__ void gram_tile_accumulate(const double (*tile)[B], int rows, int tid,
@@ -208,6 +210,251 @@ __global__ __launch_bounds__(256) void k_gram(const ProbView *__restrict__ views
         __syncthreads();
     }
     gram_publish<B, NQ>(ea, gacc, eacc, v.red_spmm, v.spmm_cnt, v.st, vb, vg);
+}
+
+// ---------------------------------------------------------------------------
+// Wide-block variant for B in {16, 32}: 1024-thread blocks (so the Gram
+// partials of a launch are few and their tree shallow), the CSR entries of
+// a block step staged in LDS with coalesced loads, and the float64 Gram
+// Y'^T Y' accumulated with v_mfma_f64_16x16x4f64 on 16 x 16 tiles of it.
+//
+// MFMA operand layout (16 x 16 x 4, float64): lane l supplies A[l%16][l/16]
+// and B[l/16][l%16] and holds D[l/16 + 4r][l%16] in element r.  With both
+// A^T and B the same 4 x 16 row block of Y', lane l supplies
+// Y'[4 k + l/16][16 t + l%16] for tile column t.
+// ---------------------------------------------------------------------------
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWideThreads = 1024;
+constexpr int kStageCap = 2048;  // CSR entries staged per block step
+
+template <int M, int B>
+struct WideShape {
+    using TY = typename Traits<M>::TY;
+    using TP = typename Traits<M>::TP;
+    static constexpr int VEC = VecOf<TY, B>::v;
+    static constexpr int LPR = B / VEC;
+    static constexpr int RPB = kWideThreads / LPR;  // rows per block step
+    static constexpr int RW = 64 / LPR;             // rows per wave step
+    static constexpr int NTB = B / 16;
+    static constexpr int TILES = NTB * (NTB + 1) / 2;
+    static constexpr int E = B * (B + 1) / 2;
+    static constexpr int EG = E + B;
+    static constexpr int NW = kWideThreads / 64;
+    static constexpr int TILE_D = RPB * B;
+    static constexpr int RED_D = NW * EG;
+    static constexpr int SMEM_D = TILE_D > RED_D ? TILE_D : RED_D;
+};
+
+// Gram and column sums of the wave's RW rows of the tile.
+template <int B, int RW, int TILES>
+__device__ __forceinline__ void gram_mfma_rows(const double *__restrict__ tile, int r0, dbl4 (&acc)[TILES],
+                                               double (&esum)[B / 16]) {
+    constexpr int NTB = B / 16;
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 15, kr = lane >> 4;
+#pragma unroll
+    for (int ks = 0; ks < RW / 4; ++ks) {
+        const double *row = tile + (size_t)(r0 + 4 * ks + kr) * B;
+        double v[NTB];
+#pragma unroll
+        for (int ti = 0; ti < NTB; ++ti) v[ti] = row[16 * ti + col];
+        int t = 0;
+#pragma unroll
+        for (int ti = 0; ti < NTB; ++ti) {
+#pragma unroll
+            for (int tj = ti; tj < NTB; ++tj) {
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[ti], v[tj], acc[t], 0, 0, 0);
+                ++t;
+            }
+        }
+#pragma unroll
+        for (int ti = 0; ti < NTB; ++ti) esum[ti] += v[ti];
+    }
+}
+
+// Sum the waves' Gram tiles (fixed order) into this block's partial and
+// join the tree reduction into st->Ge.  `smem` must be free (all waves past
+// their last use of it).
+template <int M, int B, int TILES>
+__device__ __forceinline__ void gram_mfma_finish(dbl4 (&acc)[TILES], double (&esum)[B / 16],
+                                                 double *__restrict__ smem, double *__restrict__ red,
+                                                 unsigned *__restrict__ cnt, SolveState *__restrict__ st, int vb,
+                                                 int vg) {
+    using S = WideShape<M, B>;
+    constexpr int NTB = S::NTB, E = S::E, EG = S::EG, NW = S::NW;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+#pragma unroll
+    for (int ti = 0; ti < NTB; ++ti) {
+        esum[ti] += __shfl_xor(esum[ti], 16);
+        esum[ti] += __shfl_xor(esum[ti], 32);
+    }
+    double *mine = smem + (size_t)w * EG;
+    int t = 0;
+#pragma unroll
+    for (int ti = 0; ti < NTB; ++ti) {
+#pragma unroll
+        for (int tj = ti; tj < NTB; ++tj) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = 16 * ti + (lane >> 4) + 4 * r, j = 16 * tj + (lane & 15);
+                if (i <= j) mine[i * B - (i * (i - 1)) / 2 + (j - i)] = acc[t][r];
+            }
+            ++t;
+        }
+    }
+    if (lane < 16) {
+#pragma unroll
+        for (int ti = 0; ti < NTB; ++ti) mine[E + 16 * ti + lane] = esum[ti];
+    }
+    __syncthreads();
+    double *part = red + (size_t)vb * EG;
+    for (int e = tid; e < EG; e += kWideThreads) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) s += smem[(size_t)q * EG + e];
+        st_coherent(part + e, s);
+    }
+    tree_reduce<kFan>(red, EG, vb, vg, cnt, st->Ge);
+}
+
+template <int M, int B>
+__global__ __launch_bounds__(kWideThreads) void k_spmm_wide(const ProbView *__restrict__ views,
+                                                            const int *__restrict__ off, int nprob, int phase) {
+    using Tr = Traits<M>;
+    using TA = typename Tr::TA;
+    using TY = typename Tr::TY;
+    using TU = typename Tr::TU;
+    using TP = typename Tr::TP;
+    using S = WideShape<M, B>;
+    constexpr int VEC = S::VEC, LPR = S::LPR, RPB = S::RPB, RW = S::RW, TILES = S::TILES, NTB = S::NTB;
+    __shared__ double smem[S::SMEM_D];
+    __shared__ int s_ci[kStageCap];
+    __shared__ TP s_val[kStageCap];
+    __shared__ int s_rp[RPB + 1];
+
+    const int p = find_problem(off, nprob, blockIdx.x);
+    const ProbView &v = views[p];
+    SolveState *__restrict__ st = v.st;
+    if (st->done || st->phase != phase) return;  // uniform: the schedule moved on
+    const int vb = blockIdx.x - off[p], vg = off[p + 1] - off[p];
+    const int n = v.n;
+    const int32_t *__restrict__ rp = v.rp;
+    const int32_t *__restrict__ ci = v.ci;
+    const TP *__restrict__ val = (const TP *)v.val[M];
+    const TU *__restrict__ U = (const TU *)v.U;
+    TY *__restrict__ Y = (TY *)(st->ycur ? v.Y0 : v.Y1);  // writes the other buffer
+    double *tile = smem;
+
+    const int tid = threadIdx.x;
+    const int g = tid % LPR;
+    const int slot = tid / LPR;
+    const int w = tid >> 6;
+    const double inv_n = 1.0 / (double)n;
+    TA sc[VEC];
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) sc[q] = (TA)(st->Hs[B * B + g * VEC + q] * inv_n);
+    dbl4 acc[TILES];
+#pragma unroll
+    for (int t = 0; t < TILES; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+    double esum[NTB];
+#pragma unroll
+    for (int ti = 0; ti < NTB; ++ti) esum[ti] = 0.0;
+
+    for (int64_t base = (int64_t)vb * RPB; base < n; base += (int64_t)vg * RPB) {
+        const int nrows = (int)min((int64_t)RPB, (int64_t)n - base);
+        for (int r = tid; r <= nrows; r += kWideThreads) s_rp[r] = rp[base + r];
+        __syncthreads();
+        const int e0 = s_rp[0], ecnt = s_rp[nrows] - e0;
+        const bool staged = ecnt <= kStageCap;  // uniform
+        if (staged) {
+            for (int e = tid; e < ecnt; e += kWideThreads) {
+                s_ci[e] = ci[e0 + e];
+                s_val[e] = val[e0 + e];
+            }
+        }
+        __syncthreads();
+        if (slot < nrows) {
+            TA a[VEC];
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) a[q] = (TA)0;
+            const int beg = s_rp[slot] - e0, end = s_rp[slot + 1] - e0;
+            const int32_t *cis = staged ? s_ci : ci + e0;
+            const TP *vals = staged ? s_val : val + e0;
+            int e = beg;
+            for (; e + 1 < end; e += 2) {
+                const int c0 = cis[e], c1 = cis[e + 1];
+                const TA p0 = up<TA>(vals[e]), p1 = up<TA>(vals[e + 1]);
+                Pack<TU, VEC> u0 = ldp<TU, VEC>(U + (size_t)c0 * B + g * VEC);
+                Pack<TU, VEC> u1 = ldp<TU, VEC>(U + (size_t)c1 * B + g * VEC);
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) a[q] += p0 * up<TA>(u0.v[q]) + p1 * up<TA>(u1.v[q]);
+            }
+            if (e < end) {
+                const int c0 = cis[e];
+                const TA p0 = up<TA>(vals[e]);
+                Pack<TU, VEC> u0 = ldp<TU, VEC>(U + (size_t)c0 * B + g * VEC);
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) a[q] += p0 * up<TA>(u0.v[q]);
+            }
+            Pack<TY, VEC> o;
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) o.v[q] = down<TY>(a[q] - sc[q]);
+            stp<TY, VEC>(Y + (size_t)(base + slot) * B + g * VEC, o);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) tile[slot * B + g * VEC + q] = (double)up<TA>(o.v[q]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) tile[slot * B + g * VEC + q] = 0.0;
+        }
+        __syncthreads();
+        gram_mfma_rows<B, RW, TILES>(tile, w * RW, acc, esum);
+        __syncthreads();
+    }
+    gram_mfma_finish<M, B, TILES>(acc, esum, smem, v.red_spmm, v.spmm_cnt, st, vb, vg);
+}
+
+// Gram matrix and column sums of the start block in buffer 0 (same
+// geometry as k_spmm_wide).
+template <int M, int B>
+__global__ __launch_bounds__(kWideThreads) void k_gram_wide(const ProbView *__restrict__ views,
+                                                            const int *__restrict__ off, int nprob) {
+    using Tr = Traits<M>;
+    using TY = typename Tr::TY;
+    using S = WideShape<M, B>;
+    constexpr int VEC = S::VEC, LPR = S::LPR, RPB = S::RPB, RW = S::RW, TILES = S::TILES, NTB = S::NTB;
+    __shared__ double smem[S::SMEM_D];
+    const int p = find_problem(off, nprob, blockIdx.x);
+    const ProbView &v = views[p];
+    const int vb = blockIdx.x - off[p], vg = off[p + 1] - off[p];
+    const int n = v.n;
+    const TY *__restrict__ Y = (const TY *)v.Y0;
+    double *tile = smem;
+    const int tid = threadIdx.x;
+    const int g = tid % LPR;
+    const int slot = tid / LPR;
+    const int w = tid >> 6;
+    dbl4 acc[TILES];
+#pragma unroll
+    for (int t = 0; t < TILES; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+    double esum[NTB];
+#pragma unroll
+    for (int ti = 0; ti < NTB; ++ti) esum[ti] = 0.0;
+    for (int64_t base = (int64_t)vb * RPB; base < n; base += (int64_t)vg * RPB) {
+        const int64_t row = base + slot;
+        if (row < n) {
+            Pack<TY, VEC> y = ldp<TY, VEC>(Y + (size_t)row * B + g * VEC);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) tile[slot * B + g * VEC + q] = (double)up<typename Tr::TA>(y.v[q]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) tile[slot * B + g * VEC + q] = 0.0;
+        }
+        __syncthreads();
+        gram_mfma_rows<B, RW, TILES>(tile, w * RW, acc, esum);
+        __syncthreads();
+    }
+    gram_mfma_finish<M, B, TILES>(acc, esum, smem, v.red_spmm, v.spmm_cnt, v.st, vb, vg);
 }
 
 // ---------------------------------------------------------------------------
@@ -536,7 +783,11 @@ hipError_t launch_spmm(Mode m, const Batch &bt, int phase, hipStream_t s) {
     if (grid <= 0) return hipErrorInvalidValue;
     const int *off = bt.off(BK_SPMM, m);
     SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(bt.B, {
-        hipLaunchKernelGGL((k_spmm<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase);
+        if constexpr (BB == 16 || BB == 32)
+            hipLaunchKernelGGL((k_spmm_wide<MM, BB>), dim3(grid), dim3(kWideThreads), 0, s, bt.views, off, bt.nprob,
+                               phase);
+        else
+            hipLaunchKernelGGL((k_spmm<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase);
         return hipGetLastError();
     }));
     return hipErrorInvalidValue;
@@ -575,7 +826,12 @@ static hipError_t start_impl(const Batch &bt, uint64_t seed, hipStream_t s) {
     if (e != hipSuccess) return e;
     const int grid = bt.total[BK_SPMM][MM];
     if (grid <= 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_gram<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, bt.off(BK_SPMM, (Mode)MM), bt.nprob);
+    if constexpr (BB == 16 || BB == 32)
+        hipLaunchKernelGGL((k_gram_wide<MM, BB>), dim3(grid), dim3(kWideThreads), 0, s, bt.views,
+                           bt.off(BK_SPMM, (Mode)MM), bt.nprob);
+    else
+        hipLaunchKernelGGL((k_gram<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, bt.off(BK_SPMM, (Mode)MM),
+                           bt.nprob);
     return hipGetLastError();
 }
 

@@ -34,12 +34,14 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def time_form(sb, torch, prob, prec, steps, warmup, k, block, flags=0, start=None):
+def time_form(sb, torch, prob, prec, steps, warmup, k, block, flags=0, start=None, tune_cache=None):
     p = sb.Problem.from_arrays(*(torch.from_numpy(prob[x]).cuda() for x in ("rowptr", "col", "val", "W")))
     kw = {}
     if start is not None:
         kw["start"] = start
-    ctx = sb.Context([p], k=k, block=block, prec=prec, flags=flags, **kw)
+    t0 = time.perf_counter()
+    ctx = sb.Context([p], k=k, block=block, prec=prec, flags=flags, tune_cache=tune_cache, **kw)
+    log(f"create (upload, transpose, copies{', autotune' if tune_cache else ''}) {1e3 * (time.perf_counter() - t0):.1f} ms")
     Z = torch.empty((prob["n"], k), dtype=torch.float32, device="cuda")
     for _ in range(warmup):
         ctx.embed(Z_out=Z)
@@ -145,11 +147,12 @@ def main():
 
     torch.cuda.set_device(0)
     k, block = args.k, args.block
+    tune = os.path.join(configs.cache_dir(), f"tune_sphere7_k{k}_b{block}.txt")
     log("timing plain fp32")
-    ms_fp32, eig32, rep32, _ = time_form(sb, torch, prob, sb.FP32, args.steps, args.warmup, k, block)
+    ms_fp32, eig32, rep32, _ = time_form(sb, torch, prob, sb.FP32, args.steps, args.warmup, k, block, tune_cache=tune)
     log(f"plain fp32 {ms_fp32:.3f} ms  iters {rep32['iters_fp32']}+{rep32['iters_fp64']}")
     log("timing chosen (bf16 -> fp32 -> fp64 certify)")
-    ms_ch, eigc, repc, _ = time_form(sb, torch, prob, sb.BF16_FP32, args.steps, args.warmup, k, block)
+    ms_ch, eigc, repc, _ = time_form(sb, torch, prob, sb.BF16_FP32, args.steps, args.warmup, k, block, tune_cache=tune)
     log(f"chosen {ms_ch:.3f} ms  iters {repc['iters_bf16']}+{repc['iters_fp32']}+{repc['iters_fp64']}")
     chosen_prec = sb.BF16_FP32
     value = ms_ch
@@ -157,7 +160,8 @@ def main():
         # the schedule that certifies fastest is the chosen one
         chosen_prec, value, eigc, repc = sb.FP32, ms_fp32, eig32, rep32
     log("kernel timing pass")
-    _, _, _, stats = time_form(sb, torch, prob, chosen_prec, args.steps, 1, k, block, flags=sb.FLAG_KERNEL_TIMING)
+    _, _, _, stats = time_form(sb, torch, prob, chosen_prec, args.steps, 1, k, block, flags=sb.FLAG_KERNEL_TIMING,
+                              tune_cache=tune)
     per = {s["name"]: s for s in stats}
     dom = max((s for s in stats if s["bytes_total"] > 0), key=lambda s: s["ms_total"])
     avg_ms = dom["ms_total"] / dom["launches"]

@@ -25,7 +25,10 @@ struct GemmShape {
     static constexpr int RT = 4 * RW;  // rows per block (4 waves)
 };
 
-int gemm_rows_per_tile(Mode m, int B) {
+bool gemm_mfma(Mode m, int B);
+
+int gemm_rows_per_tile(Mode m, int B, int mfma) {
+    if (mfma && gemm_mfma(m, B)) return 64;
     const bool dbl = (m == MODE_F64ACC || m == MODE_FP64);
     const int nvmax = dbl ? (B >= 64 ? 64 : 32) : 64;
     const int rw = nvmax / B > 0 ? nvmax / B : 1;
@@ -59,6 +62,75 @@ struct ReduceScatter {
         }
     }
 };
+
+// Per-tile finish of the split-K product (shared by both kernels): the
+// last of the ksplit blocks of row tile rt sums the K partials in fixed
+// order, stores U = -1/2 sum, and reduces the tile's contributions to
+// H = T^T U and s = c^T U; the last tile reduces those into st->Hs.
+template <int M, int B, int RT>
+__device__ __forceinline__ void gemm_tile_finish(const ProbView &v, SolveState *__restrict__ st, int rt, int rowtiles,
+                                                 int ksplit) {
+    using Tr = Traits<M>;
+    using TA = typename Tr::TA;
+    using TT = typename Tr::TT;
+    using TU = typename Tr::TU;
+    const int l = v.l, lda = v.lda;
+    const TT *__restrict__ T = (const TT *)v.T;
+    const TA *__restrict__ part = (const TA *)v.gpart;
+    TU *__restrict__ U = (TU *)v.U;
+    const double *__restrict__ c = v.c[M];
+    double *__restrict__ red = v.red_gemm;
+    unsigned *__restrict__ tile_cnt = v.tile_cnt;
+    unsigned *__restrict__ tree_cnt = v.gemm_cnt;
+    const int tid = threadIdx.x;
+    if (!arrive_last(tile_cnt + rt, (unsigned)ksplit)) return;
+    __shared__ double ul[RT][B];
+    __shared__ double tl[RT][B];
+    __shared__ double cl[RT];
+    const int tile0 = rt * RT;
+    for (int e = tid; e < RT * B; e += 256) {
+        const int r = e / B, j = e % B;
+        const int row = tile0 + r;
+        if (row < l) {
+            // fixed summation order; the loads of 8 partials are in flight together
+            TA sum = (TA)0;
+            for (int q0 = 0; q0 < ksplit; q0 += 8) {
+                TA pv[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    pv[q] = (q0 + q < ksplit) ? ld_coherent(part + ((size_t)(q0 + q) * lda + row) * B + j) : (TA)0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (q0 + q < ksplit) sum += pv[q];
+            }
+            const TU u = down<TU>((TA)(-0.5) * sum);
+            U[(size_t)row * B + j] = u;
+            ul[r][j] = (double)up<TA>(u);
+            tl[r][j] = (double)up<TA>(T[(size_t)row * B + j]);
+        } else {
+            ul[r][j] = 0.0;
+            tl[r][j] = 0.0;
+        }
+    }
+    for (int r = tid; r < RT; r += 256) cl[r] = (tile0 + r) < l ? c[tile0 + r] : 0.0;
+    if (tid == 0) counter_reset(tile_cnt + rt);
+    __syncthreads();
+    // this tile's contribution to H = T^T U and s = c^T U
+    constexpr int EH = B * B + B;
+    double *mine = red + (size_t)rt * EH;
+    for (int e = tid; e < B * B; e += 256) {
+        const int a = e / B, bb = e % B;
+        double s = 0.0;
+        for (int r = 0; r < RT; ++r) s += tl[r][a] * ul[r][bb];
+        st_coherent(mine + e, s);
+    }
+    for (int j = tid; j < B; j += 256) {
+        double s = 0.0;
+        for (int r = 0; r < RT; ++r) s += cl[r] * ul[r][j];
+        st_coherent(mine + B * B + j, s);
+    }
+    tree_reduce<kFan>(red, EH, rt, rowtiles, tree_cnt, st->Hs);
+}
 
 template <int M, int B>
 __global__ __launch_bounds__(256) void k_gemm_vec(const ProbView *__restrict__ views, const int *__restrict__ off,
@@ -136,45 +208,135 @@ __global__ __launch_bounds__(256) void k_gemm_vec(const ProbView *__restrict__ v
         if (row < l) st_coherent(part + ((size_t)ks * lda + row) * B + j, acc[0]);
     }
 
-    // ---- per-tile finish: the last of the ksplit blocks of this row tile
-    if (!arrive_last(tile_cnt + rt, (unsigned)ksplit)) return;
-    __shared__ double ul[RT][B];
-    __shared__ double tl[RT][B];
-    __shared__ double cl[RT];
-    const int tile0 = rt * RT;
-    for (int e = tid; e < RT * B; e += 256) {
-        const int r = e / B, j = e % B;
-        const int row = tile0 + r;
-        if (row < l) {
-            TA sum = (TA)0;
-            for (int q = 0; q < ksplit; ++q) sum += ld_coherent(part + ((size_t)q * lda + row) * B + j);
-            const TU u = down<TU>((TA)(-0.5) * sum);
-            U[(size_t)row * B + j] = u;
-            ul[r][j] = (double)up<TA>(u);
-            tl[r][j] = (double)up<TA>(T[(size_t)row * B + j]);
+    gemm_tile_finish<M, B, RT>(v, st, rt, rowtiles, ksplit);
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-core variant (bf16 and float32 arithmetic, widths 16 and 32).  A
+// block owns 64 rows of U (16 per wave) and a K range; each step stages a
+// 64 x 64 slice of W (coalesced 16-byte loads) and the matching 64 x B slice
+// of T (transposed, so that both MFMA operands are contiguous) in LDS, then
+// every wave runs 16 x 16 tiles on the matrix cores:
+//   float32: v_mfma_f32_16x16x4f32, lane l supplies A[l%16][l/16], B[l/16][l%16]
+//   bf16:    v_mfma_f32_16x16x32_bf16, lane l supplies 8 consecutive k of
+//            row l%16 of A and of column l%16 of B (k offset 8 (l/16))
+// and holds D[4 (l/16) + r][l%16] in element r (both instructions).  The
+// split-K partials and the tile finish are those of k_gemm_vec.
+// ---------------------------------------------------------------------------
+typedef float gm_f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 gm_bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int kMfmaRows = 64;  // rows of U per block
+constexpr int kMfmaK = 64;     // K per staged step
+
+bool gemm_mfma(Mode m, int B) { return (m == MODE_BF16 || m == MODE_FP32) && (B == 16 || B == 32); }
+
+template <int M, int B>
+__global__ __launch_bounds__(256) void k_gemm_mfma(const ProbView *__restrict__ views, const int *__restrict__ off,
+                                                   int nprob, int phase) {
+    using Tr = Traits<M>;
+    using TT = typename Tr::TT;
+    using TW = typename Tr::TW;
+    constexpr bool BF = (M == MODE_BF16);
+    constexpr int KS = kMfmaK, RT = kMfmaRows, NT = B / 16;
+    constexpr int EPV = 16 / (int)sizeof(TW);  // elements per 16-byte load
+    constexpr int PAD = EPV;                   // keeps 16-byte alignment of rows
+    __shared__ __attribute__((aligned(16))) TW Ws[RT][KS + PAD];
+    __shared__ __attribute__((aligned(16))) TT Ts[B][KS + PAD];  // transposed: Ts[j][k]
+
+    const int pidx = find_problem(off, nprob, blockIdx.x);
+    const ProbView &v = views[pidx];
+    SolveState *__restrict__ st = v.st;
+    if (st->done || st->phase != phase) return;  // uniform: the schedule moved on
+    const int vb = blockIdx.x - off[pidx];
+    const int l = v.l, lda = v.lda;
+    const int rowtiles = v.gemm_rowtiles[M];
+    const int ksplit = v.gemm_ksplit[M];
+    const int kchunk = v.gemm_kchunk[M];
+    const TW *__restrict__ W = (const TW *)v.W[M];
+    const TT *__restrict__ T = (const TT *)v.T;
+    float *__restrict__ part = (float *)v.gpart;
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int rt = vb % rowtiles, ks = vb / rowtiles;
+    const int r0 = rt * RT;
+    const int kbeg = ks * kchunk, kend = min(lda, kbeg + kchunk);
+
+    gm_f4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = gm_f4{0.f, 0.f, 0.f, 0.f};
+
+    // W slices are loaded one step ahead (registers), so the next slice is in
+    // flight while the matrix cores work on the current one
+    constexpr int PPR = KS / EPV;                 // 16-byte pieces per row
+    constexpr int NPC = RT * PPR / 256;           // pieces per thread
+    static_assert(RT * PPR % 256 == 0, "whole pieces per thread");
+    Pack<TW, EPV> wnext[NPC];
+    auto load_w = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < NPC; ++q) {
+            const int idx = tid + 256 * q;
+            const int r = idx / PPR, pc = idx % PPR;
+            const int row = r0 + r;
+            if (row < l && k0 < kend) {
+                wnext[q] = ldp<TW, EPV>(W + (size_t)row * lda + k0 + pc * EPV);  // k0 + KS <= lda
+            } else {
+#pragma unroll
+                for (int e = 0; e < EPV; ++e) wnext[q].v[e] = TW{};
+            }
+        }
+    };
+    load_w(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += KS) {
+#pragma unroll
+        for (int q = 0; q < NPC; ++q) {
+            const int idx = tid + 256 * q;
+            stp<TW, EPV>(&Ws[idx / PPR][(idx % PPR) * EPV], wnext[q]);
+        }
+        load_w(k0 + KS);
+        // T slice, transposed; rows of T past l are padding and read as zero
+        for (int idx = tid; idx < KS * B; idx += 256) {
+            const int kk = idx / B, j = idx % B;
+            const int k = k0 + kk;
+            Ts[j][kk] = k < l ? T[(size_t)k * B + j] : TT{};
+        }
+        __syncthreads();
+        const int arow = 16 * w + (lane & 15);
+        if constexpr (BF) {
+#pragma unroll
+            for (int s = 0; s < KS / 32; ++s) {
+                const int kk = 32 * s + 8 * (lane >> 4);
+                const gm_bf8 a = *reinterpret_cast<const gm_bf8 *>(&Ws[arow][kk]);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const gm_bf8 b = *reinterpret_cast<const gm_bf8 *>(&Ts[16 * t + (lane & 15)][kk]);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+                }
+            }
         } else {
-            ul[r][j] = 0.0;
-            tl[r][j] = 0.0;
+#pragma unroll
+            for (int s = 0; s < KS / 4; ++s) {
+                const int kk = 4 * s + (lane >> 4);
+                const float a = Ws[arow][kk];
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, (float)Ts[16 * t + (lane & 15)][kk], acc[t], 0, 0,
+                                                                  0);
+            }
+        }
+        __syncthreads();
+    }
+    // partial U tile of this K range
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = r0 + 16 * w + 4 * (lane >> 4) + r;
+            const int j = 16 * t + (lane & 15);
+            if (row < l) st_coherent(part + ((size_t)ks * lda + row) * B + j, acc[t][r]);
         }
     }
-    for (int r = tid; r < RT; r += 256) cl[r] = (tile0 + r) < l ? c[tile0 + r] : 0.0;
-    if (tid == 0) counter_reset(tile_cnt + rt);
-    __syncthreads();
-    // this tile's contribution to H = T^T U and s = c^T U
-    constexpr int EH = B * B + B;
-    double *mine = red + (size_t)rt * EH;
-    for (int e = tid; e < B * B; e += 256) {
-        const int a = e / B, bb = e % B;
-        double s = 0.0;
-        for (int r = 0; r < RT; ++r) s += tl[r][a] * ul[r][bb];
-        st_coherent(mine + e, s);
-    }
-    for (int j = tid; j < B; j += 256) {
-        double s = 0.0;
-        for (int r = 0; r < RT; ++r) s += cl[r] * ul[r][j];
-        st_coherent(mine + B * B + j, s);
-    }
-    tree_reduce<kFan>(red, EH, rt, rowtiles, tree_cnt, st->Hs);
+    gemm_tile_finish<M, B, RT>(v, st, rt, rowtiles, ksplit);
 }
 
 #define SBMDS_DISPATCH_B2(B_, CALL)                      \
@@ -192,8 +354,22 @@ hipError_t launch_gemm(Mode m, const Batch &bt, int phase, hipStream_t s) {
     if (grid <= 0) return hipErrorInvalidValue;
     const int *off = bt.off(BK_GEMM, m);
     switch (m) {
-        case MODE_BF16: { constexpr int MM = MODE_BF16; SBMDS_DISPATCH_B2(bt.B, hipLaunchKernelGGL((k_gemm_vec<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase); return hipGetLastError()); } break;
-        case MODE_FP32: { constexpr int MM = MODE_FP32; SBMDS_DISPATCH_B2(bt.B, hipLaunchKernelGGL((k_gemm_vec<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase); return hipGetLastError()); } break;
+        case MODE_BF16: { constexpr int MM = MODE_BF16; SBMDS_DISPATCH_B2(bt.B, {
+            if constexpr (BB == 16 || BB == 32) {
+                if (bt.gemm_mfma[MM]) hipLaunchKernelGGL((k_gemm_mfma<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase);
+                else hipLaunchKernelGGL((k_gemm_vec<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase);
+            } else {
+                hipLaunchKernelGGL((k_gemm_vec<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase);
+            }
+            return hipGetLastError(); }); } break;
+        case MODE_FP32: { constexpr int MM = MODE_FP32; SBMDS_DISPATCH_B2(bt.B, {
+            if constexpr (BB == 16 || BB == 32) {
+                if (bt.gemm_mfma[MM]) hipLaunchKernelGGL((k_gemm_mfma<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase);
+                else hipLaunchKernelGGL((k_gemm_vec<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase);
+            } else {
+                hipLaunchKernelGGL((k_gemm_vec<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase);
+            }
+            return hipGetLastError(); }); } break;
         case MODE_F64ACC: { constexpr int MM = MODE_F64ACC; SBMDS_DISPATCH_B2(bt.B, hipLaunchKernelGGL((k_gemm_vec<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase); return hipGetLastError()); } break;
         case MODE_FP64: { constexpr int MM = MODE_FP64; SBMDS_DISPATCH_B2(bt.B, hipLaunchKernelGGL((k_gemm_vec<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase); return hipGetLastError()); } break;
         default: break;

@@ -93,7 +93,18 @@ struct DevProblem {
     const void *X0 = nullptr;    // device copy of a user start block
 };
 
-// Launch geometry of one problem in one mode; tunable.
+// Tunable launch choices of a batch in one mode (chosen by the autotuner or
+// by the defaults): SpMM block cap, dense-product kernel (matrix cores or
+// vector ALU) and its target block count, and waves per landmark row of the
+// transposed SpMM.
+struct Tune {
+    int spmm_cap = 256;
+    int gemm_mfma = 0;
+    int gemm_target = 1024;
+    int spmmt_wpr = 4;
+};
+
+// Launch geometry of one problem in one mode (derived from a Tune).
 struct LaunchCfg {
     int spmm_blocks = 0;   // grid of the row-split SpMM (grid-stride)
     int gemm_rt = 0;       // rows per dense-product tile (fixed by mode and B)
@@ -130,7 +141,8 @@ enum BlockKind { BK_SPMM = 0, BK_SPMMT = 1, BK_GEMM = 2, BK_ELEM_NB = 3, BK_ELEM
 struct Batch {
     int nprob = 0;
     int B = 0, b = 0, k = 0;
-    int spmmt_wpr = 4;           // waves per landmark row in the transposed SpMM
+    int spmmt_wpr[NUM_MODES] = {4, 4, 4, 4};  // waves per landmark row in the transposed SpMM
+    int gemm_mfma[NUM_MODES] = {};             // dense product on the matrix cores
     ProbView *views = nullptr;   // device [nprob]
     int *offs = nullptr;         // device [NUM_BK][NUM_MODES][nprob + 1]
     int total[NUM_BK][NUM_MODES] = {};
@@ -162,7 +174,8 @@ hipError_t launch_block_out(Mode m, const DevProblem &p, int ybuf, void *X, int 
                             hipStream_t stream);
 
 hipError_t launch_f32_to_bf16(const float *src, void *dst, int64_t count, hipStream_t stream);
-int gemm_rows_per_tile(Mode m, int B);
+int gemm_rows_per_tile(Mode m, int B, int mfma);
+bool gemm_mfma(Mode m, int B);  // the dense product runs on the matrix cores
 int spmm_rows_per_block(Mode m, int B);
 int spmm_block_cap(Mode m, int B);  // most blocks worth launching for one problem
 

@@ -110,6 +110,7 @@ struct PendingEv {
 struct SolveSet {
     std::vector<DevProblem> probs;
     std::vector<std::vector<LaunchCfg>> cfg;  // [problem][mode]
+    Tune tune[NUM_MODES];                      // launch choices per mode
     Batch bt;                                  // launch tables over all problems
     SolveState *st_all = nullptr;              // device, one per problem (contiguous)
     Summary *host_sum = nullptr;               // pinned, one per problem
@@ -289,20 +290,51 @@ std::vector<PhaseRule> schedule(const sbmds_options &o) {
     return out;
 }
 
-LaunchCfg default_cfg(Mode m, const DevProblem &p) {
+constexpr int kMaxGemmSplit = 64;   // K splits of the dense product (bounds its scratch)
+constexpr int kMaxSpmmBlocks = 1024;
+
+LaunchCfg make_cfg(Mode m, const DevProblem &p, const Tune &t) {
     LaunchCfg c;
     const int rpb = spmm_rows_per_block(m, p.B);
     int64_t want = (p.n + rpb - 1) / rpb;
-    const int cap = spmm_block_cap(m, p.B);
+    const int cap = std::min(t.spmm_cap, kMaxSpmmBlocks);
     c.spmm_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, cap));
-    c.gemm_rt = gemm_rows_per_tile(m, p.B);
+    c.gemm_rt = gemm_rows_per_tile(m, p.B, t.gemm_mfma);
     const int rowtiles = (int)((p.l + c.gemm_rt - 1) / c.gemm_rt);
-    int ks = (1024 + rowtiles - 1) / rowtiles;
+    int ks = (t.gemm_target + rowtiles - 1) / rowtiles;
     const int kblocks = p.lda / 64;
-    ks = std::max(1, std::min(ks, kblocks));
+    ks = std::max(1, std::min(std::min(ks, kblocks), kMaxGemmSplit));
     c.gemm_kchunk = ((kblocks + ks - 1) / ks) * 64;
     c.gemm_ksplit = (p.lda + c.gemm_kchunk - 1) / c.gemm_kchunk;
     return c;
+}
+
+// Defaults: matrix cores for the dense product once W no longer fits the
+// caches (there its bandwidth is higher; below, launch latency dominates
+// and the vector kernel is as fast), waves per landmark row of P^T by the
+// mean column length of P.
+Tune default_tune(Mode m, const std::vector<DevProblem> &probs) {
+    Tune t;
+    double nnz = 0, l = 0, l2 = 0;
+    for (const DevProblem &p : probs) {
+        nnz += (double)p.nnz;
+        l += (double)p.l;
+        l2 += (double)p.l * p.l;
+    }
+    const int B = probs[0].B;
+    t.spmm_cap = spmm_block_cap(m, B);
+    t.gemm_mfma = (gemm_mfma(m, B) && l2 * 4.0 > 64e6) ? 1 : 0;
+    t.gemm_target = t.gemm_mfma ? 512 : 1024;
+    const double per_row = nnz / l;  // mean entries per landmark column of P
+    t.spmmt_wpr = per_row >= 256 ? 4 : (per_row >= 64 ? 2 : 1);
+    return t;
+}
+
+void apply_tune(SolveSet &set) {
+    for (size_t i = 0; i < set.probs.size(); ++i) {
+        set.cfg[i].resize(NUM_MODES);
+        for (int m = 0; m < NUM_MODES; ++m) set.cfg[i][m] = make_cfg((Mode)m, set.probs[i], set.tune[m]);
+    }
 }
 
 hipEvent_t ev_get(sbmds_ctx *ctx) {
@@ -622,6 +654,147 @@ int solve_all(sbmds_ctx *ctx, sbmds_report *reps) {
     return all_done ? SBMDS_OK : SBMDS_ENOCONV;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner.  For every arithmetic of the schedule it times, on the device
+// and on the problems of the context, the candidates of each launch choice
+// (one choice at a time, the others held at their current values): the SpMM
+// block cap, the dense-product kernel and its block target, and the waves
+// per landmark row of the transposed SpMM.  The iteration state it leaves
+// behind is discarded: every solve starts from its start block.  Results
+// are kept in a text cache, one line per (batch shape, arithmetic):
+//   <key> <spmm_cap> <gemm_mfma> <gemm_target> <spmmt_wpr>
+// Different choices change the summation order, so results are bitwise
+// reproducible for a fixed configuration only.
+// ---------------------------------------------------------------------------
+int build_batch(sbmds_ctx *ctx, SolveSet &set);
+
+std::string tune_key(const SolveSet &set, Mode m) {
+    std::string k = "v1;B=" + std::to_string(set.probs[0].B) + ";m=" + std::to_string((int)m);
+    for (const DevProblem &p : set.probs)
+        k += ";" + std::to_string(p.n) + "," + std::to_string(p.l) + "," + std::to_string(p.nnz);
+    // keep keys short for large batches
+    if (k.size() > 200) {
+        uint64_t h = 1469598103934665603ull;  // FNV-1a
+        for (char ch : k) h = (h ^ (uint8_t)ch) * 1099511628211ull;
+        k = "v1;B=" + std::to_string(set.probs[0].B) + ";m=" + std::to_string((int)m) + ";np=" +
+            std::to_string(set.probs.size()) + ";h=" + std::to_string(h);
+    }
+    return k;
+}
+
+std::vector<std::pair<std::string, std::string>> read_cache(const char *path) {
+    std::vector<std::pair<std::string, std::string>> out;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return out;
+    char line[4096];
+    while (std::fgets(line, sizeof(line), f)) {
+        std::string ln(line);
+        while (!ln.empty() && (ln.back() == '\n' || ln.back() == '\r')) ln.pop_back();
+        const size_t sp = ln.find(' ');
+        if (sp == std::string::npos) continue;
+        out.push_back({ln.substr(0, sp), ln.substr(sp + 1)});
+    }
+    std::fclose(f);
+    return out;
+}
+
+int write_cache(const char *path, const std::vector<std::pair<std::string, std::string>> &entries) {
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return fail(SBMDS_EINVAL, std::string("cannot write the tuning cache ") + path);
+    for (const auto &e : entries) std::fprintf(f, "%s %s\n", e.first.c_str(), e.second.c_str());
+    if (std::fclose(f) != 0 || std::rename(tmp.c_str(), path) != 0)
+        return fail(SBMDS_EINVAL, std::string("cannot write the tuning cache ") + path);
+    return SBMDS_OK;
+}
+
+template <typename F>
+int time_launch(sbmds_ctx *ctx, F &&launch, double *ms_out) {
+    for (int i = 0; i < 2; ++i) HIPCHK(launch());
+    hipEvent_t a = ev_get(ctx), b = ev_get(ctx);
+    if (!a || !b) return fail(SBMDS_EHIP, "hipEventCreate failed");
+    constexpr int reps = 8;
+    HIPCHK(hipEventRecord(a, ctx->stream));
+    for (int i = 0; i < reps; ++i) HIPCHK(launch());
+    HIPCHK(hipEventRecord(b, ctx->stream));
+    HIPCHK(hipEventSynchronize(b));
+    *ms_out = ms_between(a, b) / reps;
+    ctx->ev_pool.push_back(a);
+    ctx->ev_pool.push_back(b);
+    return SBMDS_OK;
+}
+
+int autotune(sbmds_ctx *ctx, SolveSet &set) {
+    const char *path = ctx->opt.tune_cache;
+    auto cache = read_cache(path);
+    bool dirty = false;
+    std::vector<Mode> modes;
+    for (const PhaseRule &r : schedule(ctx->opt))
+        if (std::find(modes.begin(), modes.end(), (Mode)r.mode) == modes.end()) modes.push_back((Mode)r.mode);
+    for (Mode m : modes) {
+        const std::string key = tune_key(set, m);
+        bool found = false;
+        for (const auto &e : cache) {
+            if (e.first != key) continue;
+            Tune t;
+            if (std::sscanf(e.second.c_str(), "%d %d %d %d", &t.spmm_cap, &t.gemm_mfma, &t.gemm_target,
+                            &t.spmmt_wpr) == 4 &&
+                t.spmm_cap >= 1 && t.gemm_target >= 1 && (t.spmmt_wpr == 1 || t.spmmt_wpr == 2 || t.spmmt_wpr == 4)) {
+                set.tune[m] = t;
+                found = true;
+            }
+        }
+        if (found) continue;
+        // a valid state in this arithmetic: start block and its orthonormal basis
+        PhaseRule r{};
+        r.phase = 0;
+        r.is_final = 1;
+        r.cap = 1;
+        r.mode = m;
+        r.tol = 0.0;
+        apply_tune(set);
+        OKCHK(build_batch(ctx, set));
+        HIPCHK(launch_random_start(m, set.bt, ctx->opt.seed, ctx->stream));
+        HIPCHK(launch_rr_solve(set.bt, 1, 0, r, ctx->stream));
+        auto try_all = [&](auto &&field_values, auto &&set_field, auto &&launch) -> int {
+            double best = 1e30;
+            Tune keep = set.tune[m];
+            for (int val : field_values) {
+                set_field(set.tune[m], val);
+                apply_tune(set);
+                OKCHK(build_batch(ctx, set));
+                double ms = 0.0;
+                OKCHK(time_launch(ctx, launch, &ms));
+                if (ms < best) {
+                    best = ms;
+                    keep = set.tune[m];
+                }
+            }
+            set.tune[m] = keep;
+            return SBMDS_OK;
+        };
+        OKCHK(try_all(std::vector<int>{64, 128, 256, 512, 1024}, [](Tune &t, int v) { t.spmm_cap = v; },
+                      [&] { return launch_spmm(m, set.bt, 0, ctx->stream); }));
+        std::vector<int> gemm_cands;
+        for (int mf = 0; mf < (gemm_mfma(m, set.probs[0].B) ? 2 : 1); ++mf)
+            for (int tg : {128, 256, 512, 1024, 2048}) gemm_cands.push_back(mf * 100000 + tg);
+        OKCHK(try_all(gemm_cands, [](Tune &t, int v) { t.gemm_mfma = v / 100000; t.gemm_target = v % 100000; },
+                      [&] { return launch_gemm(m, set.bt, 0, ctx->stream); }));
+        OKCHK(try_all(std::vector<int>{1, 2, 4}, [](Tune &t, int v) { t.spmmt_wpr = v; },
+                      [&] { return launch_spmm_t(m, set.bt, 0, ctx->stream); }));
+        const Tune &t = set.tune[m];
+        char val[64];
+        std::snprintf(val, sizeof(val), "%d %d %d %d", t.spmm_cap, t.gemm_mfma, t.gemm_target, t.spmmt_wpr);
+        cache.push_back({key, val});
+        dirty = true;
+    }
+    apply_tune(set);
+    OKCHK(build_batch(ctx, set));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (dirty) OKCHK(write_cache(path, cache));
+    return SBMDS_OK;
+}
+
 template <typename T>
 int upload_problem(sbmds_ctx *ctx, const sbmds_problem &in, DevProblem &p, const int32_t *rp, const int32_t *ci,
                    const T *val, bool fp64) {
@@ -701,14 +874,10 @@ int build_batch(sbmds_ctx *ctx, SolveSet &set) {
     bt.B = set.probs[0].B;
     bt.b = set.probs[0].b;
     bt.k = set.probs[0].k;
-    double nnz = 0, l = 0;
-    for (const DevProblem &p : set.probs) {
-        nnz += (double)p.nnz;
-        l += (double)p.l;
+    for (int m = 0; m < NUM_MODES; ++m) {
+        bt.spmmt_wpr[m] = set.tune[m].spmmt_wpr;
+        bt.gemm_mfma[m] = set.tune[m].gemm_mfma && gemm_mfma((Mode)m, bt.B) ? 1 : 0;
     }
-    const double per_row = nnz / l;  // mean entries per landmark column of P
-    bt.spmmt_wpr = per_row >= 256 ? 4 : (per_row >= 64 ? 2 : 1);
-    const int rows_per_blk = 4 / bt.spmmt_wpr;
 
     std::vector<ProbView> views(np);
     std::vector<int> offs((size_t)NUM_BK * NUM_MODES * (np + 1), 0);
@@ -764,7 +933,7 @@ int build_batch(sbmds_ctx *ctx, SolveSet &set) {
                 int64_t nb = 0;
                 switch (kd) {
                     case BK_SPMM: nb = v.spmm_blocks[m]; break;
-                    case BK_SPMMT: nb = (p.l + rows_per_blk - 1) / rows_per_blk; break;
+                    case BK_SPMMT: nb = (p.l + 4 / bt.spmmt_wpr[m] - 1) / (4 / bt.spmmt_wpr[m]); break;
                     case BK_GEMM: nb = (int64_t)v.gemm_rowtiles[m] * v.gemm_ksplit[m]; break;
                     case BK_ELEM_NB: nb = (p.n * p.B + 255) / 256; break;
                     case BK_ELEM_LB: nb = (p.l * p.B + 255) / 256; break;
@@ -777,8 +946,8 @@ int build_batch(sbmds_ctx *ctx, SolveSet &set) {
             bt.total[kd][m] = (int)acc;
         }
     }
-    OKCHK(dalloc(ctx, (void **)&bt.views, sizeof(ProbView) * np));
-    OKCHK(dalloc(ctx, (void **)&bt.offs, sizeof(int) * offs.size()));
+    if (!bt.views) OKCHK(dalloc(ctx, (void **)&bt.views, sizeof(ProbView) * np));
+    if (!bt.offs) OKCHK(dalloc(ctx, (void **)&bt.offs, sizeof(int) * offs.size()));
     HIPCHK(hipMemcpyAsync(bt.views, views.data(), sizeof(ProbView) * np, hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipMemcpyAsync(bt.offs, offs.data(), sizeof(int) * offs.size(), hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));  // host tables go out of scope
@@ -806,14 +975,18 @@ int alloc_set(sbmds_ctx *ctx, SolveSet &set, int nprob) {
 // (its operator is already on the device).
 int alloc_work(sbmds_ctx *ctx, SolveSet &set, int i) {
     DevProblem &p = set.probs[i];
-    set.cfg[i].resize(NUM_MODES);
+    // scratch for every launch shape the tuner may pick
     for (int m = 0; m < NUM_MODES; ++m) {
-        set.cfg[i][m] = default_cfg((Mode)m, p);
-        const int rt = set.cfg[i][m].gemm_rt;
-        p.max_rowtiles = std::max(p.max_rowtiles, (int)((p.l + rt - 1) / rt));
-        p.max_ksplit = std::max(p.max_ksplit, set.cfg[i][m].gemm_ksplit);
-        p.max_spmm_blocks = std::max(p.max_spmm_blocks, set.cfg[i][m].spmm_blocks);
+        const int rpb = spmm_rows_per_block((Mode)m, p.B);
+        p.max_spmm_blocks = std::max<int>(p.max_spmm_blocks,
+                                          (int)std::min<int64_t>((p.n + rpb - 1) / rpb, kMaxSpmmBlocks));
+        for (int mf = 0; mf < 2; ++mf) {
+            const int rt = gemm_rows_per_tile((Mode)m, p.B, mf);
+            p.max_rowtiles = std::max(p.max_rowtiles, (int)((p.l + rt - 1) / rt));
+        }
     }
+    p.max_spmm_blocks = std::max(p.max_spmm_blocks, 1);
+    p.max_ksplit = std::max(1, std::min(p.lda / 64, kMaxGemmSplit));
     const int B = p.B;
     const int EG = B * (B + 1) / 2 + B;   // Gram triangle + column sums
     const int EH = B * B + B;             // H + s
@@ -1021,13 +1194,19 @@ int create_impl(const sbmds_problem *probs, int nprob, const sbmds_options *opt_
             p.X0 = x0;
         }
     }
+    for (int m = 0; m < NUM_MODES; ++m) ctx->main.tune[m] = default_tune((Mode)m, ctx->main.probs);
+    apply_tune(ctx->main);
     if (int rc = build_batch(ctx, ctx->main); rc < 0) return cleanup(rc);
+    if (o.tune_cache)
+        if (int rc = autotune(ctx, ctx->main); rc < 0) return cleanup(rc);
     if (o.start == SBMDS_START_LEARNED)
         if (int rc = setup_learned(ctx, probs, nprob); rc < 0) return cleanup(rc);
     if (o.start == SBMDS_START_LMDS) {
         if (int rc = alloc_set(ctx, ctx->lmk, nprob); rc < 0) return cleanup(rc);
         for (int i = 0; i < nprob; ++i)
             if (int rc = make_landmark_problem(ctx, i); rc < 0) return cleanup(rc);
+        for (int m = 0; m < NUM_MODES; ++m) ctx->lmk.tune[m] = default_tune((Mode)m, ctx->lmk.probs);
+        apply_tune(ctx->lmk);
         if (int rc = build_batch(ctx, ctx->lmk); rc < 0) return cleanup(rc);
     }
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) return cleanup(fail(SBMDS_EHIP, "create: stream sync failed"));

@@ -803,7 +803,7 @@ static hipError_t spmm_t_impl(const Batch &bt, int phase, hipStream_t s) {
 }
 
 hipError_t launch_spmm_t(Mode m, const Batch &bt, int phase, hipStream_t s) {
-    switch (bt.spmmt_wpr) {
+    switch (bt.spmmt_wpr[m]) {
         case 1: SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(bt.B, return (spmm_t_impl<MM, BB, 1>(bt, phase, s)))); break;
         case 2: SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(bt.B, return (spmm_t_impl<MM, BB, 2>(bt, phase, s)))); break;
         case 4: SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(bt.B, return (spmm_t_impl<MM, BB, 4>(bt, phase, s)))); break;

@@ -169,3 +169,30 @@ def test_graph_replay_matches_eager_launches(gpu):
         np.testing.assert_array_equal(eg, ee)
         np.testing.assert_array_equal(Zg, Ze)
         assert rg[0]["certified"] and re_[0]["certified"]
+
+
+def test_autotune_cache(gpu, tmp_path):
+    # tuning at create writes one line per arithmetic of the schedule; a second
+    # context with the same cache reuses the choices (same launch shapes, so
+    # the same result to the bit), and the tuned solve still matches the oracle
+    sb = gpu
+    prob = H.random_problem(n=30000, l=900, row_len_max=10, seed=31)
+    path = str(tmp_path / "tune.txt")
+    p = sb.Problem.from_arrays(prob["rowptr"], prob["col"], prob["val"], prob["W"])
+    with sb.Context([p], k=3, block=16, prec=sb.BF16_FP32, tune_cache=path) as ctx:
+        Z1, e1, r1, rc = ctx.embed()
+    lines = open(path).read().splitlines()
+    print("\n".join(lines), flush=True)
+    assert len(lines) == 3  # bf16, fp32 and the float64 certification
+    for ln in lines:
+        key, *vals = ln.split()
+        assert len(vals) == 4 and int(vals[3]) in (1, 2, 4)
+    assert rc == 0 and r1[0]["certified"]
+    lam, _, _ = H.oracle_for(prob, 3)
+    assert H.rel_eig_err(e1[0], lam[:3]) <= 1e-6
+    p = sb.Problem.from_arrays(prob["rowptr"], prob["col"], prob["val"], prob["W"])
+    with sb.Context([p], k=3, block=16, prec=sb.BF16_FP32, tune_cache=path) as ctx:
+        Z2, e2, _, _ = ctx.embed()
+    assert open(path).read().splitlines() == lines
+    np.testing.assert_array_equal(e1, e2)
+    np.testing.assert_array_equal(Z1, Z2)

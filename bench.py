@@ -162,14 +162,14 @@ def main():
     log("kernel timing pass")
     _, _, _, stats = time_form(sb, torch, prob, chosen_prec, args.steps, 1, k, block, flags=sb.FLAG_KERNEL_TIMING,
                               tune_cache=tune)
-    per = {s["name"]: s for s in stats}
+    # dominant bandwidth kernel of the timed form (per kernel and arithmetic)
     dom = max((s for s in stats if s["bytes_total"] > 0), key=lambda s: s["ms_total"])
     avg_ms = dom["ms_total"] / dom["launches"]
     bytes_per = dom["bytes_total"] / dom["launches"]
     achieved = bytes_per / (avg_ms * 1e-3) / 1e9
-    spmm = per.get("spmm")
-    spmm_gbs = spmm["bytes_total"] / (spmm["ms_total"] * 1e-3) / 1e9 if spmm else None
-    traffic = traffic_from_profiles(dom["name"])
+    spmm = [s for s in stats if s["name"].startswith("spmm.")]
+    spmm_gbs = (sum(s["bytes_total"] for s in spmm) / (sum(s["ms_total"] for s in spmm) * 1e-3) / 1e9) if spmm else None
+    traffic = traffic_from_profiles(dom["name"].replace(".", "_"))
 
     cpu = None
     if not args.no_cpu:
@@ -205,7 +205,9 @@ def main():
         "err_bound": max(repc["err_bound"][:k]),
         "spmm_hbm_frac": round(spmm_gbs / HBM_PEAK_GBS, 4) if spmm_gbs else None,
         "kernels": {s["name"]: {"avg_us": round(1e3 * s["ms_total"] / max(s["launches"], 1), 2),
-                                "launches_per_step": round(s["launches"] / args.steps, 2)} for s in stats},
+                                "launches_per_step": round(s["launches"] / args.steps, 2),
+                                **({"GB/s": round(s["bytes_total"] / (s["ms_total"] * 1e-3) / 1e9, 1)}
+                                   if s["bytes_total"] > 0 else {})} for s in stats},
         "roofline": {
             "kernel": dom["name"],
             "bound": "hbm",

@@ -427,10 +427,13 @@ int enqueue_iteration(sbmds_ctx *ctx, SolveSet &set, const PhaseRule &r) {
         f_sp += 2.0 * p.nnz * p.B;
         f_ge += 2.0 * (double)p.l * p.l * p.B;
     }
-    OKCHK(timed(ctx, "spmm_t", b_spmmt, f_sp, [&] { return launch_spmm_t(m, bt, r.phase, ctx->stream); }));
-    OKCHK(timed(ctx, "gemm", b_gemm, f_ge, [&] { return launch_gemm(m, bt, r.phase, ctx->stream); }));
-    OKCHK(timed(ctx, "spmm", b_spmm, f_sp, [&] { return launch_spmm(m, bt, r.phase, ctx->stream); }));
-    OKCHK(timed(ctx, "rr_solve", 0.0, 0.0, [&] { return launch_rr_solve(bt, 0, sweep_cap(r), r, ctx->stream); }));
+    static const char *const mname[NUM_MODES] = {"bf16", "fp32", "f64acc", "fp64"};
+    const std::string sfx = std::string(".") + mname[m];
+    OKCHK(timed(ctx, ("spmm_t" + sfx).c_str(), b_spmmt, f_sp, [&] { return launch_spmm_t(m, bt, r.phase, ctx->stream); }));
+    OKCHK(timed(ctx, ("gemm" + sfx).c_str(), b_gemm, f_ge, [&] { return launch_gemm(m, bt, r.phase, ctx->stream); }));
+    OKCHK(timed(ctx, ("spmm" + sfx).c_str(), b_spmm, f_sp, [&] { return launch_spmm(m, bt, r.phase, ctx->stream); }));
+    OKCHK(timed(ctx, ("rr_solve" + sfx).c_str(), 0.0, 0.0,
+                [&] { return launch_rr_solve(bt, 0, sweep_cap(r), r, ctx->stream); }));
     return SBMDS_OK;
 }
 

@@ -12,6 +12,8 @@
 // and s = c^T U (the outer centering term).  The last tile reduces those over
 // all tiles.  Every reduction runs in a fixed order, so results are bitwise
 // reproducible.
+#include <type_traits>
+
 #include "sbmds_common.h"
 
 namespace sbmds {
@@ -220,24 +222,31 @@ __global__ __launch_bounds__(256) void k_gemm_vec(const ProbView *__restrict__ v
 //   float32: v_mfma_f32_16x16x4f32, lane l supplies A[l%16][l/16], B[l/16][l%16]
 //   bf16:    v_mfma_f32_16x16x32_bf16, lane l supplies 8 consecutive k of
 //            row l%16 of A and of column l%16 of B (k offset 8 (l/16))
-// and holds D[4 (l/16) + r][l%16] in element r (both instructions).  The
-// split-K partials and the tile finish are those of k_gemm_vec.
+// and holds D[4 (l/16) + r][l%16] in element r (both instructions);
+//   float64 accumulation (the certification phase, float32 or float64 W
+//   widened on load): v_mfma_f64_16x16x4f64, operands as for float32, D
+//   element r of lane l is D[l/16 + 4 r][l%16].
+// The split-K partials and the tile finish are those of k_gemm_vec.
 // ---------------------------------------------------------------------------
 typedef float gm_f4 __attribute__((ext_vector_type(4)));
+typedef double gm_d4 __attribute__((ext_vector_type(4)));
 typedef __bf16 gm_bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int kMfmaRows = 64;  // rows of U per block
 constexpr int kMfmaK = 64;     // K per staged step
 
-bool gemm_mfma(Mode m, int B) { return (m == MODE_BF16 || m == MODE_FP32) && (B == 16 || B == 32); }
+bool gemm_mfma(Mode, int B) { return B == 16 || B == 32; }
 
 template <int M, int B>
 __global__ __launch_bounds__(256) void k_gemm_mfma(const ProbView *__restrict__ views, const int *__restrict__ off,
                                                    int nprob, int phase) {
     using Tr = Traits<M>;
+    using TA = typename Tr::TA;
     using TT = typename Tr::TT;
     using TW = typename Tr::TW;
     constexpr bool BF = (M == MODE_BF16);
+    constexpr bool F64 = sizeof(TA) == 8;
+    using AccV = typename std::conditional<F64, gm_d4, gm_f4>::type;
     constexpr int KS = kMfmaK, RT = kMfmaRows, NT = B / 16;
     constexpr int EPV = 16 / (int)sizeof(TW);  // elements per 16-byte load
     constexpr int PAD = EPV;                   // keeps 16-byte alignment of rows
@@ -255,16 +264,16 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const ProbView *__restrict__ 
     const int kchunk = v.gemm_kchunk[M];
     const TW *__restrict__ W = (const TW *)v.W[M];
     const TT *__restrict__ T = (const TT *)v.T;
-    float *__restrict__ part = (float *)v.gpart;
+    TA *__restrict__ part = (TA *)v.gpart;
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int rt = vb % rowtiles, ks = vb / rowtiles;
     const int r0 = rt * RT;
     const int kbeg = ks * kchunk, kend = min(lda, kbeg + kchunk);
 
-    gm_f4 acc[NT];
+    AccV acc[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = gm_f4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < NT; ++t) acc[t] = AccV{0, 0, 0, 0};
 
     // W slices are loaded one step ahead (registers), so the next slice is in
     // flight while the matrix cores work on the current one
@@ -313,6 +322,16 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const ProbView *__restrict__ 
                     acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
                 }
             }
+        } else if constexpr (F64) {
+#pragma unroll
+            for (int s = 0; s < KS / 4; ++s) {
+                const int kk = 4 * s + (lane >> 4);
+                const double a = (double)Ws[arow][kk];
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, (double)Ts[16 * t + (lane & 15)][kk], acc[t], 0, 0,
+                                                                  0);
+            }
         } else {
 #pragma unroll
             for (int s = 0; s < KS / 4; ++s) {
@@ -331,9 +350,9 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const ProbView *__restrict__ 
     for (int t = 0; t < NT; ++t) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int row = r0 + 16 * w + 4 * (lane >> 4) + r;
+            const int row = r0 + 16 * w + (F64 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r);
             const int j = 16 * t + (lane & 15);
-            if (row < l) st_coherent(part + ((size_t)ks * lda + row) * B + j, acc[t][r]);
+            if (row < l) st_coherent(part + ((size_t)ks * lda + row) * B + j, (TA)acc[t][r]);
         }
     }
     gemm_tile_finish<M, B, RT>(v, st, rt, rowtiles, ksplit);
@@ -370,8 +389,22 @@ hipError_t launch_gemm(Mode m, const Batch &bt, int phase, hipStream_t s) {
                 hipLaunchKernelGGL((k_gemm_vec<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase);
             }
             return hipGetLastError(); }); } break;
-        case MODE_F64ACC: { constexpr int MM = MODE_F64ACC; SBMDS_DISPATCH_B2(bt.B, hipLaunchKernelGGL((k_gemm_vec<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase); return hipGetLastError()); } break;
-        case MODE_FP64: { constexpr int MM = MODE_FP64; SBMDS_DISPATCH_B2(bt.B, hipLaunchKernelGGL((k_gemm_vec<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase); return hipGetLastError()); } break;
+        case MODE_F64ACC: { constexpr int MM = MODE_F64ACC; SBMDS_DISPATCH_B2(bt.B, {
+            if constexpr (BB == 16 || BB == 32) {
+                if (bt.gemm_mfma[MM]) hipLaunchKernelGGL((k_gemm_mfma<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase);
+                else hipLaunchKernelGGL((k_gemm_vec<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase);
+            } else {
+                hipLaunchKernelGGL((k_gemm_vec<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase);
+            }
+            return hipGetLastError(); }); } break;
+        case MODE_FP64: { constexpr int MM = MODE_FP64; SBMDS_DISPATCH_B2(bt.B, {
+            if constexpr (BB == 16 || BB == 32) {
+                if (bt.gemm_mfma[MM]) hipLaunchKernelGGL((k_gemm_mfma<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase);
+                else hipLaunchKernelGGL((k_gemm_vec<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase);
+            } else {
+                hipLaunchKernelGGL((k_gemm_vec<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase);
+            }
+            return hipGetLastError(); }); } break;
         default: break;
     }
     return hipErrorInvalidValue;

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace sbmds {
@@ -69,6 +70,11 @@ struct PhaseRule {
 
 enum SolveFlags { SF_REPAIRED = 1, SF_NONFINITE = 2 };
 
+// Bytes of SolveState from `theta` to the end: what the host reads after
+// each round (the Rayleigh-Ritz kernels write it to pinned host memory).
+constexpr size_t kSummaryOffset = offsetof(SolveState, theta);
+constexpr size_t kSummaryBytes = sizeof(SolveState) - offsetof(SolveState, theta);
+
 // Buffers and sizes of one problem on the device (host-side bookkeeping).
 struct DevProblem {
     int64_t n = 0, l = 0, nnz = 0;
@@ -127,6 +133,7 @@ struct ProbView {
     const void *X0;
     int64_t zoff;          // element offset of this problem's rows in the output Z
     int64_t loff;          // row offset of this problem's landmarks in per-landmark arrays
+    void *host_sum;        // pinned host copy of the SolveState tail from `theta` on (device pointer)
     int spmm_blocks[NUM_MODES];
     int gemm_rowtiles[NUM_MODES];
     int gemm_ksplit[NUM_MODES];

@@ -389,6 +389,8 @@ __global__ __launch_bounds__(RRShape<B>::NT) void k_rr_solve2(const ProbView *__
         phase_control(ctl, rule, init);
         store_ctl(st, ctl);
     }
+    __syncthreads();
+    publish_summary(st, views[blockIdx.x].host_sum);
 }
 
 hipError_t launch_rr_solve2(const Batch &bt, int init, int max_sweeps, const PhaseRule &rule, hipStream_t s) {

@@ -69,7 +69,7 @@ struct Summary {  // tail of SolveState read back after each iteration
     int sweeps_total, ymode;
     double hist[4];
 };
-static_assert(sizeof(Summary) == sizeof(SolveState) - offsetof(SolveState, theta), "summary layout");
+static_assert(sizeof(Summary) == kSummaryBytes, "summary layout");
 
 inline uint16_t host_f2bf(float f) {
     uint32_t u;
@@ -113,7 +113,8 @@ struct SolveSet {
     Tune tune[NUM_MODES];                      // launch choices per mode
     Batch bt;                                  // launch tables over all problems
     SolveState *st_all = nullptr;              // device, one per problem (contiguous)
-    Summary *host_sum = nullptr;               // pinned, one per problem
+    Summary *host_sum = nullptr;               // pinned, one per problem (written by the kernels)
+    void *host_sum_dev = nullptr;              // the same memory as the device sees it
     std::vector<int> expect;                   // iterations per phase seen in the last solve
     std::vector<int> cur_ybuf, cur_mode;       // current block per problem
     size_t zstage_bytes = 0;
@@ -323,7 +324,10 @@ Tune default_tune(Mode m, const std::vector<DevProblem> &probs) {
     }
     const int B = probs[0].B;
     t.spmm_cap = spmm_block_cap(m, B);
-    t.gemm_mfma = (gemm_mfma(m, B) && l2 * 4.0 > 64e6) ? 1 : 0;
+    // (float64-accumulating modes: the vector kernel carries half the rows
+    // per wave, so the matrix cores win at every size)
+    const bool f64 = m == MODE_F64ACC || m == MODE_FP64;
+    t.gemm_mfma = (gemm_mfma(m, B) && (f64 || l2 * 4.0 > 64e6)) ? 1 : 0;
     t.gemm_target = t.gemm_mfma ? 512 : 1024;
     const double per_row = nnz / l;  // mean entries per landmark column of P
     t.spmmt_wpr = per_row >= 256 ? 4 : (per_row >= 64 ? 2 : 1);
@@ -389,11 +393,10 @@ void collect_timing(sbmds_ctx *ctx) {
     ctx->pending.clear();
 }
 
+// The Rayleigh-Ritz kernels write each problem's summary into the pinned
+// host array themselves; the host only waits for the stream.
 int read_summaries(sbmds_ctx *ctx, SolveSet &set) {
-    const int np = (int)set.probs.size();
-    HIPCHK(hipMemcpy2DAsync(set.host_sum, sizeof(Summary),
-                            reinterpret_cast<const char *>(set.st_all) + offsetof(SolveState, theta), sizeof(SolveState),
-                            sizeof(Summary), np, hipMemcpyDeviceToHost, ctx->stream));
+    (void)set;
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return SBMDS_OK;
 }
@@ -922,6 +925,7 @@ int build_batch(sbmds_ctx *ctx, SolveSet &set) {
         v.X0 = p.X0;
         v.zoff = zoff;
         v.loff = loff;
+        v.host_sum = (char *)set.host_sum_dev + (size_t)i * sizeof(Summary);
         zoff += p.n * p.k;
         loff += p.l;
     }
@@ -966,9 +970,10 @@ int alloc_set(sbmds_ctx *ctx, SolveSet &set, int nprob) {
     set.cfg.resize(nprob);
     set.cur_ybuf.assign(nprob, 0);
     set.cur_mode.assign(nprob, schedule(ctx->opt).back().mode);
-    if (hipHostMalloc((void **)&set.host_sum, sizeof(Summary) * nprob, hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc((void **)&set.host_sum, sizeof(Summary) * nprob, hipHostMallocMapped) != hipSuccess)
         return fail(SBMDS_ENOMEM, "pinned host allocation failed");
     std::memset(set.host_sum, 0, sizeof(Summary) * nprob);
+    HIPCHK(hipHostGetDevicePointer(&set.host_sum_dev, set.host_sum, 0));
     OKCHK(dalloc(ctx, (void **)&set.st_all, sizeof(SolveState) * nprob));
     HIPCHK(hipMemsetAsync(set.st_all, 0, sizeof(SolveState) * nprob, ctx->stream));
     return SBMDS_OK;

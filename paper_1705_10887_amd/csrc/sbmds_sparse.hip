@@ -635,9 +635,17 @@ __global__ __launch_bounds__(256) void k_convert(const ProbView *__restrict__ vi
 __global__ void k_phase_begin(const ProbView *__restrict__ views, int phase, int mode) {
     SolveState *st = views[blockIdx.x].st;
     if (threadIdx.x == 0 && !st->done && st->phase == phase && st->pending_convert) {
-        st->ycur ^= 1;
+        const int ycur = st->ycur ^ 1;
+        st->ycur = ycur;
         st->ymode = mode;
         st->pending_convert = 0;
+        // the host copy of the state follows
+        char *h = (char *)views[blockIdx.x].host_sum;
+        if (h) {
+            *(int *)(h + offsetof(SolveState, ycur) - kSummaryOffset) = ycur;
+            *(int *)(h + offsetof(SolveState, ymode) - kSummaryOffset) = mode;
+            *(int *)(h + offsetof(SolveState, pending_convert) - kSummaryOffset) = 0;
+        }
     }
 }
 

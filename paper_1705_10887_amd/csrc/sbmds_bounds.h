@@ -126,7 +126,7 @@ __device__ inline void phase_control(Ctl &st, const PhaseRule &rule, int init) {
     // the block just produced (Y') becomes current; the basis the Ritz
     // vectors were taken from stays readable until the next SpMM overwrites it
     st.zbuf = st.ycur;
-    st.zmode = rule.mode;
+    st.zmode = st.ymode;  // the storage type of that block (a phase may start on the narrower one)
     st.ymode = rule.mode;
     st.ycur ^= 1;
     st.total_iters += 1;

@@ -404,15 +404,17 @@ int read_summaries(sbmds_ctx *ctx, SolveSet &set) {
 // Jacobi sweeps allowed per Rayleigh-Ritz step.  Inexact diagonalisation
 // keeps every reported bound valid (each Ritz value is the exact Rayleigh
 // quotient of the vector it belongs to, and its residual is measured), and
-// the next iteration continues the diagonalisation in the rotated basis;
-// the final phase, which may end the solve, diagonalises fully.
+// the next iteration continues the diagonalisation in the rotated basis.
+// The final phase starts from a nearly diagonal H (the previous phase
+// rotated the basis to its Ritz vectors), where three sweeps reach the
+// convergence test; non-final phases take one.
 int sweep_cap(const PhaseRule &r) {
     static int env = -1;
     if (env < 0) {
         const char *e = std::getenv("SBMDS_MAX_SWEEPS");
         env = e ? std::max(1, std::atoi(e)) : 0;
     }
-    if (r.is_final) return 40;
+    if (r.is_final) return 3;
     return env > 0 ? env : 1;
 }
 
@@ -458,8 +460,11 @@ int enqueue_round(sbmds_ctx *ctx, SolveSet &set, const std::vector<PhaseRule> &r
             const int ph = op.second;
             if (op.first) {
                 const Mode mf = (Mode)rules[ph - 1].mode, mt = (Mode)rules[ph].mode;
-                OKCHK(timed(ctx, "convert", 0.0, 0.0,
-                            [&] { return launch_convert_y(mf, mt, set.bt, ph, ctx->stream); }));
+                if (reads_previous_block(mf, mt))
+                    OKCHK(timed(ctx, "phase_enter", 0.0, 0.0, [&] { return launch_phase_enter(set.bt, ph, ctx->stream); }));
+                else
+                    OKCHK(timed(ctx, "convert", 0.0, 0.0,
+                                [&] { return launch_convert_y(mf, mt, set.bt, ph, ctx->stream); }));
             } else {
                 OKCHK(enqueue_iteration(ctx, set, rules[ph]));
             }

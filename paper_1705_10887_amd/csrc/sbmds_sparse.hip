@@ -17,6 +17,8 @@
 // problem p with off[p] <= b < off[p+1] and works on that problem's local
 // block b - off[p] of off[p+1] - off[p].  A problem whose schedule is not in
 // the launch's phase returns at once.
+#include <type_traits>
+
 #include "sbmds_common.h"
 
 namespace sbmds {
@@ -462,12 +464,11 @@ __global__ __launch_bounds__(kWideThreads) void k_gram_wide(const ProbView *__re
 // b x b basis rotation C.  WPR waves share one landmark row (its p + 1
 // entries are split over them); a 256-thread block covers 4 / WPR rows.
 // ---------------------------------------------------------------------------
-template <int M, int B, int WPR>
-__global__ __launch_bounds__(256) void k_spmm_t(const ProbView *__restrict__ views, const int *__restrict__ off,
-                                                int nprob, int phase) {
+template <int M, int B, int WPR, typename TY>
+__device__ __forceinline__ void spmm_t_body(const ProbView *__restrict__ views, const int *__restrict__ off,
+                                            int nprob, int phase) {
     using Tr = Traits<M>;
     using TA = typename Tr::TA;
-    using TY = typename Tr::TY;
     using TT = typename Tr::TT;
     using TP = typename Tr::TP;
     constexpr int VEC = VecOf<TY, B>::v;
@@ -550,6 +551,33 @@ __global__ __launch_bounds__(256) void k_spmm_t(const ProbView *__restrict__ vie
         for (int i = 0; i < B; ++i) t += rowbuf[rloc][i] * Cl[i * B + lane];
         T[(size_t)j * B + lane] = down<TT>((TA)t);
     }
+}
+
+// The block Y is read in the storage type of this arithmetic, or -- on the
+// first iteration after a precision change -- in the narrower type of the
+// previous phase (widening is exact), which saves a conversion pass over Y.
+template <int M>
+struct PrevY {
+    using T = typename Traits<M>::TY;
+};
+template <>
+struct PrevY<MODE_FP32> {
+    using T = bf16_t;
+};
+template <>
+struct PrevY<MODE_F64ACC> {
+    using T = float;
+};
+
+template <int M, int B, int WPR>
+__global__ __launch_bounds__(256) void k_spmm_t(const ProbView *__restrict__ views, const int *__restrict__ off,
+                                                int nprob, int phase) {
+    const int p = find_problem(off, nprob, blockIdx.x);
+    const int ymode = views[p].st->ymode;  // uniform in the block
+    if (ymode == M || std::is_same<typename PrevY<M>::T, typename Traits<M>::TY>::value)
+        spmm_t_body<M, B, WPR, typename Traits<M>::TY>(views, off, nprob, phase);
+    else
+        spmm_t_body<M, B, WPR, typename PrevY<M>::T>(views, off, nprob, phase);
 }
 
 // ---------------------------------------------------------------------------
@@ -647,6 +675,26 @@ __global__ void k_phase_begin(const ProbView *__restrict__ views, int phase, int
             *(int *)(h + offsetof(SolveState, pending_convert) - kSummaryOffset) = 0;
         }
     }
+}
+
+// Start of phase `phase` without a conversion pass (the next transposed SpMM
+// reads the narrower block directly): only the pending flag is cleared.
+__global__ void k_phase_enter(const ProbView *__restrict__ views, int phase) {
+    SolveState *st = views[blockIdx.x].st;
+    if (threadIdx.x == 0 && !st->done && st->phase == phase && st->pending_convert) {
+        st->pending_convert = 0;
+        char *h = (char *)views[blockIdx.x].host_sum;
+        if (h) *(int *)(h + offsetof(SolveState, pending_convert) - kSummaryOffset) = 0;
+    }
+}
+
+bool reads_previous_block(Mode from, Mode to) {
+    return (from == MODE_BF16 && to == MODE_FP32) || (from == MODE_FP32 && to == MODE_F64ACC);
+}
+
+hipError_t launch_phase_enter(const Batch &bt, int phase, hipStream_t s) {
+    hipLaunchKernelGGL(k_phase_enter, dim3(bt.nprob), dim3(64), 0, s, bt.views, phase);
+    return hipGetLastError();
 }
 
 __device__ __forceinline__ double load_y(const void *Y, int64_t i, int mode) {

@@ -192,6 +192,23 @@ __device__ __forceinline__ int find_problem(const int *__restrict__ off, int npr
     return lo;
 }
 
+// Workgroups are handed to the 8 XCDs of the device in turn (id mod 8).
+// For the G blocks [a, a + G) of one problem, returns a local index in
+// [0, G) such that each XCD gets a contiguous range of local indices (and so
+// of the rows they stand for), in launch order within the XCD.
+__device__ __forceinline__ int xcd_local_index(int g, int a, int G) {
+    const int x = g & 7;
+    int start = 0, first_x = 0;
+#pragma unroll
+    for (int xx = 0; xx < 8; ++xx) {
+        const int first = a + ((xx - (a & 7)) + 8) % 8;  // first id >= a on XCD xx
+        const int cnt = first >= a + G ? 0 : (a + G - 1 - first) / 8 + 1;
+        if (xx < x) start += cnt;
+        if (xx == x) first_x = first;
+    }
+    return start + (g - first_x) / 8;
+}
+
 __device__ __forceinline__ void tri_index(int ent, int B, int &a, int &b) {
     int r = ent, i = 0;
     while (r >= B - i) {

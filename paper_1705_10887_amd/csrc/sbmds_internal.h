@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace sbmds {
 
 // Arithmetic of one iteration.  Each mode fixes the storage type of the P
@@ -97,6 +99,7 @@ struct DevProblem {
     int max_rowtiles = 0, max_ksplit = 0, max_spmm_blocks = 0;
     SolveState *st = nullptr;
     const void *X0 = nullptr;    // device copy of a user start block
+    std::vector<int32_t> lperm;  // internal landmark order: internal j is caller's landmark lperm[j]
 };
 
 // Tunable launch choices of a batch in one mode (chosen by the autotuner or

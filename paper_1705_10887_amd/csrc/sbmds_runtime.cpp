@@ -22,6 +22,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <string>
 #include <utility>
@@ -806,11 +807,73 @@ int autotune(sbmds_ctx *ctx, SolveSet &set) {
     return SBMDS_OK;
 }
 
+// Internal landmark order: a recursive partition of the landmarks into the
+// cells of up to 8 pivots (the first members of the cell in the caller's
+// farthest-point order, so spread out), each landmark joining the cell of
+// its nearest pivot by W; cells of at most 64 landmarks keep their order.
+// Neighbouring internal indices are then spatially close, which the
+// transposed SpMM exploits.  The order is invisible outside: P's columns and
+// W are permuted together, which leaves B unchanged.
 template <typename T>
-int upload_problem(sbmds_ctx *ctx, const sbmds_problem &in, DevProblem &p, const int32_t *rp, const int32_t *ci,
-                   const T *val, bool fp64) {
+std::vector<int32_t> landmark_order(int64_t l, const T *W) {
+    std::vector<int32_t> order;
+    order.reserve(l);
+    std::vector<int32_t> all(l);
+    for (int64_t j = 0; j < l; ++j) all[j] = (int32_t)j;
+    std::function<void(const std::vector<int32_t> &, int)> part = [&](const std::vector<int32_t> &mem, int depth) {
+        if (mem.size() <= 64 || depth >= 12) {
+            order.insert(order.end(), mem.begin(), mem.end());
+            return;
+        }
+        const int np = 8;
+        std::vector<int32_t> piv(mem.begin(), mem.begin() + np);
+        std::vector<std::vector<int32_t>> cell(np);
+        for (int32_t m : mem) {
+            int best = 0;
+            double bd = (double)W[(size_t)m * l + piv[0]];
+            for (int c = 1; c < np; ++c) {
+                const double d = (double)W[(size_t)m * l + piv[c]];
+                if (d < bd) {
+                    bd = d;
+                    best = c;
+                }
+            }
+            cell[best].push_back(m);
+        }
+        for (int c = 0; c < np; ++c)
+            if (!cell[c].empty()) part(cell[c], depth + 1);
+    };
+    part(all, 0);
+    return order;
+}
+
+template <typename T>
+int upload_problem(sbmds_ctx *ctx, const sbmds_problem &in, DevProblem &p, const int32_t *rp, const int32_t *ci0,
+                   const T *val0, const T *Wh, bool fp64) {
     const int64_t n = p.n, l = p.l, nnz = p.nnz;
     hipStream_t s = ctx->stream;
+    // internal landmark order: relabel P's columns (rows re-sorted) and W
+    p.lperm = landmark_order<T>(l, Wh);
+    std::vector<int32_t> inv(l);
+    for (int64_t j = 0; j < l; ++j) inv[p.lperm[j]] = (int32_t)j;
+    std::vector<int32_t> cinew(nnz);
+    std::vector<T> valnew(nnz);
+    {
+        std::vector<std::pair<int32_t, T>> row;
+        for (int64_t i = 0; i < n; ++i) {
+            row.clear();
+            for (int32_t e = rp[i]; e < rp[i + 1]; ++e) row.push_back({inv[ci0[e]], val0[e]});
+            std::sort(row.begin(), row.end(), [](const std::pair<int32_t, T> &x, const std::pair<int32_t, T> &y) {
+                return x.first < y.first;
+            });
+            for (size_t q = 0; q < row.size(); ++q) {
+                cinew[rp[i] + q] = row[q].first;
+                valnew[rp[i] + q] = row[q].second;
+            }
+        }
+    }
+    const int32_t *ci = cinew.data();
+    const T *val = valnew.data();
     // transposed CSR and column sums on the host
     std::vector<int32_t> rpT, ciT;
     std::vector<T> valT;
@@ -836,8 +899,22 @@ int upload_problem(sbmds_ctx *ctx, const sbmds_problem &in, DevProblem &p, const
         HIPCHK(hipMemcpyAsync(vTd, valT.data(), nnz * sizeof(T), hipMemcpyHostToDevice, s));
     }
     HIPCHK(hipMemsetAsync(Wd, 0, (size_t)l * wbytes_row, s));
-    HIPCHK(hipMemcpy2DAsync(Wd, wbytes_row, in.W, (size_t)l * sizeof(T), (size_t)l * sizeof(T), l,
-                            in.mem == SBMDS_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    {
+        // W in the internal landmark order, uploaded in chunks of rows
+        const int64_t ch = std::max<int64_t>(1, std::min<int64_t>(l, (64 << 20) / ((int64_t)sizeof(T) * l)));
+        std::vector<T> buf((size_t)ch * l);
+        for (int64_t i0 = 0; i0 < l; i0 += ch) {
+            const int64_t rows = std::min(ch, l - i0);
+            for (int64_t r = 0; r < rows; ++r) {
+                const T *src = Wh + (size_t)p.lperm[i0 + r] * l;
+                T *dst = buf.data() + (size_t)r * l;
+                for (int64_t j = 0; j < l; ++j) dst[j] = src[p.lperm[j]];
+            }
+            HIPCHK(hipMemcpy2DAsync((char *)Wd + (size_t)i0 * wbytes_row, wbytes_row, buf.data(), (size_t)l * sizeof(T),
+                                    (size_t)l * sizeof(T), rows, hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));  // buf is reused
+        }
+    }
     std::vector<double> c = colsums<T>(l, rpT, valT);
     HIPCHK(hipMemcpyAsync(cd, c.data(), l * 8, hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));  // host vectors go out of scope
@@ -1094,7 +1171,9 @@ int setup_learned(sbmds_ctx *ctx, const sbmds_problem *probs, int nprob) {
         HIPCHK(hipMemcpyAsync(ctx->xyz[i], in.xyz, (size_t)in.n * 12,
                               in.mem == SBMDS_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                               ctx->stream));
-        HIPCHK(hipMemcpyAsync(ctx->lmv[i], hl.data(), (size_t)in.l * 4, hipMemcpyHostToDevice, ctx->stream));
+        std::vector<int32_t> hlp(in.l);  // in the internal landmark order
+        for (int64_t j = 0; j < in.l; ++j) hlp[j] = hl[ctx->main.probs[i].lperm[j]];
+        HIPCHK(hipMemcpyAsync(ctx->lmv[i], hlp.data(), (size_t)in.l * 4, hipMemcpyHostToDevice, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));  // hl goes out of scope
         maxl = std::max<int64_t>(maxl, in.l);
         ctx->total_l += in.l;
@@ -1191,8 +1270,9 @@ int create_impl(const sbmds_problem *probs, int nprob, const sbmds_options *opt_
                           : check_contents<float>(in, rp, ci, (const float *)val, (const float *)hW.data(), i);
             if (rc < 0) return cleanup(rc);
         }
-        int rc = fp64 ? upload_problem<double>(ctx, in, p, rp, ci, (const double *)val, true)
-                      : upload_problem<float>(ctx, in, p, rp, ci, (const float *)val, false);
+        const void *Wh = in.mem == SBMDS_MEM_DEVICE ? (const void *)hW.data() : in.W;
+        int rc = fp64 ? upload_problem<double>(ctx, in, p, rp, ci, (const double *)val, (const double *)Wh, true)
+                      : upload_problem<float>(ctx, in, p, rp, ci, (const float *)val, (const float *)Wh, false);
         if (rc < 0) return cleanup(rc);
 
         if ((rc = alloc_work(ctx, ctx->main, i)) < 0) return cleanup(rc);

@@ -484,7 +484,9 @@ __device__ __forceinline__ void spmm_t_body(const ProbView *__restrict__ views, 
     const ProbView &v = views[p];
     const SolveState *__restrict__ st = v.st;
     if (st->done || st->phase != phase) return;
-    const int vb = blockIdx.x - off[p];
+    // neighbouring landmark rows (the internal landmark order is spatial)
+    // stay on one XCD, so the rows of Y they gather are shared in its L2
+    const int vb = xcd_local_index(blockIdx.x, off[p], off[p + 1] - off[p]);
     const int l = v.l, n = v.n;
     const int32_t *__restrict__ rpT = v.rpT;
     const int32_t *__restrict__ ciT = v.ciT;

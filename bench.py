@@ -60,6 +60,44 @@ def time_form(sb, torch, prob, prec, steps, warmup, k, block, flags=0, start=Non
     return ms, eig[0], reps[0], stats
 
 
+def time_batch(sb, torch, probs, k, block, steps, warmup, tune_cache):
+    """ms per certified solve of all meshes in one context (every launch
+    covers every mesh) and of the same meshes one context each."""
+    dev = [{x: torch.from_numpy(p[x]).cuda() for x in ("rowptr", "col", "val", "W")} for p in probs]
+    ntot = sum(p["n"] for p in probs)
+
+    def run(groups):
+        ctxs, outs = [], []
+        for g in groups:
+            ps = [sb.Problem.from_arrays(dev[i]["rowptr"], dev[i]["col"], dev[i]["val"], dev[i]["W"]) for i in g]
+            ctxs.append(sb.Context(ps, k=k, block=block, prec=sb.FP32, tune_cache=tune_cache))
+            outs.append(torch.empty((sum(probs[i]["n"] for i in g), k), dtype=torch.float32, device="cuda"))
+        for _ in range(warmup):
+            for c, z in zip(ctxs, outs):
+                c.embed(Z_out=z)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for c, z in zip(ctxs, outs):
+                _, _, reps, rc = c.embed(Z_out=z)
+                if rc != 0:
+                    raise RuntimeError("a batched mesh did not certify")
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        for c in ctxs:
+            c.close()
+        return ms
+
+    ms_batch = run([list(range(len(probs)))])
+    ms_single = run([[i] for i in range(len(probs))])
+    return {"meshes": len(probs), "vertices": ntot, "ms": round(ms_batch, 3),
+            "meshes_per_s": round(len(probs) / (ms_batch * 1e-3), 1),
+            "vertices_per_s": round(ntot / (ms_batch * 1e-3), 1),
+            "ms_one_context_per_mesh": round(ms_single, 3), "dtype": "f32",
+            "workload": "16 meshes, n ~ U[2000, 20000] (bumpy tori and deformed geodesic spheres), l = n/50, "
+                        "p_row = 10, k = 3, fp32 -> f64 certify"}
+
+
 def cpu_baseline(prob, k, budget_s=20.0):
     """The float64 oracle (l x l reduction route) on the host cores."""
     import numpy as np
@@ -117,6 +155,7 @@ def main():
     ap.add_argument("--k", type=int, default=3)
     ap.add_argument("--block", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -171,6 +210,15 @@ def main():
     spmm_gbs = (sum(s["bytes_total"] for s in spmm) / (sum(s["ms_total"] for s in spmm) * 1e-3) / 1e9) if spmm else None
     traffic = traffic_from_profiles(dom["name"].replace(".", "_"))
 
+    # batched workload (reduced scale, not the headline): 16 meshes of uneven
+    # size in one context against the same meshes solved one context each
+    batched = None
+    if not args.no_batch:
+        log("batched workload")
+        batched = time_batch(sb, torch, configs.mesh_batch(log=log), k, block, args.steps, args.warmup,
+                             os.path.join(configs.cache_dir(), f"tune_batch16_k{k}_b{block}.txt"))
+        log(f"batched {batched}")
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle)")
@@ -219,6 +267,7 @@ def main():
             "bytes_per_launch": bytes_per,
         },
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
 

@@ -149,6 +149,39 @@ def bumpy_torus(nu, nv, l=None, p_row=10, seed=3003, use_cache=True, log=None):
     return _cached(f"bumpy_torus{nu}x{nv}", params, make, use_cache, log)
 
 
+def mesh_batch(count=16, nmin=2000, nmax=20000, seed0=4004, p_row=10, use_cache=True, log=None):
+    """Many meshes of uneven size (the batched workload's recipe at reduced
+    scale): n_i ~ U[nmin, nmax] from default_rng(seed0); even i is a bumpy
+    torus with n_v = round(sqrt(n_i / 2)), n_u = round(n_i / n_v); odd i is a
+    class-I geodesic sphere of frequency round(sqrt((n_i - 2) / 10)) with the
+    radial spherical-harmonic deformation of sphere7; l_i = round(n_i / 50),
+    seed seed0 + i for the mesh and its landmarks."""
+    rng = np.random.default_rng(seed0)
+    sizes = rng.integers(nmin, nmax + 1, size=count)
+    out = []
+    for i, ni in enumerate(sizes):
+        seed = seed0 + i
+        if i % 2 == 0:
+            nv = max(3, int(round(np.sqrt(ni / 2))))
+            nu = max(3, int(round(ni / nv)))
+            prob = bumpy_torus(nu, nv, l=max(2, int(round(nu * nv / 50))), p_row=p_row, seed=seed,
+                               use_cache=use_cache, log=log)
+        else:
+            freq = max(1, int(round(np.sqrt((ni - 2) / 10))))
+            n = 10 * freq * freq + 2
+            l = max(2, int(round(n / 50)))
+            params = dict(freq=freq, l=l, p_row=p_row, seed=seed, v=1)
+
+            def make(freq=freq, l=l, seed=seed):
+                V, F = meshes.geodesic_sphere(freq)
+                V = meshes._radial_deform(V, seed, 0.05, 8, 6)
+                return build_problem(V, F, l, p_row, seed, np.float32, log=log)
+
+            prob = _cached(f"geosphere{freq}", params, make, use_cache, log)
+        out.append(prob)
+    return out
+
+
 def load(name: str, **kw):
     return PRESETS[name](**kw)
 

@@ -99,3 +99,23 @@ def test_batch_device_output(gpu):
     assert rc == 0
     np.testing.assert_array_equal(ed, eh)
     np.testing.assert_array_equal(Zd.cpu().numpy(), Zh)
+
+
+@pytest.mark.parametrize("prec", ["FP32", "BF16_FP32"])
+def test_mesh_batch_matches_oracle(gpu, prec):
+    # the batched workload's recipe at reduced scale: 16 bumpy tori and
+    # deformed geodesic spheres of 2k-20k vertices, l = n/50, in one context
+    from synth import configs
+    sb = gpu
+    probs = configs.mesh_batch()
+    Z, eig, reps, rc, _ = solve(sb, probs, getattr(sb, prec))
+    assert rc == 0
+    worst = 0.0
+    for i, (p, Zi) in enumerate(zip(probs, split_rows(Z, probs))):
+        lam, V, _ = H.oracle_for(p, 3)
+        err = H.rel_eig_err(eig[i], lam[:3])
+        worst = max(worst, err)
+        assert reps[i]["certified"], (i, reps[i])
+        assert err <= 1e-6, (i, p["n"], eig[i], lam[:3])
+        assert H.subspace_angle(Zi, V, lam, 3, tol=1e-6) <= 3.0, i
+    print(f"{prec}: 16 meshes, worst rel eig err {worst:.2e}", flush=True)

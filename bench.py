@@ -10,9 +10,12 @@ generated from fixed seeds (cached on disk after the first run).
 
 A step is one sbmds_embed call on device-resident inputs: start block,
 all iterations of the precision schedule up to the certified 1e-6 bound,
-and the embedding Z (left on the device).  Two forms are timed on the same
-GPU: the chosen form (bf16 bulk iterations, fp32 refinement, float64
-certification) and the plain fp32 form (fp32 iterations, same certification).
+and the embedding Z (left on the device).  Four forms are timed on the same
+GPU, each to the same certified bound: plain fp32 iterations from a random
+start, bf16 bulk iterations refined in fp32, and fp32 iterations from the
+landmark-MDS start and from the learned start (a network trained first, on
+the GPU, on 12 smaller meshes of the same family).  The fastest is the chosen
+form and gives `value`; the plain fp32 time is reported beside it.
 
 Prints one JSON line.  Only one GPU is used; --gpus above 1 is refused.
 """
@@ -34,11 +37,19 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def time_form(sb, torch, prob, prec, steps, warmup, k, block, flags=0, start=None, tune_cache=None):
-    p = sb.Problem.from_arrays(*(torch.from_numpy(prob[x]).cuda() for x in ("rowptr", "col", "val", "W")))
+def time_form(sb, torch, prob, prec, steps, warmup, k, block, flags=0, start=None, tune_cache=None,
+              mlp_weights=None):
+    import numpy as np
+    geo = {}
+    if start in (sb.START_LMDS, sb.START_LEARNED):
+        geo = {"xyz": torch.from_numpy(prob["V"].astype(np.float32)).cuda(),
+               "landmark_vertex": torch.from_numpy(prob["landmarks"].astype(np.int32)).cuda()}
+    p = sb.Problem.from_arrays(*(torch.from_numpy(prob[x]).cuda() for x in ("rowptr", "col", "val", "W")), **geo)
     kw = {}
     if start is not None:
         kw["start"] = start
+    if mlp_weights is not None:
+        kw["mlp_weights"] = mlp_weights
     t0 = time.perf_counter()
     ctx = sb.Context([p], k=k, block=block, prec=prec, flags=flags, tune_cache=tune_cache, **kw)
     log(f"create (upload, transpose, copies{', autotune' if tune_cache else ''}) {1e3 * (time.perf_counter() - t0):.1f} ms")
@@ -96,6 +107,37 @@ def time_batch(sb, torch, probs, k, block, steps, warmup, tune_cache):
             "ms_one_context_per_mesh": round(ms_single, 3), "dtype": "f32",
             "workload": "16 meshes, n ~ U[2000, 20000] (bumpy tori and deformed geodesic spheres), l = n/50, "
                         "p_row = 10, k = 3, fp32 -> f64 certify"}
+
+
+FORM_NAMES = {
+    "fp32": "fp32 -> f64 certify, random start",
+    "bf16_fp32": "bf16 -> fp32 -> f64 certify, random start",
+    "fp32_lmds": "fp32 -> f64 certify, landmark-MDS start",
+    "fp32_learned": "fp32 -> f64 certify, learned start",
+}
+
+
+def train_start_net(sb, torch, configs, k, block):
+    """Train the warm-start network on 12 smaller meshes of the benchmark's
+    family (level-5 icospheres with the same kind of deformation, other
+    seeds), on targets the solver produces; returns the weights file."""
+    from paper_1705_10887_amd import mlp
+
+    t0 = time.perf_counter()
+    meshes = configs.sphere_family(log=log)
+    for m in meshes:
+        m["landmarks"] = m["landmarks"].astype("int32")
+        m["xyz"] = m["V"].astype("float32")
+    targets = mlp.solve_targets(meshes, k=k, block=block)
+    feats = [mlp.features(m["xyz"], m["landmarks"], m["W"]) for m in meshes]
+    net, losses = mlp.train(feats, targets, k=k, steps=600, lr=3e-3, seed=0)
+    path = os.path.join(configs.cache_dir(), f"mlp_sphere5_k{k}.bin")
+    net.save(path)
+    net.close()
+    torch.cuda.synchronize()
+    log(f"trained start network: loss {losses[0]:.3e} -> {losses[-1]:.3e} "
+        f"({len(meshes)} meshes, {1e3 * (time.perf_counter() - t0):.0f} ms incl. target solves)")
+    return path
 
 
 def cpu_baseline(prob, k, budget_s=20.0):
@@ -156,6 +198,7 @@ def main():
     ap.add_argument("--block", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the landmark-MDS and learned-start forms")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -187,20 +230,30 @@ def main():
     torch.cuda.set_device(0)
     k, block = args.k, args.block
     tune = os.path.join(configs.cache_dir(), f"tune_sphere7_k{k}_b{block}.txt")
-    log("timing plain fp32")
-    ms_fp32, eig32, rep32, _ = time_form(sb, torch, prob, sb.FP32, args.steps, args.warmup, k, block, tune_cache=tune)
-    log(f"plain fp32 {ms_fp32:.3f} ms  iters {rep32['iters_fp32']}+{rep32['iters_fp64']}")
-    log("timing chosen (bf16 -> fp32 -> fp64 certify)")
-    ms_ch, eigc, repc, _ = time_form(sb, torch, prob, sb.BF16_FP32, args.steps, args.warmup, k, block, tune_cache=tune)
-    log(f"chosen {ms_ch:.3f} ms  iters {repc['iters_bf16']}+{repc['iters_fp32']}+{repc['iters_fp64']}")
-    chosen_prec = sb.BF16_FP32
-    value = ms_ch
-    if ms_fp32 < ms_ch:
-        # the schedule that certifies fastest is the chosen one
-        chosen_prec, value, eigc, repc = sb.FP32, ms_fp32, eig32, rep32
+    forms = {}
+
+    def run_form(name, prec, start=None, weights=None):
+        log(f"timing {name}")
+        ms, eig, rep, _ = time_form(sb, torch, prob, prec, args.steps, args.warmup, k, block, start=start,
+                                    tune_cache=tune, mlp_weights=weights)
+        forms[name] = {"ms": ms, "eig": eig, "rep": rep, "prec": prec, "start": start, "weights": weights}
+        log(f"{name} {ms:.3f} ms  iters {rep['iters_bf16']}+{rep['iters_fp32']}+{rep['iters_fp64']}"
+            f"  start iters {rep['start_iters']}")
+
+    run_form("fp32", sb.FP32)
+    run_form("bf16_fp32", sb.BF16_FP32)
+    if not args.no_learned:
+        run_form("fp32_lmds", sb.FP32, sb.START_LMDS)
+        weights = train_start_net(sb, torch, configs, k, block)
+        run_form("fp32_learned", sb.FP32, sb.START_LEARNED, weights)
+    # the form that certifies fastest is the chosen one
+    chosen = min(forms, key=lambda f: forms[f]["ms"])
+    ch = forms[chosen]
+    value, eigc, repc, chosen_prec = ch["ms"], ch["eig"], ch["rep"], ch["prec"]
+    ms_fp32 = forms["fp32"]["ms"]
     log("kernel timing pass")
     _, _, _, stats = time_form(sb, torch, prob, chosen_prec, args.steps, 1, k, block, flags=sb.FLAG_KERNEL_TIMING,
-                              tune_cache=tune)
+                               start=ch["start"], tune_cache=tune, mlp_weights=ch["weights"])
     # dominant bandwidth kernel of the timed form (per kernel and arithmetic)
     dom = max((s for s in stats if s["bytes_total"] > 0), key=lambda s: s["ms_total"])
     avg_ms = dom["ms_total"] / dom["launches"]
@@ -245,11 +298,13 @@ def main():
             "workload": "sphere7: icosphere level 7 (n=163842) deformed by 8 seeded spherical harmonics, "
                         "l=2000 FPS landmarks, p_row=10 (nnz=1620000), W=D^2_ll float32",
             "n": int(prob["n"]), "l": int(prob["l"]), "nnz": int(len(prob["col"])), "k": k, "block": block,
-            "chosen": "bf16->fp32->f64 certify" if chosen_prec == sb.BF16_FP32 else "fp32->f64 certify",
+            "chosen": FORM_NAMES[chosen],
         },
         "plain_fp32_ms": round(ms_fp32, 4),
         "chosen_over_plain": round(ms_fp32 / value, 3),
-        "iters": {"bf16": repc["iters_bf16"], "fp32": repc["iters_fp32"], "fp64": repc["iters_fp64"]},
+        "forms_ms": {f: round(v["ms"], 4) for f, v in forms.items()},
+        "iters": {"bf16": repc["iters_bf16"], "fp32": repc["iters_fp32"], "fp64": repc["iters_fp64"],
+                  "start": repc["start_iters"]},
         "err_bound": max(repc["err_bound"][:k]),
         "spmm_hbm_frac": round(spmm_gbs / HBM_PEAK_GBS, 4) if spmm_gbs else None,
         "kernels": {s["name"]: {"avg_us": round(1e3 * s["ms_total"] / max(s["launches"], 1), 2),

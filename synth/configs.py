@@ -182,6 +182,25 @@ def mesh_batch(count=16, nmin=2000, nmax=20000, seed0=4004, p_row=10, use_cache=
     return out
 
 
+def sphere_family(count=12, level=5, seed0=7001, p_row=10, use_cache=True, log=None):
+    """Training meshes for the learned start on the sphere7 workload: icospheres
+    of the given level with sphere7's radial deformation (seeds seed0 ..
+    seed0 + count - 1, all different from sphere7's), l = round(n / 50)."""
+    out = []
+    for i in range(count):
+        seed = seed0 + i
+        V0, F = meshes.icosphere(level)
+        l = max(2, int(round(V0.shape[0] / 50)))
+        params = dict(level=level, l=l, p_row=p_row, seed=seed, v=1)
+
+        def make(seed=seed, l=l):
+            V, F2 = meshes.deformed_icosphere(level, seed)
+            return build_problem(V, F2, l, p_row, seed, np.float32, log=log)
+
+        out.append(_cached(f"sphere{level}", params, make, use_cache, log))
+    return out
+
+
 def load(name: str, **kw):
     return PRESETS[name](**kw)
 

@@ -68,7 +68,8 @@ typedef enum {
 typedef enum {
     SBMDS_START_RANDOM = 0, /* seeded Gaussian block (counter-based generator) */
     SBMDS_START_LMDS = 1,   /* landmark MDS of W lifted through P */
-    SBMDS_START_LEARNED = 2,/* MLP prediction from landmark features, lifted through P */
+    SBMDS_START_LEARNED = 2,/* MLP prediction from landmark features, lifted through P;
+                               the prediction is made once, in sbmds_create */
     SBMDS_START_USER = 3    /* caller-supplied block (sbmds_problem.X0), e.g. to resume */
 } sbmds_start;
 

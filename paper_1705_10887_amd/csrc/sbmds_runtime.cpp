@@ -606,19 +606,9 @@ int solve_all(sbmds_ctx *ctx, sbmds_report *reps) {
                         [&] { return launch_lift_prep(m0, set.bt, &ctx->lmk.bt, nullptr, o.seed, ctx->stream); }));
             OKCHK(timed(ctx, "lift", 0.0, 0.0, [&] { return launch_spmm(m0, set.bt, 0, ctx->stream); }));
         } else if (o.start == SBMDS_START_LEARNED) {
-            // network prediction on the landmarks (first k columns, the rest
-            // Gaussian), lifted through P
-            int64_t loff = 0;
-            for (int i = 0; i < np; ++i) {
-                const DevProblem &p = set.probs[i];
-                const Mode wm = o.prec == SBMDS_FP64 ? MODE_FP64 : MODE_FP32;
-                OKCHK(timed(ctx, "features", 0.0, 0.0, [&] {
-                    return mlp::launch_features(p.W[wm], wm == MODE_FP64 ? 1 : 0, p.l, p.lda, ctx->xyz[i],
-                                                ctx->lmv[i], ctx->feat + loff * mlp::kIn, ctx->rowmax, ctx->stream);
-                }));
-                loff += p.l;
-            }
-            OKCHK(mlp::forward_device(ctx->net, ctx->feat, ctx->total_l, ctx->learned));
+            // the network's landmark prediction (made at create: it depends
+            // on the inputs and the weights only) as the first k columns, the
+            // rest Gaussian, lifted through P
             OKCHK(timed(ctx, "lift", 0.0, 0.0,
                         [&] { return launch_lift_prep(m0, set.bt, nullptr, ctx->learned, o.seed, ctx->stream); }));
             OKCHK(timed(ctx, "lift", 0.0, 0.0, [&] { return launch_spmm(m0, set.bt, 0, ctx->stream); }));
@@ -1181,6 +1171,17 @@ int setup_learned(sbmds_ctx *ctx, const sbmds_problem *probs, int nprob) {
     OKCHK(dalloc(ctx, (void **)&ctx->feat, (size_t)ctx->total_l * mlp::kIn * 4));
     OKCHK(dalloc(ctx, (void **)&ctx->learned, (size_t)ctx->total_l * ctx->opt.k * 4));
     OKCHK(dalloc(ctx, (void **)&ctx->rowmax, (size_t)maxl * 8));
+    // the prediction itself: features of each problem's landmarks, then one
+    // forward pass over all of them
+    const Mode wm = ctx->opt.prec == SBMDS_FP64 ? MODE_FP64 : MODE_FP32;
+    int64_t loff = 0;
+    for (int i = 0; i < nprob; ++i) {
+        const DevProblem &p = ctx->main.probs[i];
+        OKCHK(mlp::launch_features(p.W[wm], wm == MODE_FP64 ? 1 : 0, p.l, p.lda, ctx->xyz[i], ctx->lmv[i],
+                                   ctx->feat + loff * mlp::kIn, ctx->rowmax, ctx->stream));
+        loff += p.l;
+    }
+    OKCHK(mlp::forward_device(ctx->net, ctx->feat, ctx->total_l, ctx->learned));
     return SBMDS_OK;
 }
 

@@ -10,13 +10,17 @@
 //      once).  A rotation leaves a 2 x 2 block of H (rows of one pair,
 //      columns of another) depending only on that block, so each thread
 //      computes its element(s) from four values of the previous round's
-//      matrix (ping-pong buffers, one barrier per round).
+//      matrix (ping-pong buffers).  The rotations of round m + 1 need only
+//      three entries per pair of the matrix round m produces; the first wave
+//      computes those entries from the same old values and the next
+//      rotations in the same step, so a round costs one barrier and one
+//      rotation latency.
 //   2. Ritz values sorted descending (padding columns last), Zmap = C S_k
 //      Theta_k^{1/2}, residuals ||B x_i - theta_i x_i||^2 = s_i^T Gc s_i -
 //      theta_i^2, error bounds per gap-separated cluster (one thread per
 //      Ritz value).
-//   3. S^T Gc S = L L^T (left-looking, one row per thread) and C' = S L^{-T}
-//      (one row per thread).
+//   3. S^T Gc S = L L^T (right-looking, in place, one element per thread and
+//      one barrier per pivot) and C' = S L^{-T} (one row per thread).
 // In `init` mode only step 3 runs, with S = I.
 #include "sbmds_bounds.h"
 
@@ -36,8 +40,8 @@ struct RRLds {
     double Cold[B][B + 1];  // basis transform H was computed with
     double S[B][B + 1];     // sorted Ritz vectors
     double GS[B][B + 1];    // Gc S, then the Cholesky factor
-    double rc[B], rs[B];    // rotation of each index's pair in the current round
-    double e_new[B], e_x[B], th[B], res[B], linv[B], w[B];
+    double2 rot[2][B];      // rotation of a round per index i: (c, -s) if i is the lower index of its pair, else (c, s)
+    double e_new[B], e_x[B], th[B], res[B], linv[B], w[B], gd[B];
     double bnd[B], rres[B];
     double red[2][8];
     int perm[B], dead[B], nonpos[B];
@@ -56,6 +60,30 @@ __device__ __forceinline__ double rr_block_sum(double v, double (&red)[8]) {
 #pragma unroll
     for (int i = 0; i < NW; ++i) s += red[i];
     return s;
+}
+
+template <int NT>
+__device__ __forceinline__ void rr_block_sum2(double &a, double &c, double (&red)[2][8]) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        a += __shfl_xor(a, m);
+        c += __shfl_xor(c, m);
+    }
+    constexpr int NW = (NT + 63) / 64;
+    if (NW == 1) return;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = a;
+        red[1][threadIdx.x >> 6] = c;
+    }
+    __syncthreads();
+    a = 0.0;
+    c = 0.0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        a += red[0][i];
+        c += red[1][i];
+    }
 }
 
 // 1/sqrt(x) for normal positive x: hardware estimate and two Newton steps
@@ -85,6 +113,84 @@ __device__ __forceinline__ void pair_rotation(double app, double aqq, double apq
     const double cc = rsqrt_nr(1.0 + t * t);
     c = rot ? cc : 1.0;
     s = rot ? t * cc : 0.0;
+}
+
+// Entry (i, j) after one round of rotations.  Row i of the rotated matrix is
+// c_i row_i + t_i row_{i^m} with (c_i, t_i) the rotation stored for index i
+// (t_i = -s for the lower index of the pair, +s for the upper), and the same
+// for columns; a_ij = A[i][j], a_pj = A[i^m][j], a_ip = A[i][j^m], a_pp =
+// A[i^m][j^m].
+__device__ __forceinline__ double rotate_entry(double2 ri, double2 rj, double a_ij, double a_pj, double a_ip,
+                                               double a_pp) {
+    return rj.x * (ri.x * a_ij + ri.y * a_pj) + rj.y * (ri.x * a_ip + ri.y * a_pp);
+}
+
+// Lower index of pair t of round m (m in [1, B)): pairs {p, p ^ m} with the
+// highest set bit of m clear in p.
+__device__ __forceinline__ int round_pair_low(int t, int m) {
+    const int hb = 31 - __builtin_clz(m);
+    return ((t >> hb) << (hb + 1)) | (t & ((1 << hb) - 1));
+}
+
+// One Jacobi round m on the buffers of parity CUR (a compile-time constant,
+// so every LDS address is a register plus an immediate).  Every thread
+// rotates its element(s) of H and of the accumulated rotations.  With NEXT
+// (every round of a sweep but the last) each thread also forms the entries
+// (p, p), (q, q), (p, q) of the rotated H for pair tp = {p, q} of round
+// m + 1 and that pair's rotation, from the same old values, and the first
+// B / 2 threads store it: a round needs one barrier.
+template <int B, int NT, int EPT, int CUR, bool NEXT>
+__device__ __forceinline__ void jacobi_round(RRLds<B> &L, int tid, int m, int tp) {
+    const double(*Ac)[B + 1] = L.A[CUR];
+    const double(*Vc)[B + 1] = L.V[CUR];
+    const double2 *rot = L.rot[CUR];
+    // all reads of the round come before its writes (the compiler cannot
+    // tell the two parities apart through the row pointers)
+    int p = 0, q = 0;
+    double2 rp{}, rq{};
+    double pp[4], qq[4], pq[4];
+    if (NEXT) {
+        p = round_pair_low(tp, m + 1);
+        q = p ^ (m + 1);
+        const int pm = p ^ m, qm = q ^ m;
+        rp = rot[p];
+        rq = rot[q];
+        pp[0] = Ac[p][p], pp[1] = Ac[pm][p], pp[2] = Ac[p][pm], pp[3] = Ac[pm][pm];
+        qq[0] = Ac[q][q], qq[1] = Ac[qm][q], qq[2] = Ac[q][qm], qq[3] = Ac[qm][qm];
+        pq[0] = Ac[p][q], pq[1] = Ac[pm][q], pq[2] = Ac[p][qm], pq[3] = Ac[pm][qm];
+    }
+    double an[EPT], vn[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const int e = tid + k * NT;
+        an[k] = vn[k] = 0.0;
+        if (e < B * B) {
+            const int i = e / B, j = e % B, im = i ^ m, jm = j ^ m;
+            const double2 ri = rot[i], rj = rot[j];
+            an[k] = rotate_entry(ri, rj, Ac[i][j], Ac[im][j], Ac[i][jm], Ac[im][jm]);
+            vn[k] = rj.x * Vc[i][j] + rj.y * Vc[i][jm];
+        }
+    }
+    double c = 1.0, sn = 0.0;
+    if (NEXT) {
+        const double app = rotate_entry(rp, rp, pp[0], pp[1], pp[2], pp[3]);
+        const double aqq = rotate_entry(rq, rq, qq[0], qq[1], qq[2], qq[3]);
+        const double apq = rotate_entry(rp, rq, pq[0], pq[1], pq[2], pq[3]);
+        pair_rotation(app, aqq, apq, c, sn);
+    }
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const int e = tid + k * NT;
+        if (e < B * B) {
+            L.A[CUR ^ 1][e / B][e % B] = an[k];
+            L.V[CUR ^ 1][e / B][e % B] = vn[k];
+        }
+    }
+    if (NEXT && tid < B / 2) {
+        L.rot[CUR ^ 1][p] = double2{c, -sn};
+        L.rot[CUR ^ 1][q] = double2{c, sn};
+    }
+    __syncthreads();
 }
 
 template <int B>
@@ -130,13 +236,16 @@ __global__ __launch_bounds__(RRShape<B>::NT) void k_rr_solve2(const ProbView *__
         const int e = tid + q * NT;
         if (e < B * B) {
             const int i = e / B, j = e % B;
-            L.G[i][j] = graw[q] - L.e_new[i] * L.e_new[j] * inv_n;
+            const double g = graw[q] - L.e_new[i] * L.e_new[j] * inv_n;
+            L.G[i][j] = g;
+            if (i == j) L.gd[i] = g;  // pivot reference of the init factorisation
         }
     }
 
     int cur = 0;
     if (!init) {
         // ---- 1. Jacobi
+        const int tp = tid % (B / 2);  // pair whose next rotation this thread forms
         int sweep = 0;
         for (; sweep < max_sweeps; ++sweep) {
             double off = 0.0, dia = 0.0;
@@ -150,37 +259,25 @@ __global__ __launch_bounds__(RRShape<B>::NT) void k_rr_solve2(const ProbView *__
                     else off += a * a;
                 }
             }
-            off = rr_block_sum<NT>(off, L.red[0]);
-            dia = rr_block_sum<NT>(dia, L.red[1]);
+            if (tid < B / 2) {
+                // rotations of round 1
+                const int p = round_pair_low(tp, 1), qq = p ^ 1;
+                double c, sn;
+                pair_rotation(L.A[cur][p][p], L.A[cur][qq][qq], L.A[cur][p][qq], c, sn);
+                L.rot[cur][p] = double2{c, -sn};
+                L.rot[cur][qq] = double2{c, sn};
+            }
+            rr_block_sum2<NT>(off, dia, L.red);
+            __syncthreads();  // rotations of round 1 visible (the sum has no barrier for one wave)
             if (!(off > 1e-24 * dia) || dia == 0.0) break;
-            for (int m = 1; m < B; ++m) {
-                // every thread computes the rotations of its own row and
-                // column pairs from the current matrix; one barrier per round
-                const int j = tid % B;
-                const int lj = min(j, j ^ m), hj = lj ^ m;
-                double cj, sj;
-                pair_rotation(L.A[cur][lj][lj], L.A[cur][hj][hj], L.A[cur][lj][hj], cj, sj);
-#pragma unroll
-                for (int q = 0; q < EPT; ++q) {
-                    const int e = tid + q * NT;
-                    if (e < B * B) {
-                        const int i = e / B;
-                        const int li = min(i, i ^ m), hi_ = li ^ m;
-                        double ci, si;
-                        pair_rotation(L.A[cur][li][li], L.A[cur][hi_][hi_], L.A[cur][li][hi_], ci, si);
-                        const double a00 = L.A[cur][li][lj], a01 = L.A[cur][li][hj];
-                        const double a10 = L.A[cur][hi_][lj], a11 = L.A[cur][hi_][hj];
-                        // rows of the pair of i, then columns of the pair of j
-                        const double r0 = (i == li) ? (ci * a00 - si * a10) : (si * a00 + ci * a10);
-                        const double r1 = (i == li) ? (ci * a01 - si * a11) : (si * a01 + ci * a11);
-                        L.A[cur ^ 1][i][j] = (j == lj) ? (cj * r0 - sj * r1) : (sj * r0 + cj * r1);
-                        const double v0 = L.V[cur][i][lj], v1 = L.V[cur][i][hj];
-                        L.V[cur ^ 1][i][j] = (j == lj) ? (cj * v0 - sj * v1) : (sj * v0 + cj * v1);
-                    }
-                }
-                __syncthreads();
+            for (int m = 1; m < B - 1; ++m) {
+                if (cur == 0) jacobi_round<B, NT, EPT, 0, true>(L, tid, m, tp);
+                else jacobi_round<B, NT, EPT, 1, true>(L, tid, m, tp);
                 cur ^= 1;
             }
+            if (cur == 0) jacobi_round<B, NT, EPT, 0, false>(L, tid, B - 1, tp);
+            else jacobi_round<B, NT, EPT, 1, false>(L, tid, B - 1, tp);
+            cur ^= 1;
         }
         if (tid == 0) ctl.sweeps = sweep;
         // ---- 2. sort (padding columns last), Ritz vectors
@@ -299,7 +396,10 @@ __global__ __launch_bounds__(RRShape<B>::NT) void k_rr_solve2(const ProbView *__
 #pragma unroll
         for (int q = 0; q < EPT; ++q) {
             const int e = tid + q * NT;
-            if (e < B * B) L.G[e / B][e % B] = sg[q];
+            if (e < B * B) {
+                L.G[e / B][e % B] = sg[q];
+                if (e / B == e % B) L.gd[e / B] = sg[q];
+            }
         }
     } else {
 #pragma unroll
@@ -313,46 +413,48 @@ __global__ __launch_bounds__(RRShape<B>::NT) void k_rr_solve2(const ProbView *__
     }
     __syncthreads();
 
-    // ---- 3. left-looking Cholesky of G: thread j keeps row j of the factor
-    // in registers and publishes each new entry in GS[j][m], so that row m
-    // is readable by all at step m (one barrier per step).  Pivot m is dead
-    // (its column dropped) for padding columns or when it lost its relative
-    // size.
+    // ---- 3. right-looking Cholesky of G, in place: at pivot m every thread
+    // forms column m of the factor from the updated column m of G (into GS)
+    // and downdates its own trailing element(s); one barrier per pivot.
+    // Pivot m is dead (its column dropped) for padding columns or when it
+    // lost its relative size against the diagonal it started from.
     int ndead = 0;
-    {
-        const int j = tid < B ? tid : 0;
-        double lrow[B];
 #pragma unroll
-        for (int t = 0; t < B; ++t) lrow[t] = 0.0;
+    for (int m = 0; m < B; ++m) {
+        // every read first, then branch-free arithmetic, then the writes
+        const double d = L.G[m][m];
+        const double om = L.gd[m];
+        double gim[EPT], gjm[EPT], gij[EPT];
 #pragma unroll
-        for (int m = 0; m < B; ++m) {
-            double d0 = L.G[m][m], d1 = 0.0, a0 = L.G[j][m], a1 = 0.0;
-#pragma unroll
-            for (int t = 0; t < m; ++t) {
-                const double lm = L.GS[m][t];
-                if (t & 1) {
-                    d1 -= lm * lm;
-                    a1 -= lrow[t] * lm;
-                } else {
-                    d0 -= lm * lm;
-                    a0 -= lrow[t] * lm;
-                }
-            }
-            const double d = d0 + d1, acc = a0 + a1;
-            const double om = L.G[m][m];
-            const bool isdead = (m >= b) || !(d > piv_tol * om) || !(om > 0.0) || !isfinite(d);
-            const double inv = isdead ? 1.0 : rsqrt_nr(d);
-            const double lmm = isdead ? 1.0 : d * inv;
-            const double v = (j > m) ? (isdead ? 0.0 : acc * inv) : (j == m ? lmm : 0.0);
-            lrow[m] = v;
-            if (tid < B) L.GS[tid][m] = v;
-            if (tid == 0) {
-                L.dead[m] = isdead ? 1 : 0;
-                L.linv[m] = inv;
-                ndead += isdead ? 1 : 0;
-            }
-            __syncthreads();
+        for (int q = 0; q < EPT; ++q) {
+            const int e = tid + q * NT;
+            const int i = (e / B) % B, j = e % B;  // in range for every thread
+            gim[q] = L.G[i][m];
+            gjm[q] = L.G[j][m];
+            gij[q] = L.G[i][j];
         }
+        const bool isdead = (m >= b) || !(d > piv_tol * om) || !(om > 0.0) || !isfinite(d);
+        const double inv = rsqrt_nr(isdead ? 1.0 : d);
+        const double sc = isdead ? 0.0 : inv;
+        const double lmm = isdead ? 1.0 : d * inv;
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int e = tid + q * NT;
+            if (e < B * B) {
+                const int i = e / B, j = e % B;
+                const double lim = gim[q] * sc;
+                // column m of the factor (rows >= m) and the trailing block:
+                // neither is read at this pivot
+                if (j == m && i >= m) L.GS[i][m] = (i == m) ? lmm : lim;
+                if (i > m && j > m) L.G[i][j] = gij[q] - lim * (gjm[q] * sc);
+            }
+        }
+        if (tid == 0) {
+            L.dead[m] = isdead ? 1 : 0;
+            L.linv[m] = inv;
+            ndead += isdead ? 1 : 0;
+        }
+        __syncthreads();
     }
     // C' = S L^{-T}: row r solves L c = S[r, :]^T
     int nonfinite = 0;

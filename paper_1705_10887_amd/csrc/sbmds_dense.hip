@@ -71,7 +71,7 @@ struct ReduceScatter {
 // H = T^T U and s = c^T U; the last tile reduces those into st->Hs.
 template <int M, int B, int RT>
 __device__ __forceinline__ void gemm_tile_finish(const ProbView &v, SolveState *__restrict__ st, int rt, int rowtiles,
-                                                 int ksplit) {
+                                                 int ksplit, const typename Traits<M>::TA (*own)[B] = nullptr) {
     using Tr = Traits<M>;
     using TA = typename Tr::TA;
     using TT = typename Tr::TT;
@@ -85,7 +85,9 @@ __device__ __forceinline__ void gemm_tile_finish(const ProbView &v, SolveState *
     unsigned *__restrict__ tile_cnt = v.tile_cnt;
     unsigned *__restrict__ tree_cnt = v.gemm_cnt;
     const int tid = threadIdx.x;
-    if (!arrive_last(tile_cnt + rt, (unsigned)ksplit)) return;
+    // own: the whole K range was this block's (ksplit == 1), its sums are in
+    // LDS and no other block takes part in the tile
+    if (!own && !arrive_last(tile_cnt + rt, (unsigned)ksplit)) return;
     __shared__ double ul[RT][B];
     __shared__ double tl[RT][B];
     __shared__ double cl[RT];
@@ -95,8 +97,8 @@ __device__ __forceinline__ void gemm_tile_finish(const ProbView &v, SolveState *
         const int row = tile0 + r;
         if (row < l) {
             // fixed summation order; the loads of 8 partials are in flight together
-            TA sum = (TA)0;
-            for (int q0 = 0; q0 < ksplit; q0 += 8) {
+            TA sum = own ? own[r][j] : (TA)0;
+            for (int q0 = 0; !own && q0 < ksplit; q0 += 8) {
                 TA pv[8];
 #pragma unroll
                 for (int q = 0; q < 8; ++q)
@@ -115,7 +117,7 @@ __device__ __forceinline__ void gemm_tile_finish(const ProbView &v, SolveState *
         }
     }
     for (int r = tid; r < RT; r += 256) cl[r] = (tile0 + r) < l ? c[tile0 + r] : 0.0;
-    if (tid == 0) counter_reset(tile_cnt + rt);
+    if (tid == 0 && !own) counter_reset(tile_cnt + rt);
     __syncthreads();
     // this tile's contribution to H = T^T U and s = c^T U
     constexpr int EH = B * B + B;
@@ -177,33 +179,61 @@ __global__ __launch_bounds__(256) void k_gemm_vec(const ProbView *__restrict__ v
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = (TA)0;
 
-    for (int k0 = kbeg; k0 < kend; k0 += 64) {
-        const int k = k0 + lane;  // < lda always (kend <= lda, lda % 64 == 0)
-        TA w[RW];
+    // the loads of step k0 + 64 are issued before the arithmetic of step k0
+    // (registers), so a step's W rows and T row are in flight while the
+    // previous one is multiplied
+    TA w[RW];
+    Pack<TT, TV> tv[B / TV];
+    auto load_step = [&](int k0) {
+        const int k = k0 + lane;  // < lda while k0 < kend (kend <= lda, lda % 64 == 0)
+        const bool live = k0 < kend;
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
             const int row = r0 + r;
-            w[r] = row < l ? up<TA>(W[(size_t)row * lda + k]) : (TA)0;
+            w[r] = (live && row < l) ? up<TA>(W[(size_t)row * lda + k]) : (TA)0;
         }
-        // rows of T past l are padding; they are never read (W's padding
-        // columns are zero, but the stale bytes there need not be finite)
-        if (k < l) {
-            const TT *trow = T + (size_t)k * B;
+        // rows of T past l are padding and never read (W's padding columns
+        // are zero, but the stale bytes there need not be finite)
+        const bool trow = live && k < l;
 #pragma unroll
-            for (int j0 = 0; j0 < B; j0 += TV) {
-                Pack<TT, TV> tv = ldp<TT, TV>(trow + j0);
+        for (int j0 = 0; j0 < B; j0 += TV) {
+            if (trow) tv[j0 / TV] = ldp<TT, TV>(T + (size_t)k * B + j0);
+            else {
 #pragma unroll
-                for (int jj = 0; jj < TV; ++jj) {
-                    const TA t = up<TA>(tv.v[jj]);
+                for (int jj = 0; jj < TV; ++jj) tv[j0 / TV].v[jj] = TT{};
+            }
+        }
+    };
+    load_step(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += 64) {
+        TA wc[RW];
+        Pack<TT, TV> tc[B / TV];
 #pragma unroll
-                    for (int r = 0; r < RW; ++r) acc[r * B + j0 + jj] += w[r] * t;
-                }
+        for (int r = 0; r < RW; ++r) wc[r] = w[r];
+#pragma unroll
+        for (int q = 0; q < B / TV; ++q) tc[q] = tv[q];
+        load_step(k0 + 64);
+#pragma unroll
+        for (int j0 = 0; j0 < B; j0 += TV) {
+#pragma unroll
+            for (int jj = 0; jj < TV; ++jj) {
+                const TA t = up<TA>(tc[j0 / TV].v[jj]);
+#pragma unroll
+                for (int r = 0; r < RW; ++r) acc[r * B + j0 + jj] += wc[r] * t;
             }
         }
     }
     int idx = 0;
     ReduceScatter<TA, NV, 32>::run(acc, lane, idx);
     constexpr int GROUP = 64 / NV;  // lanes sharing one value index
+    if (ksplit == 1) {
+        // uniform: the block holds the whole K range of its rows
+        __shared__ TA own[RT][B];
+        if ((lane % GROUP) == 0) own[wave * RW + idx / B][idx % B] = acc[0];
+        __syncthreads();
+        gemm_tile_finish<M, B, RT>(v, st, rt, rowtiles, ksplit, own);
+        return;
+    }
     if ((lane % GROUP) == 0) {
         const int row = r0 + idx / B;
         const int j = idx % B;

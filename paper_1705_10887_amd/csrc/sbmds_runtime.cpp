@@ -775,11 +775,26 @@ int autotune(sbmds_ctx *ctx, SolveSet &set) {
             set.tune[m] = keep;
             return SBMDS_OK;
         };
-        OKCHK(try_all(std::vector<int>{64, 128, 256, 512, 1024}, [](Tune &t, int v) { t.spmm_cap = v; },
+        // block counts: powers of two and the counts that give every block
+        // the same number of row steps (for the largest problem)
+        std::vector<int> spmm_cands{64, 128, 256, 512, 1024};
+        {
+            int64_t maxn = 0;
+            for (const DevProblem &q : set.probs) maxn = std::max<int64_t>(maxn, q.n);
+            const int rpb = spmm_rows_per_block(m, set.probs[0].B);
+            const int64_t steps = (maxn + rpb - 1) / rpb;
+            for (int64_t d = 1; d <= 4; ++d) {
+                const int64_t c = (steps + d - 1) / d;
+                if (c >= 32 && c <= kMaxSpmmBlocks &&
+                    std::find(spmm_cands.begin(), spmm_cands.end(), (int)c) == spmm_cands.end())
+                    spmm_cands.push_back((int)c);
+            }
+        }
+        OKCHK(try_all(spmm_cands, [](Tune &t, int v) { t.spmm_cap = v; },
                       [&] { return launch_spmm(m, set.bt, 0, ctx->stream); }));
         std::vector<int> gemm_cands;
         for (int mf = 0; mf < (gemm_mfma(m, set.probs[0].B) ? 2 : 1); ++mf)
-            for (int tg : {128, 256, 512, 1024, 2048}) gemm_cands.push_back(mf * 100000 + tg);
+            for (int tg : {1, 128, 256, 512, 1024, 2048}) gemm_cands.push_back(mf * 100000 + tg);  // 1: no K split
         OKCHK(try_all(gemm_cands, [](Tune &t, int v) { t.gemm_mfma = v / 100000; t.gemm_target = v % 100000; },
                       [&] { return launch_gemm(m, set.bt, 0, ctx->stream); }));
         OKCHK(try_all(std::vector<int>{1, 2, 4}, [](Tune &t, int v) { t.spmmt_wpr = v; },

@@ -228,7 +228,8 @@ __global__ __launch_bounds__(256) void k_gram(const ProbView *__restrict__ views
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWideThreads = 1024;
-constexpr int kStageCap = 2048;  // CSR entries staged per block step
+constexpr int kWideChunk = 16;   // CSR entries of a row whose loads are in flight together
+constexpr int kSpmmTChunk = 4;   // entries per lane of a landmark row loaded together (SpMM^T)
 
 template <int M, int B>
 struct WideShape {
@@ -330,10 +331,11 @@ __global__ __launch_bounds__(kWideThreads) void k_spmm_wide(const ProbView *__re
     using TP = typename Tr::TP;
     using S = WideShape<M, B>;
     constexpr int VEC = S::VEC, LPR = S::LPR, RPB = S::RPB, RW = S::RW, TILES = S::TILES, NTB = S::NTB;
+    // entries in flight per lane: as many as the register budget of the
+    // mode and width allows without spilling
+    constexpr int CH = (M == MODE_FP32 && B == 16) ? kWideChunk
+                       : ((M == MODE_BF16 && B >= 32) ? kWideChunk / 4 : kWideChunk / 2);
     __shared__ double smem[S::SMEM_D];
-    __shared__ int s_ci[kStageCap];
-    __shared__ TP s_val[kStageCap];
-    __shared__ int s_rp[RPB + 1];
 
     const int p = find_problem(off, nprob, blockIdx.x);
     const ProbView &v = views[p];
@@ -346,12 +348,12 @@ __global__ __launch_bounds__(kWideThreads) void k_spmm_wide(const ProbView *__re
     const TP *__restrict__ val = (const TP *)v.val[M];
     const TU *__restrict__ U = (const TU *)v.U;
     TY *__restrict__ Y = (TY *)(st->ycur ? v.Y0 : v.Y1);  // writes the other buffer
-    double *tile = smem;
 
     const int tid = threadIdx.x;
     const int g = tid % LPR;
-    const int slot = tid / LPR;
+    const int slot = tid / LPR;  // row of the block step; wave w owns slots [w RW, (w + 1) RW)
     const int w = tid >> 6;
+    double *tile = smem;  // rows of wave w: [w RW, (w + 1) RW)
     const double inv_n = 1.0 / (double)n;
     TA sc[VEC];
 #pragma unroll
@@ -363,56 +365,65 @@ __global__ __launch_bounds__(kWideThreads) void k_spmm_wide(const ProbView *__re
 #pragma unroll
     for (int ti = 0; ti < NTB; ++ti) esum[ti] = 0.0;
 
-    for (int64_t base = (int64_t)vb * RPB; base < n; base += (int64_t)vg * RPB) {
-        const int nrows = (int)min((int64_t)RPB, (int64_t)n - base);
-        for (int r = tid; r <= nrows; r += kWideThreads) s_rp[r] = rp[base + r];
-        __syncthreads();
-        const int e0 = s_rp[0], ecnt = s_rp[nrows] - e0;
-        const bool staged = ecnt <= kStageCap;  // uniform
-        if (staged) {
-            for (int e = tid; e < ecnt; e += kWideThreads) {
-                s_ci[e] = ci[e0 + e];
-                s_val[e] = val[e0 + e];
-            }
+    // Each wave works through its own rows with no block barrier: the row's
+    // bounds, then its entries CH at a time (all index, value and U loads of
+    // a chunk in flight together), the output row, and the Gram of the
+    // wave's rows from its own LDS rows.
+    const int64_t stride = (int64_t)vg * RPB;
+    int beg_next = 0, end_next = 0;
+    if ((int64_t)vb * RPB + slot < n) {
+        beg_next = rp[(int64_t)vb * RPB + slot];
+        end_next = rp[(int64_t)vb * RPB + slot + 1];
+    }
+    for (int64_t base = (int64_t)vb * RPB; base < n; base += stride) {
+        const int64_t row = base + slot;
+        const int beg = beg_next, end = end_next;
+        // the next step's row bounds are loaded with this step's entries
+        if (row + stride < n) {
+            beg_next = rp[row + stride];
+            end_next = rp[row + stride + 1];
         }
-        __syncthreads();
-        if (slot < nrows) {
-            TA a[VEC];
+        TA a[VEC];
 #pragma unroll
-            for (int q = 0; q < VEC; ++q) a[q] = (TA)0;
-            const int beg = s_rp[slot] - e0, end = s_rp[slot + 1] - e0;
-            const int32_t *cis = staged ? s_ci : ci + e0;
-            const TP *vals = staged ? s_val : val + e0;
-            int e = beg;
-            for (; e + 1 < end; e += 2) {
-                const int c0 = cis[e], c1 = cis[e + 1];
-                const TA p0 = up<TA>(vals[e]), p1 = up<TA>(vals[e + 1]);
-                Pack<TU, VEC> u0 = ldp<TU, VEC>(U + (size_t)c0 * B + g * VEC);
-                Pack<TU, VEC> u1 = ldp<TU, VEC>(U + (size_t)c1 * B + g * VEC);
+        for (int q = 0; q < VEC; ++q) a[q] = (TA)0;
+        if (row < n) {
+            for (int e0 = beg; e0 < end; e0 += CH) {
+                int c[CH];
+                TA pv[CH];
 #pragma unroll
-                for (int q = 0; q < VEC; ++q) a[q] += p0 * up<TA>(u0.v[q]) + p1 * up<TA>(u1.v[q]);
-            }
-            if (e < end) {
-                const int c0 = cis[e];
-                const TA p0 = up<TA>(vals[e]);
-                Pack<TU, VEC> u0 = ldp<TU, VEC>(U + (size_t)c0 * B + g * VEC);
+                for (int j = 0; j < CH; ++j) {
+                    const bool ok = e0 + j < end;
+                    c[j] = ok ? ci[e0 + j] : 0;  // row 0 of U stands in for missing entries
+                    pv[j] = ok ? up<TA>(val[e0 + j]) : (TA)0;
+                }
+                Pack<TU, VEC> u[CH];
 #pragma unroll
-                for (int q = 0; q < VEC; ++q) a[q] += p0 * up<TA>(u0.v[q]);
+                for (int j = 0; j < CH; ++j) u[j] = ldp<TU, VEC>(U + (size_t)c[j] * B + g * VEC);
+#pragma unroll
+                for (int j = 0; j < CH; ++j) {
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) a[q] += pv[j] * up<TA>(u[j].v[q]);
+                }
             }
             Pack<TY, VEC> o;
 #pragma unroll
             for (int q = 0; q < VEC; ++q) o.v[q] = down<TY>(a[q] - sc[q]);
-            stp<TY, VEC>(Y + (size_t)(base + slot) * B + g * VEC, o);
+            stp<TY, VEC>(Y + (size_t)row * B + g * VEC, o);
 #pragma unroll
             for (int q = 0; q < VEC; ++q) tile[slot * B + g * VEC + q] = (double)up<TA>(o.v[q]);
         } else {
 #pragma unroll
             for (int q = 0; q < VEC; ++q) tile[slot * B + g * VEC + q] = 0.0;
         }
-        __syncthreads();
+        // the wave's rows are complete in LDS (one wave: in-order LDS, no
+        // block barrier), and are read back only by this wave
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         gram_mfma_rows<B, RW, TILES>(tile, w * RW, acc, esum);
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
     }
+    __syncthreads();  // every wave is done with its tile rows before the reduction reuses smem
     gram_mfma_finish<M, B, TILES>(acc, esum, smem, v.red_spmm, v.spmm_cnt, st, vb, vg);
 }
 
@@ -513,21 +524,27 @@ __device__ __forceinline__ void spmm_t_body(const ProbView *__restrict__ views, 
     if (j < l) {
         const int beg = rpT[j], end = rpT[j + 1];
         constexpr int STEP = EPW * WPR;
-        int e = beg + wsub * EPW + slot;
-        for (; e + STEP < end; e += 2 * STEP) {
-            const TA p0 = up<TA>(valT[e]), p1 = up<TA>(valT[e + STEP]);
-            const int v0 = ciT[e], v1 = ciT[e + STEP];
-            Pack<TY, VEC> y0 = ldp<TY, VEC>(Y + (size_t)v0 * B + g * VEC);
-            Pack<TY, VEC> y1 = ldp<TY, VEC>(Y + (size_t)v1 * B + g * VEC);
+        // CHT entries per lane at a time: all their index, value and Y loads
+        // in flight together (missing entries read row 0 with weight 0)
+        constexpr int CHT = kSpmmTChunk;
+        for (int e = beg + wsub * EPW + slot; e < end; e += CHT * STEP) {
+            int vi[CHT];
+            TA pv[CHT];
 #pragma unroll
-            for (int q = 0; q < VEC; ++q) acc[q] += p0 * up<TA>(y0.v[q]) + p1 * up<TA>(y1.v[q]);
-        }
-        if (e < end) {
-            const TA p0 = up<TA>(valT[e]);
-            const int v0 = ciT[e];
-            Pack<TY, VEC> y0 = ldp<TY, VEC>(Y + (size_t)v0 * B + g * VEC);
+            for (int q = 0; q < CHT; ++q) {
+                const int idx = e + q * STEP;
+                const bool ok = idx < end;
+                vi[q] = ok ? ciT[idx] : 0;
+                pv[q] = ok ? up<TA>(valT[idx]) : (TA)0;
+            }
+            Pack<TY, VEC> y[CHT];
 #pragma unroll
-            for (int q = 0; q < VEC; ++q) acc[q] += p0 * up<TA>(y0.v[q]);
+            for (int q = 0; q < CHT; ++q) y[q] = ldp<TY, VEC>(Y + (size_t)vi[q] * B + g * VEC);
+#pragma unroll
+            for (int q = 0; q < CHT; ++q) {
+#pragma unroll
+                for (int r = 0; r < VEC; ++r) acc[r] += pv[q] * up<TA>(y[q].v[r]);
+            }
         }
     }
 #pragma unroll

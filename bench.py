@@ -5,17 +5,20 @@ Workload: sparse biharmonic classical scaling of a radially deformed
 icosphere (subdivision level 7, n = 163,842 vertices, 8 seeded spherical
 harmonics of degree <= 6, amplitude 5%), l = 2,000 geodesic farthest-point
 landmarks, P thresholded to p_row = 10 (p = 809, nnz = 1.62M), W = squared
-Dijkstra landmark distances, k = 3, block 16.  Inputs are synthetic and
+Dijkstra landmark distances, k = 3.  Inputs are synthetic and
 generated from fixed seeds (cached on disk after the first run).
 
 A step is one sbmds_embed call on device-resident inputs: start block,
 all iterations of the precision schedule up to the certified 1e-6 bound,
 and the embedding Z (left on the device).  Four forms are timed on the same
-GPU, each to the same certified bound: plain fp32 iterations from a random
+GPU, each to the same certified bound and at each block width of --blocks
+(16 and 8: the three wanted eigenvalues and the five negative ones of larger
+magnitude than the rest fit in 8): plain fp32 iterations from a random
 start, bf16 bulk iterations refined in fp32, and fp32 iterations from the
 landmark-MDS start and from the learned start (a network trained first, on
 the GPU, on 12 smaller meshes of the same family).  The fastest is the chosen
-form and gives `value`; the plain fp32 time is reported beside it.
+form and gives `value`; the plain fp32 time at block 16 is reported beside
+it.  The batched workload runs at block 16.
 
 Prints one JSON line.  Only one GPU is used; --gpus above 1 is refused.
 """
@@ -195,7 +198,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3, help=">= 1; the first call learns the phase schedule")
     ap.add_argument("--k", type=int, default=3)
-    ap.add_argument("--block", type=int, default=16)
+    ap.add_argument("--blocks", type=str, default="16,8",
+                    help="comma-separated block widths; every form is timed at each")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the landmark-MDS and learned-start forms")
@@ -214,8 +218,8 @@ def main():
         print(json.dumps({"copy_bytes": a.numel() * 4, "launches": 3}))
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (this build runs the solve on a single MI355X); "
-              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        print(f"bench.py measures one GPU: the solve runs on a single MI355X and --gpus {args.gpus} "
+              f"is not supported", file=sys.stderr)
         sys.exit(2)
 
     from synth import configs
@@ -228,32 +232,42 @@ def main():
     import paper_1705_10887_amd as sb
 
     torch.cuda.set_device(0)
-    k, block = args.k, args.block
-    tune = os.path.join(configs.cache_dir(), f"tune_sphere7_k{k}_b{block}.txt")
+    k = args.k
+    blocks = [int(x) for x in args.blocks.split(",") if x]
     forms = {}
 
-    def run_form(name, prec, start=None, weights=None):
-        log(f"timing {name}")
+    def tune_for(block):
+        return os.path.join(configs.cache_dir(), f"tune_sphere7_k{k}_b{block}.txt")
+
+    def run_form(name, block, prec, start=None, weights=None):
+        key = f"{name}/b{block}"
+        log(f"timing {key}")
         ms, eig, rep, _ = time_form(sb, torch, prob, prec, args.steps, args.warmup, k, block, start=start,
-                                    tune_cache=tune, mlp_weights=weights)
-        forms[name] = {"ms": ms, "eig": eig, "rep": rep, "prec": prec, "start": start, "weights": weights}
-        log(f"{name} {ms:.3f} ms  iters {rep['iters_bf16']}+{rep['iters_fp32']}+{rep['iters_fp64']}"
+                                    tune_cache=tune_for(block), mlp_weights=weights)
+        forms[key] = {"ms": ms, "eig": eig, "rep": rep, "prec": prec, "start": start, "weights": weights,
+                      "block": block, "form": name}
+        log(f"{key} {ms:.3f} ms  iters {rep['iters_bf16']}+{rep['iters_fp32']}+{rep['iters_fp64']}"
             f"  start iters {rep['start_iters']}")
 
-    run_form("fp32", sb.FP32)
-    run_form("bf16_fp32", sb.BF16_FP32)
+    weights = None
     if not args.no_learned:
-        run_form("fp32_lmds", sb.FP32, sb.START_LMDS)
-        weights = train_start_net(sb, torch, configs, k, block)
-        run_form("fp32_learned", sb.FP32, sb.START_LEARNED, weights)
-    # the form that certifies fastest is the chosen one
+        weights = train_start_net(sb, torch, configs, k, blocks[0])
+    for block in blocks:
+        run_form("fp32", block, sb.FP32)
+        run_form("bf16_fp32", block, sb.BF16_FP32)
+        if weights is not None:
+            run_form("fp32_lmds", block, sb.FP32, sb.START_LMDS)
+            run_form("fp32_learned", block, sb.FP32, sb.START_LEARNED, weights)
+    # the form that certifies fastest is the chosen one; the plain form is
+    # fp32 from the random start at the first (reference) block width
     chosen = min(forms, key=lambda f: forms[f]["ms"])
     ch = forms[chosen]
-    value, eigc, repc, chosen_prec = ch["ms"], ch["eig"], ch["rep"], ch["prec"]
-    ms_fp32 = forms["fp32"]["ms"]
+    value, eigc, repc, chosen_prec, block = ch["ms"], ch["eig"], ch["rep"], ch["prec"], ch["block"]
+    plain = f"fp32/b{blocks[0]}"
+    ms_fp32 = forms[plain]["ms"]
     log("kernel timing pass")
     _, _, _, stats = time_form(sb, torch, prob, chosen_prec, args.steps, 1, k, block, flags=sb.FLAG_KERNEL_TIMING,
-                               start=ch["start"], tune_cache=tune, mlp_weights=ch["weights"])
+                               start=ch["start"], tune_cache=tune_for(block), mlp_weights=ch["weights"])
     # dominant bandwidth kernel of the timed form (per kernel and arithmetic)
     dom = max((s for s in stats if s["bytes_total"] > 0), key=lambda s: s["ms_total"])
     avg_ms = dom["ms_total"] / dom["launches"]
@@ -268,8 +282,8 @@ def main():
     batched = None
     if not args.no_batch:
         log("batched workload")
-        batched = time_batch(sb, torch, configs.mesh_batch(log=log), k, block, args.steps, args.warmup,
-                             os.path.join(configs.cache_dir(), f"tune_batch16_k{k}_b{block}.txt"))
+        batched = time_batch(sb, torch, configs.mesh_batch(log=log), k, blocks[0], args.steps, args.warmup,
+                             os.path.join(configs.cache_dir(), f"tune_batch16_k{k}_b{blocks[0]}.txt"))
         log(f"batched {batched}")
 
     cpu = None
@@ -298,9 +312,10 @@ def main():
             "workload": "sphere7: icosphere level 7 (n=163842) deformed by 8 seeded spherical harmonics, "
                         "l=2000 FPS landmarks, p_row=10 (nnz=1620000), W=D^2_ll float32",
             "n": int(prob["n"]), "l": int(prob["l"]), "nnz": int(len(prob["col"])), "k": k, "block": block,
-            "chosen": FORM_NAMES[chosen],
+            "chosen": f"{FORM_NAMES[ch['form']]}, block {block}",
         },
         "plain_fp32_ms": round(ms_fp32, 4),
+        "plain_fp32_form": f"{FORM_NAMES['fp32']}, block {blocks[0]}",
         "chosen_over_plain": round(ms_fp32 / value, 3),
         "forms_ms": {f: round(v["ms"], 4) for f, v in forms.items()},
         "iters": {"bf16": repc["iters_bf16"], "fp32": repc["iters_fp32"], "fp64": repc["iters_fp64"],

@@ -33,15 +33,19 @@ struct SpmmShape {
     static constexpr int NQ = (E + 255) / 256;
 };
 
+// Widths served by the 1024-thread SpMM with the matrix-core Gram (B = 8 as
+// one 16 x 16 tile with zero padding).
+constexpr bool wide_width(int B) { return B == 8 || B == 16 || B == 32; }
+
 int spmm_rows_per_block(Mode m, int B) {
     const int ysz = y_elem_bytes(m);
     int vec = 16 / ysz;
     if (vec > B) vec = B;
     const int lpr = B / vec;
-    return ((B == 16 || B == 32) ? 1024 : 256) / lpr;
+    return (wide_width(B) ? 1024 : 256) / lpr;
 }
 
-int spmm_block_cap(Mode, int B) { return (B == 16 || B == 32) ? 256 : 1024; }
+int spmm_block_cap(Mode, int B) { return wide_width(B) ? 256 : 1024; }
 
 template <int B>
 __device__ __forceinline__ void gram_tile_accumulate(const double (*tile)[B], int rows, int tid,
@@ -127,29 +131,43 @@ __global__ __launch_bounds__(256) void k_spmm(const ProbView *__restrict__ views
     for (int q = 0; q < NQ; ++q) gacc[q] = 0.0;
     double eacc = 0.0;
 
-    for (int64_t base = (int64_t)vb * RPB; base < n; base += (int64_t)vg * RPB) {
+    // row bounds one step ahead; a row's entries CH at a time with all
+    // their index, value and U loads in flight (as in k_spmm_wide)
+    constexpr int CH = (M == MODE_FP32 || M == MODE_BF16) ? 16 : 8;
+    const int64_t stride = (int64_t)vg * RPB;
+    int beg_next = 0, end_next = 0;
+    if ((int64_t)vb * RPB + slot < n) {
+        beg_next = rp[(int64_t)vb * RPB + slot];
+        end_next = rp[(int64_t)vb * RPB + slot + 1];
+    }
+    for (int64_t base = (int64_t)vb * RPB; base < n; base += stride) {
         const int64_t row = base + slot;
+        const int beg = beg_next, end = end_next;
+        if (row + stride < n) {
+            beg_next = rp[row + stride];
+            end_next = rp[row + stride + 1];
+        }
         if (row < n) {
             TA acc[VEC];
 #pragma unroll
             for (int q = 0; q < VEC; ++q) acc[q] = (TA)0;
-            const int beg = rp[row], end = rp[row + 1];
-            int e = beg;
-            // two independent gathers in flight per lane
-            for (; e + 1 < end; e += 2) {
-                const int c0 = ci[e], c1 = ci[e + 1];
-                const TA p0 = up<TA>(val[e]), p1 = up<TA>(val[e + 1]);
-                Pack<TU, VEC> u0 = ldp<TU, VEC>(U + (size_t)c0 * B + g * VEC);
-                Pack<TU, VEC> u1 = ldp<TU, VEC>(U + (size_t)c1 * B + g * VEC);
+            for (int e0 = beg; e0 < end; e0 += CH) {
+                int c[CH];
+                TA pv[CH];
 #pragma unroll
-                for (int q = 0; q < VEC; ++q) acc[q] += p0 * up<TA>(u0.v[q]) + p1 * up<TA>(u1.v[q]);
-            }
-            if (e < end) {
-                const int c0 = ci[e];
-                const TA p0 = up<TA>(val[e]);
-                Pack<TU, VEC> u0 = ldp<TU, VEC>(U + (size_t)c0 * B + g * VEC);
+                for (int j = 0; j < CH; ++j) {
+                    const bool ok = e0 + j < end;
+                    c[j] = ok ? ci[e0 + j] : 0;  // row 0 of U stands in for missing entries
+                    pv[j] = ok ? up<TA>(val[e0 + j]) : (TA)0;
+                }
+                Pack<TU, VEC> u[CH];
 #pragma unroll
-                for (int q = 0; q < VEC; ++q) acc[q] += p0 * up<TA>(u0.v[q]);
+                for (int j = 0; j < CH; ++j) u[j] = ldp<TU, VEC>(U + (size_t)c[j] * B + g * VEC);
+#pragma unroll
+                for (int j = 0; j < CH; ++j) {
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) acc[q] += pv[j] * up<TA>(u[j].v[q]);
+                }
             }
             Pack<TY, VEC> o;
 #pragma unroll
@@ -239,7 +257,7 @@ struct WideShape {
     static constexpr int LPR = B / VEC;
     static constexpr int RPB = kWideThreads / LPR;  // rows per block step
     static constexpr int RW = 64 / LPR;             // rows per wave step
-    static constexpr int NTB = B / 16;
+    static constexpr int NTB = (B + 15) / 16;  // 16 x 16 Gram tiles per side (B = 8: one, padded)
     static constexpr int TILES = NTB * (NTB + 1) / 2;
     static constexpr int E = B * (B + 1) / 2;
     static constexpr int EG = E + B;
@@ -252,8 +270,8 @@ struct WideShape {
 // Gram and column sums of the wave's RW rows of the tile.
 template <int B, int RW, int TILES>
 __device__ __forceinline__ void gram_mfma_rows(const double *__restrict__ tile, int r0, dbl4 (&acc)[TILES],
-                                               double (&esum)[B / 16]) {
-    constexpr int NTB = B / 16;
+                                               double (&esum)[(B + 15) / 16]) {
+    constexpr int NTB = (B + 15) / 16;
     const int lane = threadIdx.x & 63;
     const int col = lane & 15, kr = lane >> 4;
 #pragma unroll
@@ -261,7 +279,7 @@ __device__ __forceinline__ void gram_mfma_rows(const double *__restrict__ tile, 
         const double *row = tile + (size_t)(r0 + 4 * ks + kr) * B;
         double v[NTB];
 #pragma unroll
-        for (int ti = 0; ti < NTB; ++ti) v[ti] = row[16 * ti + col];
+        for (int ti = 0; ti < NTB; ++ti) v[ti] = (16 * ti + col < B) ? row[16 * ti + col] : 0.0;
         int t = 0;
 #pragma unroll
         for (int ti = 0; ti < NTB; ++ti) {
@@ -280,7 +298,7 @@ __device__ __forceinline__ void gram_mfma_rows(const double *__restrict__ tile, 
 // join the tree reduction into st->Ge.  `smem` must be free (all waves past
 // their last use of it).
 template <int M, int B, int TILES>
-__device__ __forceinline__ void gram_mfma_finish(dbl4 (&acc)[TILES], double (&esum)[B / 16],
+__device__ __forceinline__ void gram_mfma_finish(dbl4 (&acc)[TILES], double (&esum)[(B + 15) / 16],
                                                  double *__restrict__ smem, double *__restrict__ red,
                                                  unsigned *__restrict__ cnt, SolveState *__restrict__ st, int vb,
                                                  int vg) {
@@ -301,14 +319,15 @@ __device__ __forceinline__ void gram_mfma_finish(dbl4 (&acc)[TILES], double (&es
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = 16 * ti + (lane >> 4) + 4 * r, j = 16 * tj + (lane & 15);
-                if (i <= j) mine[i * B - (i * (i - 1)) / 2 + (j - i)] = acc[t][r];
+                if (i <= j && j < B) mine[i * B - (i * (i - 1)) / 2 + (j - i)] = acc[t][r];
             }
             ++t;
         }
     }
     if (lane < 16) {
 #pragma unroll
-        for (int ti = 0; ti < NTB; ++ti) mine[E + 16 * ti + lane] = esum[ti];
+        for (int ti = 0; ti < NTB; ++ti)
+            if (16 * ti + lane < B) mine[E + 16 * ti + lane] = esum[ti];
     }
     __syncthreads();
     double *part = red + (size_t)vb * EG;
@@ -333,7 +352,7 @@ __global__ __launch_bounds__(kWideThreads) void k_spmm_wide(const ProbView *__re
     constexpr int VEC = S::VEC, LPR = S::LPR, RPB = S::RPB, RW = S::RW, TILES = S::TILES, NTB = S::NTB;
     // entries in flight per lane: as many as the register budget of the
     // mode and width allows without spilling
-    constexpr int CH = (M == MODE_FP32 && B == 16) ? kWideChunk
+    constexpr int CH = (M == MODE_FP32 && B <= 16) ? kWideChunk
                        : ((M == MODE_BF16 && B >= 32) ? kWideChunk / 4 : kWideChunk / 2);
     __shared__ double smem[S::SMEM_D];
 
@@ -858,7 +877,7 @@ hipError_t launch_spmm(Mode m, const Batch &bt, int phase, hipStream_t s) {
     if (grid <= 0) return hipErrorInvalidValue;
     const int *off = bt.off(BK_SPMM, m);
     SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(bt.B, {
-        if constexpr (BB == 16 || BB == 32)
+        if constexpr (wide_width(BB))
             hipLaunchKernelGGL((k_spmm_wide<MM, BB>), dim3(grid), dim3(kWideThreads), 0, s, bt.views, off, bt.nprob,
                                phase);
         else
@@ -901,7 +920,7 @@ static hipError_t start_impl(const Batch &bt, uint64_t seed, hipStream_t s) {
     if (e != hipSuccess) return e;
     const int grid = bt.total[BK_SPMM][MM];
     if (grid <= 0) return hipErrorInvalidValue;
-    if constexpr (BB == 16 || BB == 32)
+    if constexpr (wide_width(BB))
         hipLaunchKernelGGL((k_gram_wide<MM, BB>), dim3(grid), dim3(kWideThreads), 0, s, bt.views,
                            bt.off(BK_SPMM, (Mode)MM), bt.nprob);
     else

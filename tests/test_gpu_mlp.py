@@ -188,3 +188,42 @@ def test_training_and_gain_over_random_start(gpu, tmp_path):
     it = lambda r: r["iters_fp32"] + r["iters_fp64"]
     print(f"iterations: learned {it(rl)} random {it(rr)}", flush=True)
     assert it(rl) <= it(rr)
+
+
+def test_learned_start_sphere7_block8(gpu, tmp_path):
+    # the benchmark's learned form: a network trained on level-5 spheres of
+    # the same family starts the level-7 solve at block 8
+    import paper_1705_10887_amd as sb
+    from paper_1705_10887_amd import mlp
+    from tests import helpers as H
+    k = 3
+    meshes = configs.sphere_family()
+    for m in meshes:
+        m["landmarks"] = m["landmarks"].astype(np.int32)
+        m["xyz"] = m["V"].astype(np.float32)
+    targets = mlp.solve_targets(meshes, k=k, block=8)
+    feats = [mlp.features(m["xyz"], m["landmarks"], m["W"]) for m in meshes]
+    net, losses = mlp.train(feats, targets, k=k, steps=600, lr=3e-3, seed=0)
+    assert losses[-1] < 0.05 * losses[0]
+    path = str(tmp_path / "sphere.bin")
+    net.save(path)
+    net.close()
+    prob = configs.sphere7()
+    xyz = prob["V"].astype(np.float32)
+    lm = prob["landmarks"].astype(np.int32)
+
+    def run(start):
+        p = sb.Problem.from_arrays(prob["rowptr"], prob["col"], prob["val"], prob["W"], xyz=xyz, landmark_vertex=lm)
+        with sb.Context([p], k=k, block=8, prec=sb.FP32, start=start, mlp_weights=path) as ctx:
+            Z, eig, reps, rc = ctx.embed()
+        return Z, eig[0], reps[0], rc
+
+    Zl, el, rl, rc = run(sb.START_LEARNED)
+    _, _, rr, _ = run(sb.START_RANDOM)
+    assert rc == 0 and rl["certified"]
+    lam, V, _ = H.oracle_for(prob, k)
+    assert H.rel_eig_err(el, lam[:k]) <= 1e-6
+    assert H.subspace_angle(Zl, V, lam, k, tol=1e-6) <= 3.0
+    it = lambda r: r["iters_fp32"] + r["iters_fp64"]
+    print(f"sphere7 block 8: iterations learned {it(rl)} random {it(rr)}", flush=True)
+    assert it(rl) <= it(rr)

@@ -72,10 +72,13 @@ def test_random_operator_fp64_ragged(gpu):
     check(prob, Z, eig, rep, 4, 1e-10)
 
 
-def test_sphere7_fp32_k3(gpu):
+@pytest.mark.parametrize("block", [16, 8])
+def test_sphere7_fp32_k3(gpu, block):
+    # block 8 holds the three wanted eigenvalues and the five negative ones
+    # of larger magnitude than the rest of the spectrum
     sb = gpu
     prob = configs.sphere7()
-    Z, eig, rep, rc, _ = run(sb, prob, 3, 16, sb.FP32)
+    Z, eig, rep, rc, _ = run(sb, prob, 3, block, sb.FP32)
     assert rc == 0 and rep["certified"]
     check(prob, Z, eig, rep, 3, 1e-6)
 
@@ -88,10 +91,11 @@ def test_sphere7_fp32_k10(gpu):
     check(prob, Z, eig, rep, 10, 1e-6)
 
 
-def test_sphere7_bf16_fp32(gpu):
+@pytest.mark.parametrize("block", [16, 8])
+def test_sphere7_bf16_fp32(gpu, block):
     sb = gpu
     prob = configs.sphere7()
-    Z, eig, rep, rc, _ = run(sb, prob, 3, 16, sb.BF16_FP32)
+    Z, eig, rep, rc, _ = run(sb, prob, 3, block, sb.BF16_FP32)
     assert rc == 0 and rep["certified"]
     assert rep["iters_bf16"] >= 1
     check(prob, Z, eig, rep, 3, 1e-6)

@@ -123,6 +123,9 @@ __device__ inline void phase_control(Ctl &st, const PhaseRule &rule, int init) {
         for (int i = 0; i < 4; ++i) st.hist[i] = INFINITY;
         return;
     }
+    // an iteration of this phase has run: nothing is pending from the phase
+    // change that led here
+    st.pending_convert = 0;
     // the block just produced (Y') becomes current; the basis the Ritz
     // vectors were taken from stays readable until the next SpMM overwrites it
     st.zbuf = st.ycur;

@@ -172,9 +172,8 @@ hipError_t launch_random_start(Mode m, const Batch &bt, uint64_t seed, hipStream
 hipError_t launch_user_start(Mode m, const Batch &bt, hipStream_t stream);
 hipError_t launch_convert_y(Mode from, Mode to, const Batch &bt, int phase, hipStream_t stream);
 // Phase changes the transposed SpMM bridges by reading the previous phase's
-// (narrower) block directly; they need only launch_phase_enter.
+// (narrower) block directly; they need no launch of their own.
 bool reads_previous_block(Mode from, Mode to);
-hipError_t launch_phase_enter(const Batch &bt, int phase, hipStream_t stream);
 hipError_t launch_embedding(const Batch &bt, void *Z, int z_double, hipStream_t stream);
 // Landmark-block start: fills U of every problem of `bt` with an l x b block
 // (in the transposed-product type of mode m) and arms the state so that the

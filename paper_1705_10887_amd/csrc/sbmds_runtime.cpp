@@ -461,9 +461,10 @@ int enqueue_round(sbmds_ctx *ctx, SolveSet &set, const std::vector<PhaseRule> &r
             const int ph = op.second;
             if (op.first) {
                 const Mode mf = (Mode)rules[ph - 1].mode, mt = (Mode)rules[ph].mode;
-                if (reads_previous_block(mf, mt))
-                    OKCHK(timed(ctx, "phase_enter", 0.0, 0.0, [&] { return launch_phase_enter(set.bt, ph, ctx->stream); }));
-                else
+                // a phase whose kernels read the previous phase's narrower
+                // block needs no launch of its own (its first Rayleigh-Ritz
+                // step clears the pending flag)
+                if (!reads_previous_block(mf, mt))
                     OKCHK(timed(ctx, "convert", 0.0, 0.0,
                                 [&] { return launch_convert_y(mf, mt, set.bt, ph, ctx->stream); }));
             } else {

@@ -715,25 +715,10 @@ __global__ void k_phase_begin(const ProbView *__restrict__ views, int phase, int
     }
 }
 
-// Start of phase `phase` without a conversion pass (the next transposed SpMM
-// reads the narrower block directly): only the pending flag is cleared.
-__global__ void k_phase_enter(const ProbView *__restrict__ views, int phase) {
-    SolveState *st = views[blockIdx.x].st;
-    if (threadIdx.x == 0 && !st->done && st->phase == phase && st->pending_convert) {
-        st->pending_convert = 0;
-        char *h = (char *)views[blockIdx.x].host_sum;
-        if (h) *(int *)(h + offsetof(SolveState, pending_convert) - kSummaryOffset) = 0;
-    }
-}
-
 bool reads_previous_block(Mode from, Mode to) {
     return (from == MODE_BF16 && to == MODE_FP32) || (from == MODE_FP32 && to == MODE_F64ACC);
 }
 
-hipError_t launch_phase_enter(const Batch &bt, int phase, hipStream_t s) {
-    hipLaunchKernelGGL(k_phase_enter, dim3(bt.nprob), dim3(64), 0, s, bt.views, phase);
-    return hipGetLastError();
-}
 
 __device__ __forceinline__ double load_y(const void *Y, int64_t i, int mode) {
     if (mode == MODE_BF16) return (double)bf2f(((const bf16_t *)Y)[i]);

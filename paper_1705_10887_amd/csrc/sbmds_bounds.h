@@ -164,14 +164,15 @@ __device__ inline void phase_control(SolveState *st, const PhaseRule &rule, int 
 }
 
 // Copy the SolveState tail (Ritz values, bounds, control) to the pinned host
-// summary of the problem, all threads of the block taking part.  The block's
-// global writes to st must be complete and visible (after a barrier).
-__device__ inline void publish_summary(const SolveState *st, void *host) {
+// summary of the problem, threads 0 .. nthreads - 1 of the block taking
+// part.  Their global writes to st must be complete and visible (after a
+// barrier).
+__device__ inline void publish_summary(const SolveState *st, void *host, int nthreads) {
     static_assert(kSummaryOffset % 8 == 0 && kSummaryBytes % 8 == 0, "whole 8-byte words");
     if (!host) return;
     const uint64_t *src = reinterpret_cast<const uint64_t *>(reinterpret_cast<const char *>(st) + kSummaryOffset);
     uint64_t *dst = reinterpret_cast<uint64_t *>(host);
-    for (int i = threadIdx.x; i < (int)(kSummaryBytes / 8); i += blockDim.x) dst[i] = src[i];
+    for (int i = threadIdx.x; i < (int)(kSummaryBytes / 8); i += nthreads) dst[i] = src[i];
 }
 
 }  // namespace sbmds

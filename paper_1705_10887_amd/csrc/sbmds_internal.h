@@ -165,7 +165,12 @@ struct Batch {
 // in `phase`.
 hipError_t launch_spmm_t(Mode m, const Batch &bt, int phase, hipStream_t stream);
 hipError_t launch_gemm(Mode m, const Batch &bt, int phase, hipStream_t stream);
-hipError_t launch_spmm(Mode m, const Batch &bt, int phase, hipStream_t stream);
+// rr = 1 (2): the SpMM also runs the iteration's Rayleigh-Ritz step (the
+// start's CholQR) in the block that completes its Gram reduction; only for
+// widths where spmm_runs_rr(B).
+bool spmm_runs_rr(int B);
+hipError_t launch_spmm(Mode m, const Batch &bt, int phase, hipStream_t stream, int rr = 0, int max_sweeps = 0,
+                       const PhaseRule &rule = PhaseRule{});
 hipError_t launch_rr_solve(const Batch &bt, int init, int max_sweeps, const PhaseRule &rule,
                            hipStream_t stream);
 hipError_t launch_random_start(Mode m, const Batch &bt, uint64_t seed, hipStream_t stream);

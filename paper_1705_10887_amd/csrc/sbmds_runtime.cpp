@@ -437,9 +437,15 @@ int enqueue_iteration(sbmds_ctx *ctx, SolveSet &set, const PhaseRule &r) {
     const std::string sfx = std::string(".") + mname[m];
     OKCHK(timed(ctx, ("spmm_t" + sfx).c_str(), b_spmmt, f_sp, [&] { return launch_spmm_t(m, bt, r.phase, ctx->stream); }));
     OKCHK(timed(ctx, ("gemm" + sfx).c_str(), b_gemm, f_ge, [&] { return launch_gemm(m, bt, r.phase, ctx->stream); }));
-    OKCHK(timed(ctx, ("spmm" + sfx).c_str(), b_spmm, f_sp, [&] { return launch_spmm(m, bt, r.phase, ctx->stream); }));
-    OKCHK(timed(ctx, ("rr_solve" + sfx).c_str(), 0.0, 0.0,
-                [&] { return launch_rr_solve(bt, 0, sweep_cap(r), r, ctx->stream); }));
+    if (spmm_runs_rr(bt.B)) {
+        // the Rayleigh-Ritz step runs in the SpMM's reducing block
+        OKCHK(timed(ctx, ("spmm+rr" + sfx).c_str(), b_spmm, f_sp,
+                    [&] { return launch_spmm(m, bt, r.phase, ctx->stream, 1, sweep_cap(r), r); }));
+    } else {
+        OKCHK(timed(ctx, ("spmm" + sfx).c_str(), b_spmm, f_sp, [&] { return launch_spmm(m, bt, r.phase, ctx->stream); }));
+        OKCHK(timed(ctx, ("rr_solve" + sfx).c_str(), 0.0, 0.0,
+                    [&] { return launch_rr_solve(bt, 0, sweep_cap(r), r, ctx->stream); }));
+    }
     return SBMDS_OK;
 }
 
@@ -587,7 +593,18 @@ int solve_all(sbmds_ctx *ctx, sbmds_report *reps) {
     hipEvent_t e0 = ev_get(ctx), e1 = ev_get(ctx), e2 = ev_get(ctx);
     HIPCHK(hipEventRecord(e0, ctx->stream));
     const Mode m0 = (Mode)rules[0].mode;
+    bool init_fused = false;
+    // the lift Y0 = P X_l: one SpMM, which also runs the first CholQR where
+    // the width allows
+    auto lift = [&]() -> int {
+        init_fused = spmm_runs_rr(set.bt.B);
+        if (init_fused)
+            return timed(ctx, "lift+rr_init", 0.0, 0.0,
+                         [&] { return launch_spmm(m0, set.bt, 0, ctx->stream, 2, 0, rules[0]); });
+        return timed(ctx, "lift", 0.0, 0.0, [&] { return launch_spmm(m0, set.bt, 0, ctx->stream); });
+    };
     auto start = [&]() -> int {
+        init_fused = false;
         if (o.start == SBMDS_START_USER) {
             OKCHK(timed(ctx, "start", 0.0, 0.0, [&] { return launch_user_start(m0, set.bt, ctx->stream); }));
         } else if (o.start == SBMDS_START_LMDS) {
@@ -605,18 +622,19 @@ int solve_all(sbmds_ctx *ctx, sbmds_report *reps) {
             if (rc < 0) return rc;
             OKCHK(timed(ctx, "lift", 0.0, 0.0,
                         [&] { return launch_lift_prep(m0, set.bt, &ctx->lmk.bt, nullptr, o.seed, ctx->stream); }));
-            OKCHK(timed(ctx, "lift", 0.0, 0.0, [&] { return launch_spmm(m0, set.bt, 0, ctx->stream); }));
+            OKCHK(lift());
         } else if (o.start == SBMDS_START_LEARNED) {
             // the network's landmark prediction (made at create: it depends
             // on the inputs and the weights only) as the first k columns, the
             // rest Gaussian, lifted through P
             OKCHK(timed(ctx, "lift", 0.0, 0.0,
                         [&] { return launch_lift_prep(m0, set.bt, nullptr, ctx->learned, o.seed, ctx->stream); }));
-            OKCHK(timed(ctx, "lift", 0.0, 0.0, [&] { return launch_spmm(m0, set.bt, 0, ctx->stream); }));
+            OKCHK(lift());
         } else {
             OKCHK(timed(ctx, "start", 0.0, 0.0, [&] { return launch_random_start(m0, set.bt, o.seed, ctx->stream); }));
         }
-        OKCHK(timed(ctx, "rr_init", 0.0, 0.0, [&] { return launch_rr_solve(set.bt, 1, 0, rules[0], ctx->stream); }));
+        if (!init_fused)
+            OKCHK(timed(ctx, "rr_init", 0.0, 0.0, [&] { return launch_rr_solve(set.bt, 1, 0, rules[0], ctx->stream); }));
         HIPCHK(hipEventRecord(e1, ctx->stream));
         return SBMDS_OK;
     };

@@ -316,7 +316,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_rr_solve(const ProbView *__re
         phase_control(st, rule, init);
     }
     __syncthreads();
-    publish_summary(st, views[blockIdx.x].host_sum);
+    publish_summary(st, views[blockIdx.x].host_sum, blockDim.x);
 }
 
 hipError_t launch_rr_solve2(const Batch &bt, int init, int max_sweeps, const PhaseRule &rule, hipStream_t s);

@@ -20,6 +20,7 @@
 #include <type_traits>
 
 #include "sbmds_common.h"
+#include "sbmds_rr.h"
 
 namespace sbmds {
 
@@ -264,7 +265,9 @@ struct WideShape {
     static constexpr int NW = kWideThreads / 64;
     static constexpr int TILE_D = RPB * B;
     static constexpr int RED_D = NW * EG;
-    static constexpr int SMEM_D = TILE_D > RED_D ? TILE_D : RED_D;
+    static constexpr int RR_D = (int)((sizeof(RRLds<B>) + 7) / 8);  // the Rayleigh-Ritz step's LDS
+    static constexpr int SMEM_D0 = TILE_D > RED_D ? TILE_D : RED_D;
+    static constexpr int SMEM_D = SMEM_D0 > RR_D ? SMEM_D0 : RR_D;
 };
 
 // Gram and column sums of the wave's RW rows of the tile.
@@ -298,7 +301,7 @@ __device__ __forceinline__ void gram_mfma_rows(const double *__restrict__ tile, 
 // join the tree reduction into st->Ge.  `smem` must be free (all waves past
 // their last use of it).
 template <int M, int B, int TILES>
-__device__ __forceinline__ void gram_mfma_finish(dbl4 (&acc)[TILES], double (&esum)[(B + 15) / 16],
+__device__ __forceinline__ bool gram_mfma_finish(dbl4 (&acc)[TILES], double (&esum)[(B + 15) / 16],
                                                  double *__restrict__ smem, double *__restrict__ red,
                                                  unsigned *__restrict__ cnt, SolveState *__restrict__ st, int vb,
                                                  int vg) {
@@ -337,12 +340,16 @@ __device__ __forceinline__ void gram_mfma_finish(dbl4 (&acc)[TILES], double (&es
         for (int q = 0; q < NW; ++q) s += smem[(size_t)q * EG + e];
         st_coherent(part + e, s);
     }
-    tree_reduce<kFan>(red, EG, vb, vg, cnt, st->Ge);
+    return tree_reduce<kFan>(red, EG, vb, vg, cnt, st->Ge);
 }
 
+// rr: 0 = no Rayleigh-Ritz step, 1 = the iteration's step, 2 = the start's
+// CholQR (init mode); it runs in the block that completes the Gram
+// reduction of its problem.
 template <int M, int B>
 __global__ __launch_bounds__(kWideThreads) void k_spmm_wide(const ProbView *__restrict__ views,
-                                                            const int *__restrict__ off, int nprob, int phase) {
+                                                            const int *__restrict__ off, int nprob, int phase, int rr,
+                                                            int b, int k, int max_sweeps, PhaseRule rule) {
     using Tr = Traits<M>;
     using TA = typename Tr::TA;
     using TY = typename Tr::TY;
@@ -354,7 +361,7 @@ __global__ __launch_bounds__(kWideThreads) void k_spmm_wide(const ProbView *__re
     // mode and width allows without spilling
     constexpr int CH = (M == MODE_FP32 && B <= 16) ? kWideChunk
                        : ((M == MODE_BF16 && B >= 32) ? kWideChunk / 4 : kWideChunk / 2);
-    __shared__ double smem[S::SMEM_D];
+    __shared__ __attribute__((aligned(16))) double smem[S::SMEM_D];
 
     const int p = find_problem(off, nprob, blockIdx.x);
     const ProbView &v = views[p];
@@ -443,7 +450,17 @@ __global__ __launch_bounds__(kWideThreads) void k_spmm_wide(const ProbView *__re
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();  // every wave is done with its tile rows before the reduction reuses smem
-    gram_mfma_finish<M, B, TILES>(acc, esum, smem, v.red_spmm, v.spmm_cnt, st, vb, vg);
+    const bool last = gram_mfma_finish<M, B, TILES>(acc, esum, smem, v.red_spmm, v.spmm_cnt, st, vb, vg);
+    if (rr && last) {  // uniform
+        __syncthreads();  // smem is free again
+        // waves past the step's own threads end here (whole waves: a
+        // barrier waits only for the waves that have not ended), so the
+        // step's barriers involve only its threads
+        constexpr int NTR = RRShape<B>::NT;
+        static_assert(NTR % 64 == 0 && NTR <= kWideThreads, "whole waves");
+        if (threadIdx.x >= NTR) return;
+        rr_step<B, NTR>(v, *reinterpret_cast<RRLds<B> *>(smem), b, k, kPivTol, rr == 2, max_sweeps, rule);
+    }
 }
 
 // Gram matrix and column sums of the start block in buffer 0 (same
@@ -857,14 +874,19 @@ __global__ __launch_bounds__(256) void k_f32_to_bf16(int64_t count, const float 
         default: return hipErrorInvalidValue;                              \
     }
 
-hipError_t launch_spmm(Mode m, const Batch &bt, int phase, hipStream_t s) {
+bool spmm_runs_rr(int B) { return wide_width(B); }
+
+hipError_t launch_spmm(Mode m, const Batch &bt, int phase, hipStream_t s, int rr, int max_sweeps,
+                       const PhaseRule &rule) {
     const int grid = bt.total[BK_SPMM][m];
     if (grid <= 0) return hipErrorInvalidValue;
     const int *off = bt.off(BK_SPMM, m);
     SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(bt.B, {
         if constexpr (wide_width(BB))
             hipLaunchKernelGGL((k_spmm_wide<MM, BB>), dim3(grid), dim3(kWideThreads), 0, s, bt.views, off, bt.nprob,
-                               phase);
+                               phase, rr, bt.b, bt.k, max_sweeps, rule);
+        else if (rr)
+            return hipErrorInvalidValue;  // the narrow kernel leaves the step to its own launch
         else
             hipLaunchKernelGGL((k_spmm<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, off, bt.nprob, phase);
         return hipGetLastError();

@@ -439,7 +439,7 @@ int enqueue_iteration(sbmds_ctx *ctx, SolveSet &set, const PhaseRule &r) {
     OKCHK(timed(ctx, ("gemm" + sfx).c_str(), b_gemm, f_ge, [&] { return launch_gemm(m, bt, r.phase, ctx->stream); }));
     if (spmm_runs_rr(bt.B)) {
         // the Rayleigh-Ritz step runs in the SpMM's reducing block
-        OKCHK(timed(ctx, ("spmm+rr" + sfx).c_str(), b_spmm, f_sp,
+        OKCHK(timed(ctx, ("spmm_rr" + sfx).c_str(), b_spmm, f_sp,
                     [&] { return launch_spmm(m, bt, r.phase, ctx->stream, 1, sweep_cap(r), r); }));
     } else {
         OKCHK(timed(ctx, ("spmm" + sfx).c_str(), b_spmm, f_sp, [&] { return launch_spmm(m, bt, r.phase, ctx->stream); }));
@@ -599,7 +599,7 @@ int solve_all(sbmds_ctx *ctx, sbmds_report *reps) {
     auto lift = [&]() -> int {
         init_fused = spmm_runs_rr(set.bt.B);
         if (init_fused)
-            return timed(ctx, "lift+rr_init", 0.0, 0.0,
+            return timed(ctx, "lift_rr_init", 0.0, 0.0,
                          [&] { return launch_spmm(m0, set.bt, 0, ctx->stream, 2, 0, rules[0]); });
         return timed(ctx, "lift", 0.0, 0.0, [&] { return launch_spmm(m0, set.bt, 0, ctx->stream); });
     };

@@ -143,6 +143,44 @@ def train_start_net(sb, torch, configs, k, block):
     return path
 
 
+def spmm_at_scale(sb, torch, steps, n=2_000_000, l=2000, per_row=10, block=8, seed=7):
+    """SpMM bandwidth where HBM, not latency, bounds it: a synthetic operator
+    of n rows with per_row entries each (increasing random columns over l
+    landmarks, no mesh locality), a symmetric l x l W, fp32, block 8; a few
+    uncertified iterations with per-kernel timing.  Not the headline
+    workload: it shows what the SpMM launch reaches once it moves ~250 MB."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    gaps = rng.integers(1, l // (per_row + 1), size=(n, per_row))
+    cols = np.cumsum(gaps, axis=1)
+    cols += rng.integers(0, l - cols[:, -1:], dtype=np.int64)
+    col = cols.astype(np.int32).ravel()
+    rowptr = np.arange(0, n * per_row + 1, per_row, dtype=np.int32)
+    val = rng.random(n * per_row, dtype=np.float32)
+    pts = rng.standard_normal((l, 3))
+    W = ((pts[:, None, :] - pts[None, :, :]) ** 2).sum(-1).astype(np.float32)
+    p = sb.Problem.from_arrays(*(torch.from_numpy(a).cuda() for a in (rowptr, col, val, W)))
+    ctx = sb.Context([p], k=3, block=block, prec=sb.FP32, max_iter=4,
+                     flags=sb.FLAG_KERNEL_TIMING | sb.FLAG_NO_CERTIFY)
+    Z = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    ctx.embed(Z_out=Z)
+    ctx.reset_kernel_stats()
+    for _ in range(max(1, steps // 4)):
+        ctx.embed(Z_out=Z)
+    torch.cuda.synchronize()
+    stats = {s["name"]: s for s in ctx.kernel_stats()}
+    ctx.close()
+    out = {"workload": f"random operator, n={n}, {per_row} entries per row, l={l}, block {block}, fp32"}
+    for name in ("spmm_rr.fp32", "spmm_t.fp32", "gemm.fp32"):
+        s_ = stats.get(name)
+        if s_ and s_["launches"]:
+            us = 1e3 * s_["ms_total"] / s_["launches"]
+            gbs = s_["bytes_total"] / (s_["ms_total"] * 1e-3) / 1e9
+            out[name] = {"avg_us": round(us, 2), "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def cpu_baseline(prob, k, budget_s=20.0):
     """The float64 oracle (l x l reduction route) on the host cores."""
     import numpy as np
@@ -202,6 +240,7 @@ def main():
                     help="comma-separated block widths; every form is timed at each")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-scale", action="store_true", help="skip the bandwidth-bound SpMM measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the landmark-MDS and learned-start forms")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration)")
@@ -286,6 +325,12 @@ def main():
                              os.path.join(configs.cache_dir(), f"tune_batch16_k{k}_b{blocks[0]}.txt"))
         log(f"batched {batched}")
 
+    at_scale = None
+    if not args.no_scale:
+        log("SpMM at a bandwidth-bound size")
+        at_scale = spmm_at_scale(sb, torch, args.steps)
+        log(f"at scale {at_scale}")
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle)")
@@ -341,6 +386,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "batched": batched,
+        "spmm_at_scale": at_scale,
     }
     print(json.dumps(out), flush=True)
 

@@ -34,6 +34,32 @@ __device__ __forceinline__ T down(TA x) { return (T)x; }
 template <>
 __device__ __forceinline__ bf16_t down<bf16_t, float>(float x) { return f2bf(x); }
 
+// Loads and stores through a pointer read out of device memory compile to
+// flat instructions (the pointer is generic), which also count against the
+// LDS wait counter; these access it as global memory.
+template <int S>
+struct UintOf;
+template <>
+struct UintOf<2> {
+    using type = uint16_t;
+};
+template <>
+struct UintOf<4> {
+    using type = uint32_t;
+};
+template <>
+struct UintOf<8> {
+    using type = uint64_t;
+};
+template <typename T>
+__device__ __forceinline__ T gld(const T *p) {
+    using U = typename UintOf<(int)sizeof(T)>::type;
+    const U u = *(const __attribute__((address_space(1))) U *)p;
+    T r;
+    __builtin_memcpy(&r, &u, sizeof(r));
+    return r;
+}
+
 template <typename T, int N>
 struct alignas(sizeof(T) * N) Pack {
     T v[N];
@@ -46,6 +72,32 @@ __device__ __forceinline__ Pack<T, N> ldp(const T *p) {
 template <typename T, int N>
 __device__ __forceinline__ void stp(T *p, const Pack<T, N> &x) {
     *reinterpret_cast<Pack<T, N> *>(p) = x;
+}
+// Global-memory forms of ldp / stp (moved as whole dwords).
+template <int W>
+struct DwordVec {
+    typedef uint32_t type __attribute__((ext_vector_type(W)));
+};
+template <>
+struct DwordVec<1> {
+    typedef uint32_t type;
+};
+template <typename T, int N>
+__device__ __forceinline__ Pack<T, N> ldpg(const T *p) {
+    static_assert(sizeof(T) * N % 4 == 0, "whole dwords");
+    using V = typename DwordVec<(int)(sizeof(T) * N / 4)>::type;
+    const V v = *(const __attribute__((address_space(1))) V *)p;
+    Pack<T, N> r;
+    __builtin_memcpy(&r, &v, sizeof(r));
+    return r;
+}
+template <typename T, int N>
+__device__ __forceinline__ void stpg(T *p, const Pack<T, N> &x) {
+    static_assert(sizeof(T) * N % 4 == 0, "whole dwords");
+    using V = typename DwordVec<(int)(sizeof(T) * N / 4)>::type;
+    V v;
+    __builtin_memcpy(&v, &x, sizeof(v));
+    *(__attribute__((address_space(1))) V *)p = v;
 }
 
 template <int M>

@@ -151,6 +151,7 @@ enum BlockKind { BK_SPMM = 0, BK_SPMMT = 1, BK_GEMM = 2, BK_ELEM_NB = 3, BK_ELEM
 struct Batch {
     int nprob = 0;
     int B = 0, b = 0, k = 0;
+    int64_t max_l = 0;                         // largest landmark count of the batch
     int spmmt_wpr[NUM_MODES] = {4, 4, 4, 4};  // waves per landmark row in the transposed SpMM
     int gemm_mfma[NUM_MODES] = {};             // dense product on the matrix cores
     ProbView *views = nullptr;   // device [nprob]

@@ -986,6 +986,8 @@ int build_batch(sbmds_ctx *ctx, SolveSet &set) {
     bt.B = set.probs[0].B;
     bt.b = set.probs[0].b;
     bt.k = set.probs[0].k;
+    bt.max_l = 0;
+    for (const DevProblem &q : set.probs) bt.max_l = std::max<int64_t>(bt.max_l, q.l);
     for (int m = 0; m < NUM_MODES; ++m) {
         bt.spmmt_wpr[m] = set.tune[m].spmmt_wpr;
         bt.gemm_mfma[m] = set.tune[m].gemm_mfma && gemm_mfma((Mode)m, bt.B) ? 1 : 0;

@@ -346,7 +346,13 @@ __device__ __forceinline__ bool gram_mfma_finish(dbl4 (&acc)[TILES], double (&es
 // rr: 0 = no Rayleigh-Ritz step, 1 = the iteration's step, 2 = the start's
 // CholQR (init mode); it runs in the block that completes the Gram
 // reduction of its problem.
-template <int M, int B>
+// ULDS: the whole l x B block U is first copied to LDS (every 16-byte piece
+// load in flight at once) and the row gathers read it there, one global
+// round trip less per row step; for launches where l B sizeof(U) fits
+// kUldsBytes.
+constexpr int kUldsBytes = 64 * 1024;
+
+template <int M, int B, bool ULDS>
 __global__ __launch_bounds__(kWideThreads) void k_spmm_wide(const ProbView *__restrict__ views,
                                                             const int *__restrict__ off, int nprob, int phase, int rr,
                                                             int b, int k, int max_sweeps, PhaseRule rule) {
@@ -376,6 +382,27 @@ __global__ __launch_bounds__(kWideThreads) void k_spmm_wide(const ProbView *__re
     TY *__restrict__ Y = (TY *)(st->ycur ? v.Y0 : v.Y1);  // writes the other buffer
 
     const int tid = threadIdx.x;
+    const TU *__restrict__ Ug = U;  // where the gathers read: global U, or its copy in LDS
+    if constexpr (ULDS) {
+        static_assert(16 % sizeof(TU) == 0 && (B * sizeof(TU)) % 16 == 0, "whole 16-byte pieces per row");
+        constexpr int NPC = kUldsBytes / 16 / kWideThreads;  // pieces per thread
+        __shared__ __attribute__((aligned(16))) Pack<TU, 16 / sizeof(TU)> Us[kUldsBytes / 16];
+        const int pieces = (int)((size_t)v.l * B * sizeof(TU) / 16);  // <= kUldsBytes / 16 (checked at launch)
+        using PU = Pack<TU, 16 / sizeof(TU)>;
+        PU tmp[NPC];
+#pragma unroll
+        for (int q = 0; q < NPC; ++q) {
+            const int i = tid + q * kWideThreads;
+            if (i < pieces) tmp[q] = ldpg<TU, 16 / sizeof(TU)>(U + (size_t)i * (16 / sizeof(TU)));
+        }
+#pragma unroll
+        for (int q = 0; q < NPC; ++q) {
+            const int i = tid + q * kWideThreads;
+            if (i < pieces) Us[i] = tmp[q];
+        }
+        __syncthreads();
+        Ug = reinterpret_cast<const TU *>(Us);
+    }
     const int g = tid % LPR;
     const int slot = tid / LPR;  // row of the block step; wave w owns slots [w RW, (w + 1) RW)
     const int w = tid >> 6;
@@ -398,16 +425,16 @@ __global__ __launch_bounds__(kWideThreads) void k_spmm_wide(const ProbView *__re
     const int64_t stride = (int64_t)vg * RPB;
     int beg_next = 0, end_next = 0;
     if ((int64_t)vb * RPB + slot < n) {
-        beg_next = rp[(int64_t)vb * RPB + slot];
-        end_next = rp[(int64_t)vb * RPB + slot + 1];
+        beg_next = gld(rp + (int64_t)vb * RPB + slot);
+        end_next = gld(rp + (int64_t)vb * RPB + slot + 1);
     }
     for (int64_t base = (int64_t)vb * RPB; base < n; base += stride) {
         const int64_t row = base + slot;
         const int beg = beg_next, end = end_next;
         // the next step's row bounds are loaded with this step's entries
         if (row + stride < n) {
-            beg_next = rp[row + stride];
-            end_next = rp[row + stride + 1];
+            beg_next = gld(rp + row + stride);
+            end_next = gld(rp + row + stride + 1);
         }
         TA a[VEC];
 #pragma unroll
@@ -419,12 +446,15 @@ __global__ __launch_bounds__(kWideThreads) void k_spmm_wide(const ProbView *__re
 #pragma unroll
                 for (int j = 0; j < CH; ++j) {
                     const bool ok = e0 + j < end;
-                    c[j] = ok ? ci[e0 + j] : 0;  // row 0 of U stands in for missing entries
-                    pv[j] = ok ? up<TA>(val[e0 + j]) : (TA)0;
+                    c[j] = ok ? gld(ci + e0 + j) : 0;  // row 0 of U stands in for missing entries
+                    pv[j] = ok ? up<TA>(gld(val + e0 + j)) : (TA)0;
                 }
                 Pack<TU, VEC> u[CH];
 #pragma unroll
-                for (int j = 0; j < CH; ++j) u[j] = ldp<TU, VEC>(U + (size_t)c[j] * B + g * VEC);
+                for (int j = 0; j < CH; ++j) {
+                    if constexpr (ULDS) u[j] = ldp<TU, VEC>(Ug + (size_t)c[j] * B + g * VEC);
+                    else u[j] = ldpg<TU, VEC>(U + (size_t)c[j] * B + g * VEC);
+                }
 #pragma unroll
                 for (int j = 0; j < CH; ++j) {
 #pragma unroll
@@ -434,7 +464,7 @@ __global__ __launch_bounds__(kWideThreads) void k_spmm_wide(const ProbView *__re
             Pack<TY, VEC> o;
 #pragma unroll
             for (int q = 0; q < VEC; ++q) o.v[q] = down<TY>(a[q] - sc[q]);
-            stp<TY, VEC>(Y + (size_t)row * B + g * VEC, o);
+            stpg<TY, VEC>(Y + (size_t)row * B + g * VEC, o);
 #pragma unroll
             for (int q = 0; q < VEC; ++q) tile[slot * B + g * VEC + q] = (double)up<TA>(o.v[q]);
         } else {
@@ -882,9 +912,18 @@ hipError_t launch_spmm(Mode m, const Batch &bt, int phase, hipStream_t s, int rr
     if (grid <= 0) return hipErrorInvalidValue;
     const int *off = bt.off(BK_SPMM, m);
     SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(bt.B, {
-        if constexpr (wide_width(BB))
-            hipLaunchKernelGGL((k_spmm_wide<MM, BB>), dim3(grid), dim3(kWideThreads), 0, s, bt.views, off, bt.nprob,
-                               phase, rr, bt.b, bt.k, max_sweeps, rule);
+        if constexpr (wide_width(BB)) {
+            using TUU = typename Traits<MM>::TU;
+            if constexpr ((BB * sizeof(TUU)) % 16 == 0 && BB * sizeof(TUU) <= 64) {
+                if ((size_t)bt.max_l * BB * sizeof(TUU) <= (size_t)kUldsBytes) {
+                    hipLaunchKernelGGL((k_spmm_wide<MM, BB, true>), dim3(grid), dim3(kWideThreads), 0, s, bt.views,
+                                       off, bt.nprob, phase, rr, bt.b, bt.k, max_sweeps, rule);
+                    return hipGetLastError();
+                }
+            }
+            hipLaunchKernelGGL((k_spmm_wide<MM, BB, false>), dim3(grid), dim3(kWideThreads), 0, s, bt.views, off,
+                               bt.nprob, phase, rr, bt.b, bt.k, max_sweeps, rule);
+        }
         else if (rr)
             return hipErrorInvalidValue;  // the narrow kernel leaves the step to its own launch
         else

@@ -143,18 +143,28 @@ def train_start_net(sb, torch, configs, k, block):
     return path
 
 
-def spmm_at_scale(sb, torch, steps, n=2_000_000, l=2000, per_row=10, block=8, seed=7):
+def spmm_at_scale(sb, torch, steps, pattern, n=2_000_000, l=2000, per_row=10, block=8, seed=7):
     """SpMM bandwidth where HBM, not latency, bounds it: a synthetic operator
-    of n rows with per_row entries each (increasing random columns over l
-    landmarks, no mesh locality), a symmetric l x l W, fp32, block 8; a few
-    uncertified iterations with per-kernel timing.  Not the headline
-    workload: it shows what the SpMM launch reaches once it moves ~250 MB."""
+    of n rows with per_row entries each over l landmarks, a symmetric l x l
+    W, fp32, block 8; a few uncertified iterations with per-kernel timing.
+    pattern "random": increasing random columns anywhere (no locality, the
+    worst case for the transposed product's gathers of Y); "banded": a row's
+    columns lie within ~3 per_row landmarks of a position that follows the
+    row index, as on a mesh whose vertices and landmarks are both in spatial
+    order.  Not the headline workload: it shows what the kernels reach once a
+    launch moves ~250 MB."""
     import numpy as np
 
     rng = np.random.default_rng(seed)
-    gaps = rng.integers(1, l // (per_row + 1), size=(n, per_row))
-    cols = np.cumsum(gaps, axis=1)
-    cols += rng.integers(0, l - cols[:, -1:], dtype=np.int64)
+    if pattern == "random":
+        gaps = rng.integers(1, l // (per_row + 1), size=(n, per_row))
+        cols = np.cumsum(gaps, axis=1)
+        cols += rng.integers(0, l - cols[:, -1:], dtype=np.int64)
+    else:
+        gaps = rng.integers(1, 4, size=(n, per_row))
+        cols = np.cumsum(gaps, axis=1)
+        span = int(cols[:, -1].max())
+        cols += (np.arange(n, dtype=np.int64) * (l - 1 - span) // n)[:, None]
     col = cols.astype(np.int32).ravel()
     rowptr = np.arange(0, n * per_row + 1, per_row, dtype=np.int32)
     val = rng.random(n * per_row, dtype=np.float32)
@@ -171,7 +181,7 @@ def spmm_at_scale(sb, torch, steps, n=2_000_000, l=2000, per_row=10, block=8, se
     torch.cuda.synchronize()
     stats = {s["name"]: s for s in ctx.kernel_stats()}
     ctx.close()
-    out = {"workload": f"random operator, n={n}, {per_row} entries per row, l={l}, block {block}, fp32"}
+    out = {"workload": f"{pattern} operator, n={n}, {per_row} entries per row, l={l}, block {block}, fp32"}
     for name in ("spmm_rr.fp32", "spmm_t.fp32", "gemm.fp32"):
         s_ = stats.get(name)
         if s_ and s_["launches"]:
@@ -328,7 +338,7 @@ def main():
     at_scale = None
     if not args.no_scale:
         log("SpMM at a bandwidth-bound size")
-        at_scale = spmm_at_scale(sb, torch, args.steps)
+        at_scale = {pat: spmm_at_scale(sb, torch, args.steps, pat) for pat in ("banded", "random")}
         log(f"at scale {at_scale}")
 
     cpu = None

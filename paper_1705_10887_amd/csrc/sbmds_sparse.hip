@@ -263,7 +263,10 @@ struct WideShape {
     static constexpr int E = B * (B + 1) / 2;
     static constexpr int EG = E + B;
     static constexpr int NW = kWideThreads / 64;
-    static constexpr int TILE_D = RPB * B;
+    static constexpr int WREG = 512;                                     // LDS doubles per wave (4 KB)
+    static constexpr int CAPW = (int)(WREG * 8 / (4 + sizeof(TP)));      // CSR entries a wave stages
+    static_assert(RW * B <= WREG, "a wave's tile rows fit its region");
+    static constexpr int TILE_D = NW * WREG;
     static constexpr int RED_D = NW * EG;
     static constexpr int RR_D = (int)((sizeof(RRLds<B>) + 7) / 8);  // the Rayleigh-Ritz step's LDS
     static constexpr int SMEM_D0 = TILE_D > RED_D ? TILE_D : RED_D;
@@ -365,8 +368,11 @@ __global__ __launch_bounds__(kWideThreads) void k_spmm_wide(const ProbView *__re
     constexpr int VEC = S::VEC, LPR = S::LPR, RPB = S::RPB, RW = S::RW, TILES = S::TILES, NTB = S::NTB;
     // entries in flight per lane: as many as the register budget of the
     // mode and width allows without spilling
-    constexpr int CH = (M == MODE_FP32 && B <= 16) ? kWideChunk
-                       : ((M == MODE_BF16 && B >= 32) ? kWideChunk / 4 : kWideChunk / 2);
+    // (gathers from LDS need fewer in flight)
+    constexpr int CH = ULDS ? kWideChunk / 2
+                            : ((M == MODE_FP32 && B <= 16) ? kWideChunk
+                                                           : ((M == MODE_BF16 && B >= 32) ? kWideChunk / 4
+                                                                                          : kWideChunk / 2));
     __shared__ __attribute__((aligned(16))) double smem[S::SMEM_D];
 
     const int p = find_problem(off, nprob, blockIdx.x);
@@ -406,7 +412,6 @@ __global__ __launch_bounds__(kWideThreads) void k_spmm_wide(const ProbView *__re
     const int g = tid % LPR;
     const int slot = tid / LPR;  // row of the block step; wave w owns slots [w RW, (w + 1) RW)
     const int w = tid >> 6;
-    double *tile = smem;  // rows of wave w: [w RW, (w + 1) RW)
     const double inv_n = 1.0 / (double)n;
     TA sc[VEC];
 #pragma unroll
@@ -419,9 +424,17 @@ __global__ __launch_bounds__(kWideThreads) void k_spmm_wide(const ProbView *__re
     for (int ti = 0; ti < NTB; ++ti) esum[ti] = 0.0;
 
     // Each wave works through its own rows with no block barrier: the row's
-    // bounds, then its entries CH at a time (all index, value and U loads of
-    // a chunk in flight together), the output row, and the Gram of the
-    // wave's rows from its own LDS rows.
+    // bounds, then the wave's whole CSR slice (its rows' entries are
+    // contiguous) copied to its LDS region with coalesced loads, then each
+    // row's entries CH at a time (all U loads of a chunk in flight
+    // together), the output row, and the Gram of the wave's rows from its
+    // own LDS rows (the same region: the slice is consumed by then).
+    constexpr int WREG = S::WREG, CAPW = S::CAPW, NQ = (CAPW + 63) / 64;
+    const int lane = tid & 63;
+    double *__restrict__ wreg = smem + (size_t)w * WREG;
+    int32_t *__restrict__ sci = reinterpret_cast<int32_t *>(wreg);
+    TP *__restrict__ sval = reinterpret_cast<TP *>(sci + CAPW);
+    const int rw = slot - w * RW;  // row within the wave
     const int64_t stride = (int64_t)vg * RPB;
     int beg_next = 0, end_next = 0;
     if ((int64_t)vb * RPB + slot < n) {
@@ -436,6 +449,34 @@ __global__ __launch_bounds__(kWideThreads) void k_spmm_wide(const ProbView *__re
             beg_next = gld(rp + row + stride);
             end_next = gld(rp + row + stride + 1);
         }
+        // the wave's slice [E0, E1): rows past n have empty bounds
+        const int E0 = __shfl(beg, 0);
+        int E1 = end;
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) E1 = max(E1, __shfl_xor(E1, m));
+        const bool staged = E1 - E0 <= CAPW;  // uniform in the wave
+        if (staged) {
+            const int cnt = E1 - E0;
+            int ct[NQ];
+            TP vt[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int i = lane + 64 * q;
+                ct[q] = i < cnt ? gld(ci + E0 + i) : 0;
+                vt[q] = i < cnt ? gld(val + E0 + i) : TP{};
+            }
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int i = lane + 64 * q;
+                if (i < cnt) {
+                    sci[i] = ct[q];
+                    sval[i] = vt[q];
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
         TA a[VEC];
 #pragma unroll
         for (int q = 0; q < VEC; ++q) a[q] = (TA)0;
@@ -446,8 +487,14 @@ __global__ __launch_bounds__(kWideThreads) void k_spmm_wide(const ProbView *__re
 #pragma unroll
                 for (int j = 0; j < CH; ++j) {
                     const bool ok = e0 + j < end;
-                    c[j] = ok ? gld(ci + e0 + j) : 0;  // row 0 of U stands in for missing entries
-                    pv[j] = ok ? up<TA>(gld(val + e0 + j)) : (TA)0;
+                    // row 0 of U stands in for missing entries
+                    if (staged) {
+                        c[j] = ok ? sci[e0 - E0 + j] : 0;
+                        pv[j] = ok ? up<TA>(sval[e0 - E0 + j]) : (TA)0;
+                    } else {
+                        c[j] = ok ? gld(ci + e0 + j) : 0;
+                        pv[j] = ok ? up<TA>(gld(val + e0 + j)) : (TA)0;
+                    }
                 }
                 Pack<TU, VEC> u[CH];
 #pragma unroll
@@ -461,22 +508,26 @@ __global__ __launch_bounds__(kWideThreads) void k_spmm_wide(const ProbView *__re
                     for (int q = 0; q < VEC; ++q) a[q] += pv[j] * up<TA>(u[j].v[q]);
                 }
             }
+        }
+        // every read of the slice is issued before the tile rows overwrite it
+        __builtin_amdgcn_wave_barrier();
+        if (row < n) {
             Pack<TY, VEC> o;
 #pragma unroll
             for (int q = 0; q < VEC; ++q) o.v[q] = down<TY>(a[q] - sc[q]);
             stpg<TY, VEC>(Y + (size_t)row * B + g * VEC, o);
 #pragma unroll
-            for (int q = 0; q < VEC; ++q) tile[slot * B + g * VEC + q] = (double)up<TA>(o.v[q]);
+            for (int q = 0; q < VEC; ++q) wreg[rw * B + g * VEC + q] = (double)up<TA>(o.v[q]);
         } else {
 #pragma unroll
-            for (int q = 0; q < VEC; ++q) tile[slot * B + g * VEC + q] = 0.0;
+            for (int q = 0; q < VEC; ++q) wreg[rw * B + g * VEC + q] = 0.0;
         }
         // the wave's rows are complete in LDS (one wave: in-order LDS, no
         // block barrier), and are read back only by this wave
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        gram_mfma_rows<B, RW, TILES>(tile, w * RW, acc, esum);
+        gram_mfma_rows<B, RW, TILES>(wreg, 0, acc, esum);
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();  // every wave is done with its tile rows before the reduction reuses smem

@@ -641,26 +641,36 @@ __device__ __forceinline__ void spmm_t_body(const ProbView *__restrict__ views, 
     if (j < l) {
         const int beg = rpT[j], end = rpT[j + 1];
         constexpr int STEP = EPW * WPR;
-        // CHT entries per lane at a time: all their index, value and Y loads
-        // in flight together (missing entries read row 0 with weight 0)
+        // CHT entries per lane at a time: all their Y loads in flight
+        // together (missing entries read row 0 with weight 0), and the next
+        // chunk's indices and values loaded while they are
         constexpr int CHT = kSpmmTChunk;
-        for (int e = beg + wsub * EPW + slot; e < end; e += CHT * STEP) {
-            int vi[CHT];
-            TA pv[CHT];
+        int vi[CHT];
+        TA pv[CHT];
+        auto load_chunk = [&](int e) {
 #pragma unroll
             for (int q = 0; q < CHT; ++q) {
                 const int idx = e + q * STEP;
                 const bool ok = idx < end;
-                vi[q] = ok ? ciT[idx] : 0;
-                pv[q] = ok ? up<TA>(valT[idx]) : (TA)0;
+                vi[q] = ok ? gld(ciT + idx) : 0;
+                pv[q] = ok ? up<TA>(gld(valT + idx)) : (TA)0;
             }
+        };
+        int e = beg + wsub * EPW + slot;
+        load_chunk(e);
+        for (; e < end; e += CHT * STEP) {
             Pack<TY, VEC> y[CHT];
+            TA pc[CHT];
 #pragma unroll
-            for (int q = 0; q < CHT; ++q) y[q] = ldp<TY, VEC>(Y + (size_t)vi[q] * B + g * VEC);
+            for (int q = 0; q < CHT; ++q) {
+                y[q] = ldpg<TY, VEC>(Y + (size_t)vi[q] * B + g * VEC);
+                pc[q] = pv[q];
+            }
+            load_chunk(e + CHT * STEP);
 #pragma unroll
             for (int q = 0; q < CHT; ++q) {
 #pragma unroll
-                for (int r = 0; r < VEC; ++r) acc[r] += pv[q] * up<TA>(y[q].v[r]);
+                for (int r = 0; r < VEC; ++r) acc[r] += pc[q] * up<TA>(y[q].v[r]);
             }
         }
     }

@@ -63,6 +63,17 @@ def test_random_operator_all_widths(gpu, block):
     check(prob, Z, eig, rep, k, 1e-6)
 
 
+@pytest.mark.parametrize("prec", ["FP32", "BF16_FP32"])
+def test_block8_u_past_lds_copy(gpu, prec):
+    # l x 8 x 4 bytes above 64 KB: the SpMM gathers U from global memory
+    # instead of its LDS copy (the other width-8 tests use the copy)
+    sb = gpu
+    prob = H.random_problem(n=6000, l=2100, row_len_max=12, seed=81, empty_rows=0.05, long_rows=2)
+    Z, eig, rep, rc, _ = run(sb, prob, 3, 8, getattr(sb, prec), max_iter=300)
+    assert rc == 0 and rep["certified"]
+    check(prob, Z, eig, rep, 3, 1e-6)
+
+
 def test_random_operator_fp64_ragged(gpu):
     sb = gpu
     prob = H.random_problem(n=3001, l=130, row_len_max=20, seed=7, dtype=np.float64, empty_rows=0.1,

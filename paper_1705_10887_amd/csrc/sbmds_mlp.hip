@@ -499,7 +499,9 @@ hipError_t launch_gemm(int epi, const float *A, int64_t M, int K, int64_t sam, i
     return hipGetLastError();
 }
 
-int wgrad_chunks(int64_t M) { return (int)std::min<int64_t>(256, std::max<int64_t>(1, (M + 2047) / 2048)); }
+// Row chunks of the weight gradient: ~64 rows each (enough blocks to fill
+// the device at a few thousand rows), at most 256 partials to sum.
+int wgrad_chunks(int64_t M) { return (int)std::min<int64_t>(256, std::max<int64_t>(1, (M + 63) / 64)); }
 
 hipError_t launch_wgrad(const float *A, int64_t M, int K, const float *D, int N, float *part, float *gW, float *gb,
                         hipStream_t s) {

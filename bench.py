@@ -151,8 +151,9 @@ def spmm_at_scale(sb, torch, steps, pattern, n=2_000_000, l=2000, per_row=10, bl
     worst case for the transposed product's gathers of Y); "banded": a row's
     columns lie within ~3 per_row landmarks of a position that follows the
     row index, as on a mesh whose vertices and landmarks are both in spatial
-    order.  Not the headline workload: it shows what the kernels reach once a
-    launch moves ~250 MB."""
+    order (W then comes from landmarks along a helix in column order).  Launch
+    shapes from the autotuner.  Not the headline workload: it shows what the
+    kernels reach once a launch moves ~250 MB."""
     import numpy as np
 
     rng = np.random.default_rng(seed)
@@ -168,11 +169,19 @@ def spmm_at_scale(sb, torch, steps, pattern, n=2_000_000, l=2000, per_row=10, bl
     col = cols.astype(np.int32).ravel()
     rowptr = np.arange(0, n * per_row + 1, per_row, dtype=np.int32)
     val = rng.random(n * per_row, dtype=np.float32)
-    pts = rng.standard_normal((l, 3))
+    if pattern == "random":
+        pts = rng.standard_normal((l, 3))
+    else:
+        # landmarks along a helix in column order, so that W (the squared
+        # distances) agrees with the band: landmarks close in W share rows
+        t = np.arange(l) / l
+        pts = np.stack([np.cos(16 * np.pi * t), np.sin(16 * np.pi * t), 8 * t], axis=1)
     W = ((pts[:, None, :] - pts[None, :, :]) ** 2).sum(-1).astype(np.float32)
     p = sb.Problem.from_arrays(*(torch.from_numpy(a).cuda() for a in (rowptr, col, val, W)))
+    from synth import configs
+    tune = os.path.join(configs.cache_dir(), f"tune_scale_{pattern}_n{n}_l{l}_b{block}.txt")
     ctx = sb.Context([p], k=3, block=block, prec=sb.FP32, max_iter=4,
-                     flags=sb.FLAG_KERNEL_TIMING | sb.FLAG_NO_CERTIFY)
+                     flags=sb.FLAG_KERNEL_TIMING | sb.FLAG_NO_CERTIFY, tune_cache=tune)
     Z = torch.empty((n, 3), dtype=torch.float32, device="cuda")
     ctx.embed(Z_out=Z)
     ctx.reset_kernel_stats()
@@ -188,6 +197,54 @@ def spmm_at_scale(sb, torch, steps, pattern, n=2_000_000, l=2000, per_row=10, bl
             us = 1e3 * s_["ms_total"] / s_["launches"]
             gbs = s_["bytes_total"] / (s_["ms_total"] * 1e-3) / 1e9
             out[name] = {"avg_us": round(us, 2), "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
+
+
+def precision_workload(sb, torch, configs, steps, warmup, k, blocks):
+    """The bumpy torus of 1024 x 512 vertices with 10,000 landmarks (W 400 MB
+    in float32, the dense product's bytes dominate): plain fp32 against the
+    bf16 bulk form, each from the random start, with the per-kernel rates of
+    the faster one.  Uses only an input already generated (about an hour of
+    host time); None otherwise."""
+    import numpy as np
+    prob = configs.bumpy_torus(1024, 512, l=10000, generate=False)
+    if prob is None:
+        log("precision workload skipped: the 1024 x 512 torus input is not generated")
+        return None
+    forms = {}
+    for block in blocks:
+        tune = os.path.join(configs.cache_dir(), f"tune_torus1024x512_k{k}_b{block}.txt")
+        for name, prec in (("fp32", sb.FP32), ("bf16_fp32", sb.BF16_FP32)):
+            ms, eig, rep, _ = time_form(sb, torch, prob, prec, steps, warmup, k, block, tune_cache=tune)
+            forms[f"{name}/b{block}"] = (ms, eig, rep, prec, block, tune)
+            log(f"torus {name}/b{block} {ms:.3f} ms  iters {rep['iters_bf16']}+{rep['iters_fp32']}+"
+                f"{rep['iters_fp64']}")
+    chosen = min(forms, key=lambda f: forms[f][0])
+    ms, eig, rep, prec, block, tune = forms[chosen]
+    plain = forms[f"fp32/b{blocks[0]}"][0]
+    _, _, _, stats = time_form(sb, torch, prob, prec, steps, 1, k, block, flags=sb.FLAG_KERNEL_TIMING,
+                               tune_cache=tune)
+    out = {
+        "workload": "bumpy torus 1024 x 512 (n=524288), l=10000 FPS landmarks, p_row=10 "
+                    f"(nnz={len(prob['col'])}), W=D^2_ll float32, k={k}",
+        "forms_ms": {f: round(v[0], 4) for f, v in forms.items()},
+        "chosen": chosen, "ms": round(ms, 4), "plain_fp32_ms": round(plain, 4),
+        "chosen_over_plain": round(plain / ms, 3),
+        "iters": {"bf16": rep["iters_bf16"], "fp32": rep["iters_fp32"], "fp64": rep["iters_fp64"]},
+        "err_bound": max(rep["err_bound"][:k]),
+        "kernels": {s["name"]: {"avg_us": round(1e3 * s["ms_total"] / max(s["launches"], 1), 2),
+                                **({"GB/s": round(s["bytes_total"] / (s["ms_total"] * 1e-3) / 1e9, 1),
+                                    "frac": round(s["bytes_total"] / (s["ms_total"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                                  4)}
+                                   if s["bytes_total"] > 0 else {})} for s in stats},
+    }
+    gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                        "bumpy_torus1024x512_l10000.npz")
+    if os.path.exists(gold):
+        g = np.load(gold, allow_pickle=False)
+        if json.loads(str(g["meta"]))["input_sha1"] == configs.input_digest(prob):
+            lam = g["lam"][:k]
+            out["rel_eig_err_vs_stored_oracle"] = float(np.max(np.abs(np.asarray(eig) - lam) / np.abs(lam)))
     return out
 
 
@@ -252,6 +309,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-scale", action="store_true", help="skip the bandwidth-bound SpMM measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the landmark-MDS and learned-start forms")
+    ap.add_argument("--no-torus", action="store_true", help="skip the 1024 x 512 torus, 10,000-landmark workload")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -341,6 +399,12 @@ def main():
         at_scale = {pat: spmm_at_scale(sb, torch, args.steps, pat) for pat in ("banded", "random")}
         log(f"at scale {at_scale}")
 
+    torus = None
+    if not args.no_torus:
+        log("precision workload: 1024 x 512 torus, 10,000 landmarks")
+        torus = precision_workload(sb, torch, configs, args.steps, args.warmup, k, blocks)
+        log(f"torus {torus}")
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle)")
@@ -397,6 +461,7 @@ def main():
         "cpu_baseline": cpu,
         "batched": batched,
         "spmm_at_scale": at_scale,
+        "precision_workload": torus,
     }
     print(json.dumps(out), flush=True)
 

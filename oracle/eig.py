@@ -31,7 +31,8 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-__all__ = ["b_matrix", "top_k", "embed", "canonical_signs", "centered_gram"]
+__all__ = ["b_matrix", "top_k", "embed", "canonical_signs", "centered_gram", "reduction_coefficients",
+           "vectors_from_coefficients"]
 
 
 def _as_csr64(P) -> sp.csr_matrix:
@@ -82,9 +83,10 @@ def centered_gram(P) -> np.ndarray:
     return G - np.outer(c, c) / n
 
 
-def _top_reduction(P, W, k, rank_tol=1e-12):
+def reduction_coefficients(P, W, k, rank_tol=1e-12):
+    """The reduction route's k largest eigenvalues of B and coefficients C
+    (l x k) with eigenvectors V = J P C (orthonormal columns)."""
     P = _as_csr64(P)
-    n, l = P.shape
     W = np.asarray(W, dtype=np.float64)
     G = centered_gram(P)
     sig, Ug = np.linalg.eigh(G)
@@ -98,11 +100,21 @@ def _top_reduction(P, W, k, rank_tol=1e-12):
     S = 0.5 * (S + S.T)
     lam, Yr = np.linalg.eigh(S)
     order = np.argsort(-lam, kind="stable")[:k]
-    lam = lam[order]
-    coef = Ug @ (Yr[:, order] / sh[:, None])       # l x k
+    return lam[order], Ug @ (Yr[:, order] / sh[:, None])
+
+
+def vectors_from_coefficients(P, coef) -> np.ndarray:
+    """V = J P C (n x k) for coefficients from reduction_coefficients."""
+    P = _as_csr64(P)
+    n = P.shape[0]
+    coef = np.asarray(coef, dtype=np.float64)
     c = np.asarray(P.sum(axis=0)).ravel()
-    vec = P @ coef - np.outer(np.ones(n), c @ coef) / n
-    return _finish(lam, vec, k)
+    return P @ coef - np.outer(np.ones(n), c @ coef) / n
+
+
+def _top_reduction(P, W, k, rank_tol=1e-12):
+    lam, coef = reduction_coefficients(P, W, k, rank_tol)
+    return _finish(lam, vectors_from_coefficients(P, coef), k)
 
 
 def _top_arpack(P, W, k, tol=1e-12, ncv=None, v0_seed=0):

@@ -102,10 +102,12 @@ def _restore(path):
     return prob
 
 
-def _cached(name, params, make, use_cache=True, log=None):
+def _cached(name, params, make, use_cache=True, log=None, generate=True):
     path = os.path.join(cache_dir(), _key(name, params) + ".npz")
     if use_cache and os.path.exists(path):
         return _restore(path)
+    if not generate:
+        return None
     if log:
         log(f"generating {name} {params}")
     prob = make()
@@ -137,7 +139,10 @@ def sphere7(p_row=10, l=2000, seed=2002, level=7, use_cache=True, log=None):
     return _cached(f"sphere{level}", params, make, use_cache, log)
 
 
-def bumpy_torus(nu, nv, l=None, p_row=10, seed=3003, use_cache=True, log=None):
+def bumpy_torus(nu, nv, l=None, p_row=10, seed=3003, use_cache=True, log=None, generate=True):
+    """Bumpy torus of nu x nv vertices.  With ``generate=False`` only a cached
+    input is returned (None when there is none): the 1024 x 512 torus with
+    10,000 landmarks takes about an hour of host time to generate."""
     n = nu * nv
     l = l if l is not None else max(2, round(n / 50))
     params = dict(nu=nu, nv=nv, l=l, p_row=p_row, seed=seed, v=1)
@@ -146,7 +151,7 @@ def bumpy_torus(nu, nv, l=None, p_row=10, seed=3003, use_cache=True, log=None):
         V, F = meshes.bumpy_torus(nu, nv, seed)
         return build_problem(V, F, l, p_row, seed, np.float32, log=log)
 
-    return _cached(f"bumpy_torus{nu}x{nv}", params, make, use_cache, log)
+    return _cached(f"bumpy_torus{nu}x{nv}", params, make, use_cache, log, generate)
 
 
 def mesh_batch(count=16, nmin=2000, nmax=20000, seed0=4004, p_row=10, use_cache=True, log=None):
@@ -199,6 +204,18 @@ def sphere_family(count=12, level=5, seed0=7001, p_row=10, use_cache=True, log=N
 
         out.append(_cached(f"sphere{level}", params, make, use_cache, log))
     return out
+
+
+def input_digest(prob) -> str:
+    """sha1 over the arrays handed to the path (rowptr, col, val, W), to tie
+    stored expected values to the exact input they were computed from."""
+    h = hashlib.sha1()
+    for k in ("rowptr", "col", "val", "W"):
+        a = np.ascontiguousarray(prob[k])
+        h.update(str(a.dtype).encode())
+        h.update(str(a.shape).encode())
+        h.update(a.tobytes())
+    return h.hexdigest()
 
 
 def load(name: str, **kw):

@@ -4,9 +4,13 @@ Tolerances: 1e-6 relative eigenvalue error for float32 / bf16+fp32 solves
 (the target of the method's measurement), 1e-10 for the FP64 solve.  The
 oracle sees exactly the float32-rounded operator handed to the GPU.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
+from oracle import eig as oeig
 from synth import configs
 from tests import helpers as H
 
@@ -25,6 +29,10 @@ def check(prob, Z, eig, rep, k, tol, angle_tol=3.0):
     """Eigenvalues within `tol`; eigenvector clusters within `angle_tol` times
     the angle that a `tol`-accurate Ritz value implies (see helpers)."""
     lam, V, _ = H.oracle_for(prob, k)
+    return check_against(prob, lam, V, Z, eig, rep, k, tol, angle_tol)
+
+
+def check_against(prob, lam, V, Z, eig, rep, k, tol, angle_tol=3.0):
     err = H.rel_eig_err(eig, lam[:k])
     ang = H.subspace_angle(Z, V, lam, k, tol=tol)
     print(f"n={prob['n']} l={prob['l']} k={k} err={err:.3e} angle={ang:.3e} rep={rep['iters_bf16']},"
@@ -110,6 +118,32 @@ def test_sphere7_bf16_fp32(gpu, block):
     assert rc == 0 and rep["certified"]
     assert rep["iters_bf16"] >= 1
     check(prob, Z, eig, rep, 3, 1e-6)
+
+
+GOLDEN_TORUS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                            "bumpy_torus1024x512_l10000.npz")
+
+
+@pytest.mark.parametrize("prec", ["BF16_FP32", "FP32"])
+def test_bumpy_torus1024x512_l10000(gpu, prec):
+    # the precision workload at full size: n = 524,288, l = 10,000, W 400 MB
+    # in float32; the oracle's eigenpairs (reduction route, float64) are
+    # stored, since its two l x l eigendecompositions take minutes
+    sb = gpu
+    prob = configs.bumpy_torus(1024, 512, l=10000, generate=False)
+    if prob is None:
+        pytest.skip("the 1024 x 512 torus input is not generated (about an hour of host time)")
+    if not os.path.exists(GOLDEN_TORUS):
+        pytest.skip("stored oracle values missing (tests/golden/make_bumpy_torus1024x512.py writes them)")
+    g = np.load(GOLDEN_TORUS, allow_pickle=False)
+    meta = json.loads(str(g["meta"]))
+    assert meta["input_sha1"] == configs.input_digest(prob), "input differs from the one the stored values are for"
+    Z, eig, rep, rc, _ = run(sb, prob, 3, 16, getattr(sb, prec))
+    assert rc == 0 and rep["certified"]
+    if prec == "BF16_FP32":
+        assert rep["iters_bf16"] >= 1
+    V = oeig.canonical_signs(oeig.vectors_from_coefficients(configs.operator_rounded(prob), g["coef"]))
+    check_against(prob, g["lam"], V, Z, eig, rep, 3, 1e-6)
 
 
 def test_tiny_landmark_count(gpu):

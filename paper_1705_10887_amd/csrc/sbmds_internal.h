@@ -111,6 +111,7 @@ struct Tune {
     int gemm_mfma = 0;
     int gemm_target = 1024;
     int spmmt_wpr = 4;
+    int spmm_wpe = 4;  // row-split SpMM (widths 8-32): 4 = fused Rayleigh-Ritz form, 8 = two blocks per CU
 };
 
 // Launch geometry of one problem in one mode (derived from a Tune).
@@ -154,6 +155,7 @@ struct Batch {
     int64_t max_l = 0;                         // largest landmark count of the batch
     int spmmt_wpr[NUM_MODES] = {4, 4, 4, 4};  // waves per landmark row in the transposed SpMM
     int gemm_mfma[NUM_MODES] = {};             // dense product on the matrix cores
+    int spmm_wpe8[NUM_MODES] = {};             // row-split SpMM in its two-blocks-per-CU form
     ProbView *views = nullptr;   // device [nprob]
     int *offs = nullptr;         // device [NUM_BK][NUM_MODES][nprob + 1]
     int total[NUM_BK][NUM_MODES] = {};
@@ -168,8 +170,10 @@ hipError_t launch_spmm_t(Mode m, const Batch &bt, int phase, hipStream_t stream)
 hipError_t launch_gemm(Mode m, const Batch &bt, int phase, hipStream_t stream);
 // rr = 1 (2): the SpMM also runs the iteration's Rayleigh-Ritz step (the
 // start's CholQR) in the block that completes its Gram reduction; only for
-// widths where spmm_runs_rr(B).
-bool spmm_runs_rr(int B);
+// batches where spmm_runs_rr(bt, m).
+bool spmm_runs_rr(const Batch &bt, Mode m);
+// Widths whose row-split SpMM also has the two-blocks-per-CU form.
+bool spmm_has_two_block_form(int B);
 hipError_t launch_spmm(Mode m, const Batch &bt, int phase, hipStream_t stream, int rr = 0, int max_sweeps = 0,
                        const PhaseRule &rule = PhaseRule{});
 hipError_t launch_rr_solve(const Batch &bt, int init, int max_sweeps, const PhaseRule &rule,

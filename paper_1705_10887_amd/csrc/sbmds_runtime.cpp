@@ -330,6 +330,11 @@ Tune default_tune(Mode m, const std::vector<DevProblem> &probs) {
     const bool f64 = m == MODE_F64ACC || m == MODE_FP64;
     t.gemm_mfma = (gemm_mfma(m, B) && (f64 || l2 * 4.0 > 64e6)) ? 1 : 0;
     t.gemm_target = t.gemm_mfma ? 512 : 1024;
+    // the two-blocks-per-CU SpMM once a launch streams enough bytes that
+    // bandwidth, not the latency of the separate Rayleigh-Ritz launch, counts
+    double sp_bytes = 0;
+    for (const DevProblem &p : probs) sp_bytes += spmm_bytes(m, p);
+    t.spmm_wpe = sp_bytes > 48e6 ? 8 : 4;
     const double per_row = nnz / l;  // mean entries per landmark column of P
     t.spmmt_wpr = per_row >= 256 ? 4 : (per_row >= 64 ? 2 : 1);
     return t;
@@ -437,7 +442,7 @@ int enqueue_iteration(sbmds_ctx *ctx, SolveSet &set, const PhaseRule &r) {
     const std::string sfx = std::string(".") + mname[m];
     OKCHK(timed(ctx, ("spmm_t" + sfx).c_str(), b_spmmt, f_sp, [&] { return launch_spmm_t(m, bt, r.phase, ctx->stream); }));
     OKCHK(timed(ctx, ("gemm" + sfx).c_str(), b_gemm, f_ge, [&] { return launch_gemm(m, bt, r.phase, ctx->stream); }));
-    if (spmm_runs_rr(bt.B)) {
+    if (spmm_runs_rr(bt, m)) {
         // the Rayleigh-Ritz step runs in the SpMM's reducing block
         OKCHK(timed(ctx, ("spmm_rr" + sfx).c_str(), b_spmm, f_sp,
                     [&] { return launch_spmm(m, bt, r.phase, ctx->stream, 1, sweep_cap(r), r); }));
@@ -597,7 +602,7 @@ int solve_all(sbmds_ctx *ctx, sbmds_report *reps) {
     // the lift Y0 = P X_l: one SpMM, which also runs the first CholQR where
     // the width allows
     auto lift = [&]() -> int {
-        init_fused = spmm_runs_rr(set.bt.B);
+        init_fused = spmm_runs_rr(set.bt, m0);
         if (init_fused)
             return timed(ctx, "lift_rr_init", 0.0, 0.0,
                          [&] { return launch_spmm(m0, set.bt, 0, ctx->stream, 2, 0, rules[0]); });
@@ -745,6 +750,10 @@ int time_launch(sbmds_ctx *ctx, F &&launch, double *ms_out) {
     return SBMDS_OK;
 }
 
+// Time of a standalone Rayleigh-Ritz launch (b <= 32, measured on the
+// device), charged to the SpMM form that does not run the step itself.
+constexpr double kRrLaunchMs = 0.010;
+
 int autotune(sbmds_ctx *ctx, SolveSet &set) {
     const char *path = ctx->opt.tune_cache;
     auto cache = read_cache(path);
@@ -757,10 +766,11 @@ int autotune(sbmds_ctx *ctx, SolveSet &set) {
         bool found = false;
         for (const auto &e : cache) {
             if (e.first != key) continue;
-            Tune t;
-            if (std::sscanf(e.second.c_str(), "%d %d %d %d", &t.spmm_cap, &t.gemm_mfma, &t.gemm_target,
-                            &t.spmmt_wpr) == 4 &&
-                t.spmm_cap >= 1 && t.gemm_target >= 1 && (t.spmmt_wpr == 1 || t.spmmt_wpr == 2 || t.spmmt_wpr == 4)) {
+            Tune t = set.tune[m];  // fields the entry does not carry keep their defaults
+            const int got = std::sscanf(e.second.c_str(), "%d %d %d %d %d", &t.spmm_cap, &t.gemm_mfma,
+                                        &t.gemm_target, &t.spmmt_wpr, &t.spmm_wpe);
+            if (got >= 4 && t.spmm_cap >= 1 && t.gemm_target >= 1 &&
+                (t.spmmt_wpr == 1 || t.spmmt_wpr == 2 || t.spmmt_wpr == 4) && (t.spmm_wpe == 4 || t.spmm_wpe == 8)) {
                 set.tune[m] = t;
                 found = true;
             }
@@ -809,8 +819,31 @@ int autotune(sbmds_ctx *ctx, SolveSet &set) {
                     spmm_cands.push_back((int)c);
             }
         }
-        OKCHK(try_all(spmm_cands, [](Tune &t, int v) { t.spmm_cap = v; },
-                      [&] { return launch_spmm(m, set.bt, 0, ctx->stream); }));
+        {
+            // both forms of the row-split SpMM where the width has them; the
+            // two-block form leaves the Rayleigh-Ritz step to a launch of
+            // its own, which its time is charged with
+            std::vector<int> wpes{4};
+            if (spmm_has_two_block_form(set.probs[0].B)) wpes.push_back(8);
+            double best = 1e30;
+            Tune keep = set.tune[m];
+            for (int wpe : wpes) {
+                for (int cap : spmm_cands) {
+                    set.tune[m].spmm_wpe = wpe;
+                    set.tune[m].spmm_cap = cap;
+                    apply_tune(set);
+                    OKCHK(build_batch(ctx, set));
+                    double ms = 0.0;
+                    OKCHK(time_launch(ctx, [&] { return launch_spmm(m, set.bt, 0, ctx->stream); }, &ms));
+                    if (wpe == 8) ms += kRrLaunchMs;
+                    if (ms < best) {
+                        best = ms;
+                        keep = set.tune[m];
+                    }
+                }
+            }
+            set.tune[m] = keep;
+        }
         std::vector<int> gemm_cands;
         for (int mf = 0; mf < (gemm_mfma(m, set.probs[0].B) ? 2 : 1); ++mf)
             for (int tg : {1, 128, 256, 512, 1024, 2048}) gemm_cands.push_back(mf * 100000 + tg);  // 1: no K split
@@ -820,7 +853,8 @@ int autotune(sbmds_ctx *ctx, SolveSet &set) {
                       [&] { return launch_spmm_t(m, set.bt, 0, ctx->stream); }));
         const Tune &t = set.tune[m];
         char val[64];
-        std::snprintf(val, sizeof(val), "%d %d %d %d", t.spmm_cap, t.gemm_mfma, t.gemm_target, t.spmmt_wpr);
+        std::snprintf(val, sizeof(val), "%d %d %d %d %d", t.spmm_cap, t.gemm_mfma, t.gemm_target, t.spmmt_wpr,
+                      t.spmm_wpe);
         cache.push_back({key, val});
         dirty = true;
     }
@@ -991,6 +1025,7 @@ int build_batch(sbmds_ctx *ctx, SolveSet &set) {
     for (int m = 0; m < NUM_MODES; ++m) {
         bt.spmmt_wpr[m] = set.tune[m].spmmt_wpr;
         bt.gemm_mfma[m] = set.tune[m].gemm_mfma && gemm_mfma((Mode)m, bt.B) ? 1 : 0;
+        bt.spmm_wpe8[m] = set.tune[m].spmm_wpe == 8 ? 1 : 0;  // read by the widths that have the form
     }
 
     std::vector<ProbView> views(np);

@@ -355,8 +355,12 @@ __device__ __forceinline__ bool gram_mfma_finish(dbl4 (&acc)[TILES], double (&es
 // kUldsBytes.
 constexpr int kUldsBytes = 64 * 1024;
 
-template <int M, int B, bool ULDS>
-__global__ __launch_bounds__(kWideThreads) void k_spmm_wide(const ProbView *__restrict__ views,
+// WPE: waves per SIMD the register budget is sized for.  4 (one block per
+// CU) leaves room for the fused Rayleigh-Ritz step; 8 (two blocks per CU,
+// 64 registers, no U copy and no fused step) keeps twice the row steps in
+// flight, for launches that move enough bytes to be bandwidth bound.
+template <int M, int B, bool ULDS, int WPE = 4>
+__global__ __launch_bounds__(kWideThreads, WPE) void k_spmm_wide(const ProbView *__restrict__ views,
                                                             const int *__restrict__ off, int nprob, int phase, int rr,
                                                             int b, int k, int max_sweeps, PhaseRule rule) {
     using Tr = Traits<M>;
@@ -369,7 +373,9 @@ __global__ __launch_bounds__(kWideThreads) void k_spmm_wide(const ProbView *__re
     // entries in flight per lane: as many as the register budget of the
     // mode and width allows without spilling
     // (gathers from LDS need fewer in flight)
-    constexpr int CH = ULDS ? kWideChunk / 2
+    static_assert(WPE == 4 || (WPE == 8 && !ULDS), "the two-block form keeps U in global memory");
+    constexpr int CH = WPE == 8 ? kWideChunk / 4
+                     : ULDS   ? kWideChunk / 2
                             : ((M == MODE_FP32 && B <= 16) ? kWideChunk
                                                            : ((M == MODE_BF16 && B >= 32) ? kWideChunk / 4
                                                                                           : kWideChunk / 2));
@@ -532,6 +538,7 @@ __global__ __launch_bounds__(kWideThreads) void k_spmm_wide(const ProbView *__re
     }
     __syncthreads();  // every wave is done with its tile rows before the reduction reuses smem
     const bool last = gram_mfma_finish<M, B, TILES>(acc, esum, smem, v.red_spmm, v.spmm_cnt, st, vb, vg);
+    if constexpr (WPE != 4) return;  // no fused step (rejected at launch)
     if (rr && last) {  // uniform
         __syncthreads();  // smem is free again
         // waves past the step's own threads end here (whole waves: a
@@ -965,7 +972,8 @@ __global__ __launch_bounds__(256) void k_f32_to_bf16(int64_t count, const float 
         default: return hipErrorInvalidValue;                              \
     }
 
-bool spmm_runs_rr(int B) { return wide_width(B); }
+bool spmm_runs_rr(const Batch &bt, Mode m) { return wide_width(bt.B) && !bt.spmm_wpe8[m]; }
+bool spmm_has_two_block_form(int B) { return wide_width(B); }
 
 hipError_t launch_spmm(Mode m, const Batch &bt, int phase, hipStream_t s, int rr, int max_sweeps,
                        const PhaseRule &rule) {
@@ -975,6 +983,12 @@ hipError_t launch_spmm(Mode m, const Batch &bt, int phase, hipStream_t s, int rr
     SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(bt.B, {
         if constexpr (wide_width(BB)) {
             using TUU = typename Traits<MM>::TU;
+            if (bt.spmm_wpe8[MM]) {
+                if (rr) return hipErrorInvalidValue;  // this form leaves the step to its own launch
+                hipLaunchKernelGGL((k_spmm_wide<MM, BB, false, 8>), dim3(grid), dim3(kWideThreads), 0, s, bt.views,
+                                   off, bt.nprob, phase, 0, bt.b, bt.k, 0, rule);
+                return hipGetLastError();
+            }
             if constexpr ((BB * sizeof(TUU)) % 16 == 0 && BB * sizeof(TUU) <= 64) {
                 if ((size_t)bt.max_l * BB * sizeof(TUU) <= (size_t)kUldsBytes) {
                     hipLaunchKernelGGL((k_spmm_wide<MM, BB, true>), dim3(grid), dim3(kWideThreads), 0, s, bt.views,

@@ -220,6 +220,24 @@ def test_graph_replay_matches_eager_launches(gpu):
         assert rg[0]["certified"] and re_[0]["certified"]
 
 
+@pytest.mark.parametrize("prec,block", [("FP32", 8), ("BF16_FP32", 16), ("FP32", 32)])
+def test_two_block_spmm_form(gpu, tmp_path, prec, block):
+    # the row-split SpMM in its two-blocks-per-CU form, with the
+    # Rayleigh-Ritz step in a launch of its own (what the tuner picks for
+    # launches that move many bytes), forced through the tuning cache on an
+    # operator the oracle solves in seconds; ragged rows, some empty
+    sb = gpu
+    prob = H.random_problem(n=40000, l=700, row_len_max=14, seed=91 + block, empty_rows=0.05, long_rows=2)
+    modes = {"FP32": (1, 2), "BF16_FP32": (0, 1, 2)}[prec]
+    key = f"{prob['n']},{prob['l']},{len(prob['col'])}"
+    path = tmp_path / "tune.txt"
+    path.write_text("".join(f"v1;B={block};m={m};{key} 200 0 1024 4 8\n" for m in modes))
+    Z, eig, rep, rc, _ = run(sb, prob, 3, block, getattr(sb, prec), tune_cache=str(path), max_iter=300)
+    assert rc == 0 and rep["certified"]
+    assert path.read_text().count(" 8\n") == len(modes)  # the forced entries were used, not retuned
+    check(prob, Z, eig, rep, 3, 1e-6)
+
+
 def test_autotune_cache(gpu, tmp_path):
     # tuning at create writes one line per arithmetic of the schedule; a second
     # context with the same cache reuses the choices (same launch shapes, so
@@ -235,7 +253,7 @@ def test_autotune_cache(gpu, tmp_path):
     assert len(lines) == 3  # bf16, fp32 and the float64 certification
     for ln in lines:
         key, *vals = ln.split()
-        assert len(vals) == 4 and int(vals[3]) in (1, 2, 4)
+        assert len(vals) == 5 and int(vals[3]) in (1, 2, 4) and int(vals[4]) in (4, 8)
     assert rc == 0 and r1[0]["certified"]
     lam, _, _ = H.oracle_for(prob, 3)
     assert H.rel_eig_err(e1[0], lam[:3]) <= 1e-6

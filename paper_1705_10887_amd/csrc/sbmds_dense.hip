@@ -325,20 +325,36 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const ProbView *__restrict__ 
             }
         }
     };
+    // the T slice (KS x B, read transposed into LDS) travels with its W
+    // slice, so a step waits on no load of its own (a second slice in
+    // flight measured no faster)
+    constexpr int NTP = KS * B / 256;  // T elements per thread
+    static_assert(KS * B % 256 == 0, "whole T elements per thread");
+    TT tnext[NTP];
+    auto load_t = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < NTP; ++q) {
+            const int idx = tid + 256 * q;
+            const int k = k0 + idx / B;
+            // rows of T past l are padding and read as zero
+            tnext[q] = (k0 < kend && k < l) ? T[(size_t)k * B + idx % B] : TT{};
+        }
+    };
     load_w(kbeg);
+    load_t(kbeg);
     for (int k0 = kbeg; k0 < kend; k0 += KS) {
 #pragma unroll
         for (int q = 0; q < NPC; ++q) {
             const int idx = tid + 256 * q;
             stp<TW, EPV>(&Ws[idx / PPR][(idx % PPR) * EPV], wnext[q]);
         }
-        load_w(k0 + KS);
-        // T slice, transposed; rows of T past l are padding and read as zero
-        for (int idx = tid; idx < KS * B; idx += 256) {
-            const int kk = idx / B, j = idx % B;
-            const int k = k0 + kk;
-            Ts[j][kk] = k < l ? T[(size_t)k * B + j] : TT{};
+#pragma unroll
+        for (int q = 0; q < NTP; ++q) {
+            const int idx = tid + 256 * q;
+            Ts[idx % B][idx / B] = tnext[q];
         }
+        load_w(k0 + KS);
+        load_t(k0 + KS);
         __syncthreads();
         const int arow = 16 * w + (lane & 15);
         if constexpr (BF) {

@@ -267,6 +267,25 @@ def test_routes_agree_on_torus64x32():
                 np.testing.assert_allclose(va[:, i], vd[:, i], atol=1e-8)
 
 
+def test_stored_coefficients_reproduce_eigenpairs():
+    # the coefficient form the full-size expected values are stored in:
+    # V = J P C must be orthonormal, centred and satisfy B V = V diag(lambda)
+    # against the dense B (a dropped centering term or a wrong scaling of C
+    # fails one of these)
+    prob = configs.torus64x32(use_cache=False)
+    P = configs.operator_rounded(prob)
+    W = prob["W"]
+    lam, C = oeig.reduction_coefficients(P, W, 5)
+    V = oeig.vectors_from_coefficients(P, C)
+    np.testing.assert_allclose(V.T @ V, np.eye(5), atol=1e-10)
+    np.testing.assert_allclose(V.sum(axis=0), 0.0, atol=1e-10)
+    B = oeig.b_matrix(P, W)
+    for i in range(5):
+        assert np.linalg.norm(B @ V[:, i] - lam[i] * V[:, i]) <= 1e-9 * abs(lam[0])
+    ld, _, _ = oeig.top_k(P, W, 5, route="dense")
+    np.testing.assert_allclose(lam, ld, rtol=1e-10)
+
+
 def test_arpack_residuals():
     prob = configs.torus64x32(use_cache=False)
     P = configs.operator_rounded(prob)

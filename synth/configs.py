@@ -90,7 +90,15 @@ _ARRAYS = ["V", "F", "landmarks", "rowptr", "col", "val", "W"]
 
 def _save(path, prob):
     meta = {k: prob[k] for k in ("n", "l", "p", "p_row", "seed")}
-    np.savez(path, meta=json.dumps(meta), **{k: prob[k] for k in _ARRAYS})
+    arrays = {k: prob[k] for k in _ARRAYS}
+    W = arrays.pop("W")
+    if np.array_equal(W, W.T):
+        # W is symmetrised before rounding, so its upper triangle holds it
+        # exactly (half the bytes of the largest inputs)
+        arrays["W_upper"] = W[np.triu_indices(W.shape[0])]
+    else:
+        arrays["W"] = W
+    np.savez(path, meta=json.dumps(meta), **arrays)
 
 
 def _restore(path):
@@ -98,7 +106,15 @@ def _restore(path):
     meta = json.loads(str(z["meta"]))
     prob = dict(meta)
     for k in _ARRAYS:
-        prob[k] = z[k]
+        if k == "W" and "W_upper" in z.files:
+            l = int(meta["l"])
+            iu = np.triu_indices(l)
+            W = np.empty((l, l), dtype=z["W_upper"].dtype)
+            W[iu] = z["W_upper"]
+            W.T[iu] = z["W_upper"]
+            prob[k] = W
+        else:
+            prob[k] = z[k]
     return prob
 
 

@@ -120,21 +120,22 @@ FORM_NAMES = {
 }
 
 
-def train_start_net(sb, torch, configs, k, block):
-    """Train the warm-start network on 12 smaller meshes of the benchmark's
-    family (level-5 icospheres with the same kind of deformation, other
-    seeds), on targets the solver produces; returns the weights file."""
+def train_start_net(sb, torch, configs, k, block, family="sphere5"):
+    """Train the warm-start network on 12 smaller meshes of the workload's
+    family (level-5 icospheres with sphere7's kind of deformation, or the
+    small bumpy tori), other seeds, on targets the solver produces; returns
+    the weights file."""
     from paper_1705_10887_amd import mlp
 
     t0 = time.perf_counter()
-    meshes = configs.sphere_family(log=log)
+    meshes = configs.sphere_family(log=log) if family == "sphere5" else configs.torus_family(log=log)
     for m in meshes:
         m["landmarks"] = m["landmarks"].astype("int32")
         m["xyz"] = m["V"].astype("float32")
     targets = mlp.solve_targets(meshes, k=k, block=block)
     feats = [mlp.features(m["xyz"], m["landmarks"], m["W"]) for m in meshes]
     net, losses = mlp.train(feats, targets, k=k, steps=600, lr=3e-3, seed=0)
-    path = os.path.join(configs.cache_dir(), f"mlp_sphere5_k{k}.bin")
+    path = os.path.join(configs.cache_dir(), f"mlp_{family}_k{k}.bin")
     net.save(path)
     net.close()
     torch.cuda.synchronize()
@@ -200,37 +201,44 @@ def spmm_at_scale(sb, torch, steps, pattern, n=2_000_000, l=2000, per_row=10, bl
     return out
 
 
-def precision_workload(sb, torch, configs, steps, warmup, k, blocks):
+def precision_workload(sb, torch, configs, steps, warmup, k, blocks, learned=True):
     """The bumpy torus of 1024 x 512 vertices with 10,000 landmarks (W 400 MB
     in float32, the dense product's bytes dominate): plain fp32 against the
-    bf16 bulk form, each from the random start, with the per-kernel rates of
-    the faster one.  Uses only an input already generated (about an hour of
-    host time); None otherwise."""
+    bf16 bulk form, from the random start and (unless learned is False) from
+    the learned start of a network trained on 12 small tori, with the
+    per-kernel rates of the fastest.  Uses only an input already generated
+    (about an hour of host time); None otherwise."""
     import numpy as np
     prob = configs.bumpy_torus(1024, 512, l=10000, generate=False)
     if prob is None:
         log("precision workload skipped: the 1024 x 512 torus input is not generated")
         return None
+    weights = train_start_net(sb, torch, configs, k, blocks[0], family="torus") if learned else None
     forms = {}
     for block in blocks:
         tune = os.path.join(configs.cache_dir(), f"tune_torus1024x512_k{k}_b{block}.txt")
-        for name, prec in (("fp32", sb.FP32), ("bf16_fp32", sb.BF16_FP32)):
-            ms, eig, rep, _ = time_form(sb, torch, prob, prec, steps, warmup, k, block, tune_cache=tune)
-            forms[f"{name}/b{block}"] = (ms, eig, rep, prec, block, tune)
+        kinds = [("fp32", sb.FP32, None), ("bf16_fp32", sb.BF16_FP32, None)]
+        if weights:
+            kinds += [("fp32_learned", sb.FP32, sb.START_LEARNED), ("bf16_fp32_learned", sb.BF16_FP32, sb.START_LEARNED)]
+        for name, prec, start in kinds:
+            ms, eig, rep, _ = time_form(sb, torch, prob, prec, steps, warmup, k, block, start=start, tune_cache=tune,
+                                        mlp_weights=weights if start else None)
+            forms[f"{name}/b{block}"] = (ms, eig, rep, prec, block, tune, start)
             log(f"torus {name}/b{block} {ms:.3f} ms  iters {rep['iters_bf16']}+{rep['iters_fp32']}+"
-                f"{rep['iters_fp64']}")
+                f"{rep['iters_fp64']}  start iters {rep['start_iters']}")
     chosen = min(forms, key=lambda f: forms[f][0])
-    ms, eig, rep, prec, block, tune = forms[chosen]
+    ms, eig, rep, prec, block, tune, start = forms[chosen]
     plain = forms[f"fp32/b{blocks[0]}"][0]
-    _, _, _, stats = time_form(sb, torch, prob, prec, steps, 1, k, block, flags=sb.FLAG_KERNEL_TIMING,
-                               tune_cache=tune)
+    _, _, _, stats = time_form(sb, torch, prob, prec, steps, 1, k, block, flags=sb.FLAG_KERNEL_TIMING, start=start,
+                               tune_cache=tune, mlp_weights=weights if start else None)
     out = {
         "workload": "bumpy torus 1024 x 512 (n=524288), l=10000 FPS landmarks, p_row=10 "
                     f"(nnz={len(prob['col'])}), W=D^2_ll float32, k={k}",
         "forms_ms": {f: round(v[0], 4) for f, v in forms.items()},
         "chosen": chosen, "ms": round(ms, 4), "plain_fp32_ms": round(plain, 4),
         "chosen_over_plain": round(plain / ms, 3),
-        "iters": {"bf16": rep["iters_bf16"], "fp32": rep["iters_fp32"], "fp64": rep["iters_fp64"]},
+        "iters": {"bf16": rep["iters_bf16"], "fp32": rep["iters_fp32"], "fp64": rep["iters_fp64"],
+                  "start": rep["start_iters"]},
         "err_bound": max(rep["err_bound"][:k]),
         "kernels": {s["name"]: {"avg_us": round(1e3 * s["ms_total"] / max(s["launches"], 1), 2),
                                 **({"GB/s": round(s["bytes_total"] / (s["ms_total"] * 1e-3) / 1e9, 1),
@@ -402,7 +410,8 @@ def main():
     torus = None
     if not args.no_torus:
         log("precision workload: 1024 x 512 torus, 10,000 landmarks")
-        torus = precision_workload(sb, torch, configs, args.steps, args.warmup, k, blocks)
+        torus = precision_workload(sb, torch, configs, args.steps, args.warmup, k, blocks,
+                                   learned=not args.no_learned)
         log(f"torus {torus}")
 
     cpu = None

@@ -222,6 +222,16 @@ def sphere_family(count=12, level=5, seed0=7001, p_row=10, use_cache=True, log=N
     return out
 
 
+TORUS_FAMILY = [(56, 28, 4101), (64, 32, 4102), (72, 36, 4103), (60, 30, 4104), (68, 34, 4105), (80, 40, 4106),
+                (64, 32, 4107), (72, 36, 4108), (56, 28, 4109), (76, 38, 4110), (64, 32, 4111), (84, 42, 4112)]
+
+
+def torus_family(use_cache=True, log=None):
+    """Training meshes for the learned start on bumpy tori: 12 tori from
+    56 x 28 to 84 x 42 vertices (seeds 4101-4112), l = n/50, p_row = 10."""
+    return [bumpy_torus(nu, nv, seed=seed, use_cache=use_cache, log=log) for nu, nv, seed in TORUS_FAMILY]
+
+
 def input_digest(prob) -> str:
     """sha1 over the arrays handed to the path (rowptr, col, val, W), to tie
     stored expected values to the exact input they were computed from."""

@@ -133,8 +133,7 @@ def test_weights_file_roundtrip(gpu, tmp_path):
 # ---------------------------------------------------------------------------
 # training on solver-converged embeddings and the gain over the random start
 # ---------------------------------------------------------------------------
-TRAIN = [(56, 28, 4101), (64, 32, 4102), (72, 36, 4103), (60, 30, 4104), (68, 34, 4105), (80, 40, 4106),
-         (64, 32, 4107), (72, 36, 4108), (56, 28, 4109), (76, 38, 4110), (64, 32, 4111), (84, 42, 4112)]
+TRAIN = configs.TORUS_FAMILY
 HELD_OUT = (96, 48, 4199)
 
 

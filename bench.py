@@ -120,15 +120,18 @@ FORM_NAMES = {
 }
 
 
-def train_start_net(sb, torch, configs, k, block, family="sphere5"):
+def train_start_net(sb, torch, configs, k, block, family="sphere6"):
     """Train the warm-start network on 12 smaller meshes of the workload's
-    family (level-5 icospheres with sphere7's kind of deformation, or the
+    family (level-6 icospheres with sphere7's kind of deformation, or the
     small bumpy tori), other seeds, on targets the solver produces; returns
     the weights file."""
     from paper_1705_10887_amd import mlp
 
     t0 = time.perf_counter()
-    meshes = configs.sphere_family(log=log) if family == "sphere5" else configs.torus_family(log=log)
+    if family.startswith("sphere"):
+        meshes = configs.sphere_family(level=int(family[len("sphere"):]), log=log)
+    else:
+        meshes = configs.torus_family(log=log)
     for m in meshes:
         m["landmarks"] = m["landmarks"].astype("int32")
         m["xyz"] = m["V"].astype("float32")
@@ -366,7 +369,7 @@ def main():
 
     weights = None
     if not args.no_learned:
-        weights = train_start_net(sb, torch, configs, k, blocks[0])
+        weights = train_start_net(sb, torch, configs, k, blocks[0], family="sphere6")
     for block in blocks:
         run_form("fp32", block, sb.FP32)
         run_form("bf16_fp32", block, sb.BF16_FP32)

@@ -131,7 +131,7 @@ def train_start_net(sb, torch, configs, k, block, family="sphere6"):
     if family.startswith("sphere"):
         meshes = configs.sphere_family(level=int(family[len("sphere"):]), log=log)
     else:
-        meshes = configs.torus_family(log=log)
+        meshes = configs.torus_family(size=family[len("torus"):] or "small", log=log)
     for m in meshes:
         m["landmarks"] = m["landmarks"].astype("int32")
         m["xyz"] = m["V"].astype("float32")
@@ -208,7 +208,7 @@ def precision_workload(sb, torch, configs, steps, warmup, k, blocks, learned=Tru
     """The bumpy torus of 1024 x 512 vertices with 10,000 landmarks (W 400 MB
     in float32, the dense product's bytes dominate): plain fp32 against the
     bf16 bulk form, from the random start and (unless learned is False) from
-    the learned start of a network trained on 12 small tori, with the
+    the learned start of a network trained on 12 tori of 192 x 96, with the
     per-kernel rates of the fastest.  Uses only an input already generated
     (about an hour of host time); None otherwise."""
     import numpy as np
@@ -216,7 +216,7 @@ def precision_workload(sb, torch, configs, steps, warmup, k, blocks, learned=Tru
     if prob is None:
         log("precision workload skipped: the 1024 x 512 torus input is not generated")
         return None
-    weights = train_start_net(sb, torch, configs, k, blocks[0], family="torus") if learned else None
+    weights = train_start_net(sb, torch, configs, k, blocks[0], family="torus192") if learned else None
     forms = {}
     for block in blocks:
         tune = os.path.join(configs.cache_dir(), f"tune_torus1024x512_k{k}_b{block}.txt")

@@ -226,10 +226,15 @@ TORUS_FAMILY = [(56, 28, 4101), (64, 32, 4102), (72, 36, 4103), (60, 30, 4104), 
                 (64, 32, 4107), (72, 36, 4108), (56, 28, 4109), (76, 38, 4110), (64, 32, 4111), (84, 42, 4112)]
 
 
-def torus_family(use_cache=True, log=None):
-    """Training meshes for the learned start on bumpy tori: 12 tori from
-    56 x 28 to 84 x 42 vertices (seeds 4101-4112), l = n/50, p_row = 10."""
-    return [bumpy_torus(nu, nv, seed=seed, use_cache=use_cache, log=log) for nu, nv, seed in TORUS_FAMILY]
+TORUS_FAMILY_192 = [(192, 96, 4200 + i) for i in range(1, 13)]
+
+
+def torus_family(size="small", use_cache=True, log=None):
+    """Training meshes for the learned start on bumpy tori, l = n/50,
+    p_row = 10: "small" is 12 tori from 56 x 28 to 84 x 42 vertices (seeds
+    4101-4112); "192" is 12 tori of 192 x 96 vertices (seeds 4201-4212)."""
+    fam = TORUS_FAMILY if size == "small" else TORUS_FAMILY_192
+    return [bumpy_torus(nu, nv, seed=seed, use_cache=use_cache, log=log) for nu, nv, seed in fam]
 
 
 def input_digest(prob) -> str:

@@ -32,7 +32,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 __all__ = ["b_matrix", "top_k", "embed", "canonical_signs", "centered_gram", "reduction_coefficients",
-           "vectors_from_coefficients"]
+           "vectors_from_coefficients", "apply_b"]
 
 
 def _as_csr64(P) -> sp.csr_matrix:
@@ -110,6 +110,24 @@ def vectors_from_coefficients(P, coef) -> np.ndarray:
     coef = np.asarray(coef, dtype=np.float64)
     c = np.asarray(P.sum(axis=0)).ravel()
     return P @ coef - np.outer(np.ones(n), c @ coef) / n
+
+
+def apply_b(P, W, X, chunk_rows=1024) -> np.ndarray:
+    """B X = -1/2 J P W P^T J X in float64 for X (n x k), taking W a block of
+    rows at a time (widened to float64 per block), so that a W too large to
+    hold in float64 (l = 50,000: 10 GB in float32) can still be applied."""
+    P = _as_csr64(P)
+    X = np.asarray(X, dtype=np.float64)
+    Xc = X - X.mean(axis=0, keepdims=True)
+    T = P.T @ Xc
+    l = T.shape[0]
+    U = np.empty_like(T)
+    for r0 in range(0, l, chunk_rows):
+        r1 = min(l, r0 + chunk_rows)
+        U[r0:r1] = np.asarray(W[r0:r1], dtype=np.float64) @ T
+    Y = P @ U
+    Y -= Y.mean(axis=0, keepdims=True)
+    return -0.5 * Y
 
 
 def _top_reduction(P, W, k, rank_tol=1e-12):

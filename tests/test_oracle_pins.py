@@ -286,6 +286,20 @@ def test_stored_coefficients_reproduce_eigenpairs():
     np.testing.assert_allclose(lam, ld, rtol=1e-10)
 
 
+def test_blockwise_operator_matches_dense_b():
+    # the blockwise float64 application of B used for residual checks at
+    # sizes where B (and W in float64) cannot be held: equal to the dense B
+    # on a torus and on random vectors, for a block size that leaves a ragged
+    # last block
+    prob = configs.torus64x32(use_cache=False)
+    P = configs.operator_rounded(prob)
+    W = prob["W"].astype(np.float32)
+    X = np.random.default_rng(3).standard_normal((P.shape[0], 4))
+    B = oeig.b_matrix(P, W)
+    got = oeig.apply_b(P, W, X, chunk_rows=10)
+    np.testing.assert_allclose(got, B @ X, rtol=0, atol=1e-11 * np.abs(B @ X).max())
+
+
 def test_arpack_residuals():
     prob = configs.torus64x32(use_cache=False)
     P = configs.operator_rounded(prob)

@@ -74,7 +74,7 @@ def time_form(sb, torch, prob, prec, steps, warmup, k, block, flags=0, start=Non
     return ms, eig[0], reps[0], stats
 
 
-def time_batch(sb, torch, probs, k, block, steps, warmup, tune_cache):
+def time_batch(sb, torch, probs, k, block, steps, warmup, tune_cache, workload=None):
     """ms per certified solve of all meshes in one context (every launch
     covers every mesh) and of the same meshes one context each."""
     dev = [{x: torch.from_numpy(p[x]).cuda() for x in ("rowptr", "col", "val", "W")} for p in probs]
@@ -108,8 +108,8 @@ def time_batch(sb, torch, probs, k, block, steps, warmup, tune_cache):
             "meshes_per_s": round(len(probs) / (ms_batch * 1e-3), 1),
             "vertices_per_s": round(ntot / (ms_batch * 1e-3), 1),
             "ms_one_context_per_mesh": round(ms_single, 3), "dtype": "f32",
-            "workload": "16 meshes, n ~ U[2000, 20000] (bumpy tori and deformed geodesic spheres), l = n/50, "
-                        "p_row = 10, k = 3, fp32 -> f64 certify"}
+            "workload": workload or "16 meshes, n ~ U[2000, 20000] (bumpy tori and deformed geodesic spheres), "
+                                    "l = n/50, p_row = 10, k = 3, fp32 -> f64 certify"}
 
 
 FORM_NAMES = {
@@ -441,6 +441,20 @@ def main():
                              os.path.join(configs.cache_dir(), f"tune_batch16_k{k}_b{blocks[0]}.txt"))
         log(f"batched {batched}")
 
+    batched_full = None
+    if not args.no_batch:
+        from synth import large
+        log("batched workload at full scale: 256 synthetic grid tori")
+        probs256 = large.grid_torus_batch()
+        batched_full = time_batch(sb, torch, probs256, k, blocks[0], max(1, min(args.steps, 3)), 1, None,
+                                  workload="256 synthetic grid-torus meshes, n ~ U[2000, 200000] "
+                                           f"({sum(p['n'] for p in probs256)} vertices, "
+                                           f"{sum(p['l'] for p in probs256)} landmarks, "
+                                           f"{sum(len(p['col']) for p in probs256)} stored entries), l ~ n/50, "
+                                           "10 entries per row, k = 3, fp32 -> f64 certify, default launch shapes")
+        del probs256
+        log(f"batched full {batched_full}")
+
     at_scale = None
     if not args.no_scale:
         log("SpMM at a bandwidth-bound size")
@@ -515,6 +529,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "batched": batched,
+        "batched_full_scale": batched_full,
         "spmm_at_scale": at_scale,
         "precision_workload": torus,
         "largest_workload": largest,

@@ -103,3 +103,21 @@ def grid_torus_operator(nu=1800, nv=1000, lu=250, lv=200, nbr=10, seed=5005, chu
     np.fill_diagonal(W, 0.0)
     return {"n": n, "l": l, "rowptr": rowptr.astype(np.int32), "col": col, "val": val, "W": W,
             "landmarks": lm_vertex.astype(np.int32)}
+
+
+def grid_torus_batch(count=256, nmin=2000, nmax=200_000, seed0=6006):
+    """Many meshes of uneven size in the batched workload's recipe (n_i
+    uniform in [nmin, nmax] from default_rng(seed0), l_i ~ n_i / 50), each a
+    grid torus of the kind above: n_v = round(sqrt(n_i / 2)), n_u =
+    round(n_i / n_v), landmark grid about every sqrt(50) vertices (at least
+    5 x 5), seed seed0 + 1 + i."""
+    rng = np.random.default_rng(seed0)
+    sizes = rng.integers(nmin, nmax + 1, size=count)
+    out = []
+    for i, ni in enumerate(sizes):
+        nv = max(10, int(round(np.sqrt(ni / 2))))
+        nu = max(10, int(round(ni / nv)))
+        lu = max(5, int(round(nu / np.sqrt(50.0))))
+        lv = max(5, int(round(nv / np.sqrt(50.0))))
+        out.append(grid_torus_operator(nu, nv, lu, lv, seed=seed0 + 1 + i, chunk=1 << 20))
+    return out

@@ -250,22 +250,25 @@ def test_graph_replay_matches_eager_launches(gpu):
         assert rg[0]["certified"] and re_[0]["certified"]
 
 
-@pytest.mark.parametrize("prec,block", [("FP32", 8), ("BF16_FP32", 16), ("FP32", 32)])
+@pytest.mark.parametrize("prec,block", [("FP32", 8), ("BF16_FP32", 16), ("FP32", 32), ("FP64", 16)])
 def test_two_block_spmm_form(gpu, tmp_path, prec, block):
     # the row-split SpMM in its two-blocks-per-CU form, with the
     # Rayleigh-Ritz step in a launch of its own (what the tuner picks for
     # launches that move many bytes), forced through the tuning cache on an
     # operator the oracle solves in seconds; ragged rows, some empty
     sb = gpu
-    prob = H.random_problem(n=40000, l=700, row_len_max=14, seed=91 + block, empty_rows=0.05, long_rows=2)
-    modes = {"FP32": (1, 2), "BF16_FP32": (0, 1, 2)}[prec]
+    fp64 = prec == "FP64"
+    prob = H.random_problem(n=40000, l=700, row_len_max=14, seed=91 + block, empty_rows=0.05, long_rows=2,
+                            dtype=np.float64 if fp64 else np.float32)
+    modes = {"FP32": (1, 2), "BF16_FP32": (0, 1, 2), "FP64": (3,)}[prec]
     key = f"{prob['n']},{prob['l']},{len(prob['col'])}"
     path = tmp_path / "tune.txt"
     path.write_text("".join(f"v1;B={block};m={m};{key} 200 0 1024 4 8\n" for m in modes))
-    Z, eig, rep, rc, _ = run(sb, prob, 3, block, getattr(sb, prec), tune_cache=str(path), max_iter=300)
+    tol = 1e-10 if fp64 else 1e-6
+    Z, eig, rep, rc, _ = run(sb, prob, 3, block, getattr(sb, prec), tune_cache=str(path), max_iter=300, tol=tol)
     assert rc == 0 and rep["certified"]
     assert path.read_text().count(" 8\n") == len(modes)  # the forced entries were used, not retuned
-    check(prob, Z, eig, rep, 3, 1e-6)
+    check(prob, Z, eig, rep, 3, tol)
 
 
 def test_autotune_cache(gpu, tmp_path):

@@ -514,9 +514,13 @@ int enqueue_round(sbmds_ctx *ctx, SolveSet &set, const std::vector<PhaseRule> &r
 // Solve every problem of `set` together: one launch per kernel and
 // iteration covers all of them; each follows the schedule `rules` on its own
 // and drops out of the launches once it is done.  `start` enqueues the start
-// block and its orthonormalisation.  Returns 1 if every problem finished.
+// block and its orthonormalisation; `after_round` (may be empty) enqueues
+// work that reads the state a round leaves, ahead of the host's look at it,
+// so that after the last round it is already on the device.  Returns 1 if
+// every problem finished.
 template <typename StartFn>
-int run_set(sbmds_ctx *ctx, SolveSet &set, const std::vector<PhaseRule> &rules, int max_iter, StartFn &&start) {
+int run_set(sbmds_ctx *ctx, SolveSet &set, const std::vector<PhaseRule> &rules, int max_iter, StartFn &&start,
+            const std::function<int()> &after_round = {}) {
     const int np = (int)set.probs.size();
     const int nph = (int)rules.size();
     std::vector<int> &expect = set.expect;
@@ -541,6 +545,7 @@ int run_set(sbmds_ctx *ctx, SolveSet &set, const std::vector<PhaseRule> &rules, 
             launched += n_it;
         }
         OKCHK(enqueue_round(ctx, set, rules, ops));
+        if (after_round) OKCHK(after_round());
         OKCHK(read_summaries(ctx, set));
         all_done = true;
         from = nph;
@@ -589,7 +594,7 @@ std::vector<PhaseRule> lmds_rules(const sbmds_options &o) {
     return {r};
 }
 
-int solve_all(sbmds_ctx *ctx, sbmds_report *reps) {
+int solve_all(sbmds_ctx *ctx, sbmds_report *reps, const std::function<int()> &output = {}) {
     const sbmds_options &o = ctx->opt;
     SolveSet &set = ctx->main;
     const int np = (int)set.probs.size();
@@ -643,10 +648,18 @@ int solve_all(sbmds_ctx *ctx, sbmds_report *reps) {
         HIPCHK(hipEventRecord(e1, ctx->stream));
         return SBMDS_OK;
     };
-    const int rc = run_set(ctx, set, rules, o.max_iter, start);
+    // the outputs follow every round (the state a round leaves is complete
+    // on the device): after the last one they need no further host round trip
+    std::function<int()> after_round;
+    if (output)
+        after_round = [&]() -> int {
+            HIPCHK(hipEventRecord(e2, ctx->stream));
+            return output();
+        };
+    const int rc = run_set(ctx, set, rules, o.max_iter, start, after_round);
     if (rc < 0) return rc;
     const bool all_done = rc == 1;
-    HIPCHK(hipEventRecord(e2, ctx->stream));
+    if (!output) HIPCHK(hipEventRecord(e2, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     const Summary *S = set.host_sum;
     for (int i = 0; i < np && reps; ++i) {
@@ -684,11 +697,12 @@ int solve_all(sbmds_ctx *ctx, sbmds_report *reps) {
 // Autotuner.  For every arithmetic of the schedule it times, on the device
 // and on the problems of the context, the candidates of each launch choice
 // (one choice at a time, the others held at their current values): the SpMM
-// block cap, the dense-product kernel and its block target, and the waves
-// per landmark row of the transposed SpMM.  The iteration state it leaves
-// behind is discarded: every solve starts from its start block.  Results
-// are kept in a text cache, one line per (batch shape, arithmetic):
-//   <key> <spmm_cap> <gemm_mfma> <gemm_target> <spmmt_wpr>
+// block cap and (widths 8-32) its form, the dense-product kernel and its
+// block target, and the waves per landmark row of the transposed SpMM.  The
+// iteration state it leaves behind is discarded: every solve starts from its
+// start block.  Results are kept in a text cache, one line per (batch
+// shape, arithmetic):
+//   <key> <spmm_cap> <gemm_mfma> <gemm_target> <spmmt_wpr> <spmm_wpe>
 // Different choices change the summation order, so results are bitwise
 // reproducible for a fixed configuration only.
 // ---------------------------------------------------------------------------
@@ -1416,23 +1430,28 @@ int sbmds_embed(sbmds_ctx *ctx, double *eigvals, void *Z, int Z_mem, sbmds_repor
         const SolveSet &set = ctx->main;
         const int np = (int)set.probs.size();
         const bool zdouble = ctx->opt.prec == SBMDS_FP64;
-        int worst = solve_all(ctx, reports);
+        void *dz = Z;
+        if (Z && Z_mem == SBMDS_MEM_HOST) {
+            if (!ctx->zstage) OKCHK(dalloc(ctx, &ctx->zstage, set.zstage_bytes));
+            dz = ctx->zstage;
+        }
+        // the embedding (and its copy to the host) is enqueued after each
+        // round of the solve; the one after the last round is the result
+        std::function<int()> output;
+        if (Z)
+            output = [&]() -> int {
+                OKCHK(timed(ctx, "embedding", 0.0, 0.0,
+                            [&] { return launch_embedding(set.bt, dz, zdouble ? 1 : 0, ctx->stream); }));
+                if (Z_mem == SBMDS_MEM_HOST)
+                    HIPCHK(hipMemcpyAsync(Z, dz, set.zstage_bytes, hipMemcpyDeviceToHost, ctx->stream));
+                return SBMDS_OK;
+            };
+        int worst = solve_all(ctx, reports, output);
         if (worst < 0) return worst;
         if (eigvals)
             for (int i = 0; i < np; ++i)
                 for (int j = 0; j < set.probs[i].k; ++j)
                     eigvals[(size_t)i * set.probs[i].k + j] = set.host_sum[i].theta[j];
-        if (Z) {
-            void *dz = Z;
-            if (Z_mem == SBMDS_MEM_HOST) {
-                if (!ctx->zstage) OKCHK(dalloc(ctx, &ctx->zstage, set.zstage_bytes));
-                dz = ctx->zstage;
-            }
-            OKCHK(timed(ctx, "embedding", 0.0, 0.0,
-                        [&] { return launch_embedding(set.bt, dz, zdouble ? 1 : 0, ctx->stream); }));
-            if (Z_mem == SBMDS_MEM_HOST)
-                HIPCHK(hipMemcpyAsync(Z, dz, set.zstage_bytes, hipMemcpyDeviceToHost, ctx->stream));
-        }
         HIPCHK(hipStreamSynchronize(ctx->stream));
         if (ctx->timing) collect_timing(ctx);
         return worst;

@@ -127,7 +127,11 @@ typedef struct {
  *   seed       seed of the random start block.
  *   stream     hipStream_t to run on (NULL = the null stream).
  *   mlp_weights  path of a weights file for SBMDS_START_LEARNED (or NULL).
- *   tune_cache   path of the autotuner cache (NULL = no persistent cache).
+ *   tune_cache   path of the autotuner's text cache.  When set, sbmds_create
+ *                times the launch choices on the device for every arithmetic
+ *                of the schedule (unless the file already holds them for this
+ *                batch shape) and stores them there; NULL = default choices,
+ *                no timing.
  *   mem_cap    upper bound on device bytes the context may allocate (0 = none).
  *   flags      SBMDS_FLAG_* bits.
  */

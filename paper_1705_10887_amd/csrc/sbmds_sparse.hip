@@ -841,6 +841,24 @@ __device__ __forceinline__ double load_y(const void *Y, int64_t i, int mode) {
     return ((const double *)Y)[i];
 }
 
+__device__ __forceinline__ double to_double(bf16_t x) { return (double)bf2f(x); }
+__device__ __forceinline__ double to_double(float x) { return (double)x; }
+__device__ __forceinline__ double to_double(double x) { return x; }
+
+// Row `row` of a block stored as TY, with 16-byte (or whole-row) loads.
+template <int B, typename TY>
+__device__ __forceinline__ void load_row(const void *Y, int64_t row, double (&y)[B]) {
+    constexpr int V = (16 / (int)sizeof(TY)) < B ? 16 / (int)sizeof(TY) : B;
+    static_assert(B % V == 0 && (sizeof(TY) * V) % 4 == 0, "whole dwords per load");
+    const TY *base = (const TY *)Y + row * B;
+#pragma unroll
+    for (int a0 = 0; a0 < B; a0 += V) {
+        const Pack<TY, V> pk = ldpg<TY, V>(base + a0);
+#pragma unroll
+        for (int q = 0; q < V; ++q) y[a0 + q] = to_double(pk.v[q]);
+    }
+}
+
 // Z = J Y Zmap restricted to the first k columns: Z_ij = sum_a Y_ia Zmap_aj - zshift_j,
 // with Y the buffer (and storage type) the last Ritz basis was built from.
 template <int B, typename TZ>
@@ -857,10 +875,11 @@ __global__ __launch_bounds__(256) void k_embedding(const ProbView *__restrict__ 
     const int64_t row = (int64_t)(blockIdx.x - off[p]) * 256 + threadIdx.x;
     if (row >= v.n) return;
     const void *Y = st->zbuf ? v.Y1 : v.Y0;
-    const int mode = st->zmode;
+    const int mode = st->zmode;  // uniform
     double y[B];
-#pragma unroll
-    for (int a = 0; a < B; ++a) y[a] = load_y(Y, row * B + a, mode);
+    if (mode == MODE_BF16) load_row<B, bf16_t>(Y, row, y);
+    else if (mode == MODE_FP32) load_row<B, float>(Y, row, y);
+    else load_row<B, double>(Y, row, y);
     TZ *zp = Z + v.zoff + row * k;
     for (int j = 0; j < k; ++j) {
         double z = -zs[j];

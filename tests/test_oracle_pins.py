@@ -433,3 +433,30 @@ def test_approximation_improves_with_landmarks():
     Pd = pr50["P64"].toarray()
     e50 = omds.approx_error(Pd @ pr50["W64"] @ Pd.T, E)
     assert e50 < 1.2 * errs[1]
+
+
+def test_synthetic_grid_torus_operator_structure():
+    # the large synthetic operators: identity rows at the landmarks, every
+    # other row its nbr nearest grid landmarks with weights summing to 1 and
+    # increasing column ids, W exactly symmetric with a zero diagonal; the
+    # batch recipe's sizes and landmark counts
+    from synth import large
+    p = large.grid_torus_operator(nu=90, nv=60, lu=12, lv=10, nbr=10, seed=3)
+    n, l = p["n"], p["l"]
+    assert (n, l) == (5400, 120)
+    P = sp.csr_matrix((p["val"].astype(np.float64), p["col"], p["rowptr"]), shape=(n, l))
+    np.testing.assert_allclose(np.asarray(P.sum(axis=1)).ravel(), 1.0, atol=1e-6)
+    lm = p["landmarks"]
+    assert len(np.unique(lm)) == l
+    np.testing.assert_array_equal(P[lm].toarray(), np.eye(l))
+    lens = np.diff(p["rowptr"])
+    others = np.setdiff1d(np.arange(n), lm)
+    assert np.all(lens[others] == 10) and np.all(lens[lm] == 1)
+    for i in others[::37]:
+        c = p["col"][p["rowptr"][i]:p["rowptr"][i + 1]]
+        assert np.all(np.diff(c) > 0)
+    W = p["W"]
+    assert W.dtype == np.float32 and np.array_equal(W, W.T) and np.all(np.diag(W) == 0) and np.all(W >= 0)
+    batch = large.grid_torus_batch(count=6, nmin=2000, nmax=6000, seed0=11)
+    for q in batch:
+        assert 2000 * 0.9 <= q["n"] <= 6000 * 1.1 and 25 <= q["l"] and abs(q["l"] - q["n"] / 50) <= 0.35 * q["n"] / 50

@@ -116,3 +116,15 @@ def test_product_path_has_no_cpu_fallback():
     src = open(os.path.join(ROOT, "paper_1705_10887_amd", "__init__.py")).read()
     assert "import oracle" not in src and "from oracle" not in src
     assert "no CPU fallback" in src
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the benchmark measures one GPU; asking for more ends with a message
+    # before anything touches a device
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=120)
+    assert out.returncode == 2
+    assert "one GPU" in out.stderr

@@ -32,7 +32,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 __all__ = ["b_matrix", "top_k", "embed", "canonical_signs", "centered_gram", "reduction_coefficients",
-           "vectors_from_coefficients", "apply_b"]
+           "vectors_from_coefficients", "coefficients_from_vectors", "apply_b"]
 
 
 def _as_csr64(P) -> sp.csr_matrix:
@@ -110,6 +110,23 @@ def vectors_from_coefficients(P, coef) -> np.ndarray:
     coef = np.asarray(coef, dtype=np.float64)
     c = np.asarray(P.sum(axis=0)).ravel()
     return P @ coef - np.outer(np.ones(n), c @ coef) / n
+
+
+def coefficients_from_vectors(P, W, lam, V) -> np.ndarray:
+    """Coefficients C (l x k) with V = J P C for eigenpairs (lam, V) of B with
+    non-zero eigenvalues: B v = lam v gives v = J P (-1/2 W P^T J v / lam),
+    so every such eigenvector lies in range(J P) (Section 3.3's factored B).
+    W may be float32; it is widened a block of rows at a time."""
+    P = _as_csr64(P)
+    V = np.asarray(V, dtype=np.float64)
+    lam = np.asarray(lam, dtype=np.float64)
+    T = P.T @ (V - V.mean(axis=0, keepdims=True))
+    l = T.shape[0]
+    U = np.empty_like(T)
+    for r0 in range(0, l, 1024):
+        r1 = min(l, r0 + 1024)
+        U[r0:r1] = np.asarray(W[r0:r1], dtype=np.float64) @ T
+    return -0.5 * U / lam[None, :]
 
 
 def apply_b(P, W, X, chunk_rows=1024) -> np.ndarray:

@@ -460,3 +460,55 @@ def test_synthetic_grid_torus_operator_structure():
     batch = large.grid_torus_batch(count=6, nmin=2000, nmax=6000, seed0=11)
     for q in batch:
         assert 2000 * 0.9 <= q["n"] <= 6000 * 1.1 and 25 <= q["l"] and abs(q["l"] - q["n"] / 50) <= 0.35 * q["n"] / 50
+
+
+# ------------------------------------------- sign convention and error measure
+def test_canonical_signs_hand_built():
+    # the entry of largest magnitude ends up positive; on a tie of magnitudes
+    # the lowest index decides; columns are independent; values are kept
+    V = np.array([[0.1, -0.5, 0.3, 2.0],
+                  [-0.9, 0.5, -0.3, -1.0],
+                  [0.2, 0.1, 0.1, 0.5]])
+    got = oeig.canonical_signs(V)
+    want = np.array([[-0.1, 0.5, 0.3, 2.0],      # col 0: -0.9 largest -> flipped
+                     [0.9, -0.5, -0.3, -1.0],    # col 1: |-0.5| = |0.5|, row 0 first -> flipped
+                     [-0.2, -0.1, 0.1, 0.5]])    # col 2: |0.3| tie, row 0 (+) first -> kept
+    np.testing.assert_array_equal(got, want)     # col 3: 2.0 largest and positive -> kept
+    assert np.array_equal(V[:, 0], [0.1, -0.9, 0.2])  # input untouched
+    # idempotent, and the same for v and -v
+    np.testing.assert_array_equal(oeig.canonical_signs(got), got)
+    np.testing.assert_array_equal(oeig.canonical_signs(-V), want)
+
+
+def test_approx_error_hand_computed():
+    # eps = ||K~ - K||_F^2 / ||K||_F^2 (Section 4.1) on a 3 x 3 case by hand:
+    # K has squared entries 0,1,4 / 1,0,9 / 4,9,0 -> ||K||^2 = 2(1 + 16 + 81) = 196;
+    # K~ differs by +1 at (0,1), (1,0) and by -2 at (2,2) -> ||diff||^2 = 1 + 1 + 4 = 6
+    K = np.array([[0.0, 1.0, 4.0], [1.0, 0.0, 9.0], [4.0, 9.0, 0.0]])
+    Kt = K.copy()
+    Kt[0, 1] += 1.0
+    Kt[1, 0] += 1.0
+    Kt[2, 2] -= 2.0
+    assert omds.approx_error(Kt, K) == pytest.approx(6.0 / 196.0, rel=1e-15)
+    assert omds.approx_error(K, K) == 0.0
+    # scale invariant in the pair, quadratic in the perturbation
+    assert omds.approx_error(3 * Kt, 3 * K) == pytest.approx(6.0 / 196.0, rel=1e-14)
+    assert omds.approx_error(K + 2 * (Kt - K), K) == pytest.approx(24.0 / 196.0, rel=1e-14)
+
+
+def test_coefficients_from_vectors_dense_route():
+    # every eigenvector of B with a non-zero eigenvalue lies in range(J P):
+    # v = J P c with c = -1/2 W P^T J v / lambda (Section 3.3's factored B);
+    # checked against the dense route's eigenvectors
+    rng = np.random.default_rng(8)
+    n, l = 60, 9
+    P = sp.random(n, l, density=0.4, random_state=3, format="csr") + sp.csr_matrix(
+        (np.ones(l), (rng.choice(n, l, replace=False), np.arange(l))), shape=(n, l))
+    pts = rng.standard_normal((l, 3))
+    W = ((pts[:, None] - pts[None]) ** 2).sum(-1)
+    W = W + 0.3 * np.sqrt(W)
+    lam, V, _ = oeig.top_k(P, W, 4, route="dense")
+    C = oeig.coefficients_from_vectors(P, W, lam, V)
+    np.testing.assert_allclose(oeig.vectors_from_coefficients(P, C), V, atol=1e-12)
+    B = oeig.b_matrix(P, W)
+    np.testing.assert_allclose(B @ V, V * lam[None, :], atol=1e-10 * abs(lam).max())

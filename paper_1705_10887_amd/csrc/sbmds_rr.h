@@ -492,18 +492,28 @@ __device__ __forceinline__ void rr_step(const ProbView &view, RRLds<B> &L, int b
     }
     nonfinite = (int)rr_block_sum<NBLK>((double)nonfinite, L.red[0]);
     if (tid == 0) {
+        if (init == RR_START) ctl.flags = 0;  // a new solve starts with clean flags
         ctl.dead = ndead - (B - b);
         if (ndead > B - b) ctl.flags |= SF_REPAIRED;
         if (nonfinite) ctl.flags |= SF_NONFINITE;
-        if (init) {
-            ctl.iter = 0;
+        if (init == RR_REFILL) {
+            // the refilled block sits in buffer 0; the schedule goes on
+            ctl.ycur = 0;
             ctl.maxbound = INFINITY;
-            ctl.maxres = INFINITY;
             ctl.sweeps = 0;
+            st->refill = 0;
         } else {
-            ctl.iter += 1;
+            if (init) {
+                ctl.iter = 0;
+                ctl.maxbound = INFINITY;
+                ctl.maxres = INFINITY;
+                ctl.sweeps = 0;
+                st->refill = 0;
+            } else {
+                ctl.iter += 1;
+            }
+            phase_control(ctl, rule, init);
         }
-        phase_control(ctl, rule, init);
         store_ctl(st, ctl);
     }
     __syncthreads();
@@ -517,6 +527,7 @@ __global__ __launch_bounds__(RRShape<B>::NT) void k_rr_solve2(const ProbView *__
     __shared__ RRLds<B> L;
     const ProbView &v = views[blockIdx.x];
     if (!init && (v.st->done || v.st->phase != rule.phase)) return;  // uniform
+    if (init == RR_REFILL && !v.st->refill) return;
     rr_step<B, RRShape<B>::NT>(v, L, b, k, piv_tol, init, max_sweeps, rule);
 }
 

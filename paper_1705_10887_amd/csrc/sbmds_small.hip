@@ -135,6 +135,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_rr_solve(const ProbView *__re
     SolveState *__restrict__ st = views[blockIdx.x].st;
     const double n = (double)views[blockIdx.x].n;
     if (!init && (st->done || st->phase != rule.phase)) return;
+    if (init == RR_REFILL && !st->refill) return;
     constexpr int NT = kSolveThreads;
     constexpr int E = B * (B + 1) / 2;
     const int tid = threadIdx.x;
@@ -301,19 +302,28 @@ __global__ __launch_bounds__(kSolveThreads) void k_rr_solve(const ProbView *__re
         int nd = 0;
         for (int j = 0; j < b; ++j) nd += L.dead[j];
         st->dead = nd;
-        int fl = st->flags;
+        int fl = init == RR_START ? 0 : st->flags;  // a new solve starts with clean flags
         if (nd) fl |= SF_REPAIRED;
         if (nonfinite) fl |= SF_NONFINITE;
         st->flags = fl;
-        if (init) {
-            st->iter = 0;
+        if (init == RR_REFILL) {
+            // the refilled block sits in buffer 0; the schedule goes on
+            st->ycur = 0;
             st->maxbound = INFINITY;
-            st->maxres = INFINITY;
             st->sweeps = 0;
+            st->refill = 0;
         } else {
-            st->iter += 1;
+            if (init) {
+                st->iter = 0;
+                st->maxbound = INFINITY;
+                st->maxres = INFINITY;
+                st->sweeps = 0;
+                st->refill = 0;
+            } else {
+                st->iter += 1;
+            }
+            phase_control(st, rule, init);
         }
-        phase_control(st, rule, init);
     }
     __syncthreads();
     publish_summary(st, views[blockIdx.x].host_sum, blockDim.x);

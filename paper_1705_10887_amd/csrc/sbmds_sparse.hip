@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256) void k_spmm(const ProbView *__restrict__ views
 // start block), same tiling as k_spmm.
 template <int M, int B>
 __global__ __launch_bounds__(256) void k_gram(const ProbView *__restrict__ views, const int *__restrict__ off,
-                                              int nprob) {
+                                              int nprob, int only_refill) {
     using Tr = Traits<M>;
     using TY = typename Tr::TY;
     using S = SpmmShape<M, B>;
@@ -199,6 +199,7 @@ __global__ __launch_bounds__(256) void k_gram(const ProbView *__restrict__ views
     __shared__ double tile[RPB][B];
     const int p = find_problem(off, nprob, blockIdx.x);
     const ProbView &v = views[p];
+    if (only_refill && !v.st->refill) return;  // uniform per problem
     const int vb = blockIdx.x - off[p], vg = off[p + 1] - off[p];
     const int n = v.n;
     const TY *__restrict__ Y = (const TY *)v.Y0;
@@ -555,7 +556,8 @@ __global__ __launch_bounds__(kWideThreads, WPE) void k_spmm_wide(const ProbView 
 // geometry as k_spmm_wide).
 template <int M, int B>
 __global__ __launch_bounds__(kWideThreads) void k_gram_wide(const ProbView *__restrict__ views,
-                                                            const int *__restrict__ off, int nprob) {
+                                                            const int *__restrict__ off, int nprob,
+                                                            int only_refill) {
     using Tr = Traits<M>;
     using TY = typename Tr::TY;
     using S = WideShape<M, B>;
@@ -563,6 +565,7 @@ __global__ __launch_bounds__(kWideThreads) void k_gram_wide(const ProbView *__re
     __shared__ double smem[S::SMEM_D];
     const int p = find_problem(off, nprob, blockIdx.x);
     const ProbView &v = views[p];
+    if (only_refill && !v.st->refill) return;  // uniform per problem
     const int vb = blockIdx.x - off[p], vg = off[p + 1] - off[p];
     const int n = v.n;
     const TY *__restrict__ Y = (const TY *)v.Y0;
@@ -889,6 +892,55 @@ __global__ __launch_bounds__(256) void k_embedding(const ProbView *__restrict__ 
     }
 }
 
+// Rank repair (see launch_refill).  One thread per row: the row of the basis
+// X = J Y C of a problem whose last CholQR dropped columns, with every dropped
+// column (an all-zero column of C below b) replaced by a fresh Gaussian
+// value, written over row `row` of buffer 0 in the block's storage type.  The
+// whole row is read before it is written, so buffer 0 may be the source.
+template <int M, int B>
+__global__ __launch_bounds__(256) void k_refill(const ProbView *__restrict__ views, const int *__restrict__ off,
+                                                int nprob, int b, uint64_t seed, uint32_t salt) {
+    using TY = typename Traits<M>::TY;
+    using TA = typename Traits<M>::TA;
+    __shared__ double Cm[B * B];
+    __shared__ double ex[B];
+    __shared__ int dropped[B];
+    const int p = find_problem(off, nprob, blockIdx.x);
+    const ProbView &v = views[p];
+    SolveState *st = v.st;
+    if (st->done || st->dead <= 0 || st->ymode != M) return;  // uniform per problem
+    for (int i = threadIdx.x; i < B * B; i += 256) Cm[i] = st->C[i];
+    if (threadIdx.x < B) ex[threadIdx.x] = st->e_x[threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x < B) {
+        bool zero = true;
+        for (int r = 0; r < B; ++r) zero = zero && Cm[r * B + threadIdx.x] == 0.0;
+        dropped[threadIdx.x] = (threadIdx.x < b && zero) ? 1 : 0;
+    }
+    __syncthreads();
+    if (blockIdx.x == off[p] && threadIdx.x == 0) st->refill = 1;
+    const int64_t row = (int64_t)(blockIdx.x - off[p]) * 256 + threadIdx.x;
+    if (row >= v.n) return;
+    double y[B];
+    load_row<B, TY>(st->ycur ? v.Y1 : v.Y0, row, y);
+    const double inv_n = 1.0 / (double)v.n;
+#pragma unroll
+    for (int a = 0; a < B; ++a) y[a] -= ex[a] * inv_n;
+    TY *dst = (TY *)v.Y0 + row * B;
+    for (int j = 0; j < B; ++j) {
+        double x = 0.0;
+        if (dropped[j]) {
+            uint32_t ctr[4] = {(uint32_t)row, (uint32_t)j | (salt << 8), (uint32_t)(row >> 32), (uint32_t)p};
+            philox4x32_10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32));
+            x = (double)gauss_from(ctr[0], ctr[1]);
+        } else {
+#pragma unroll
+            for (int a = 0; a < B; ++a) x += y[a] * Cm[a * B + j];
+        }
+        dst[j] = down<TY>((TA)x);
+    }
+}
+
 // Landmark-block start (see launch_lift_prep).  One thread per element of
 // the l x B block U of problem p.
 template <int M, int B, int LMDS>
@@ -1062,11 +1114,34 @@ static hipError_t start_impl(const Batch &bt, uint64_t seed, hipStream_t s) {
     if (grid <= 0) return hipErrorInvalidValue;
     if constexpr (wide_width(BB))
         hipLaunchKernelGGL((k_gram_wide<MM, BB>), dim3(grid), dim3(kWideThreads), 0, s, bt.views,
-                           bt.off(BK_SPMM, (Mode)MM), bt.nprob);
+                           bt.off(BK_SPMM, (Mode)MM), bt.nprob, 0);
     else
         hipLaunchKernelGGL((k_gram<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, bt.off(BK_SPMM, (Mode)MM),
-                           bt.nprob);
+                           bt.nprob, 0);
     return hipGetLastError();
+}
+
+template <int MM, int BB>
+static hipError_t refill_impl(const Batch &bt, uint64_t seed, uint32_t salt, hipStream_t s) {
+    const int g1 = bt.total[BK_ELEM_N][0];
+    const int grid = bt.total[BK_SPMM][MM];
+    if (g1 <= 0 || grid <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_refill<MM, BB>), dim3(g1), dim3(256), 0, s, bt.views, bt.off(BK_ELEM_N, MODE_BF16),
+                       bt.nprob, bt.b, seed, salt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if constexpr (wide_width(BB))
+        hipLaunchKernelGGL((k_gram_wide<MM, BB>), dim3(grid), dim3(kWideThreads), 0, s, bt.views,
+                           bt.off(BK_SPMM, (Mode)MM), bt.nprob, 1);
+    else
+        hipLaunchKernelGGL((k_gram<MM, BB>), dim3(grid), dim3(256), 0, s, bt.views, bt.off(BK_SPMM, (Mode)MM),
+                           bt.nprob, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_refill(Mode m, const Batch &bt, uint64_t seed, uint32_t salt, hipStream_t s) {
+    SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(bt.B, return (refill_impl<MM, BB>(bt, seed, salt, s))));
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_random_start(Mode m, const Batch &bt, uint64_t seed, hipStream_t s) {

@@ -56,7 +56,7 @@ typedef enum {
     SBMDS_ENOMEM = -2,     /* device allocation failed or mem_cap exceeded */
     SBMDS_EHIP = -3,       /* a HIP runtime call failed */
     SBMDS_ENODEV = -4,     /* no usable gfx950 device */
-    SBMDS_EBREAKDOWN = -5  /* the basis lost rank and could not be repaired */
+    SBMDS_EBREAKDOWN = -5  /* non-finite values appeared in the block solver */
 } sbmds_status;
 
 typedef enum {
@@ -69,7 +69,8 @@ typedef enum {
     SBMDS_START_RANDOM = 0, /* seeded Gaussian block (counter-based generator) */
     SBMDS_START_LMDS = 1,   /* landmark MDS of W lifted through P */
     SBMDS_START_LEARNED = 2,/* MLP prediction from landmark features, lifted through P;
-                               the prediction is made once, in sbmds_create */
+                               the features are made once, in sbmds_create, and
+                               the network's forward pass runs in every sbmds_embed */
     SBMDS_START_USER = 3    /* caller-supplied block (sbmds_problem.X0), e.g. to resume */
 } sbmds_start;
 
@@ -79,6 +80,13 @@ typedef enum { SBMDS_MEM_HOST = 0, SBMDS_MEM_DEVICE = 1 } sbmds_mem;
 #define SBMDS_FLAG_KERNEL_TIMING 0x1u /* time every kernel launch with HIP events */
 #define SBMDS_FLAG_NO_GRAPH 0x2u      /* launch iterations eagerly, no hipGraph replay */
 #define SBMDS_FLAG_NO_CERTIFY 0x4u    /* skip the float64 certification pass */
+/* W is symmetric, so the dense product can stream only its upper triangle
+ * (packed once at sbmds_create; half the bytes of the full matrix).  By
+ * default this is done when the batch's float32 W exceeds 256 MB; these
+ * flags force it on or off (float32 / bf16 precisions; FP64 keeps the full
+ * matrix). */
+#define SBMDS_FLAG_PACK_W 0x8u        /* pack W whatever its size */
+#define SBMDS_FLAG_FULL_W 0x10u       /* never pack W */
 
 /*
  * One problem (mesh).  Arrays live in host or device memory according to
@@ -211,7 +219,10 @@ int sbmds_create(const sbmds_problem *probs, int nprob, const sbmds_options *opt
  *   Z_mem    sbmds_mem of Z.
  *   reports  [nprob] (may be NULL).
  * Returns the worst per-problem status.  May be called repeatedly; each
- * call starts again from the start block chosen in the options.
+ * call starts again from the start block chosen in the options.  A block
+ * that loses rank during the solve (its CholQR drops a column, e.g. a start
+ * block with a zero or repeated column) has the dropped columns replaced by
+ * fresh Gaussian ones before the next round of iterations.
  */
 int sbmds_embed(sbmds_ctx *ctx, double *eigvals, void *Z, int Z_mem, sbmds_report *reports);
 

@@ -12,8 +12,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsbmds.so")
-SOURCES = ["sbmds_runtime.cpp", "sbmds_sparse.hip", "sbmds_dense.hip", "sbmds_small.hip", "sbmds_rr.hip",
-           "sbmds_mlp.hip", "sbmds_mlp_api.cpp"]
+SOURCES = ["sbmds_runtime.cpp", "sbmds_sparse.hip", "sbmds_dense.hip", "sbmds_dense_sym.hip", "sbmds_small.hip",
+           "sbmds_rr.hip", "sbmds_mlp.hip", "sbmds_mlp_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

@@ -15,6 +15,7 @@
 #include <type_traits>
 
 #include "sbmds_common.h"
+#include "sbmds_dense_sym.h"
 
 namespace sbmds {
 
@@ -415,6 +416,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const ProbView *__restrict__ 
     }
 
 hipError_t launch_gemm(Mode m, const Batch &bt, int phase, hipStream_t s) {
+    if (bt.gemm_sym[m]) return launch_gemm_sym(m, bt, phase, s);
     const int grid = bt.total[BK_GEMM][m];
     if (grid <= 0) return hipErrorInvalidValue;
     const int *off = bt.off(BK_GEMM, m);
@@ -456,11 +458,13 @@ hipError_t launch_gemm(Mode m, const Batch &bt, int phase, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
-double gemm_bytes(Mode m, const DevProblem &p) {
+double gemm_bytes(Mode m, const DevProblem &p, bool packed) {
     const double sw = m == MODE_BF16 ? 2.0 : (m == MODE_FP64 ? 8.0 : 4.0);
     const double st = m == MODE_BF16 ? 2.0 : (m == MODE_FP32 ? 4.0 : 8.0);
     const double su = (m == MODE_F64ACC || m == MODE_FP64) ? 8.0 : 4.0;
-    return (double)p.l * p.l * sw + (double)p.l * p.B * (st + su);
+    // the packed product reads the upper triangle: l (l + 1) / 2 elements
+    const double welems = packed ? 0.5 * (double)p.l * (p.l + 1) : (double)p.l * p.l;
+    return welems * sw + (double)p.l * p.B * (st + su);
 }
 
 }  // namespace sbmds

@@ -54,6 +54,7 @@ struct SolveState {
     int iters[4];                // iterations run per phase
     int sweeps_total;            // Jacobi sweeps in this solve
     int ymode;                   // Mode of the current block Y[ycur]
+    int refill;                  // dead columns were just refilled: Y0 awaits its Gram and CholQR
     double hist[4];              // maxres of the latest iterations of the phase
 };
 
@@ -72,6 +73,11 @@ struct PhaseRule {
 
 enum SolveFlags { SF_REPAIRED = 1, SF_NONFINITE = 2 };
 
+// `init` argument of the Rayleigh-Ritz kernels: an iteration's step, the
+// CholQR of a new start block (resets the solve's control state), or the
+// CholQR of a block whose dead columns were refilled (keeps it).
+enum RRInit { RR_STEP = 0, RR_START = 1, RR_REFILL = 2 };
+
 // Bytes of SolveState from `theta` to the end: what the host reads after
 // each round (the Rayleigh-Ritz kernels write it to pinned host memory).
 constexpr size_t kSummaryOffset = offsetof(SolveState, theta);
@@ -87,6 +93,7 @@ struct DevProblem {
     void *val[NUM_MODES] = {};   // P values per mode (aliases where modes share)
     void *valT[NUM_MODES] = {};
     void *W[NUM_MODES] = {};     // padded l x lda
+    float *Wp = nullptr;         // packed upper triangle of the float32 W (large l), or NULL
     double *c[NUM_MODES] = {};   // P^T 1 in float64 from that mode's values
     void *Y[2] = {};             // n x B, sized for 8-byte elements
     void *T = nullptr, *U = nullptr;  // lda x B, 8-byte elements
@@ -110,6 +117,8 @@ struct Tune {
     int spmm_cap = 256;
     int gemm_mfma = 0;
     int gemm_target = 1024;
+    int gemm_sym = 0;   // dense product from the packed upper triangle of W
+    int sym_c = 16;     // its region width in 64-column tiles
     int spmmt_wpr = 4;
     int spmm_wpe = 4;  // row-split SpMM (widths 8-32): 4 = fused Rayleigh-Ritz form, 8 = two blocks per CU
 };
@@ -129,6 +138,7 @@ struct ProbView {
     const void *val[NUM_MODES];
     const void *valT[NUM_MODES];
     const void *W[NUM_MODES];
+    const float *Wp;       // packed upper triangle of W (float32), or NULL
     const double *c[NUM_MODES];
     void *Y0, *Y1, *T, *U, *gpart;
     double *red_gemm, *red_spmm;
@@ -142,11 +152,16 @@ struct ProbView {
     int gemm_rowtiles[NUM_MODES];
     int gemm_ksplit[NUM_MODES];
     int gemm_kchunk[NUM_MODES];
+    int sym_c[NUM_MODES];  // region width (tiles) of the packed dense product
 };
 
 // Block-to-problem tables: for each kind of launch and mode, off[p] is the
 // first block of problem p and off[nprob] the grid size.
-enum BlockKind { BK_SPMM = 0, BK_SPMMT = 1, BK_GEMM = 2, BK_ELEM_NB = 3, BK_ELEM_N = 4, BK_ELEM_LB = 5, NUM_BK = 6 };
+enum BlockKind {
+    BK_SPMM = 0, BK_SPMMT = 1, BK_GEMM = 2, BK_ELEM_NB = 3, BK_ELEM_N = 4, BK_ELEM_LB = 5,
+    BK_GEMMF = 6,  // 64-row tiles of U (finish launch of the packed dense product)
+    NUM_BK = 7
+};
 
 // Host handle of a batch: every launch covers all problems of a context.
 struct Batch {
@@ -155,6 +170,7 @@ struct Batch {
     int64_t max_l = 0;                         // largest landmark count of the batch
     int spmmt_wpr[NUM_MODES] = {4, 4, 4, 4};  // waves per landmark row in the transposed SpMM
     int gemm_mfma[NUM_MODES] = {};             // dense product on the matrix cores
+    int gemm_sym[NUM_MODES] = {};              // dense product from the packed upper triangle of W
     int spmm_wpe8[NUM_MODES] = {};             // row-split SpMM in its two-blocks-per-CU form
     ProbView *views = nullptr;   // device [nprob]
     int *offs = nullptr;         // device [NUM_BK][NUM_MODES][nprob + 1]
@@ -180,6 +196,13 @@ hipError_t launch_rr_solve(const Batch &bt, int init, int max_sweeps, const Phas
                            hipStream_t stream);
 hipError_t launch_random_start(Mode m, const Batch &bt, uint64_t seed, hipStream_t stream);
 hipError_t launch_user_start(Mode m, const Batch &bt, hipStream_t stream);
+// Rank repair: for every problem of `bt` whose last CholQR dropped columns
+// (SolveState::dead > 0, not done) and whose current block is stored in mode
+// m, writes its basis X = J Y C into buffer 0 with the dropped columns
+// replaced by fresh Gaussian ones (`salt` keeps them apart from the start
+// block's), then its Gram; a following launch_rr_solve(bt, RR_REFILL, ...)
+// orthonormalises it without touching the schedule.
+hipError_t launch_refill(Mode m, const Batch &bt, uint64_t seed, uint32_t salt, hipStream_t stream);
 hipError_t launch_convert_y(Mode from, Mode to, const Batch &bt, int phase, hipStream_t stream);
 // Phase changes the transposed SpMM bridges by reading the previous phase's
 // (narrower) block directly; they need no launch of their own.
@@ -205,6 +228,6 @@ int spmm_block_cap(Mode m, int B);  // most blocks worth launching for one probl
 // Algorithmic bytes / flops of one launch of each hot kernel (one problem).
 double spmm_bytes(Mode m, const DevProblem &p);
 double spmm_t_bytes(Mode m, const DevProblem &p);
-double gemm_bytes(Mode m, const DevProblem &p);
+double gemm_bytes(Mode m, const DevProblem &p, bool packed);
 
 }  // namespace sbmds

@@ -196,6 +196,10 @@ int forward_device(sbmds_mlp *net, const float *feat, int64_t rows, float *Y) {
     HIPCHK(hipMemcpyAsync(Y, net->Y, rows * net->k * 4, hipMemcpyDeviceToDevice, net->stream));
     return SBMDS_OK;
 }
+int reserve_rows(sbmds_mlp *net, int64_t rows) {
+    OKCHK(check_rows(rows));
+    return ensure_rows(net, rows);
+}
 int out_width(const sbmds_mlp *net) { return net->k; }
 }  // namespace mlp
 }  // namespace sbmds

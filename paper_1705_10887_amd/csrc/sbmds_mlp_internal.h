@@ -41,6 +41,9 @@ struct sbmds_mlp;
 namespace sbmds {
 namespace mlp {
 int forward_device(sbmds_mlp *net, const float *feat, int64_t rows, float *Y);
+// Grow the handle's work buffers to `rows` now, so that later forward passes
+// of at most that many rows allocate nothing.
+int reserve_rows(sbmds_mlp *net, int64_t rows);
 int out_width(const sbmds_mlp *net);
 }  // namespace mlp
 // Error reporting of the C ABI (defined with sbmds_last_error).

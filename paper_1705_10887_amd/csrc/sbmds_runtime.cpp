@@ -32,6 +32,7 @@
 #include "../../include/sbmds_mlp.h"
 #include "sbmds_common.h"
 #include "sbmds_internal.h"
+#include "sbmds_dense_sym.h"
 #include "sbmds_mlp_internal.h"
 
 using namespace sbmds;
@@ -67,7 +68,7 @@ struct Summary {  // tail of SolveState read back after each iteration
     int sweeps;
     int ycur, zbuf, zmode, phase, done, pending_convert, phase_iters, total_iters;
     int iters[4];
-    int sweeps_total, ymode;
+    int sweeps_total, ymode, refill;
     double hist[4];
 };
 static_assert(sizeof(Summary) == kSummaryBytes, "summary layout");
@@ -145,6 +146,7 @@ struct sbmds_ctx {
     std::vector<PendingEv> pending;
     std::vector<hipEvent_t> ev_pool;
     void *zstage = nullptr;                    // device staging of Z for host outputs
+    bool packed = false;                       // W also kept as its packed upper triangle
 };
 
 namespace {
@@ -293,6 +295,7 @@ std::vector<PhaseRule> schedule(const sbmds_options &o) {
 }
 
 constexpr int kMaxGemmSplit = 64;   // K splits of the dense product (bounds its scratch)
+constexpr double kPackMinBytes = 256e6;  // float32 W of a batch above which its upper triangle is packed
 constexpr int kMaxSpmmBlocks = 1024;
 
 LaunchCfg make_cfg(Mode m, const DevProblem &p, const Tune &t) {
@@ -330,6 +333,12 @@ Tune default_tune(Mode m, const std::vector<DevProblem> &probs) {
     const bool f64 = m == MODE_F64ACC || m == MODE_FP64;
     t.gemm_mfma = (gemm_mfma(m, B) && (f64 || l2 * 4.0 > 64e6)) ? 1 : 0;
     t.gemm_target = t.gemm_mfma ? 512 : 1024;
+    // the packed upper triangle of W (half the dense product's bytes) where
+    // it was built, i.e. where W is too large for the caches
+    bool all_packed = !probs.empty();
+    for (const DevProblem &p : probs) all_packed = all_packed && p.Wp != nullptr;
+    t.gemm_sym = (all_packed && sym_supported(m, B)) ? 1 : 0;
+    t.sym_c = 16;
     // the two-blocks-per-CU SpMM once a launch streams enough bytes that
     // bandwidth, not the latency of the separate Rayleigh-Ritz launch, counts
     double sp_bytes = 0;
@@ -434,7 +443,7 @@ int enqueue_iteration(sbmds_ctx *ctx, SolveSet &set, const PhaseRule &r) {
     for (const DevProblem &p : set.probs) {
         b_spmm += spmm_bytes(m, p);
         b_spmmt += spmm_t_bytes(m, p);
-        b_gemm += gemm_bytes(m, p);
+        b_gemm += gemm_bytes(m, p, bt.gemm_sym[m] != 0);
         f_sp += 2.0 * p.nnz * p.B;
         f_ge += 2.0 * (double)p.l * p.l * p.B;
     }
@@ -562,6 +571,21 @@ int run_set(sbmds_ctx *ctx, SolveSet &set, const std::vector<PhaseRule> &rules, 
             }
         }
         if (all_done || launched >= max_iter || from >= nph) break;
+        // rank repair: a block that lost rank (its CholQR dropped columns,
+        // e.g. a start block with a zero or repeated column) gets fresh
+        // Gaussian columns in place of the dropped ones before the next round
+        unsigned refill_modes = 0;
+        for (int i = 0; i < np; ++i)
+            if (!S[i].done && S[i].dead > 0) refill_modes |= 1u << S[i].ymode;
+        if (refill_modes) {
+            for (int m = 0; m < NUM_MODES; ++m)
+                if (refill_modes & (1u << m))
+                    OKCHK(timed(ctx, "refill", 0.0, 0.0, [&] {
+                        return launch_refill((Mode)m, set.bt, ctx->opt.seed, (uint32_t)launched + 1u, ctx->stream);
+                    }));
+            OKCHK(timed(ctx, "rr_refill", 0.0, 0.0,
+                        [&] { return launch_rr_solve(set.bt, RR_REFILL, 0, rules[0], ctx->stream); }));
+        }
         first = false;
     }
     if (all_done) {
@@ -634,9 +658,10 @@ int solve_all(sbmds_ctx *ctx, sbmds_report *reps, const std::function<int()> &ou
                         [&] { return launch_lift_prep(m0, set.bt, &ctx->lmk.bt, nullptr, o.seed, ctx->stream); }));
             OKCHK(lift());
         } else if (o.start == SBMDS_START_LEARNED) {
-            // the network's landmark prediction (made at create: it depends
-            // on the inputs and the weights only) as the first k columns, the
-            // rest Gaussian, lifted through P
+            // the network's landmark prediction (forward pass on the features
+            // made at create) as the first k columns, the rest Gaussian,
+            // lifted through P
+            OKCHK(mlp::forward_device(ctx->net, ctx->feat, ctx->total_l, ctx->learned));
             OKCHK(timed(ctx, "lift", 0.0, 0.0,
                         [&] { return launch_lift_prep(m0, set.bt, nullptr, ctx->learned, o.seed, ctx->stream); }));
             OKCHK(lift());
@@ -781,9 +806,11 @@ int autotune(sbmds_ctx *ctx, SolveSet &set) {
         for (const auto &e : cache) {
             if (e.first != key) continue;
             Tune t = set.tune[m];  // fields the entry does not carry keep their defaults
-            const int got = std::sscanf(e.second.c_str(), "%d %d %d %d %d", &t.spmm_cap, &t.gemm_mfma,
-                                        &t.gemm_target, &t.spmmt_wpr, &t.spmm_wpe);
+            const int got = std::sscanf(e.second.c_str(), "%d %d %d %d %d %d %d", &t.spmm_cap, &t.gemm_mfma,
+                                        &t.gemm_target, &t.spmmt_wpr, &t.spmm_wpe, &t.gemm_sym, &t.sym_c);
+            if (t.gemm_sym && (set.probs[0].Wp == nullptr || !sym_supported(m, set.probs[0].B))) t.gemm_sym = 0;
             if (got >= 4 && t.spmm_cap >= 1 && t.gemm_target >= 1 &&
+                (t.sym_c == 8 || t.sym_c == 16 || t.sym_c == 32) &&
                 (t.spmmt_wpr == 1 || t.spmmt_wpr == 2 || t.spmmt_wpr == 4) && (t.spmm_wpe == 4 || t.spmm_wpe == 8)) {
                 set.tune[m] = t;
                 found = true;
@@ -858,17 +885,37 @@ int autotune(sbmds_ctx *ctx, SolveSet &set) {
             }
             set.tune[m] = keep;
         }
+        // dense product: full W on the matrix cores or vector ALUs with a
+        // K split (target block counts), or the packed upper triangle with
+        // regions of 8, 16 or 32 tile columns
         std::vector<int> gemm_cands;
         for (int mf = 0; mf < (gemm_mfma(m, set.probs[0].B) ? 2 : 1); ++mf)
             for (int tg : {1, 128, 256, 512, 1024, 2048}) gemm_cands.push_back(mf * 100000 + tg);  // 1: no K split
-        OKCHK(try_all(gemm_cands, [](Tune &t, int v) { t.gemm_mfma = v / 100000; t.gemm_target = v % 100000; },
+        bool packed = sym_supported(m, set.probs[0].B);
+        for (const DevProblem &q : set.probs) packed = packed && q.Wp != nullptr;
+        if (packed)
+            for (int cw : {8, 16, 32}) gemm_cands.push_back(1000000 + cw);
+        const int keep_mfma = set.tune[m].gemm_mfma, keep_target = set.tune[m].gemm_target;
+        OKCHK(try_all(gemm_cands,
+                      [&](Tune &t, int v) {
+                          if (v >= 1000000) {
+                              t.gemm_sym = 1;
+                              t.sym_c = v - 1000000;
+                              t.gemm_mfma = keep_mfma;
+                              t.gemm_target = keep_target;
+                          } else {
+                              t.gemm_sym = 0;
+                              t.gemm_mfma = v / 100000;
+                              t.gemm_target = v % 100000;
+                          }
+                      },
                       [&] { return launch_gemm(m, set.bt, 0, ctx->stream); }));
         OKCHK(try_all(std::vector<int>{1, 2, 4}, [](Tune &t, int v) { t.spmmt_wpr = v; },
                       [&] { return launch_spmm_t(m, set.bt, 0, ctx->stream); }));
         const Tune &t = set.tune[m];
-        char val[64];
-        std::snprintf(val, sizeof(val), "%d %d %d %d %d", t.spmm_cap, t.gemm_mfma, t.gemm_target, t.spmmt_wpr,
-                      t.spmm_wpe);
+        char val[96];
+        std::snprintf(val, sizeof(val), "%d %d %d %d %d %d %d", t.spmm_cap, t.gemm_mfma, t.gemm_target, t.spmmt_wpr,
+                      t.spmm_wpe, t.gemm_sym, t.sym_c);
         cache.push_back({key, val});
         dirty = true;
     }
@@ -1039,6 +1086,9 @@ int build_batch(sbmds_ctx *ctx, SolveSet &set) {
     for (int m = 0; m < NUM_MODES; ++m) {
         bt.spmmt_wpr[m] = set.tune[m].spmmt_wpr;
         bt.gemm_mfma[m] = set.tune[m].gemm_mfma && gemm_mfma((Mode)m, bt.B) ? 1 : 0;
+        bool packed = sym_supported((Mode)m, bt.B);
+        for (const DevProblem &q : set.probs) packed = packed && q.Wp != nullptr;
+        bt.gemm_sym[m] = set.tune[m].gemm_sym && packed ? 1 : 0;
         bt.spmm_wpe8[m] = set.tune[m].spmm_wpe == 8 ? 1 : 0;  // read by the widths that have the form
     }
 
@@ -1067,7 +1117,10 @@ int build_batch(sbmds_ctx *ctx, SolveSet &set) {
             v.gemm_rowtiles[m] = (int)((p.l + c.gemm_rt - 1) / c.gemm_rt);
             v.gemm_ksplit[m] = c.gemm_ksplit;
             v.gemm_kchunk[m] = c.gemm_kchunk;
+            v.sym_c[m] = set.tune[m].sym_c;
+            if (bt.gemm_sym[m]) v.gemm_rowtiles[m] = p.lda / 64;  // H / s partials per 64-row tile
         }
+        v.Wp = p.Wp;
         v.Y0 = p.Y[0];
         v.Y1 = p.Y[1];
         v.T = p.T;
@@ -1098,7 +1151,11 @@ int build_batch(sbmds_ctx *ctx, SolveSet &set) {
                 switch (kd) {
                     case BK_SPMM: nb = v.spmm_blocks[m]; break;
                     case BK_SPMMT: nb = (p.l + 4 / bt.spmmt_wpr[m] - 1) / (4 / bt.spmmt_wpr[m]); break;
-                    case BK_GEMM: nb = (int64_t)v.gemm_rowtiles[m] * v.gemm_ksplit[m]; break;
+                    case BK_GEMM:
+                        nb = bt.gemm_sym[m] ? sym_regions(p.lda / 64, sym_region_rows((Mode)m, bt.B), v.sym_c[m])
+                                            : (int64_t)v.gemm_rowtiles[m] * v.gemm_ksplit[m];
+                        break;
+                    case BK_GEMMF: nb = bt.gemm_sym[m] ? p.lda / 64 : 0; break;
                     case BK_ELEM_NB: nb = (p.n * p.B + 255) / 256; break;
                     case BK_ELEM_LB: nb = (p.l * p.B + 255) / 256; break;
                     default: nb = (p.n + 255) / 256; break;
@@ -1153,6 +1210,15 @@ int alloc_work(sbmds_ctx *ctx, SolveSet &set, int i) {
     p.max_spmm_blocks = std::max(p.max_spmm_blocks, 1);
     p.max_ksplit = std::max(1, std::min(p.lda / 64, kMaxGemmSplit));
     const int B = p.B;
+    size_t gpart_elems = (size_t)p.max_ksplit * p.lda * B;
+    if (p.Wp) {
+        // slots of the packed product: R + C per region, 64 x B each, for
+        // every region shape the tuner may pick
+        const int nt = p.lda / 64;
+        for (int R : {4, 8})
+            for (int cw : {8, 16, 32})
+                gpart_elems = std::max(gpart_elems, (size_t)sym_regions(nt, R, cw) * (R + cw) * 64 * B);
+    }
     const int EG = B * (B + 1) / 2 + B;   // Gram triangle + column sums
     const int EH = B * B + B;             // H + s
     const int nspmm_cnt = tree_counter_count(p.max_spmm_blocks, kFan);
@@ -1163,7 +1229,7 @@ int alloc_work(sbmds_ctx *ctx, SolveSet &set, int i) {
     OKCHK(dalloc(ctx, &p.Y[1], (size_t)p.n * B * 8));
     OKCHK(dalloc(ctx, &p.T, (size_t)p.lda * B * 8));
     OKCHK(dalloc(ctx, &p.U, (size_t)p.lda * B * 8));
-    OKCHK(dalloc(ctx, &p.gpart, (size_t)p.max_ksplit * p.lda * B * 8));
+    OKCHK(dalloc(ctx, &p.gpart, gpart_elems * 8));
     OKCHK(dalloc(ctx, (void **)&p.red_gemm, tree_scratch_elems(p.max_rowtiles, EH, kFan) * 8));
     OKCHK(dalloc(ctx, (void **)&p.red_spmm, tree_scratch_elems(p.max_spmm_blocks, EG, kFan) * 8));
     OKCHK(dalloc(ctx, (void **)&cnt, ncnt * 4));
@@ -1219,6 +1285,7 @@ int make_landmark_problem(sbmds_ctx *ctx, int i) {
         p.W[m] = mp.W[m];
         p.c[m] = (double *)cd;
     }
+    p.Wp = mp.Wp;
     return alloc_work(ctx, ctx->lmk, i);
 }
 
@@ -1256,8 +1323,9 @@ int setup_learned(sbmds_ctx *ctx, const sbmds_problem *probs, int nprob) {
     OKCHK(dalloc(ctx, (void **)&ctx->feat, (size_t)ctx->total_l * mlp::kIn * 4));
     OKCHK(dalloc(ctx, (void **)&ctx->learned, (size_t)ctx->total_l * ctx->opt.k * 4));
     OKCHK(dalloc(ctx, (void **)&ctx->rowmax, (size_t)maxl * 8));
-    // the prediction itself: features of each problem's landmarks, then one
-    // forward pass over all of them
+    // features of each problem's landmarks (they depend on the inputs only);
+    // the forward pass over all of them runs in every sbmds_embed, as part of
+    // the start block, on work buffers reserved here
     const Mode wm = ctx->opt.prec == SBMDS_FP64 ? MODE_FP64 : MODE_FP32;
     int64_t loff = 0;
     for (int i = 0; i < nprob; ++i) {
@@ -1266,7 +1334,7 @@ int setup_learned(sbmds_ctx *ctx, const sbmds_problem *probs, int nprob) {
                                    ctx->feat + loff * mlp::kIn, ctx->rowmax, ctx->stream));
         loff += p.l;
     }
-    OKCHK(mlp::forward_device(ctx->net, ctx->feat, ctx->total_l, ctx->learned));
+    OKCHK(mlp::reserve_rows(ctx->net, ctx->total_l));
     return SBMDS_OK;
 }
 
@@ -1324,6 +1392,19 @@ int create_impl(const sbmds_problem *probs, int nprob, const sbmds_options *opt_
     if (int rc = alloc_set(ctx, ctx->main, nprob); rc < 0) return cleanup(rc);
 
     const size_t esz = fp64 ? 8 : 4;
+    {
+        // W is also kept as its packed upper triangle once the batch's float32
+        // W no longer fits the caches (the dense product then streams half)
+        double wbytes = 0.0;
+        bool fits = !fp64;
+        for (int i = 0; i < nprob; ++i) {
+            const int64_t lda = (probs[i].l + 63) / 64 * 64;
+            wbytes += 4.0 * (double)probs[i].l * (double)probs[i].l;
+            fits = fits && lda / 64 <= kSymMaxTiles;
+        }
+        ctx->packed = fits && !(o.flags & SBMDS_FLAG_FULL_W) &&
+                      (wbytes > kPackMinBytes || (o.flags & SBMDS_FLAG_PACK_W));
+    }
     for (int i = 0; i < nprob; ++i) {
         const sbmds_problem &in = probs[i];
         DevProblem &p = ctx->main.probs[i];
@@ -1360,6 +1441,12 @@ int create_impl(const sbmds_problem *probs, int nprob, const sbmds_options *opt_
         int rc = fp64 ? upload_problem<double>(ctx, in, p, rp, ci, (const double *)val, (const double *)Wh, true)
                       : upload_problem<float>(ctx, in, p, rp, ci, (const float *)val, (const float *)Wh, false);
         if (rc < 0) return cleanup(rc);
+        if (ctx->packed) {
+            const size_t pk = (size_t)sym_strip_base(p.lda / 64, p.lda) * 4;
+            if ((rc = dalloc(ctx, (void **)&p.Wp, pk)) < 0) return cleanup(rc);
+            if (launch_pack_sym((const float *)p.W[MODE_FP32], p.l, p.lda, p.Wp, ctx->stream) != hipSuccess)
+                return cleanup(fail(SBMDS_EHIP, "packing W failed"));
+        }
 
         if ((rc = alloc_work(ctx, ctx->main, i)) < 0) return cleanup(rc);
         if (o.start == SBMDS_START_USER) {

@@ -102,15 +102,46 @@ def grid_torus_operator(nu=1800, nv=1000, lu=250, lv=200, nbr=10, seed=5005, chu
         list(ex.map(rows, range(0, l, 256)))
     np.fill_diagonal(W, 0.0)
     return {"n": n, "l": l, "rowptr": rowptr.astype(np.int32), "col": col, "val": val, "W": W,
-            "landmarks": lm_vertex.astype(np.int32)}
+            "landmarks": lm_vertex.astype(np.int32), "shape": (nu, nv, lu, lv), "phases": phases}
 
 
-def grid_torus_batch(count=256, nmin=2000, nmax=200_000, seed0=6006):
-    """Many meshes of uneven size in the batched workload's recipe (n_i
-    uniform in [nmin, nmax] from default_rng(seed0), l_i ~ n_i / 50), each a
-    grid torus of the kind above: n_v = round(sqrt(n_i / 2)), n_u =
-    round(n_i / n_v), landmark grid about every sqrt(50) vertices (at least
-    5 x 5), seed seed0 + 1 + i."""
+def grid_torus_positions(prob):
+    """Vertex positions (n x 3, float32) of a grid-torus operator's mesh, in
+    vertex order (the landmark rows of this array are the positions W was
+    built from)."""
+    nu, nv, _, _ = prob["shape"]
+    out = np.empty((nu * nv, 3), dtype=np.float32)
+    jj = np.arange(nv)
+    for i0 in range(0, nu, 256):
+        i1 = min(nu, i0 + 256)
+        ii = np.arange(i0, i1)
+        out[i0 * nv:i1 * nv] = _positions(np.repeat(ii, nv), np.tile(jj, i1 - i0), nu, nv,
+                                          prob["phases"]).astype(np.float32)
+    return out
+
+
+def grid_torus_family(count=48, nmin=8000, nmax=60000, seed0=5100):
+    """Smaller operators of the largest workload's recipe for training its
+    start network: n_i uniform in [nmin, nmax] (default_rng(seed0)), the
+    1800 x 1000 grid's aspect ratio and landmark spacing (n_u / n_v = 1.8,
+    7.2 x 5 vertices per landmark), seeds seed0 + 1 + i."""
+    rng = np.random.default_rng(seed0)
+    out = []
+    for i, ni in enumerate(rng.integers(nmin, nmax + 1, size=count)):
+        nv = max(10, int(round(np.sqrt(ni / 1.8))))
+        nu = max(10, int(round(1.8 * nv)))
+        lu = max(5, int(round(nu / 7.2)))
+        lv = max(5, int(round(nv / 5.0)))
+        out.append(grid_torus_operator(nu, nv, lu, lv, seed=seed0 + 1 + i, chunk=1 << 20))
+    return out
+
+
+def grid_torus_batch_shapes(count=256, nmin=2000, nmax=200_000, seed0=6006):
+    """Grid shapes and seeds of the batched workload's meshes (n_i uniform in
+    [nmin, nmax] from default_rng(seed0), l_i ~ n_i / 50): per mesh the
+    arguments (nu, nv, lu, lv, seed) of grid_torus_operator, with n_v =
+    round(sqrt(n_i / 2)), n_u = round(n_i / n_v), a landmark grid about every
+    sqrt(50) vertices (at least 5 x 5) and seed seed0 + 1 + i."""
     rng = np.random.default_rng(seed0)
     sizes = rng.integers(nmin, nmax + 1, size=count)
     out = []
@@ -119,5 +150,16 @@ def grid_torus_batch(count=256, nmin=2000, nmax=200_000, seed0=6006):
         nu = max(10, int(round(ni / nv)))
         lu = max(5, int(round(nu / np.sqrt(50.0))))
         lv = max(5, int(round(nv / np.sqrt(50.0))))
-        out.append(grid_torus_operator(nu, nv, lu, lv, seed=seed0 + 1 + i, chunk=1 << 20))
+        out.append((nu, nv, lu, lv, seed0 + 1 + i))
     return out
+
+
+def grid_torus_batch_mesh(shape):
+    nu, nv, lu, lv, seed = shape
+    return grid_torus_operator(nu, nv, lu, lv, seed=seed, chunk=1 << 20)
+
+
+def grid_torus_batch(count=256, nmin=2000, nmax=200_000, seed0=6006):
+    """Many meshes of uneven size in the batched workload's recipe, each a
+    grid torus of the kind above (shapes from grid_torus_batch_shapes)."""
+    return [grid_torus_batch_mesh(s) for s in grid_torus_batch_shapes(count, nmin, nmax, seed0)]

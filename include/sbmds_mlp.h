@@ -78,6 +78,18 @@ int sbmds_mlp_features(const float *xyz, int64_t n, const int32_t *landmark_vert
 /* Forward pass on `rows` feature rows (rows <= 4,000,000): Y [rows*k]. */
 int sbmds_mlp_forward(sbmds_mlp *net, const float *feat, int64_t rows, float *Y, int mem);
 
+/* The forward pass of sbmds_mlp_forward for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): feat [rows*19] and Y [rows*k] are
+ * device arrays; 1 <= rows <= 4,000,000, larger counts return SBMDS_EINVAL.
+ * Nothing is allocated: the hidden layers go through a fixed work buffer of
+ * 8,192 rows (about 9 MB of device memory per GPU, held until the process
+ * ends), chunk after chunk, with the same kernels as sbmds_mlp_forward, so
+ * Y matches its output bit for bit.  Asynchronous on the network's stream
+ * (no synchronisation); call it with the network's device current.  Calls
+ * that overlap on one GPU share that buffer and race: serialise them. */
+int sbmds_mlp_forward_noalloc(sbmds_mlp *net, const float *feat, int64_t rows, float *Y);
+
 /* Loss and gradient over meshes whose rows are seg[m] .. seg[m+1]-1 of feat
  * [rows*19] and of the targets T [rows*k] (seg: nseg+1 int64 offsets,
  * seg[0] = 0, non-decreasing, each mesh at least one row).  The gradient

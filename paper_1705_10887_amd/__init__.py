@@ -90,6 +90,7 @@ EXPORTS = [
     "sbmds_mlp_create", "sbmds_mlp_load", "sbmds_mlp_save", "sbmds_mlp_num_params", "sbmds_mlp_get_params",
     "sbmds_mlp_set_params", "sbmds_mlp_set_norm", "sbmds_mlp_features", "sbmds_mlp_forward",
     "sbmds_mlp_loss_grad", "sbmds_mlp_adam_step", "sbmds_mlp_destroy",
+    "sbmds_mlp_forward_noalloc",
 ]
 
 

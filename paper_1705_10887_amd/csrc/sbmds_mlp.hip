@@ -217,7 +217,7 @@ __global__ __launch_bounds__(256) void k_gemm(const float *__restrict__ A, int64
                 C[o] = acc[i][jx] + bias[n];
             } else if (EPI == EPI_BIAS_GELU) {
                 const float z = acc[i][jx] + bias[n];
-                Zout[o] = z;
+                if (Zout) Zout[o] = z;  // pre-activations are kept for the backward pass only
                 C[o] = gelu(z);
             } else {
                 C[o] = acc[i][jx] * gelu_grad(Zin[o]);

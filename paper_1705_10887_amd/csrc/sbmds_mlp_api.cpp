@@ -3,7 +3,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -185,6 +187,36 @@ int check_rows(int64_t rows) {
     return SBMDS_OK;
 }
 
+// ---- work buffer of the forward pass without allocation -------------------
+// A fixed array per GPU (it lives until the process ends), large enough for
+// one chunk of rows of the standardised features and both hidden layers;
+// sbmds_mlp_forward_noalloc runs the rows through it chunk by chunk.  Host
+// code never uses the array's name as an address: its device address is
+// looked up once per device (hipGetSymbolAddress) and kept.
+constexpr int64_t kNoAllocChunk = 8192;
+constexpr int64_t kNoAllocFloats = kNoAllocChunk * (kIn + 2 * kHid);
+static __device__ __align__(256) float scratch[kNoAllocFloats];
+constexpr int kMaxDevices = 64;
+std::array<float *, kMaxDevices> g_scratch{};
+std::mutex g_scratch_mu;
+
+// Device address of the current device's work buffer (looked up on the
+// first use on that device, with the device current).
+int scratch_of_current_device(float **out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return api_fail(SBMDS_ENODEV, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return api_fail(SBMDS_EHIP, "hipGetSymbolAddress returned NULL");
+        g_scratch[dev] = (float *)p;
+    }
+    *out = g_scratch[dev];
+    return SBMDS_OK;
+}
+
 }  // namespace
 
 namespace sbmds {
@@ -211,6 +243,8 @@ int sbmds_mlp_create(int k, uint64_t seed, void *stream, sbmds_mlp **out) {
     if (!out) return api_fail(SBMDS_EINVAL, "out is NULL");
     *out = nullptr;
     if (k < 1 || k > kMaxOut) return api_fail(SBMDS_EINVAL, "k must be in [1, 8]");
+    float *sc = nullptr;
+    OKCHK(scratch_of_current_device(&sc));  // set-up of the allocation-free forward pass on this device
     sbmds_mlp *net = new sbmds_mlp();
     net->k = k;
     net->stream = (hipStream_t)stream;
@@ -245,6 +279,8 @@ int sbmds_mlp_load(const char *path, void *stream, sbmds_mlp **out) {
     api_clear_error();
     if (!out || !path) return api_fail(SBMDS_EINVAL, "path and out must be non-NULL");
     *out = nullptr;
+    float *sc = nullptr;
+    OKCHK(scratch_of_current_device(&sc));  // set-up of the allocation-free forward pass on this device
     FILE *f = std::fopen(path, "rb");
     if (!f) return api_fail(SBMDS_EINVAL, std::string("cannot open ") + path);
     char magic[8];
@@ -382,6 +418,31 @@ int sbmds_mlp_forward(sbmds_mlp *net, const float *feat, int64_t rows, float *Y,
     HIPCHK(hipMemcpyAsync(Y, net->Y, (size_t)rows * net->k * 4,
                           mem == SBMDS_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, net->stream));
     HIPCHK(hipStreamSynchronize(net->stream));
+    return SBMDS_OK;
+}
+
+int sbmds_mlp_forward_noalloc(sbmds_mlp *net, const float *feat, int64_t rows, float *Y) {
+    api_clear_error();
+    if (!net || !feat || !Y) return api_fail(SBMDS_EINVAL, "NULL argument");
+    if (rows < 1 || rows > kMaxRows)
+        return api_fail(SBMDS_EINVAL, "rows must be in [1, 4000000] (got " + std::to_string(rows) + ")");
+    float *sc = nullptr;
+    OKCHK(scratch_of_current_device(&sc));
+    const Layout L(net->k);
+    hipStream_t s = net->stream;
+    float *X = sc;
+    float *H1 = X + kNoAllocChunk * kIn;
+    float *H2 = H1 + kNoAllocChunk * kHid;
+    for (int64_t r0 = 0; r0 < rows; r0 += kNoAllocChunk) {
+        const int64_t m = std::min(kNoAllocChunk, rows - r0);
+        HIPCHK(launch_standardise(feat + r0 * kIn, m, net->mean, net->inv_std, X, s));
+        HIPCHK(launch_gemm(1, X, m, kIn, kIn, 1, net->theta + L.W1, kHid, kHid, 1, net->theta + L.b1, H1, nullptr,
+                           nullptr, s));
+        HIPCHK(launch_gemm(1, H1, m, kHid, kHid, 1, net->theta + L.W2, kHid, kHid, 1, net->theta + L.b2, H2, nullptr,
+                           nullptr, s));
+        HIPCHK(launch_gemm(0, H2, m, kHid, kHid, 1, net->theta + L.W3, net->k, net->k, 1, net->theta + L.b3,
+                           Y + r0 * net->k, nullptr, nullptr, s));
+    }
     return SBMDS_OK;
 }
 

@@ -5,6 +5,9 @@ own certified bound, so each must agree with the float64 oracle exactly as a
 single-problem solve does, and the trajectory of a problem must not depend on
 the other problems it shares launches with.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -121,37 +124,39 @@ def test_mesh_batch_matches_oracle(gpu, prec):
     print(f"{prec}: 16 meshes, worst rel eig err {worst:.2e}", flush=True)
 
 
+GOLDEN_256 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "grid_torus_batch256.npz")
+
+
 def test_batch_256_meshes_full_scale(gpu):
     # the batched workload's full shape: 256 grid-torus meshes with n from
-    # 2,048 to ~200,000 (24.9M vertices, 499k landmarks, 245M stored entries,
-    # 5.2 GB of W) in one context.  The smallest meshes are checked against
-    # the oracle's eigenpairs; a sample of the others by B applied in float64
-    # on the host (Rayleigh quotients and residuals against the reported ones)
+    # about 2,000 to 200,000 (24.9M vertices, 499k landmarks, 245M stored
+    # entries, 5.2 GB of W, so W is packed) in one context; every mesh
+    # against the float64 oracle's eigenpairs (reduction route, stored with
+    # each input's sha1 by tests/golden/make_grid_torus_batch256.py):
+    # eigenvalues within 1e-6, eigenvector clusters within the angle that
+    # accuracy implies
     from oracle import eig as oeig
     from synth import configs, large
     sb = gpu
+    g = np.load(GOLDEN_256, allow_pickle=False)
+    meta = json.loads(str(g["meta"]))
     probs = large.grid_torus_batch()
+    assert len(probs) == meta["count"]
+    for i, p in enumerate(probs):
+        assert meta["input_sha1"][i] == configs.input_digest(p), f"mesh {i} differs from its stored values"
     Z, eig, reps, rc, _ = solve(sb, probs, sb.FP32)
     assert rc == 0
     assert all(r["status"] == 0 and r["certified"] for r in reps)
     Zs = split_rows(Z, probs)
-    order = np.argsort([p["n"] for p in probs])
-    for i in order[:3]:
-        p = probs[i]
-        lam, V, _ = H.oracle_for(p, 3)
+    offs = g["offsets"]
+    worst_err = worst_ang = 0.0
+    for i, p in enumerate(probs):
+        lam = g["lam"][i]
+        coef = g["coef"][offs[i]:offs[i + 1]].astype(np.float64)
+        V = oeig.vectors_from_coefficients(configs.operator_rounded(p), coef)
         err = H.rel_eig_err(eig[i], lam[:3])
         ang = H.subspace_angle(Zs[i], V, lam, 3, tol=1e-6)
-        print(f"mesh {i} n={p['n']} l={p['l']} err={err:.2e} angle={ang:.2e}", flush=True)
-        assert err <= 1e-6 and ang <= 3.0
-    for i in order[len(order) // 2::len(order) // 8]:
-        p = probs[i]
-        V = np.asarray(Zs[i], dtype=np.float64) / np.sqrt(np.asarray(eig[i][:3], dtype=np.float64))
-        BV = oeig.apply_b(configs.operator_rounded(p), p["W"], V)
-        for j in range(3):
-            v = V[:, j]
-            rho = v @ BV[:, j] / (v @ v)
-            res = np.linalg.norm(BV[:, j] - eig[i][j] * v) / np.linalg.norm(v) / abs(eig[i][j])
-            print(f"mesh {i} n={p['n']} l={p['l']} pair {j}: rayleigh err {abs(rho - eig[i][j]) / abs(eig[i][j]):.2e} "
-                  f"residual host {res:.3e} reported {reps[i]['resid'][j]:.3e}", flush=True)
-            assert abs(rho - eig[i][j]) <= 1e-6 * abs(eig[i][j])
-            assert res <= 1.2 * reps[i]["resid"][j] + 1e-5
+        worst_err, worst_ang = max(worst_err, err), max(worst_ang, ang)
+        assert err <= 1e-6, (i, p["n"], eig[i], lam[:3])
+        assert ang <= 3.0, (i, p["n"], ang)
+    print(f"256 meshes: worst rel eig err {worst_err:.2e}, worst relative subspace angle {worst_ang:.2e}", flush=True)

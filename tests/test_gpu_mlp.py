@@ -186,7 +186,7 @@ def test_training_and_gain_over_random_start(gpu, tmp_path):
     assert H.subspace_angle(Zl, V, lam, k, tol=1e-6) <= 3.0
     it = lambda r: r["iters_fp32"] + r["iters_fp64"]
     print(f"iterations: learned {it(rl)} random {it(rr)}", flush=True)
-    assert it(rl) <= it(rr)
+    assert it(rl) < it(rr)  # measured: learned 4, random 5
 
 
 def test_learned_start_sphere7_block8(gpu, tmp_path):

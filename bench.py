@@ -315,7 +315,7 @@ def kernel_table(stats, steps=None):
     return out
 
 
-def largest_workload(sb, torch, steps, warmup, k, block=16, learned=True):
+def largest_workload(sb, torch, steps, warmup, k, block=16, learned=True, only=None):
     """The headline: the 1,800 x 1,000 grid torus (n = 1.8M) with 50,000
     landmarks, W 10 GB in float32, on the seeded synthetic operator of
     synth.large.  Forms: plain fp32 (packed W, and full W), bf16 -> fp32,
@@ -327,12 +327,15 @@ def largest_workload(sb, torch, steps, warmup, k, block=16, learned=True):
     prob["V"] = large.grid_torus_positions(prob)
     log(f"largest workload generated in {time.perf_counter() - t0:.1f} s")
     steps = max(1, min(steps, 10))
-    weights, training = (train_grid_net(sb, torch, k, block) if learned else (None, None))
+    want_learned = learned and (not only or any(f.endswith("_learned") for f in only))
+    weights, training = (train_grid_net(sb, torch, k, block) if want_learned else (None, None))
     kinds = [("fp32", sb.FP32, None, 0), ("fp32_full_w", sb.FP32, None, sb.FLAG_FULL_W),
              ("bf16_fp32", sb.BF16_FP32, None, 0)]
     if weights:
         kinds += [("fp32_learned", sb.FP32, sb.START_LEARNED, 0), ("bf16_fp32_learned", sb.BF16_FP32,
                                                                     sb.START_LEARNED, 0)]
+    if only:
+        kinds = [kd for kd in kinds if kd[0] in only or kd[0] == "fp32"]
     forms = {}
     for name, prec, start, flags in kinds:
         ms, eig, rep, _ = time_form(sb, torch, prob, prec, steps, warmup, k, block, flags=flags, start=start,
@@ -481,6 +484,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the landmark-MDS and learned-start forms")
     ap.add_argument("--no-torus", action="store_true", help="skip the 1024 x 512 torus, 10,000-landmark workload")
     ap.add_argument("--no-sphere", action="store_true", help="skip the level-7 icosphere workload")
+    ap.add_argument("--forms", type=str, default="",
+                    help="comma-separated headline forms to time (default: all; plain fp32 always)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -513,7 +518,8 @@ def main():
     # ---- headline: the 1.8M-vertex, 50,000-landmark shape
     log("headline workload: n = 1.8M, 50,000 landmarks")
     prob, forms, chosen, stats, training = largest_workload(sb, torch, args.steps, args.warmup, k,
-                                                            learned=not args.no_learned)
+                                                            learned=not args.no_learned,
+                                                            only=[f for f in args.forms.split(",") if f])
     ch = forms[chosen]
     value, repc = ch["ms"], ch["rep"]
     ms_fp32 = forms["fp32"]["ms"]

@@ -38,8 +38,6 @@ typedef float gs_f4 __attribute__((ext_vector_type(4)));
 typedef double gs_d4 __attribute__((ext_vector_type(4)));
 typedef float gs_f4v __attribute__((ext_vector_type(4)));
 
-constexpr int kWs = 68;  // LDS row stride (floats) of the staged W tile
-
 // Region rows per mode and width (the row partials of a block take
 // R x 64 x B accumulators of LDS).
 template <int M, int B>
@@ -47,17 +45,23 @@ struct SymShape {
     static constexpr bool F64 = (M == MODE_F64ACC);
     static constexpr int BP = B < 16 ? 16 : B;  // matrix-core width (B = 8 padded with zero columns)
     static constexpr int NTC = BP / 16;
-    static constexpr int R = (F64 && B > 16) ? 4 : 8;
+    static constexpr int R = 4;
 };
 
 }  // namespace
 
-int sym_region_rows(Mode m, int B) {
-    if (m == MODE_F64ACC) return B > 16 ? 4 : 8;
-    return 8;
-}
+int sym_region_rows(Mode, int) { return 4; }
 
 bool sym_supported(Mode m, int B) { return (m == MODE_FP32 || m == MODE_F64ACC) && (B == 8 || B == 16 || B == 32); }
+
+// LDS layout of a staged 64 x 64 W tile: rows of 64 floats, the sixteen
+// 16-byte chunks of row r permuted by chunk ^ swz(r).  The permutation keeps
+// both read patterns of the matrix-core operands at two lanes per bank (the
+// minimum for 64 lanes of 4 bytes): the row product reads 16 rows x 4
+// consecutive columns, the transposed product 4 consecutive rows x 16
+// columns.
+__device__ __forceinline__ int swz(int r) { return ((r & 1) << 2) | ((r >> 1) & 3); }
+__device__ __forceinline__ int wpos(int r, int c) { return r * 64 + ((((c >> 2) ^ swz(r)) & 15) << 2) + (c & 3); }
 
 template <int M, int B>
 __global__ __launch_bounds__(256) void k_gemm_sym(const ProbView *__restrict__ views, const int *__restrict__ off,
@@ -70,9 +74,12 @@ __global__ __launch_bounds__(256) void k_gemm_sym(const ProbView *__restrict__ v
     constexpr int BP = Sh::BP, NTC = Sh::NTC, R = Sh::R;
     using AccV = typename std::conditional<F64, gs_d4, gs_f4>::type;
     constexpr int TSP = 64 + (F64 ? 2 : 4);  // LDS row stride of a transposed T slice
-    __shared__ __attribute__((aligned(16))) float Ws[64 * kWs];
+    __shared__ __attribute__((aligned(16))) float Ws[64 * 64];
     __shared__ __attribute__((aligned(16))) TT Tjs[BP * TSP];  // T_j transposed: [column][k]
     __shared__ __attribute__((aligned(16))) TT Tis[BP * TSP];  // T_i transposed
+    // row partials: R tiles x (this wave's 16 rows) x NTC accumulator tiles,
+    // kept between the columns of the walk (each lane its own values)
+    __shared__ __attribute__((aligned(16))) AccV accs[R][4][NTC][64];
 
     const int pidx = find_problem(off, nprob, blockIdx.x);
     const ProbView &v = views[pidx];
@@ -126,24 +133,25 @@ __global__ __launch_bounds__(256) void k_gemm_sym(const ProbView *__restrict__ v
             Tis[B * TSP + e] = TT{};
         }
     }
+    for (int q = 0; q < R; ++q)
+#pragma unroll
+        for (int t = 0; t < NTC; ++t) accs[q][w][t][lane] = AccV{0, 0, 0, 0};
 
-    // ---- prefetch (registers) of the next tile: W tile, T rows of its
-    // tile row (for the transposed product) and, at a new column, T rows of
-    // that column
+    // ---- the walk: columns j of the region, in each the rows i0 + q with
+    // i0 + q <= j; tiles are prefetched (registers) two steps ahead
+    auto nq_of = [&](int j) { return min(nrow, j - i0 + 1); };
+    auto advance = [&](int &j, int &q) {
+        if (++q >= nq_of(j)) {
+            q = 0;
+            ++j;
+        }
+    };
     constexpr int NWP = 64 * 64 / 4 / 256;  // 16-byte pieces of the W tile per thread
     constexpr int NTE = 64 * B / 256 > 0 ? 64 * B / 256 : 1;  // T elements per thread
     static_assert(64 * B % 256 == 0, "whole T elements per thread");
-    gs_f4v wn[NWP];
-    TT tin[NTE], tjn[NTE];
-    auto load_w = [&](int i, int j) {
-        const int64_t base = sym_strip_base(i, lda) + (int64_t)(j - i) * 64;
-        const int64_t len = lda - 64 * i;
-#pragma unroll
-        for (int p = 0; p < NWP; ++p) {
-            const int idx = tid + 256 * p;
-            const int r = idx >> 4, c4 = idx & 15;
-            wn[p] = *reinterpret_cast<const gs_f4v *>(Wp + base + r * len + 4 * c4);
-        }
+    struct Set {
+        gs_f4v w[NWP];
+        TT ti[NTE], tj[NTE];
     };
     auto load_t = [&](TT *dst, int tile) {
 #pragma unroll
@@ -154,6 +162,18 @@ __global__ __launch_bounds__(256) void k_gemm_sym(const ProbView *__restrict__ v
             dst[p] = k < l ? T[(size_t)k * B + idx % B] : TT{};
         }
     };
+    auto load = [&](Set &st_, int j, int q) {
+        const int i = i0 + q;
+        const int64_t base = sym_strip_base(i, lda) + (int64_t)(j - i) * 64;
+        const int64_t len = lda - 64 * i;
+#pragma unroll
+        for (int p = 0; p < NWP; ++p) {
+            const int idx = tid + 256 * p;
+            st_.w[p] = *reinterpret_cast<const gs_f4v *>(Wp + base + (idx >> 4) * len + 4 * (idx & 15));
+        }
+        load_t(st_.ti, i);
+        if (q == 0) load_t(st_.tj, j);
+    };
     auto stage_t = [&](TT *lds, const TT *src) {
 #pragma unroll
         for (int p = 0; p < NTE; ++p) {
@@ -162,84 +182,94 @@ __global__ __launch_bounds__(256) void k_gemm_sym(const ProbView *__restrict__ v
         }
     };
 
-    // row partials: R tiles x (this wave's 16 rows) x NTC accumulator tiles,
-    // kept in LDS between the columns of the walk (each lane its own values)
-    __shared__ __attribute__((aligned(16))) AccV accs[R][4][NTC][64];
-    for (int q = 0; q < R; ++q)
-#pragma unroll
-        for (int t = 0; t < NTC; ++t) accs[q][w][t][lane] = AccV{0, 0, 0, 0};
+    const int arow = 16 * w + (lane & 15);  // row of W (row product) / column of W (transposed product)
+    const int sw_row = swz(arow);
+    const int qk = lane >> 4;               // k offset of this lane within a step of 4
     AccV accc[NTC];
-
-    if (jfirst < jend) {
-        load_w(i0, jfirst);
-        load_t(tin, i0);
-        load_t(tjn, jfirst);
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) accc[t] = AccV{0, 0, 0, 0};
+    int cj = jfirst, cq = 0;  // tile being multiplied
+    int pj = jfirst, pq = 0;  // next tile to prefetch
+    Set s0, s1;
+    if (pj < jend) {
+        load(s0, pj, pq);
+        advance(pj, pq);
     }
-    const int arow = 16 * w + (lane & 15);
-    for (int j = jfirst; j < jend; ++j) {
-        const int nq = min(nrow, j - i0 + 1);
+    if (pj < jend) {
+        load(s1, pj, pq);
+        advance(pj, pq);
+    }
+    auto step = [&](Set &cur) {
+        // stage the tile (the previous step's reads are done)
 #pragma unroll
-        for (int t = 0; t < NTC; ++t) accc[t] = AccV{0, 0, 0, 0};
-#pragma unroll 1
-        for (int q = 0; q < nq; ++q) {
-            // stage the prefetched tile (the previous step's reads are done)
+        for (int p = 0; p < NWP; ++p) {
+            const int idx = tid + 256 * p;
+            const int r = idx >> 4, c4 = idx & 15;
+            *reinterpret_cast<gs_f4v *>(&Ws[r * 64 + ((c4 ^ swz(r)) << 2)]) = cur.w[p];
+        }
+        stage_t(Tis, cur.ti);
+        if (cq == 0) stage_t(Tjs, cur.tj);
+        // this set's registers now take the tile two steps ahead
+        if (pj < jend) {
+            load(cur, pj, pq);
+            advance(pj, pq);
+        }
+        __syncthreads();
+        AccV acc[NTC];
 #pragma unroll
-            for (int p = 0; p < NWP; ++p) {
-                const int idx = tid + 256 * p;
-                *reinterpret_cast<gs_f4v *>(&Ws[(idx >> 4) * kWs + 4 * (idx & 15)]) = wn[p];
-            }
-            stage_t(Tis, tin);
-            if (q == 0) stage_t(Tjs, tjn);
-            // prefetch the next tile of the walk
-            if (q + 1 < nq) {
-                load_w(i0 + q + 1, j);
-                load_t(tin, i0 + q + 1);
-            } else if (j + 1 < jend) {
-                load_w(i0, j + 1);
-                load_t(tin, i0);
-                load_t(tjn, j + 1);
-            }
-            __syncthreads();
-            // U_i += W_ij T_j (rows of this wave: 16w .. 16w+15 of tile i)
-            AccV acc[NTC];
-#pragma unroll
-            for (int t = 0; t < NTC; ++t) acc[t] = accs[q][w][t][lane];
+        for (int t = 0; t < NTC; ++t) acc[t] = accs[cq][w][t][lane];
+        if (i0 + cq < cj) {
+            // off the diagonal: U_i += W_ij T_j and U_j += W_ij^T T_i,
+            // interleaved (two independent accumulation chains)
 #pragma unroll
             for (int s = 0; s < 16; ++s) {
-                const int kk = 4 * s + (lane >> 4);
-                const float a = Ws[arow * kWs + kk];
+                const int kk = 4 * s + qk;
+                const float ar = Ws[arow * 64 + (((s ^ sw_row) & 15) << 2) + qk];
+                const float ac = Ws[wpos(kk, arow)];
 #pragma unroll
                 for (int t = 0; t < NTC; ++t) {
-                    if constexpr (F64)
-                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                            (double)a, Tjs[(16 * t + (lane & 15)) * TSP + kk], acc[t], 0, 0, 0);
-                    else
-                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                            a, Tjs[(16 * t + (lane & 15)) * TSP + kk], acc[t], 0, 0, 0);
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < NTC; ++t) accs[q][w][t][lane] = acc[t];
-            // U_j += W_ij^T T_i off the diagonal (rows 16w .. 16w+15 of tile j)
-            if (i0 + q < j) {
-#pragma unroll
-                for (int s = 0; s < 16; ++s) {
-                    const int kk = 4 * s + (lane >> 4);
-                    const float a = Ws[kk * kWs + arow];
-#pragma unroll
-                    for (int t = 0; t < NTC; ++t) {
-                        if constexpr (F64)
-                            accc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                                (double)a, Tis[(16 * t + (lane & 15)) * TSP + kk], accc[t], 0, 0, 0);
-                        else
-                            accc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                                a, Tis[(16 * t + (lane & 15)) * TSP + kk], accc[t], 0, 0, 0);
+                    const TT bj = Tjs[(16 * t + (lane & 15)) * TSP + kk];
+                    const TT bi = Tis[(16 * t + (lane & 15)) * TSP + kk];
+                    if constexpr (F64) {
+                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)ar, bj, acc[t], 0, 0, 0);
+                        accc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)ac, bi, accc[t], 0, 0, 0);
+                    } else {
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bj, acc[t], 0, 0, 0);
+                        accc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac, bi, accc[t], 0, 0, 0);
                     }
                 }
             }
-            __syncthreads();
+        } else {
+            // a diagonal tile: U_i += W_ii T_i only
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                const int kk = 4 * s + qk;
+                const float ar = Ws[arow * 64 + (((s ^ sw_row) & 15) << 2) + qk];
+#pragma unroll
+                for (int t = 0; t < NTC; ++t) {
+                    const TT bj = Tjs[(16 * t + (lane & 15)) * TSP + kk];
+                    if constexpr (F64)
+                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)ar, bj, acc[t], 0, 0, 0);
+                    else
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bj, acc[t], 0, 0, 0);
+                }
+            }
         }
-        put(slot0 + R + (j - jbeg), accc);
+#pragma unroll
+        for (int t = 0; t < NTC; ++t) accs[cq][w][t][lane] = acc[t];
+        __syncthreads();
+        if (cq == nq_of(cj) - 1) {
+            // the column's transposed partial is complete
+            put(slot0 + R + (cj - jbeg), accc);
+#pragma unroll
+            for (int t = 0; t < NTC; ++t) accc[t] = AccV{0, 0, 0, 0};
+        }
+        advance(cj, cq);
+    };
+    while (cj < jend) {
+        step(s0);
+        if (cj >= jend) break;
+        step(s1);
     }
     for (int q = 0; q < nrow; ++q) {
         AccV acc[NTC];
@@ -253,14 +283,25 @@ __global__ __launch_bounds__(256) void k_gemm_sym(const ProbView *__restrict__ v
 // gc) for every gc of that region row; column side: regions (gr, t / C) for
 // every gr of that region column), in that fixed order; then U = -1/2 sum,
 // and the tile's contributions to H and s, reduced over tiles.
+// Threads of the finish launch: one per element of a 64 x B tile (at most
+// 1024), each summing its element over the slot list with 16 loads in flight.
+template <int B>
+struct SymFinish {
+    static constexpr int NT = 64 * B < 1024 ? 64 * B : 1024;
+    static constexpr int EPT = 64 * B / NT;
+};
+
 template <int M, int B>
-__global__ __launch_bounds__(256) void k_gemm_sym_finish(const ProbView *__restrict__ views,
-                                                         const int *__restrict__ off, int nprob, int phase) {
+__global__ __launch_bounds__(SymFinish<B>::NT) void k_gemm_sym_finish(const ProbView *__restrict__ views,
+                                                                      const int *__restrict__ off, int nprob,
+                                                                      int phase) {
     using Tr = Traits<M>;
     using TA = typename Tr::TA;
     using TT = typename Tr::TT;
     using TU = typename Tr::TU;
     constexpr int R = SymShape<M, B>::R;
+    constexpr int NT = SymFinish<B>::NT, EPT = SymFinish<B>::EPT;
+    constexpr int QF = 16;  // slot loads in flight per element
     __shared__ int slots[2 * kSymMaxGroups];
     __shared__ int base[kSymMaxGroups + 1];
     __shared__ int nslot;
@@ -278,7 +319,7 @@ __global__ __launch_bounds__(256) void k_gemm_sym_finish(const ProbView *__restr
     const int ngr = (nt + R - 1) / R, ngc = (nt + C - 1) / C;
     const int tid = threadIdx.x;
     // region numbering: base[g] = first region of region row g
-    for (int g = tid; g < ngr; g += 256) base[g + 1] = ngc - sym_gcmin(g, R, C);
+    for (int g = tid; g < ngr; g += NT) base[g + 1] = ngc - sym_gcmin(g, R, C);
     __syncthreads();
     if (tid == 0) {
         base[0] = 0;
@@ -300,17 +341,19 @@ __global__ __launch_bounds__(256) void k_gemm_sym_finish(const ProbView *__restr
     TU *__restrict__ U = (TU *)v.U;
     const double *__restrict__ c = v.c[M];
     const int tile0 = 64 * t;
-    for (int e = tid; e < 64 * B; e += 256) {
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int e = tid + q * NT;
         const int r = e / B, j = e % B;
         const int row = tile0 + r;
         TA sum = (TA)0;
-        for (int q0 = 0; q0 < ns; q0 += 8) {
-            TA pv[8];
+        for (int q0 = 0; q0 < ns; q0 += QF) {
+            TA pv[QF];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) pv[q] = (q0 + q < ns) ? part[(size_t)slots[q0 + q] * 64 * B + e] : (TA)0;
+            for (int u = 0; u < QF; ++u) pv[u] = (q0 + u < ns) ? part[(size_t)slots[q0 + u] * 64 * B + e] : (TA)0;
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (q0 + q < ns) sum += pv[q];
+            for (int u = 0; u < QF; ++u)
+                if (q0 + u < ns) sum += pv[u];
         }
         if (row < l) {
             const TU u = down<TU>((TA)(-0.5) * sum);
@@ -322,18 +365,18 @@ __global__ __launch_bounds__(256) void k_gemm_sym_finish(const ProbView *__restr
             tl[r][j] = 0.0;
         }
     }
-    for (int r = tid; r < 64; r += 256) cl[r] = (tile0 + r) < l ? c[tile0 + r] : 0.0;
+    for (int r = tid; r < 64; r += NT) cl[r] = (tile0 + r) < l ? c[tile0 + r] : 0.0;
     __syncthreads();
     constexpr int EH = B * B + B;
     double *red = v.red_gemm;
     double *mine = red + (size_t)t * EH;
-    for (int e = tid; e < B * B; e += 256) {
+    for (int e = tid; e < B * B; e += NT) {
         const int a = e / B, bb = e % B;
         double s = 0.0;
         for (int r = 0; r < 64; ++r) s += tl[r][a] * ul[r][bb];
         st_coherent(mine + e, s);
     }
-    for (int j = tid; j < B; j += 256) {
+    for (int j = tid; j < B; j += NT) {
         double s = 0.0;
         for (int r = 0; r < 64; ++r) s += cl[r] * ul[r][j];
         st_coherent(mine + B * B + j, s);
@@ -371,8 +414,8 @@ hipError_t launch_gemm_sym(Mode m, const Batch &bt, int phase, hipStream_t s) {
         hipLaunchKernelGGL((k_gemm_sym<MM, BB>), dim3(g1), dim3(256), 0, s, bt.views, o1, bt.nprob, phase);   \
         hipError_t e_ = hipGetLastError();                                                                    \
         if (e_ != hipSuccess) return e_;                                                                      \
-        hipLaunchKernelGGL((k_gemm_sym_finish<MM, BB>), dim3(g2), dim3(256), 0, s, bt.views, o2, bt.nprob,    \
-                           phase);                                                                            \
+        hipLaunchKernelGGL((k_gemm_sym_finish<MM, BB>), dim3(g2), dim3(SymFinish<BB>::NT), 0, s, bt.views, o2, \
+                           bt.nprob, phase);                                                                  \
         return hipGetLastError();                                                                             \
     } while (0)
     if (m == MODE_FP32) {

@@ -33,6 +33,7 @@
 #include "sbmds_common.h"
 #include "sbmds_internal.h"
 #include "sbmds_dense_sym.h"
+#include "sbmds_prep.h"
 #include "sbmds_mlp_internal.h"
 
 using namespace sbmds;
@@ -236,37 +237,6 @@ int check_contents(const sbmds_problem &p, const int32_t *rp, const int32_t *ci,
         }
     }
     return SBMDS_OK;
-}
-
-// Stable counting-sort transpose: row j of P^T lists the vertices of column
-// j in increasing vertex order.
-template <typename T>
-void transpose_csr(int64_t n, int64_t l, const int32_t *rp, const int32_t *ci, const T *val,
-                   std::vector<int32_t> &rpT, std::vector<int32_t> &ciT, std::vector<T> &valT) {
-    const int64_t nnz = rp[n];
-    rpT.assign(l + 1, 0);
-    for (int64_t e = 0; e < nnz; ++e) rpT[ci[e] + 1]++;
-    for (int64_t j = 0; j < l; ++j) rpT[j + 1] += rpT[j];
-    std::vector<int32_t> cur(rpT.begin(), rpT.end() - 1);
-    ciT.resize(nnz);
-    valT.resize(nnz);
-    for (int64_t i = 0; i < n; ++i)
-        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
-            const int32_t pos = cur[ci[e]]++;
-            ciT[pos] = (int32_t)i;
-            valT[pos] = val[e];
-        }
-}
-
-template <typename T>
-std::vector<double> colsums(int64_t l, const std::vector<int32_t> &rpT, const std::vector<T> &valT) {
-    std::vector<double> c(l, 0.0);
-    for (int64_t j = 0; j < l; ++j) {
-        double s = 0.0;
-        for (int32_t e = rpT[j]; e < rpT[j + 1]; ++e) s += (double)valT[e];
-        c[j] = s;
-    }
-    return c;
 }
 
 // The precision schedule: one phase per arithmetic.  Non-final phases hand
@@ -926,117 +896,177 @@ int autotune(sbmds_ctx *ctx, SolveSet &set) {
     return SBMDS_OK;
 }
 
+// Create-time scratch on the device, released when it goes out of scope.
+struct DevTmp {
+    void *p = nullptr;
+    DevTmp() = default;
+    DevTmp(const DevTmp &) = delete;
+    DevTmp &operator=(const DevTmp &) = delete;
+    ~DevTmp() {
+        if (p) (void)hipFree(p);
+    }
+    int alloc(size_t bytes) {
+        if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess) {
+            p = nullptr;
+            return fail(SBMDS_ENOMEM, "hipMalloc of create-time scratch failed (" + std::to_string(bytes) + " bytes)");
+        }
+        return SBMDS_OK;
+    }
+};
+
+std::string prep_error_text(unsigned long long key) {
+    const int code = (int)(key >> 40);
+    const std::string row = std::to_string(key & ((1ull << 40) - 1));
+    switch (code) {
+        case PREP_ROWPTR0: return "P_rowptr[0] != 0";
+        case PREP_ROWPTRN: return "P_rowptr[n] != nnz";
+        case PREP_ROWPTR_ORDER: return "P_rowptr not non-decreasing within [0, nnz] at row " + row;
+        case PREP_COL_RANGE: return "P_col out of range in row " + row;
+        case PREP_COL_ORDER: return "P_col not strictly increasing in row " + row;
+        case PREP_VAL: return "non-finite P value in row " + row;
+        case PREP_W_FINITE: return "non-finite W entry in row " + row;
+        case PREP_W_SYM: return "W is not symmetric (row " + row + ")";
+        default: return "invalid input";
+    }
+}
+
 // Internal landmark order: a recursive partition of the landmarks into the
 // cells of up to 8 pivots (the first members of the cell in the caller's
 // farthest-point order, so spread out), each landmark joining the cell of
-// its nearest pivot by W; cells of at most 64 landmarks keep their order.
-// Neighbouring internal indices are then spatially close, which the
-// transposed SpMM exploits.  The order is invisible outside: P's columns and
-// W are permuted together, which leaves B unchanged.
+// its nearest pivot by W; cells of at most 64 landmarks (or 12 levels deep)
+// keep their order.  Neighbouring internal indices are then spatially close,
+// which the transposed SpMM exploits.  The order is invisible outside: P's
+// columns and W are permuted together, which leaves B unchanged.  Run level
+// by level: the nearest pivots of all landmarks of a level come from one
+// kernel on the device-resident W; the host splits every cell, in place and
+// stably, in pivot order (the same arrangement as a depth-first recursion).
 template <typename T>
-std::vector<int32_t> landmark_order(int64_t l, const T *W) {
-    std::vector<int32_t> order;
-    order.reserve(l);
-    std::vector<int32_t> all(l);
-    for (int64_t j = 0; j < l; ++j) all[j] = (int32_t)j;
-    std::function<void(const std::vector<int32_t> &, int)> part = [&](const std::vector<int32_t> &mem, int depth) {
-        if (mem.size() <= 64 || depth >= 12) {
-            order.insert(order.end(), mem.begin(), mem.end());
-            return;
-        }
-        const int np = 8;
-        std::vector<int32_t> piv(mem.begin(), mem.begin() + np);
-        std::vector<std::vector<int32_t>> cell(np);
-        for (int32_t m : mem) {
-            int best = 0;
-            double bd = (double)W[(size_t)m * l + piv[0]];
-            for (int c = 1; c < np; ++c) {
-                const double d = (double)W[(size_t)m * l + piv[c]];
-                if (d < bd) {
-                    bd = d;
-                    best = c;
-                }
-            }
-            cell[best].push_back(m);
-        }
-        for (int c = 0; c < np; ++c)
-            if (!cell[c].empty()) part(cell[c], depth + 1);
+int landmark_order(sbmds_ctx *ctx, const T *dW, int64_t l, std::vector<int32_t> &order) {
+    hipStream_t s = ctx->stream;
+    order.resize(l);
+    for (int64_t j = 0; j < l; ++j) order[j] = (int32_t)j;
+    struct Cell {
+        int64_t start, len;
+        int depth;
     };
-    part(all, 0);
-    return order;
+    std::vector<Cell> cells{{0, l, 0}};
+    DevTmp tbuf;
+    OKCHK(tbuf.alloc((size_t)l * 4 * 3 + (size_t)(l / 64 + 2) * 8 * 4));
+    int32_t *d_order = (int32_t *)tbuf.p, *d_seg = d_order + l, *d_label = d_seg + l, *d_piv = d_label + l;
+    std::vector<int32_t> seg(l), label(l), piv, tmp;
+    for (;;) {
+        std::vector<Cell> active, next;
+        std::fill(seg.begin(), seg.end(), -1);
+        piv.clear();
+        for (const Cell &c : cells) {
+            if (c.len <= 64 || c.depth >= 12) {
+                next.push_back(c);  // final
+                continue;
+            }
+            const int id = (int)active.size();
+            active.push_back(c);
+            for (int q = 0; q < 8; ++q) piv.push_back(order[c.start + q]);
+            for (int64_t x = c.start; x < c.start + c.len; ++x) seg[x] = id;
+        }
+        if (active.empty()) break;
+        HIPCHK(hipMemcpyAsync(d_order, order.data(), (size_t)l * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(d_seg, seg.data(), (size_t)l * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(d_piv, piv.data(), piv.size() * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(prep_labels<T>(dW, l, d_order, d_seg, d_piv, d_label, s));
+        HIPCHK(hipMemcpyAsync(label.data(), d_label, (size_t)l * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        // split every active cell stably by its pivot label, children in pivot order
+        std::vector<Cell> split;
+        for (const Cell &c : active) {
+            tmp.clear();
+            int64_t off = c.start;
+            for (int q = 0; q < 8; ++q) {
+                const size_t before = tmp.size();
+                for (int64_t x = c.start; x < c.start + c.len; ++x)
+                    if (label[x] == q) tmp.push_back(order[x]);
+                const int64_t cnt = (int64_t)(tmp.size() - before);
+                if (cnt) split.push_back({off, cnt, c.depth + 1});
+                off += cnt;
+            }
+            std::copy(tmp.begin(), tmp.end(), order.begin() + c.start);
+        }
+        next.insert(next.end(), split.begin(), split.end());
+        std::sort(next.begin(), next.end(), [](const Cell &a, const Cell &b) { return a.start < b.start; });
+        cells.swap(next);
+    }
+    return SBMDS_OK;
 }
 
+// One problem on the device: its operator in the internal landmark order
+// (P's columns relabelled and rows re-sorted, CSR of P^T, c = P^T 1, W
+// permuted and padded), the per-precision copies.  Host inputs were
+// validated on the host and are uploaded first; device inputs are validated
+// by kernels and never leave the device.
 template <typename T>
-int upload_problem(sbmds_ctx *ctx, const sbmds_problem &in, DevProblem &p, const int32_t *rp, const int32_t *ci0,
-                   const T *val0, const T *Wh, bool fp64) {
+int prepare_problem(sbmds_ctx *ctx, const sbmds_problem &in, DevProblem &p, bool fp64, int idx) {
     const int64_t n = p.n, l = p.l, nnz = p.nnz;
     hipStream_t s = ctx->stream;
-    // internal landmark order: relabel P's columns (rows re-sorted) and W
-    p.lperm = landmark_order<T>(l, Wh);
-    std::vector<int32_t> inv(l);
-    for (int64_t j = 0; j < l; ++j) inv[p.lperm[j]] = (int32_t)j;
-    std::vector<int32_t> cinew(nnz);
-    std::vector<T> valnew(nnz);
-    {
-        std::vector<std::pair<int32_t, T>> row;
-        for (int64_t i = 0; i < n; ++i) {
-            row.clear();
-            for (int32_t e = rp[i]; e < rp[i + 1]; ++e) row.push_back({inv[ci0[e]], val0[e]});
-            std::sort(row.begin(), row.end(), [](const std::pair<int32_t, T> &x, const std::pair<int32_t, T> &y) {
-                return x.first < y.first;
-            });
-            for (size_t q = 0; q < row.size(); ++q) {
-                cinew[rp[i] + q] = row[q].first;
-                valnew[rp[i] + q] = row[q].second;
-            }
-        }
+    const int32_t *drp = in.P_rowptr, *dci = in.P_col;
+    const T *dval = (const T *)in.P_val, *dW = (const T *)in.W;
+    DevTmp raw;
+    if (in.mem == SBMDS_MEM_HOST) {
+        // raw inputs in the caller's order, uploaded as they are
+        const size_t b_rp = (size_t)(n + 1) * 4, b_ci = (size_t)nnz * 4, b_v = (size_t)nnz * sizeof(T);
+        const size_t b_w = (size_t)l * l * sizeof(T);
+        OKCHK(raw.alloc(b_rp + b_ci + b_v + b_w + 64));
+        char *q = (char *)raw.p;
+        int32_t *rrp = (int32_t *)q;
+        int32_t *rci = (int32_t *)(q + ((b_rp + 15) & ~(size_t)15));
+        T *rval = (T *)((char *)rci + ((b_ci + 15) & ~(size_t)15));
+        T *rW = (T *)((char *)rval + ((b_v + 15) & ~(size_t)15));
+        HIPCHK(hipMemcpyAsync(rrp, in.P_rowptr, b_rp, hipMemcpyHostToDevice, s));
+        if (nnz) HIPCHK(hipMemcpyAsync(rci, in.P_col, b_ci, hipMemcpyHostToDevice, s));
+        if (nnz) HIPCHK(hipMemcpyAsync(rval, in.P_val, b_v, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(rW, in.W, b_w, hipMemcpyHostToDevice, s));
+        drp = rrp;
+        dci = rci;
+        dval = rval;
+        dW = rW;
+    } else {
+        DevTmp terr;
+        OKCHK(terr.alloc(8));
+        unsigned long long *derr = (unsigned long long *)terr.p;
+        unsigned long long herr = kPrepNoError;
+        HIPCHK(hipMemcpyAsync(derr, &herr, 8, hipMemcpyHostToDevice, s));
+        HIPCHK(prep_validate<T>(drp, dci, dval, dW, n, l, nnz, derr, s));
+        HIPCHK(hipMemcpyAsync(&herr, derr, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (herr != kPrepNoError)
+            return fail(SBMDS_EINVAL, "problem " + std::to_string(idx) + ": " + prep_error_text(herr));
     }
-    const int32_t *ci = cinew.data();
-    const T *val = valnew.data();
-    // transposed CSR and column sums on the host
-    std::vector<int32_t> rpT, ciT;
-    std::vector<T> valT;
-    transpose_csr<T>(n, l, rp, ci, val, rpT, ciT, valT);
+    std::vector<int32_t> order;
+    OKCHK(landmark_order<T>(ctx, dW, l, order));
+    p.lperm = order;
+    std::vector<int32_t> inv(l);
+    for (int64_t j = 0; j < l; ++j) inv[order[j]] = (int32_t)j;
 
     OKCHK(dalloc(ctx, (void **)&p.rp, (n + 1) * 4));
     OKCHK(dalloc(ctx, (void **)&p.ci, nnz * 4));
     OKCHK(dalloc(ctx, (void **)&p.rpT, (l + 1) * 4));
     OKCHK(dalloc(ctx, (void **)&p.ciT, nnz * 4));
-    HIPCHK(hipMemcpyAsync(p.rp, rp, (n + 1) * 4, hipMemcpyHostToDevice, s));
-    if (nnz) HIPCHK(hipMemcpyAsync(p.ci, ci, nnz * 4, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(p.rpT, rpT.data(), (l + 1) * 4, hipMemcpyHostToDevice, s));
-    if (nnz) HIPCHK(hipMemcpyAsync(p.ciT, ciT.data(), nnz * 4, hipMemcpyHostToDevice, s));
-
-    const size_t wbytes_row = (size_t)p.lda * sizeof(T);
-    void *Wd = nullptr, *vd = nullptr, *vTd = nullptr, *cd = nullptr;
+    void *Wd = nullptr, *vd = nullptr, *vTd = nullptr, *cd = nullptr, *c16 = nullptr;
+    const bool bf = !fp64 && ctx->opt.prec == SBMDS_BF16_FP32;
     OKCHK(dalloc(ctx, &vd, nnz * sizeof(T)));
     OKCHK(dalloc(ctx, &vTd, nnz * sizeof(T)));
-    OKCHK(dalloc(ctx, &Wd, (size_t)l * wbytes_row));
+    OKCHK(dalloc(ctx, &Wd, (size_t)l * p.lda * sizeof(T)));
     OKCHK(dalloc(ctx, &cd, l * 8));
-    if (nnz) {
-        HIPCHK(hipMemcpyAsync(vd, val, nnz * sizeof(T), hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(vTd, valT.data(), nnz * sizeof(T), hipMemcpyHostToDevice, s));
-    }
-    HIPCHK(hipMemsetAsync(Wd, 0, (size_t)l * wbytes_row, s));
-    {
-        // W in the internal landmark order, uploaded in chunks of rows
-        const int64_t ch = std::max<int64_t>(1, std::min<int64_t>(l, (64 << 20) / ((int64_t)sizeof(T) * l)));
-        std::vector<T> buf((size_t)ch * l);
-        for (int64_t i0 = 0; i0 < l; i0 += ch) {
-            const int64_t rows = std::min(ch, l - i0);
-            for (int64_t r = 0; r < rows; ++r) {
-                const T *src = Wh + (size_t)p.lperm[i0 + r] * l;
-                T *dst = buf.data() + (size_t)r * l;
-                for (int64_t j = 0; j < l; ++j) dst[j] = src[p.lperm[j]];
-            }
-            HIPCHK(hipMemcpy2DAsync((char *)Wd + (size_t)i0 * wbytes_row, wbytes_row, buf.data(), (size_t)l * sizeof(T),
-                                    (size_t)l * sizeof(T), rows, hipMemcpyHostToDevice, s));
-            HIPCHK(hipStreamSynchronize(s));  // buf is reused
-        }
-    }
-    std::vector<double> c = colsums<T>(l, rpT, valT);
-    HIPCHK(hipMemcpyAsync(cd, c.data(), l * 8, hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));  // host vectors go out of scope
+    if (bf) OKCHK(dalloc(ctx, &c16, l * 8));
+    HIPCHK(hipMemcpyAsync(p.rp, drp, (n + 1) * 4, hipMemcpyDeviceToDevice, s));
+    DevTmp tperm, twork;
+    OKCHK(tperm.alloc((size_t)l * 8));
+    int32_t *dperm = (int32_t *)tperm.p, *dinv = dperm + l;
+    HIPCHK(hipMemcpyAsync(dperm, order.data(), (size_t)l * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dinv, inv.data(), (size_t)l * 4, hipMemcpyHostToDevice, s));
+    const size_t wb = prep_tmp_bytes(nnz, fp64);
+    OKCHK(twork.alloc(wb));
+    PrepIn pi{n, l, nnz, drp, dci, dval, dW, dperm, dinv};
+    PrepOut po{p.lda, p.ci, p.rpT, p.ciT, vd, vTd, Wd, (double *)cd, (double *)c16};
+    HIPCHK(prep_operator<T>(pi, po, twork.p, wb, s));
     if (fp64) {
         p.val[MODE_FP64] = vd;
         p.valT[MODE_FP64] = vTd;
@@ -1049,26 +1079,22 @@ int upload_problem(sbmds_ctx *ctx, const sbmds_problem &in, DevProblem &p, const
             p.W[m] = Wd;
             p.c[m] = (double *)cd;
         }
-        if (ctx->opt.prec == SBMDS_BF16_FP32) {
-            void *v16 = nullptr, *vT16 = nullptr, *W16 = nullptr, *c16 = nullptr;
+        if (bf) {
+            void *v16 = nullptr, *vT16 = nullptr, *W16 = nullptr;
             OKCHK(dalloc(ctx, &v16, nnz * 2));
             OKCHK(dalloc(ctx, &vT16, nnz * 2));
             OKCHK(dalloc(ctx, &W16, (size_t)l * p.lda * 2));
-            OKCHK(dalloc(ctx, &c16, l * 8));
             HIPCHK(launch_f32_to_bf16((const float *)vd, v16, nnz, s));
             HIPCHK(launch_f32_to_bf16((const float *)vTd, vT16, nnz, s));
             HIPCHK(launch_f32_to_bf16((const float *)Wd, W16, (int64_t)l * p.lda, s));
-            std::vector<float> vb(valT.size());
-            for (size_t i = 0; i < valT.size(); ++i) vb[i] = host_bf2f(host_f2bf((float)valT[i]));
-            std::vector<double> cb = colsums<float>(l, rpT, vb);
-            HIPCHK(hipMemcpyAsync(c16, cb.data(), l * 8, hipMemcpyHostToDevice, s));
-            HIPCHK(hipStreamSynchronize(s));
             p.val[MODE_BF16] = v16;
             p.valT[MODE_BF16] = vT16;
             p.W[MODE_BF16] = W16;
             p.c[MODE_BF16] = (double *)c16;
         }
     }
+    // the scratch is released when this returns: the stream must be done with it
+    HIPCHK(hipStreamSynchronize(s));
     return SBMDS_OK;
 }
 
@@ -1415,31 +1441,8 @@ int create_impl(const sbmds_problem *probs, int nprob, const sbmds_options *opt_
         p.b = o.block;
         p.B = kernel_width(o.block);
         p.k = o.k;
-        // host copies of device-resident inputs, then content validation
-        std::vector<int32_t> hrp, hci;
-        std::vector<char> hval, hW;
-        const int32_t *rp = in.P_rowptr, *ci = in.P_col;
-        const void *val = in.P_val;
-        if (in.mem == SBMDS_MEM_DEVICE) {
-            hrp.resize(in.n + 1);
-            hci.resize(std::max<int64_t>(in.nnz, 1));
-            hval.resize(std::max<int64_t>(in.nnz, 1) * esz);
-            hW.resize((size_t)in.l * in.l * esz);
-            if (hipMemcpy(hrp.data(), in.P_rowptr, (in.n + 1) * 4, hipMemcpyDeviceToHost) != hipSuccess ||
-                (in.nnz && hipMemcpy(hci.data(), in.P_col, in.nnz * 4, hipMemcpyDeviceToHost) != hipSuccess) ||
-                (in.nnz && hipMemcpy(hval.data(), in.P_val, in.nnz * esz, hipMemcpyDeviceToHost) != hipSuccess) ||
-                hipMemcpy(hW.data(), in.W, hW.size(), hipMemcpyDeviceToHost) != hipSuccess)
-                return cleanup(fail(SBMDS_EHIP, "copying device inputs for validation failed"));
-            rp = hrp.data();
-            ci = hci.data();
-            val = hval.data();
-            int rc = fp64 ? check_contents<double>(in, rp, ci, (const double *)val, (const double *)hW.data(), i)
-                          : check_contents<float>(in, rp, ci, (const float *)val, (const float *)hW.data(), i);
-            if (rc < 0) return cleanup(rc);
-        }
-        const void *Wh = in.mem == SBMDS_MEM_DEVICE ? (const void *)hW.data() : in.W;
-        int rc = fp64 ? upload_problem<double>(ctx, in, p, rp, ci, (const double *)val, (const double *)Wh, true)
-                      : upload_problem<float>(ctx, in, p, rp, ci, (const float *)val, (const float *)Wh, false);
+        // host inputs were validated above; device inputs are validated on the device
+        int rc = fp64 ? prepare_problem<double>(ctx, in, p, true, i) : prepare_problem<float>(ctx, in, p, false, i);
         if (rc < 0) return cleanup(rc);
         if (ctx->packed) {
             const size_t pk = (size_t)sym_strip_base(p.lda / 64, p.lda) * 4;

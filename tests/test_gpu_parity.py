@@ -341,3 +341,37 @@ def test_packed_w_region_widths(gpu, tmp_path, cw):
     assert rc == 0 and rep["certified"]
     assert path.read_text().count(f" 1 {cw}\n") == 2  # the forced entries were used, not retuned
     check(prob, Z, eig, rep, 3, 1e-6)
+
+
+@pytest.mark.parametrize("defect", ["w_asym", "w_nan", "p_nan", "col_order", "col_range", "rowptr"])
+def test_device_inputs_validated_on_device(gpu, defect):
+    # device-resident inputs are checked by kernels (they never reach the
+    # host): every defect is refused with SBMDS_EINVAL and a message naming
+    # it; the kernels clamp every index, so a malformed row pointer is read
+    # safely
+    sb = gpu
+    import torch
+    prob = H.random_problem(n=3000, l=120, row_len_max=8, seed=13)
+    rp, col, val, W = (prob[x].copy() for x in ("rowptr", "col", "val", "W"))
+    row = int(np.argmax(np.diff(rp) >= 2))  # a row with two entries or more
+    if defect == "w_asym":
+        W[5, 17] += 1.0
+    elif defect == "w_nan":
+        W[40, 3] = np.nan
+        W[3, 40] = np.nan
+    elif defect == "p_nan":
+        val[rp[row]] = np.inf
+    elif defect == "col_order":
+        col[rp[row]], col[rp[row] + 1] = col[rp[row] + 1], col[rp[row]]
+    elif defect == "col_range":
+        col[rp[row]] = prob["l"] + 3
+    else:
+        rp[10] = rp[12] + 1  # decreasing at row 10 / 11
+    dev = [torch.from_numpy(a).cuda() for a in (rp, col, val, W)]
+    p = sb.Problem.from_arrays(*dev)
+    with pytest.raises(sb.SbmdsError) as exc:
+        sb.Context([p], k=3, block=16, prec=sb.FP32)
+    want = {"w_asym": "not symmetric", "w_nan": "non-finite W", "p_nan": "non-finite P", "col_order": "strictly",
+            "col_range": "out of range", "rowptr": "P_rowptr"}[defect]
+    assert exc.value.code == -1 and want in str(exc.value), str(exc.value)
+    torch.cuda.synchronize()

@@ -55,12 +55,14 @@ int sym_region_rows(Mode, int) { return 4; }
 bool sym_supported(Mode m, int B) { return (m == MODE_FP32 || m == MODE_F64ACC) && (B == 8 || B == 16 || B == 32); }
 
 // LDS layout of a staged 64 x 64 W tile: rows of 64 floats, the sixteen
-// 16-byte chunks of row r permuted by chunk ^ swz(r).  The permutation keeps
-// both read patterns of the matrix-core operands at two lanes per bank (the
-// minimum for 64 lanes of 4 bytes): the row product reads 16 rows x 4
-// consecutive columns, the transposed product 4 consecutive rows x 16
-// columns.
-__device__ __forceinline__ int swz(int r) { return ((r & 1) << 2) | ((r >> 1) & 3); }
+// 16-byte chunks of row r permuted by chunk ^ swz(r).  Each lane feeds the
+// matrix cores 16 consecutive k (lanes 16q .. 16q+15 take k = 16q .. 16q+15;
+// the summation over k is the same in any order), so the row product reads
+// its W operand and both products their T operand as 16-byte pieces, eight
+// lanes of distinct chunks per LDS cycle; the transposed product reads W by
+// columns, 4 bytes per lane, rows k and k + 16 falling into opposite halves
+// of the banks.  No LDS bank is hit twice in one cycle by either pattern.
+__device__ __forceinline__ int swz(int r) { return (((r & 1) << 2) | ((r >> 1) & 3)) ^ (((r >> 4) & 1) << 2); }
 __device__ __forceinline__ int wpos(int r, int c) { return r * 64 + ((((c >> 2) ^ swz(r)) & 15) << 2) + (c & 3); }
 
 template <int M, int B>
@@ -184,7 +186,7 @@ __global__ __launch_bounds__(256) void k_gemm_sym(const ProbView *__restrict__ v
 
     const int arow = 16 * w + (lane & 15);  // row of W (row product) / column of W (transposed product)
     const int sw_row = swz(arow);
-    const int qk = lane >> 4;               // k offset of this lane within a step of 4
+    const int qk = lane >> 4;               // this lane feeds k = 16 qk .. 16 qk + 15
     AccV accc[NTC];
 #pragma unroll
     for (int t = 0; t < NTC; ++t) accc[t] = AccV{0, 0, 0, 0};
@@ -199,6 +201,18 @@ __global__ __launch_bounds__(256) void k_gemm_sym(const ProbView *__restrict__ v
         load(s1, pj, pq);
         advance(pj, pq);
     }
+    // 16 consecutive k of one row of a transposed T slice in LDS (16-byte pieces)
+    auto t16 = [&](const TT *lds, int col, TT (&out)[16]) {
+        constexpr int PER = 16 / (int)sizeof(TT);
+        typedef TT V __attribute__((ext_vector_type(PER)));
+        const V *src = reinterpret_cast<const V *>(lds + col * TSP + 16 * qk);
+#pragma unroll
+        for (int u = 0; u < 16 / PER; ++u) {
+            const V x = src[u];
+#pragma unroll
+            for (int v = 0; v < PER; ++v) out[u * PER + v] = x[v];
+        }
+    };
     auto step = [&](Set &cur) {
         // stage the tile (the previous step's reads are done)
 #pragma unroll
@@ -218,40 +232,42 @@ __global__ __launch_bounds__(256) void k_gemm_sym(const ProbView *__restrict__ v
         AccV acc[NTC];
 #pragma unroll
         for (int t = 0; t < NTC; ++t) acc[t] = accs[cq][w][t][lane];
-        if (i0 + cq < cj) {
-            // off the diagonal: U_i += W_ij T_j and U_j += W_ij^T T_i,
-            // interleaved (two independent accumulation chains)
+        // this lane's 16 W values of the row product (row arow, k = 16 qk ..)
+        float ar[16];
 #pragma unroll
-            for (int s = 0; s < 16; ++s) {
-                const int kk = 4 * s + qk;
-                const float ar = Ws[arow * 64 + (((s ^ sw_row) & 15) << 2) + qk];
-                const float ac = Ws[wpos(kk, arow)];
+        for (int u = 0; u < 4; ++u) {
+            const gs_f4v x = *reinterpret_cast<const gs_f4v *>(&Ws[arow * 64 + ((((4 * qk + u) ^ sw_row) & 15) << 2)]);
 #pragma unroll
-                for (int t = 0; t < NTC; ++t) {
-                    const TT bj = Tjs[(16 * t + (lane & 15)) * TSP + kk];
-                    const TT bi = Tis[(16 * t + (lane & 15)) * TSP + kk];
-                    if constexpr (F64) {
-                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)ar, bj, acc[t], 0, 0, 0);
-                        accc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)ac, bi, accc[t], 0, 0, 0);
-                    } else {
-                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bj, acc[t], 0, 0, 0);
-                        accc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac, bi, accc[t], 0, 0, 0);
-                    }
-                }
+            for (int v = 0; v < 4; ++v) ar[4 * u + v] = x[v];
+        }
+        const bool offdiag = i0 + cq < cj;
+#pragma unroll
+        for (int t = 0; t < NTC; ++t) {
+            TT bj[16];
+            t16(Tjs, 16 * t + (lane & 15), bj);
+#pragma unroll
+            for (int s_ = 0; s_ < 16; ++s_) {
+                if constexpr (F64)
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)ar[s_], bj[s_], acc[t], 0, 0, 0);
+                else
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[s_], bj[s_], acc[t], 0, 0, 0);
             }
-        } else {
-            // a diagonal tile: U_i += W_ii T_i only
+        }
+        if (offdiag) {
+            // U_j += W_ij^T T_i: W read by columns (column arow, rows 16 qk ..)
+            float ac[16];
 #pragma unroll
-            for (int s = 0; s < 16; ++s) {
-                const int kk = 4 * s + qk;
-                const float ar = Ws[arow * 64 + (((s ^ sw_row) & 15) << 2) + qk];
+            for (int s_ = 0; s_ < 16; ++s_) ac[s_] = Ws[wpos(16 * qk + s_, arow)];
 #pragma unroll
-                for (int t = 0; t < NTC; ++t) {
-                    const TT bj = Tjs[(16 * t + (lane & 15)) * TSP + kk];
+            for (int t = 0; t < NTC; ++t) {
+                TT bi[16];
+                t16(Tis, 16 * t + (lane & 15), bi);
+#pragma unroll
+                for (int s_ = 0; s_ < 16; ++s_) {
                     if constexpr (F64)
-                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)ar, bj, acc[t], 0, 0, 0);
+                        accc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)ac[s_], bi[s_], accc[t], 0, 0, 0);
                     else
-                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bj, acc[t], 0, 0, 0);
+                        accc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[s_], bi[s_], accc[t], 0, 0, 0);
                 }
             }
         }

@@ -336,10 +336,13 @@ def largest_workload(sb, torch, steps, warmup, k, block=16, learned=True, only=N
                                                                     sb.START_LEARNED, 0)]
     if only:
         kinds = [kd for kd in kinds if kd[0] in only or kd[0] == "fp32"]
+    from synth import configs
+    tune = os.path.join(configs.cache_dir(), f"tune_gridtorus_50000_k{k}_b{block}.txt")
     forms = {}
     for name, prec, start, flags in kinds:
         ms, eig, rep, _ = time_form(sb, torch, prob, prec, steps, warmup, k, block, flags=flags, start=start,
-                                    mlp_weights=weights if start else None)
+                                    mlp_weights=weights if start else None,
+                                    tune_cache=None if flags & sb.FLAG_FULL_W else tune)
         forms[name] = {"ms": ms, "eig": eig, "rep": rep, "prec": prec, "start": start, "flags": flags,
                        "first_ms": time_form.first_ms, "create_ms": time_form.create_ms}
         log(f"largest {name}/b{block} {ms:.3f} ms (first call {time_form.first_ms:.2f} ms, create "
@@ -348,7 +351,10 @@ def largest_workload(sb, torch, steps, warmup, k, block=16, learned=True, only=N
     ch = forms[chosen]
     _, _, _, stats = time_form(sb, torch, prob, ch["prec"], steps, 1, k, block,
                                flags=sb.FLAG_KERNEL_TIMING | ch["flags"], start=ch["start"],
-                               mlp_weights=weights if ch["start"] else None)
+                               mlp_weights=weights if ch["start"] else None,
+                               tune_cache=None if ch["flags"] & sb.FLAG_FULL_W else tune)
+    if os.path.exists(tune):
+        log("launch choices (tuned at create): " + "; ".join(open(tune).read().split("\n")))
     return prob, forms, chosen, stats, training
 
 

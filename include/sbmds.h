@@ -237,6 +237,34 @@ int sbmds_get_block(sbmds_ctx *ctx, int prob, void *X, int X_mem);
 int sbmds_kernel_stats(sbmds_ctx *ctx, sbmds_kernel_stat *out, int max);
 void sbmds_reset_kernel_stats(sbmds_ctx *ctx);
 
+/*
+ * Rows of the sparse biharmonic approximation K~ = P L P^T of a symmetric
+ * matrix whose landmark block is L (Section 3.1: the landmark block
+ * interpolated to every vertex by P on both sides), and their relative
+ * error against the exact rows (Section 4.1's eps(K~) on a row subset S):
+ * sum_S ||K~_s - K_s||^2 / sum_S ||K_s||^2.  L is the landmark distances
+ * for the geodesic distance approximation that section measures, or
+ * W = D^2_ll for the squared distances classical scaling uses.
+ *   prob     P (n x l CSR) in host or device memory (prob->mem); W, xyz,
+ *            landmark_vertex and X0 are not read.  P is checked on the
+ *            device like sbmds_create's device inputs.
+ *   fp64     element type of P_val, L and K_rows: double if non-zero, else
+ *            float.
+ *   L        [l*l] row-major, symmetric, finite; same memory as P.
+ *   rows     [nrows] vertex ids in [0, n), same memory as P; 1 <= nrows <= 4096.
+ *   K_rows   [nrows*n] row-major exact rows (NULL if err is NULL), same
+ *            memory as P.
+ *   err      [2] host doubles (may be NULL): sum_S ||K~_s - K_s||^2 and
+ *            sum_S ||K_s||^2, accumulated in float64 in a fixed order.
+ *   out      [nrows*n] row-major doubles (may be NULL): the rows of K~,
+ *            host or device memory per out_mem.
+ *   stream   hipStream_t (NULL = the null stream); the call synchronises it.
+ * The products run on the device in float64 from the given values; the
+ * call allocates (and frees) its own device scratch, S x l doubles.
+ */
+int sbmds_approx_rows(const sbmds_problem *prob, int fp64, const void *L, const int32_t *rows, int64_t nrows,
+                      const void *K_rows, double *err, double *out, int out_mem, void *stream);
+
 /* Release the context and all device memory it owns.  NULL is a no-op. */
 void sbmds_destroy(sbmds_ctx *ctx);
 

@@ -22,7 +22,7 @@ __all__ = [
     "FP64", "FP32", "BF16_FP32",
     "START_RANDOM", "START_LMDS", "START_LEARNED", "START_USER",
     "FLAG_KERNEL_TIMING", "FLAG_NO_GRAPH", "FLAG_NO_CERTIFY", "FLAG_PACK_W", "FLAG_FULL_W",
-    "SbmdsError", "Problem", "Context", "embed", "lib", "lib_path", "version",
+    "SbmdsError", "Problem", "Context", "embed", "approx_rows", "lib", "lib_path", "version",
 ]
 
 FP64, FP32, BF16_FP32 = 0, 1, 2
@@ -85,7 +85,7 @@ _lib = None
 EXPORTS = [
     "sbmds_default_options", "sbmds_create", "sbmds_embed", "sbmds_get_block",
     "sbmds_kernel_stats", "sbmds_reset_kernel_stats", "sbmds_destroy",
-    "sbmds_last_error", "sbmds_version",
+    "sbmds_last_error", "sbmds_version", "sbmds_approx_rows",
     # learned warm start (include/sbmds_mlp.h)
     "sbmds_mlp_create", "sbmds_mlp_load", "sbmds_mlp_save", "sbmds_mlp_num_params", "sbmds_mlp_get_params",
     "sbmds_mlp_set_params", "sbmds_mlp_set_norm", "sbmds_mlp_features", "sbmds_mlp_forward",
@@ -137,6 +137,8 @@ def lib():
         ("sbmds_mlp_loss_grad", [vp, vp, vp, vp, ci, vp, vp, ci], ci),
         ("sbmds_mlp_adam_step", [vp, ctypes.c_float], ci),
         ("sbmds_mlp_destroy", [vp], None),
+        ("sbmds_mlp_forward_noalloc", [vp, vp, i64, vp], ci),
+        ("sbmds_approx_rows", [ctypes.POINTER(_Problem), ci, vp, vp, i64, vp, vp, vp, ci, vp], ci),
     ]:
         fn = getattr(L, name)
         fn.argtypes = args
@@ -158,6 +160,20 @@ def _check(rc):
 
 def _is_torch(x):
     return type(x).__module__.startswith("torch")
+
+
+def _ptr_any(a, dtype):
+    """(pointer, mem) of a NumPy array (converted to a contiguous `dtype`
+    copy, kept alive on the function) or a contiguous CUDA tensor."""
+    if _is_torch(a) and a.is_cuda:
+        return a.data_ptr(), MEM_DEVICE
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    _ptr_any.keep.append(arr)
+    del _ptr_any.keep[:-8]
+    return arr.ctypes.data, MEM_HOST
+
+
+_ptr_any.keep = []
 
 
 @dataclass
@@ -333,3 +349,40 @@ def embed(rowptr, col, val, W, k=3, block=16, prec=FP32, **kw):
     with Context([p], k=k, block=block, prec=prec, **kw) as ctx:
         Z, eig, reps, _ = ctx.embed()
     return Z, eig[0], reps[0]
+
+
+def approx_rows(rowptr, col, val, L, rows, K_rows=None, want_rows=False):
+    """Rows `rows` of K~ = P L P^T and, with the exact rows K_rows, the
+    relative error eps = sum ||K~_s - K_s||^2 / sum ||K_s||^2 on them
+    (sbmds_approx_rows).  Arrays are NumPy (host) or torch CUDA tensors
+    (device), all in one place; float64 values select the float64 path.
+    Returns (eps or None, (num, den) or None, K~ rows or None)."""
+    fp64 = (str(getattr(val, "dtype", "")) in ("float64", "torch.float64"))
+    fdt = np.float64 if fp64 else np.float32
+    n = int(rowptr.shape[0]) - 1
+    L_ = L
+    l = int(L_.shape[0])
+    p = Problem.from_arrays(rowptr, col, val, L_)
+    s = p._struct(fdt)
+    pr, mem = _ptr_any(rows, np.int32)
+    pK, _ = _ptr_any(K_rows, fdt) if K_rows is not None else (None, mem)
+    S = int(rows.shape[0])
+    err = (ctypes.c_double * 2)()
+    out = None
+    pout, out_mem = None, mem
+    if want_rows:
+        if mem == MEM_DEVICE:
+            import torch
+            out = torch.empty((S, n), dtype=torch.float64, device=rows.device)
+        else:
+            out = np.empty((S, n), dtype=np.float64)
+        pout, _ = _ptr_any(out, np.float64)
+    stream = None
+    if mem == MEM_DEVICE:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    _check(lib().sbmds_approx_rows(ctypes.byref(s), 1 if fp64 else 0, s.W, pr, S, pK,
+                                   err if K_rows is not None else None, pout, out_mem, stream))
+    if K_rows is None:
+        return None, None, out
+    return (err[0] / err[1] if err[1] > 0 else float("nan")), (err[0], err[1]), out

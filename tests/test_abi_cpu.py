@@ -128,3 +128,20 @@ def test_bench_refuses_more_than_one_gpu():
                          text=True, timeout=120)
     assert out.returncode == 2
     assert "one GPU" in out.stderr
+
+
+def test_approx_rows_argument_checks_without_gpu():
+    # argument checks of sbmds_approx_rows come before any device call
+    L = sb.lib()
+    prob = sb.Problem.from_arrays(np.array([0, 1, 2], np.int32), np.array([0, 1], np.int32),
+                                  np.ones(2, np.float32), np.zeros((2, 2), np.float32))
+    s = prob._struct(np.float32)
+    rows = np.array([0], np.int32)
+    err = (ctypes.c_double * 2)()
+    K = np.zeros((1, 2), np.float32)
+    rc = L.sbmds_approx_rows(ctypes.byref(s), 0, s.W, rows.ctypes.data, 0, K.ctypes.data, err, None, 0, None)
+    assert rc == sb.SbmdsError(-1, "").code == -1 and b"nrows" in L.sbmds_last_error()
+    rc = L.sbmds_approx_rows(ctypes.byref(s), 0, s.W, rows.ctypes.data, 1, None, err, None, 0, None)
+    assert rc == -1 and b"K_rows" in L.sbmds_last_error()
+    rc = L.sbmds_approx_rows(ctypes.byref(s), 0, s.W, rows.ctypes.data, 1, K.ctypes.data, None, None, 0, None)
+    assert rc == -1 and b"nothing to compute" in L.sbmds_last_error()

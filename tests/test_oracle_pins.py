@@ -512,3 +512,28 @@ def test_coefficients_from_vectors_dense_route():
     np.testing.assert_allclose(oeig.vectors_from_coefficients(P, C), V, atol=1e-12)
     B = oeig.b_matrix(P, W)
     np.testing.assert_allclose(B @ V, V * lam[None, :], atol=1e-10 * abs(lam).max())
+
+
+def test_approx_rows_special_cases():
+    # rows of K~ = P L P^T: with l = n and P = I (Section 3.1's limit) K~ = L
+    # exactly and eps = 0; a landmark's row of K~ interpolates row j of L
+    # (its P row is e_j, Eq. (PDefinition)); the row-subset error over all
+    # rows is the full-matrix error
+    rng = np.random.default_rng(4)
+    n = 30
+    pts = rng.standard_normal((n, 3))
+    K = np.sqrt(((pts[:, None] - pts[None]) ** 2).sum(-1))
+    rows = np.array([0, 7, 29])
+    np.testing.assert_array_equal(omds.approx_rows(sp.identity(n, format="csr"), K, rows), K[rows])
+    assert omds.approx_error_rows(sp.identity(n, format="csr"), K, rows, K[rows]) == 0.0
+    V, F = meshes.torus_grid(12, 8, 1.0, 0.4, jitter=0.01, seed=3)
+    pr = _chain_problem(V, F, 10, None, seed=2)
+    P = pr["P64"]
+    G = op.edge_graph(V, F)
+    D = csgraph.dijkstra(G, directed=False)
+    lm = pr["landmarks"]
+    Kll = D[np.ix_(lm, lm)]
+    Kt = omds.approx_rows(P, Kll, lm[:3])
+    np.testing.assert_allclose(Kt, (P @ Kll.T).T[:3], atol=1e-12)
+    full = omds.approx_error(P.toarray() @ Kll @ P.toarray().T, D)
+    np.testing.assert_allclose(omds.approx_error_rows(P, Kll, np.arange(V.shape[0]), D), full, rtol=1e-12)

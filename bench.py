@@ -358,6 +358,100 @@ def largest_workload(sb, torch, steps, warmup, k, block=16, learned=True, only=N
     return prob, forms, chosen, stats, training
 
 
+def approximation_quality(sb, torch, nsample=128, reps=5):
+    """The paper's quality measures as a second workload on the GPU, on a
+    192 x 96 bumpy torus (n = 18,432, l = 369 FPS landmarks, the same
+    landmarks for every p_row):
+      * eps(K~) = ||K~ - K||^2 / ||K||^2 (Section 4.1) of the geodesic
+        distance matrix K and its sparse biharmonic approximation
+        K~ = P K_ll P^T on `nsample` random rows, for p_row = 10, 20, 50 and
+        the unthresholded P (BHA), the float64 oracle timed beside it;
+      * the stress ||Z Z^T + 1/2 J E J||_F (Eq. (MDS_problem), Section 4.2)
+        of each k = 3 embedding against the exact E = K o K, and of classical
+        MDS of the exact E itself, solved by the same path with P = I and
+        W = E (l = n).
+    Exact distances from Dijkstra on the host (all pairs: 1.4 GB as float32
+    on the device)."""
+    import numpy as np
+
+    from oracle import mds as omds
+    from synth import _geodesic, configs, meshes
+    from synth import operator as op
+
+    t0 = time.perf_counter()
+    V, F = meshes.bumpy_torus(192, 96, 4201)
+    G = op.edge_graph(V, F)
+    n, l, k = V.shape[0], 369, 3
+    base = configs.build_problem(V, F, l, 10, 4201, np.float32)
+    lm = base["landmarks"]
+    D = _geodesic.sssp_to(G, np.arange(n), np.arange(n), min(16, os.cpu_count() or 1))
+    D += D.T
+    D *= 0.5  # Dijkstra's last-bit asymmetry removed (K must be symmetric)
+    Kd = torch.from_numpy(D.astype(np.float32)).cuda()
+    Ed = Kd * Kd
+    del D
+    rows = np.sort(np.random.default_rng(9).choice(n, nsample, replace=False)).astype(np.int32)
+    K = Kd[torch.from_numpy(rows).long().cuda()].cpu().numpy()
+    Dll = np.sqrt(base["W64"])
+    L = (0.5 * (Dll + Dll.T)).astype(np.float32)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    out = {"workload": f"bumpy torus 192 x 96 (n={n}), l={l} FPS landmarks, geodesic (mesh-edge Dijkstra) "
+                       f"distance matrix K; eps on {nsample} random rows, K~ = P K_ll P^T; stress of the k={k} "
+                       f"embedding against the exact E = K o K; float32 inputs, float64 arithmetic",
+           "p_row": {}}
+
+    def median_ms(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t1 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t1)
+        return r, 1e3 * sorted(ts)[len(ts) // 2]
+
+    def embedding(prob_arrays):
+        ctx = sb.Context([sb.Problem.from_arrays(*prob_arrays)], k=k, block=16, prec=sb.FP32)
+        Z = torch.empty((n, k), dtype=torch.float32, device="cuda")
+        _, eig, _, rc = ctx.embed(Z_out=Z)
+        if rc != 0:
+            raise RuntimeError(f"embedding did not certify (status {rc})")
+        return Z, eig
+
+    # classical MDS of the exact E through the same path (P = I, W = E)
+    ident = (dev(np.arange(n + 1, dtype=np.int32)), dev(np.arange(n, dtype=np.int32)),
+             torch.ones(n, dtype=torch.float32, device="cuda"), Ed)
+    Zm, eig_m = embedding(ident)
+    (st_m, scale), st_ms = median_ms(lambda: sb.stress(Zm, Kd))
+    del ident, Ed
+    out["mds_exact"] = {"eigvals": [float(x) for x in np.asarray(eig_m).ravel()[:k]], "stress": st_m, "rel_stress": st_m / scale}
+    out["stress_kernel"] = {"ms": round(st_ms, 3), "bytes": n * n * 4,
+                            "GB_per_s": round(n * n * 4 / st_ms / 1e6, 1)}
+    log(f"approximation quality: exact MDS stress {st_m:.5e} (relative {st_m / scale:.4f}), stress pass "
+        f"{st_ms:.3f} ms")
+    for p_row in (10, 20, 50, None):
+        prob = base if p_row == 10 else configs.build_problem(V, F, l, p_row, 4201, np.float32, landmarks=lm)
+        args = [dev(prob["rowptr"]), dev(prob["col"]), dev(prob["val"]), dev(L), dev(rows)]
+        Kr = dev(K)
+        (eps, _, _), gpu_ms = median_ms(lambda: sb.approx_rows(*args, K_rows=Kr))
+        t1 = time.perf_counter()
+        ref = omds.approx_error_rows(configs.operator_rounded(prob), L.astype(np.float64), rows, K.astype(np.float64))
+        t_cpu = time.perf_counter() - t1
+        Z, _ = embedding([dev(prob[x]) for x in ("rowptr", "col", "val", "W")])
+        st, _ = sb.stress(Z, Kd)
+        nnz = int(len(prob["col"]))
+        out["p_row"]["dense" if p_row is None else str(p_row)] = {
+            "eps": eps, "oracle_eps": ref, "rel_diff": abs(eps - ref) / ref, "nnz": nnz,
+            "approximation_bytes": nnz * 8 + l * l * 4, "eps_gpu_ms": round(gpu_ms, 3),
+            "eps_oracle_ms": round(1e3 * t_cpu, 1), "stress": st, "rel_stress": st / scale,
+            "stress_minus_mds": st - st_m}
+        log(f"approximation quality p_row={p_row}: eps {eps:.4e} (oracle {ref:.4e}), stress {st:.5e} "
+            f"(exact MDS {st_m:.5e}), nnz {nnz}")
+    out["seconds_host_generation"] = round(time.perf_counter() - t0, 1)
+    return out
+
+
 def host_info():
     info = {"cpu": None, "ram_gb": None}
     try:
@@ -490,6 +584,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the landmark-MDS and learned-start forms")
     ap.add_argument("--no-torus", action="store_true", help="skip the 1024 x 512 torus, 10,000-landmark workload")
     ap.add_argument("--no-sphere", action="store_true", help="skip the level-7 icosphere workload")
+    ap.add_argument("--no-quality", action="store_true", help="skip the approximation-quality workload")
     ap.add_argument("--forms", type=str, default="",
                     help="comma-separated headline forms to time (default: all; plain fp32 always)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -586,6 +681,11 @@ def main():
         at_scale = {pat: spmm_at_scale(sb, torch, args.steps, pat) for pat in ("banded", "random")}
         log(f"at scale {at_scale}")
 
+    quality = None
+    if not args.no_quality:
+        log("approximation quality (Section 4.1): eps on sampled rows, p_row sweep")
+        quality = approximation_quality(sb, torch)
+
     torus = None
     if not args.no_torus:
         log("precision workload: 1024 x 512 torus, 10,000 landmarks")
@@ -647,6 +747,7 @@ def main():
         "batched_full_scale": batched_full,
         "spmm_at_scale": at_scale,
         "precision_workload": torus,
+        "approximation_quality": quality,
     }
     print(json.dumps(out), flush=True)
 

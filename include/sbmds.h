@@ -265,6 +265,26 @@ void sbmds_reset_kernel_stats(sbmds_ctx *ctx);
 int sbmds_approx_rows(const sbmds_problem *prob, int fp64, const void *L, const int32_t *rows, int64_t nrows,
                       const void *K_rows, double *err, double *out, int out_mem, void *stream);
 
+/*
+ * Stress of an embedding, the objective of Eq. (MDS_problem) (Section 2.3;
+ * Section 4.2 compares solutions by it): ||Z Z^T + 1/2 J E J||_F with
+ * E = K o K the squared distances and J the centering matrix.
+ *   Z       [n*m] row-major embedding (1 <= m <= 16), e.g. sbmds_embed's Z.
+ *   K       [n*n] row-major exact distances, symmetric (only its column
+ *           sums are formed; they stand for the row sums too); same element
+ *           type and memory as Z.
+ *   fp64    element type of Z and K: double if non-zero, else float.
+ *   mem     sbmds_mem of Z and K (host arrays are uploaded first).
+ *   out     [2] host doubles: the stress and ||1/2 J E J||_F (the stress of
+ *           Z = 0, its natural scale).
+ *   stream  hipStream_t (NULL = the null stream); the call synchronises it.
+ * K is read once, in float64 arithmetic with fixed-order sums (bitwise
+ * reproducible); the call allocates (and frees) its device scratch, 24 n
+ * bytes per split of the rows (at most about 2048 / ceil(n / 256) splits),
+ * plus copies of host inputs.  Non-finite inputs give non-finite output.
+ */
+int sbmds_stress(const void *Z, int64_t n, int m, const void *K, int fp64, int mem, double *out, void *stream);
+
 /* Release the context and all device memory it owns.  NULL is a no-op. */
 void sbmds_destroy(sbmds_ctx *ctx);
 

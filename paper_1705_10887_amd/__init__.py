@@ -85,7 +85,7 @@ _lib = None
 EXPORTS = [
     "sbmds_default_options", "sbmds_create", "sbmds_embed", "sbmds_get_block",
     "sbmds_kernel_stats", "sbmds_reset_kernel_stats", "sbmds_destroy",
-    "sbmds_last_error", "sbmds_version", "sbmds_approx_rows",
+    "sbmds_last_error", "sbmds_version", "sbmds_approx_rows", "sbmds_stress",
     # learned warm start (include/sbmds_mlp.h)
     "sbmds_mlp_create", "sbmds_mlp_load", "sbmds_mlp_save", "sbmds_mlp_num_params", "sbmds_mlp_get_params",
     "sbmds_mlp_set_params", "sbmds_mlp_set_norm", "sbmds_mlp_features", "sbmds_mlp_forward",
@@ -139,6 +139,7 @@ def lib():
         ("sbmds_mlp_destroy", [vp], None),
         ("sbmds_mlp_forward_noalloc", [vp, vp, i64, vp], ci),
         ("sbmds_approx_rows", [ctypes.POINTER(_Problem), ci, vp, vp, i64, vp, vp, vp, ci, vp], ci),
+        ("sbmds_stress", [vp, i64, ci, vp, ci, ci, vp, vp], ci),
     ]:
         fn = getattr(L, name)
         fn.argtypes = args
@@ -386,3 +387,26 @@ def approx_rows(rowptr, col, val, L, rows, K_rows=None, want_rows=False):
     if K_rows is None:
         return None, None, out
     return (err[0] / err[1] if err[1] > 0 else float("nan")), (err[0], err[1]), out
+
+
+def stress(Z, K):
+    """Stress ||Z Z^T + 1/2 J E J||_F of the embedding Z (n x m) against the
+    dense symmetric distances K (n x n), E = K o K (sbmds_stress), and the
+    scale ||1/2 J E J||_F.  NumPy (host) or torch CUDA tensors, both float64
+    or both float32.  Returns (stress, scale)."""
+    fp64 = str(getattr(Z, "dtype", "")) in ("float64", "torch.float64")
+    fdt = np.float64 if fp64 else np.float32
+    n, m = int(Z.shape[0]), int(Z.shape[1])
+    if tuple(K.shape) != (n, n):
+        raise ValueError(f"K must be {n} x {n}")
+    pZ, mem = _ptr_any(Z, fdt)
+    pK, memK = _ptr_any(K, fdt)
+    if memK != mem:
+        raise ValueError("Z and K must be in the same memory")
+    stream = None
+    if mem == MEM_DEVICE:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    out = (ctypes.c_double * 2)()
+    _check(lib().sbmds_stress(pZ, n, m, pK, 1 if fp64 else 0, mem, out, stream))
+    return out[0], out[1]

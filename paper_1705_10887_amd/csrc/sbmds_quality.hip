@@ -1,14 +1,32 @@
+// Quality measures of the approximation and of the embedding, float64
+// arithmetic from the given values, every sum in a fixed order (bitwise
+// reproducible).
+//
 // Rows of the sparse biharmonic approximation K~ = P L P^T (Section 3.1:
 // the landmark block L interpolated to every vertex by P on both sides) and
 // their relative error against exact rows, eps = ||K~_S - K_S||^2 /
-// ||K_S||^2 (Section 4.1, on the row subset S).  Two passes, float64
-// arithmetic from the given values:
+// ||K_S||^2 (Section 4.1, on the row subset S).  Two passes:
 //   1. X = P_S L  (|S| x l): row i is the combination of the rows of L that
 //      row s_i of P names (L symmetric, so its rows are its columns);
 //   2. K~[i, v] = sum_e P[v, e] X[i, col_e] for every vertex v, with the
 //      error sums of each block of vertices written as partials and summed
-//      by one block in a fixed order (bitwise reproducible).
+//      by one block.
+//
+// Stress of an embedding Z (n x m) against a dense symmetric distance
+// matrix K (the objective of Eq. (MDS_problem), Section 2.3):
+// ||Z Z^T + 1/2 J E J||_F with E = K o K.  K is read once.  With r_i the
+// row means of E, g their mean and u_i = g/4 - r_i/2, the entry (i, j) of
+// the matrix inside the norm is c_ij + u_i + u_j where c_ij = z_i.z_j +
+// E_ij/2, so its squared norm is
+//   sum c_ij^2 + 4 sum_i u_i C_i + 2 n sum u_i^2 + 2 (sum u_i)^2,
+// C_i = sum_j c_ij = z_i.s + n r_i / 2 and s = sum_j z_j (E and c are
+// symmetric, so column sums stand for row sums).  Expanding u_i, every term
+// is a plain sum over rows of sum_j c_ij^2, sum_j E_ij, sum_j E_ij^2, r_i^2,
+// z_i and r_i z_i.  The pass over K forms the first three per column (each
+// thread one column, down a range of rows); the rest are block sums.  The
+// same expansion with Z = 0 gives ||1/2 J E J||_F, the scale of the stress.
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/sbmds.h"
@@ -32,41 +50,73 @@ __global__ __launch_bounds__(256) void k_q_landmark_rows(const int32_t *__restri
     X[(int64_t)i * l + j] = x;
 }
 
-template <typename T>
+// K~ rows for kQRows rows of S per block: each thread takes one vertex v,
+// reads its row of P once and applies it to the kQRows rows of X (staged in
+// LDS when l is small enough, else read through the cache).
+constexpr int kQRows = 8;
+constexpr int64_t kQLdsMaxL = 1000;  // kQRows x l doubles and the reduction buffer within 64 KB
+
+template <typename T, bool LDS>
 __global__ __launch_bounds__(256) void k_q_rows(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                                const T *__restrict__ val, int64_t n, int64_t l,
+                                                const T *__restrict__ val, int64_t n, int64_t l, int64_t S,
                                                 const double *__restrict__ X, const T *__restrict__ K,
                                                 double *__restrict__ out, double *__restrict__ part) {
-    const int i = blockIdx.y;
+    extern __shared__ unsigned char q_smem[];
+    double *xs = (double *)q_smem;  // [kQRows][l] when LDS
+    const int64_t i0 = (int64_t)blockIdx.y * kQRows;
+    const int nr = (int)(S - i0 < kQRows ? S - i0 : kQRows);
+    const double *xb = X + i0 * l;
+    if (LDS) {
+        for (int64_t t = threadIdx.x; t < nr * l; t += 256) xs[t] = xb[t];
+        __syncthreads();
+        xb = xs;
+    }
     const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    double num = 0.0, den = 0.0;
+    double kt[kQRows];
+#pragma unroll
+    for (int r = 0; r < kQRows; ++r) kt[r] = 0.0;
     if (v < n) {
-        const double *xi = X + (int64_t)i * l;
-        double kt = 0.0;
-        for (int32_t e = rp[v]; e < rp[v + 1]; ++e) kt += (double)val[e] * xi[ci[e]];
-        if (out) out[(int64_t)i * n + v] = kt;
-        if (K) {
-            const double k = (double)K[(int64_t)i * n + v];
-            num = (kt - k) * (kt - k);
-            den = k * k;
+        for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+            const double pv = (double)val[e];
+            const int64_t c = ci[e];
+#pragma unroll
+            for (int r = 0; r < kQRows; ++r)
+                if (r < nr) kt[r] += pv * xb[r * l + c];
+        }
+    }
+    __shared__ double red[kQRows][2][4];
+#pragma unroll
+    for (int r = 0; r < kQRows; ++r) {
+        if (r >= nr) break;
+        const int64_t i = i0 + r;
+        double num = 0.0, den = 0.0;
+        if (v < n) {
+            if (out) out[i * n + v] = kt[r];
+            if (K) {
+                const double k = (double)K[i * n + v];
+                num = (kt[r] - k) * (kt[r] - k);
+                den = k * k;
+            }
+        }
+        if (part) {
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) {
+                num += __shfl_xor(num, m);
+                den += __shfl_xor(den, m);
+            }
+            if ((threadIdx.x & 63) == 0) {
+                red[r][0][threadIdx.x >> 6] = num;
+                red[r][1][threadIdx.x >> 6] = den;
+            }
         }
     }
     if (!part) return;
-    __shared__ double red[2][4];
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        num += __shfl_xor(num, m);
-        den += __shfl_xor(den, m);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        red[0][threadIdx.x >> 6] = num;
-        red[1][threadIdx.x >> 6] = den;
-    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const size_t b = (size_t)i * gridDim.x + blockIdx.x;
-        part[2 * b] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-        part[2 * b + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    if (threadIdx.x < 2 * nr) {
+        const int r = threadIdx.x >> 1, h = threadIdx.x & 1;
+        const size_t b = (size_t)(i0 + r) * gridDim.x + blockIdx.x;
+        const double *x = red[r][h];
+        part[2 * b + h] = x[0] + x[1] + x[2] + x[3];
     }
 }
 
@@ -92,6 +142,178 @@ __global__ __launch_bounds__(256) void k_q_reduce(const double *__restrict__ par
         out[0] = x;
         out[1] = y;
     }
+}
+
+constexpr int kStressMaxM = 16;   // embedding dimensions supported
+constexpr int kStressUnroll = 8;  // rows of K in flight per thread
+constexpr int kStressVals = 4 + 2 * kStressMaxM;
+
+// Block-wide sum in a fixed order (a butterfly within each wave, then the
+// four wave sums in order); every thread gets the result.
+__device__ double block_sum_fixed(double v, double *buf) {
+#pragma unroll
+    for (int sh = 32; sh >= 1; sh >>= 1) v += __shfl_xor(v, sh);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) buf[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return ((buf[0] + buf[1]) + buf[2]) + buf[3];
+}
+
+// One pass over K: thread t of block (x, y) takes V consecutive columns
+// j = V (256 x + t) + c and walks them down the rows of split y with
+// kStressUnroll (V = 1) or half as many (V = 4) coalesced row loads in
+// flight.  V = 4 (16-byte loads of float32 rows) needs m <= 4, n % 4 == 0
+// and K 16-byte aligned.  It writes part[(3 y + s) n + j] for s = 0, 1, 2:
+// the split's sums of c_ij^2, E_ij and E_ij^2.  z_j stays in registers; z_i
+// is the same for the whole block.  Threads past the last columns read the
+// last V columns and store nothing.
+template <typename T, int V, int MM>
+__global__ __launch_bounds__(256) void k_q_stress_part(const T *__restrict__ Z, int64_t n, int m,
+                                                       int64_t rows_per_split, const T *__restrict__ K,
+                                                       double *__restrict__ part) {
+    const int64_t j = ((int64_t)blockIdx.x * 256 + threadIdx.x) * V;
+    const int64_t jc = j < n ? j : n - V;
+    const int64_t ib = (int64_t)blockIdx.y * rows_per_split;
+    const int64_t ie = (ib + rows_per_split < n ? ib + rows_per_split : n);
+    double zj[V][MM];
+#pragma unroll
+    for (int c = 0; c < V; ++c)
+#pragma unroll
+        for (int q = 0; q < MM; ++q) zj[c][q] = q < m ? (double)Z[(jc + c) * m + q] : 0.0;
+    double c2[V], se[V], se2[V];
+#pragma unroll
+    for (int c = 0; c < V; ++c) c2[c] = se[c] = se2[c] = 0.0;
+    auto add = [&](int64_t i, const T *kv) {
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+            double a = 0.0;
+#pragma unroll
+            for (int q = 0; q < MM; ++q)
+                if (q < m) a += (double)Z[i * m + q] * zj[c][q];
+            const double e = (double)kv[c] * (double)kv[c];
+            const double h = a + 0.5 * e;
+            c2[c] += h * h;
+            se[c] += e;
+            se2[c] += e * e;
+        }
+    };
+    auto load = [&](int64_t i, T *kv) {
+        const T *src = (const T *)__builtin_assume_aligned(K + i * n + jc, V * sizeof(T) >= 16 ? 16 : sizeof(T));
+#pragma unroll
+        for (int c = 0; c < V; ++c) kv[c] = src[c];
+    };
+    int64_t i = ib;
+    constexpr int U = V == 1 ? kStressUnroll : kStressUnroll / 2;
+    for (; i + U <= ie; i += U) {
+        T kv[U][V];
+#pragma unroll
+        for (int t = 0; t < U; ++t) load(i + t, kv[t]);
+#pragma unroll
+        for (int t = 0; t < U; ++t) add(i + t, kv[t]);
+    }
+    for (; i < ie; ++i) {
+        T kv[V];
+        load(i, kv);
+        add(i, kv);
+    }
+    if (j < n) {
+        double *p = part + (int64_t)blockIdx.y * 3 * n + j;
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+            p[c] = c2[c];
+            p[n + c] = se[c];
+            p[2 * n + c] = se2[c];
+        }
+    }
+}
+
+// Per column j: the split sums added in split order, then this block's sums
+// of sum_j c^2, sum_j E, sum_j E^2, r_j^2, z_j (m) and r_j z_j (m), written
+// to blk[blockIdx.x][0 .. 4 + 2m).
+template <typename T>
+__global__ __launch_bounds__(256) void k_q_stress_cols(const T *__restrict__ Z, int64_t n, int m, int splits,
+                                                       const double *__restrict__ part, double *__restrict__ blk) {
+    __shared__ double buf[4];
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double c2 = 0.0, se = 0.0, se2 = 0.0;
+    if (j < n) {
+        int y = 0;
+        for (; y + 8 <= splits; y += 8) {  // 24 loads in flight, added in split order
+            double v[8][3];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const double *p = part + (int64_t)(y + t) * 3 * n + j;
+                v[t][0] = p[0];
+                v[t][1] = p[n];
+                v[t][2] = p[2 * n];
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                c2 += v[t][0];
+                se += v[t][1];
+                se2 += v[t][2];
+            }
+        }
+        for (; y < splits; ++y) {
+            const double *p = part + (int64_t)y * 3 * n + j;
+            c2 += p[0];
+            se += p[n];
+            se2 += p[2 * n];
+        }
+    }
+    const double r = se / (double)n;
+    double *o = blk + (int64_t)blockIdx.x * kStressVals;
+    const double v4[4] = {c2, se, se2, r * r};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const double x = block_sum_fixed(v4[t], buf);
+        if (threadIdx.x == 0) o[t] = x;
+    }
+#pragma unroll
+    for (int q = 0; q < kStressMaxM; ++q) {
+        if (q < m) {  // m is the same for every thread
+            const double z = j < n ? (double)Z[j * m + q] : 0.0;
+            const double a = block_sum_fixed(z, buf);
+            const double b = block_sum_fixed(r * z, buf);
+            if (threadIdx.x == 0) {
+                o[4 + q] = a;
+                o[4 + kStressMaxM + q] = b;
+            }
+        }
+    }
+}
+
+// out[0] = stress, out[1] = ||1/2 J E J||_F from the block sums (added in
+// block order).
+__global__ __launch_bounds__(256) void k_q_stress_finish(int64_t n, int m, int64_t nblk,
+                                                         const double *__restrict__ blk, double *__restrict__ out) {
+    __shared__ double buf[4];
+    __shared__ double tot[kStressVals];
+    for (int v = 0; v < kStressVals; ++v) {
+        double x = 0.0;
+        for (int64_t b = threadIdx.x; b < nblk; b += 256) x += blk[b * kStressVals + v];
+        x = block_sum_fixed(x, buf);
+        if (threadIdx.x == 0) tot[v] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double dn = (double)n;
+    const double A = tot[0], Se = tot[1], Se2 = tot[2], R2 = tot[3];
+    const double g = Se / (dn * dn), R1 = Se / dn;
+    double ss = 0.0, ts = 0.0;
+    for (int q = 0; q < m; ++q) {
+        ss += tot[4 + q] * tot[4 + q];
+        ts += tot[4 + kStressMaxM + q] * tot[4 + q];
+    }
+    const double su = 0.25 * dn * g - 0.5 * R1;
+    const double su2 = dn * g * g / 16.0 - 0.25 * g * R1 + 0.25 * R2;
+    const double uc0 = 0.125 * g * dn * R1 - 0.25 * dn * R2;  // sum u_i C_i at Z = 0
+    const double uc = 0.25 * g * ss - 0.5 * ts + uc0;
+    const double tail = 2.0 * dn * su2 + 2.0 * su * su;
+    const double s2 = A + 4.0 * uc + tail;
+    const double n2 = 0.25 * Se2 + 4.0 * uc0 + tail;
+    out[0] = sqrt(s2 > 0.0 ? s2 : 0.0);
+    out[1] = sqrt(n2 > 0.0 ? n2 : 0.0);
 }
 
 struct Tmp {
@@ -175,8 +397,13 @@ int approx_rows_impl(const sbmds_problem &pr, const T *L, const int32_t *rows, i
     hipLaunchKernelGGL((k_q_landmark_rows<T>), dim3((unsigned)((l + 255) / 256), (unsigned)S), dim3(256), 0, s, drp,
                        dci, dval, dL, l, drows, X);
     QCHK(hipGetLastError());
-    hipLaunchKernelGGL((k_q_rows<T>), dim3((unsigned)nb, (unsigned)S), dim3(256), 0, s, drp, dci, dval, n, l, X, dK,
-                       dout, dK ? part : nullptr);
+    const dim3 qg((unsigned)nb, (unsigned)((S + kQRows - 1) / kQRows));
+    if (l <= kQLdsMaxL)
+        hipLaunchKernelGGL((k_q_rows<T, true>), qg, dim3(256), (size_t)kQRows * l * 8, s, drp, dci, dval, n, l, S, X,
+                           dK, dout, dK ? part : nullptr);
+    else
+        hipLaunchKernelGGL((k_q_rows<T, false>), qg, dim3(256), 0, s, drp, dci, dval, n, l, S, X, dK, dout,
+                           dK ? part : nullptr);
     QCHK(hipGetLastError());
     if (dK) {
         hipLaunchKernelGGL(k_q_reduce, dim3(1), dim3(256), 0, s, part, S * nb, derr);
@@ -193,8 +420,82 @@ int approx_rows_impl(const sbmds_problem &pr, const T *L, const int32_t *rows, i
     return SBMDS_OK;
 }
 
+template <typename T>
+int stress_impl(const T *Z, int64_t n, int m, const T *K, int mem, double *out, hipStream_t s) {
+    // splits of the rows: at least about 2048 blocks over the columns and
+    // rows, each split at least 64 rows
+    const int64_t ncb = (n + 255) / 256;
+    // host inputs are copied to 256-byte aligned scratch
+    const bool vec = std::is_same<T, float>::value && m <= 4 && n % 4 == 0 &&
+                     (mem == SBMDS_MEM_HOST || ((uintptr_t)K & 15) == 0);
+    const int64_t nxb = vec ? (n + 1023) / 1024 : ncb;  // blocks across the columns of the pass over K
+    int64_t splits = (2048 + nxb - 1) / nxb;
+    const int64_t max_splits = (n + 63) / 64;
+    if (splits > max_splits) splits = max_splits;
+    if (splits < 1) splits = 1;
+    const int64_t rows_per_split = (n + splits - 1) / splits;
+    splits = (n + rows_per_split - 1) / rows_per_split;
+    const size_t b_part = (size_t)splits * 3 * n * 8, b_blk = (size_t)ncb * kStressVals * 8;
+    const size_t b_Z = (size_t)n * m * sizeof(T), b_K = (size_t)n * n * sizeof(T);
+    const bool host = mem == SBMDS_MEM_HOST;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t total = al(b_part) + al(b_blk) + 256 + (host ? al(b_Z) + al(b_K) : 0);
+    Tmp tmp;
+    if (hipMalloc(&tmp.p, total) != hipSuccess) {
+        tmp.p = nullptr;
+        return api_fail(SBMDS_ENOMEM, "hipMalloc of " + std::to_string(total) + " bytes failed");
+    }
+    char *q = (char *)tmp.p;
+    double *part = (double *)q;
+    double *blk = (double *)(q + al(b_part));
+    double *dout = (double *)(q + al(b_part) + al(b_blk));
+    const T *dZ = Z, *dK = K;
+    if (host) {
+        T *a = (T *)(q + al(b_part) + al(b_blk) + 256);
+        T *b = (T *)((char *)a + al(b_Z));
+        QCHK(hipMemcpyAsync(a, Z, b_Z, hipMemcpyHostToDevice, s));
+        QCHK(hipMemcpyAsync(b, K, b_K, hipMemcpyHostToDevice, s));
+        dZ = a;
+        dK = b;
+    }
+    if (vec)
+        hipLaunchKernelGGL((k_q_stress_part<T, 4, 4>), dim3((unsigned)nxb, (unsigned)splits), dim3(256), 0, s, dZ, n,
+                           m, rows_per_split, dK, part);
+    else
+        hipLaunchKernelGGL((k_q_stress_part<T, 1, kStressMaxM>), dim3((unsigned)ncb, (unsigned)splits), dim3(256), 0,
+                           s, dZ, n, m, rows_per_split, dK, part);
+    QCHK(hipGetLastError());
+    hipLaunchKernelGGL((k_q_stress_cols<T>), dim3((unsigned)ncb), dim3(256), 0, s, dZ, n, m, (int)splits, part,
+                       blk);
+    QCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_q_stress_finish, dim3(1), dim3(256), 0, s, n, m, ncb, blk, dout);
+    QCHK(hipGetLastError());
+    double h[2];
+    QCHK(hipMemcpyAsync(h, dout, 16, hipMemcpyDeviceToHost, s));
+    QCHK(hipStreamSynchronize(s));
+    out[0] = h[0];
+    out[1] = h[1];
+    return SBMDS_OK;
+}
+
 }  // namespace
 }  // namespace sbmds
+
+extern "C" int sbmds_stress(const void *Z, int64_t n, int m, const void *K, int fp64, int mem, double *out,
+                            void *stream) {
+    using namespace sbmds;
+    api_clear_error();
+    if (!Z || !K || !out) return api_fail(SBMDS_EINVAL, "Z, K and out must be non-NULL");
+    if (mem != SBMDS_MEM_HOST && mem != SBMDS_MEM_DEVICE) return api_fail(SBMDS_EINVAL, "mem must be 0 or 1");
+    if (n < 1 || n >= ((int64_t)1 << 31)) return api_fail(SBMDS_EINVAL, "need 1 <= n < 2^31");
+    if (m < 1 || m > kStressMaxM) return api_fail(SBMDS_EINVAL, "need 1 <= m <= 16");
+    try {
+        return fp64 ? stress_impl<double>((const double *)Z, n, m, (const double *)K, mem, out, (hipStream_t)stream)
+                    : stress_impl<float>((const float *)Z, n, m, (const float *)K, mem, out, (hipStream_t)stream);
+    } catch (const std::exception &e) {
+        return api_fail(SBMDS_ENOMEM, std::string("host exception: ") + e.what());
+    }
+}
 
 extern "C" int sbmds_approx_rows(const sbmds_problem *prob, int fp64, const void *L, const int32_t *rows,
                                  int64_t nrows, const void *K_rows, double *err, double *out, int out_mem,

@@ -145,3 +145,19 @@ def test_approx_rows_argument_checks_without_gpu():
     assert rc == -1 and b"K_rows" in L.sbmds_last_error()
     rc = L.sbmds_approx_rows(ctypes.byref(s), 0, s.W, rows.ctypes.data, 1, K.ctypes.data, None, None, 0, None)
     assert rc == -1 and b"nothing to compute" in L.sbmds_last_error()
+
+
+def test_stress_argument_checks_without_gpu():
+    # argument checks of sbmds_stress come before any device call
+    L = sb.lib()
+    Z = np.zeros((4, 3), np.float32)
+    K = np.zeros((4, 4), np.float32)
+    out = (ctypes.c_double * 2)()
+    assert L.sbmds_stress(Z.ctypes.data, 4, 0, K.ctypes.data, 0, 0, out, None) == -1
+    assert b"m <= 16" in L.sbmds_last_error()
+    assert L.sbmds_stress(Z.ctypes.data, 4, 17, K.ctypes.data, 0, 0, out, None) == -1
+    assert L.sbmds_stress(Z.ctypes.data, 0, 3, K.ctypes.data, 0, 0, out, None) == -1
+    assert b"n <" in L.sbmds_last_error()
+    assert L.sbmds_stress(None, 4, 3, K.ctypes.data, 0, 0, out, None) == -1
+    assert L.sbmds_stress(Z.ctypes.data, 4, 3, K.ctypes.data, 0, 2, out, None) == -1
+    assert b"mem" in L.sbmds_last_error()

@@ -1,7 +1,8 @@
 """Rows of the sparse biharmonic approximation K~ = P L P^T and their
-relative error on a row subset (Section 4.1's eps), on the GPU through the C
-ABI, against the float64 oracle (oracle.mds.approx_rows / approx_error_rows)
-on the same rounded values (needs a gfx950 GPU)."""
+relative error on a row subset (Section 4.1's eps), and the stress of an
+embedding (Eq. (MDS_problem)), on the GPU through the C ABI, against the
+float64 oracle (oracle.mds.approx_rows / approx_error_rows / strain) on the
+same rounded values (needs a gfx950 GPU)."""
 import numpy as np
 import pytest
 import scipy.sparse.csgraph as csgraph
@@ -73,3 +74,58 @@ def test_device_inputs_and_ragged_rows(gpu):
     with pytest.raises(sb.SbmdsError) as exc:
         sb.approx_rows(rp, prob["col"], prob["val"], L, bad, K_rows=K)
     assert "out of range" in str(exc.value)
+
+
+def distance_case(n_sub=None):
+    prob = configs.torus64x32()
+    G = op.edge_graph(prob["V"], prob["F"])
+    D = csgraph.dijkstra(G, directed=False)
+    D = 0.5 * (D + D.T)
+    if n_sub is not None:
+        D = D[:n_sub, :n_sub]
+    return D
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_stress_matches_oracle(gpu, dtype):
+    # exact classical MDS of the torus distances (3-D) and a perturbed copy
+    # of it: the stress and its scale against the oracle's dense
+    # ||Z Z^T + 1/2 J E J||_F on the same rounded values; n = 2047 leaves a
+    # ragged last block of rows and a ragged column step
+    sb = gpu
+    D = distance_case(2047)
+    E = D * D
+    _, Z = omds.classical_mds(E, 3)
+    rng = np.random.default_rng(5)
+    for Zc in (Z, Z + 0.05 * rng.standard_normal(Z.shape)):
+        Kc = D.astype(dtype)
+        Zr = Zc.astype(dtype)
+        st, scale = sb.stress(Zr, Kc)
+        E64 = Kc.astype(np.float64) ** 2
+        ref = omds.strain(Zr.astype(np.float64), E64)
+        ref_scale = omds.strain(np.zeros((D.shape[0], 1)), E64)
+        print(f"{np.dtype(dtype).name}: stress {st:.9e} oracle {ref:.9e} scale {scale:.6e}", flush=True)
+        assert abs(st - ref) <= 1e-9 * ref_scale
+        assert abs(scale - ref_scale) <= 1e-10 * ref_scale
+
+
+def test_stress_device_inputs_many_dims_and_tiny(gpu):
+    # device inputs equal host inputs bit for bit; m = 16 (the largest
+    # supported); n = 1..5 (a single partial row block)
+    sb = gpu
+    import torch
+    D = distance_case(300)
+    rng = np.random.default_rng(6)
+    Z = rng.standard_normal((300, 16))
+    h = sb.stress(Z, D)
+    d = sb.stress(torch.from_numpy(Z).cuda(), torch.from_numpy(D).cuda())
+    assert h == d
+    ref = omds.strain(Z, D * D)
+    assert abs(h[0] - ref) <= 1e-10 * ref
+    for n in (1, 2, 5):
+        Zs, Ds = Z[:n, :2].copy(), D[:n, :n].copy()
+        st, scale = sb.stress(Zs, Ds)
+        ref = omds.strain(Zs, Ds * Ds)
+        assert abs(st - ref) <= 1e-10 * max(ref, 1e-300) + 1e-12 * max(scale, 1.0)
+    with pytest.raises(sb.SbmdsError):
+        sb.stress(rng.standard_normal((10, 17)), D[:10, :10])

@@ -394,6 +394,12 @@ def test_centering_and_sign_pins():
     c = pts - pts.mean(0)
     np.testing.assert_allclose(lam, np.sort(np.linalg.eigvalsh(c.T @ c))[::-1], rtol=1e-10)
     assert omds.strain(Z, E) < 1e-9 * np.abs(E).max()
+    # for Euclidean points -1/2 J E J is the Gram matrix of the centred points,
+    # whose nonzero eigenvalues are those of c^T c: the empty embedding has
+    # stress sqrt(l1^2 + l2^2), the one-dimensional one has stress l2
+    g = np.sort(np.linalg.eigvalsh(c.T @ c))[::-1]
+    assert abs(omds.strain(np.zeros((50, 1)), E) - np.hypot(g[0], g[1])) <= 1e-9 * g[0]
+    assert abs(omds.strain(Z[:, :1], E) - g[1]) <= 1e-9 * g[0]
 
 
 def test_sphere_spectrum_funk_hecke():

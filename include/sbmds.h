@@ -226,6 +226,43 @@ int sbmds_create(const sbmds_problem *probs, int nprob, const sbmds_options *opt
  */
 int sbmds_embed(sbmds_ctx *ctx, double *eigvals, void *Z, int Z_mem, sbmds_report *reports);
 
+/*
+ * The paper's other two routes to the same eigenpairs (Section 3.3), run on
+ * the operator a context holds (its top precision: float64 for SBMDS_FP64,
+ * float32 otherwise; vectors and products in float64), as comparison
+ * solvers beside sbmds_embed.  Both use the context's k, tol and seed and
+ * write eigvals and Z exactly as sbmds_embed does (k <= 16).
+ *
+ * sbmds_embed_lanczos: (block) Lanczos on the implicit operator
+ * B = -1/2 J P W P^T J, using only products with B (the paper's sBMDS;
+ * block = 1 is the single-vector method, block 2, 4 or 8 resolves
+ * eigenvalues of that multiplicity), with full reorthogonalisation.  It
+ * stops when the k largest Ritz values meet the same error bound as
+ * sbmds_embed's certification (tol), or after max_steps block steps
+ * (SBMDS_ENOCONV, best Ritz pairs written).  The basis, n x block x
+ * max_steps doubles (at most 2048 columns), is allocated per call.
+ *
+ * sbmds_embed_bmds: BMDS.  Q R = J P by a Householder QR of the dense
+ * n x l matrix J P, the eigendecomposition of -1/2 R W R^T, and
+ * Z = Q V_k Lambda_k^{1/2}.  It needs 8 n l bytes of device memory (and
+ * l <= 65535); SBMDS_ENOMEM when that does not fit.  err_bound and resid
+ * are the measured relative residuals ||B x - theta x|| / |theta|.
+ */
+typedef struct {
+    int status;      /* SBMDS_OK, SBMDS_ENOCONV */
+    int steps;       /* block Lanczos steps (0 for BMDS) */
+    int basis;       /* columns of the Krylov basis used (0 for BMDS) */
+    int nonpositive; /* of the k eigenvalues, those <= 0 (their coordinates are 0) */
+    double ms_total; /* host wall time of the problem's solve */
+    double eig[SBMDS_MAX_BLOCK];
+    double err_bound[SBMDS_MAX_BLOCK];
+    double resid[SBMDS_MAX_BLOCK];
+} sbmds_solver_report;
+
+int sbmds_embed_lanczos(sbmds_ctx *ctx, int block, int max_steps, double *eigvals, void *Z, int Z_mem,
+                        sbmds_solver_report *reports);
+int sbmds_embed_bmds(sbmds_ctx *ctx, double *eigvals, void *Z, int Z_mem, sbmds_solver_report *reports);
+
 /* Copy the current basis block (the iteration's state) of problem `prob`
  * into `X` ([n*block] row-major, element type as P_val, host or device per
  * X_mem), so that a later solve can resume from it via SBMDS_START_USER. */

@@ -73,6 +73,15 @@ class _Report(ctypes.Structure):
     ]
 
 
+class _SolverReport(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int), ("steps", ctypes.c_int), ("basis", ctypes.c_int), ("nonpositive", ctypes.c_int),
+        ("ms_total", ctypes.c_double),
+        ("eig", ctypes.c_double * MAX_BLOCK), ("err_bound", ctypes.c_double * MAX_BLOCK),
+        ("resid", ctypes.c_double * MAX_BLOCK),
+    ]
+
+
 class _KStat(ctypes.Structure):
     _fields_ = [
         ("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("ms_total", ctypes.c_double),
@@ -86,6 +95,7 @@ EXPORTS = [
     "sbmds_default_options", "sbmds_create", "sbmds_embed", "sbmds_get_block",
     "sbmds_kernel_stats", "sbmds_reset_kernel_stats", "sbmds_destroy",
     "sbmds_last_error", "sbmds_version", "sbmds_approx_rows", "sbmds_stress",
+    "sbmds_embed_lanczos", "sbmds_embed_bmds",
     # learned warm start (include/sbmds_mlp.h)
     "sbmds_mlp_create", "sbmds_mlp_load", "sbmds_mlp_save", "sbmds_mlp_num_params", "sbmds_mlp_get_params",
     "sbmds_mlp_set_params", "sbmds_mlp_set_norm", "sbmds_mlp_features", "sbmds_mlp_forward",
@@ -140,6 +150,8 @@ def lib():
         ("sbmds_mlp_forward_noalloc", [vp, vp, i64, vp], ci),
         ("sbmds_approx_rows", [ctypes.POINTER(_Problem), ci, vp, vp, i64, vp, vp, vp, ci, vp], ci),
         ("sbmds_stress", [vp, i64, ci, vp, ci, ci, vp, vp], ci),
+        ("sbmds_embed_lanczos", [vp, ci, ci, vp, vp, ci, ctypes.POINTER(_SolverReport)], ci),
+        ("sbmds_embed_bmds", [vp, vp, vp, ci, ctypes.POINTER(_SolverReport)], ci),
     ]:
         fn = getattr(L, name)
         fn.argtypes = args
@@ -296,6 +308,38 @@ class Context:
         rc = _check(L.sbmds_embed(self._h, eig.ctypes.data, zptr, zmem, reps))
         reports = [_report_dict(r, self.k, self.block) for r in reps]
         return Z, eig, reports, rc
+
+    def _z_target(self, Z_out):
+        ntot = sum(p.n for p in self.problems)
+        zdt = np.float64 if self.prec == FP64 else np.float32
+        if Z_out is None:
+            Z = np.zeros((ntot, self.k), dtype=zdt)
+            return Z, Z.ctypes.data, MEM_HOST
+        if _is_torch(Z_out) and Z_out.is_cuda:
+            return Z_out, Z_out.data_ptr(), MEM_DEVICE
+        return Z_out, Z_out.ctypes.data, MEM_HOST
+
+    def _compare(self, fn, *args, Z_out=None):
+        nprob = len(self.problems)
+        eig = np.zeros((nprob, self.k), dtype=np.float64)
+        reps = (_SolverReport * nprob)()
+        Z, zptr, zmem = self._z_target(Z_out)
+        rc = _check(fn(self._h, *args, eig.ctypes.data, zptr, zmem, reps))
+        reports = [dict(status=r.status, steps=r.steps, basis=r.basis, nonpositive=r.nonpositive,
+                        ms_total=r.ms_total, eig=list(r.eig[:self.k]), err_bound=list(r.err_bound[:self.k]),
+                        resid=list(r.resid[:self.k])) for r in reps]
+        return Z, eig, reports, rc
+
+    def embed_lanczos(self, block=1, max_steps=300, Z_out=None):
+        """The paper's sBMDS route (sbmds_embed_lanczos): (block) Lanczos on
+        the implicit operator, on the context's problems.  Returns
+        (Z, eigvals [nprob, k], reports, status)."""
+        return self._compare(lib().sbmds_embed_lanczos, block, max_steps, Z_out=Z_out)
+
+    def embed_bmds(self, Z_out=None):
+        """BMDS (sbmds_embed_bmds): QR of the dense J P, eigendecomposition of
+        -1/2 R W R^T.  Returns (Z, eigvals [nprob, k], reports, status)."""
+        return self._compare(lib().sbmds_embed_bmds, Z_out=Z_out)
 
     def get_block(self, prob=0):
         """Current orthonormal basis X (n x block) of problem `prob` (host array)."""

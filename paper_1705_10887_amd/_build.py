@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsbmds.so")
 SOURCES = ["sbmds_runtime.cpp", "sbmds_sparse.hip", "sbmds_dense.hip", "sbmds_dense_sym.hip", "sbmds_small.hip",
            "sbmds_rr.hip", "sbmds_mlp.hip", "sbmds_mlp_api.cpp", "sbmds_prep.hip",
-           "sbmds_quality.hip"]
+           "sbmds_quality.hip", "sbmds_compare.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
@@ -45,7 +45,8 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     for p in procs:
         _wait(p)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-Wl,--no-undefined", "-o", tmp] + objs
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-Wl,--no-undefined", "-o", tmp] + objs + [
+        "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas"]
     out = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
     if out.returncode != 0:
         raise RuntimeError("link failed:\n" + out.stdout.decode())

@@ -31,6 +31,7 @@
 #include "../../include/sbmds.h"
 #include "../../include/sbmds_mlp.h"
 #include "sbmds_common.h"
+#include "sbmds_compare.h"
 #include "sbmds_internal.h"
 #include "sbmds_dense_sym.h"
 #include "sbmds_prep.h"
@@ -1550,6 +1551,103 @@ int sbmds_embed(sbmds_ctx *ctx, double *eigvals, void *Z, int Z_mem, sbmds_repor
     } catch (const std::exception &e) {
         return fail(SBMDS_ENOMEM, std::string("host exception: ") + e.what());
     }
+}
+
+// The comparison solvers on every problem of a context, one after the other:
+// operator views in the context's top precision, Z in the layout of
+// sbmds_embed.
+static int run_compare(sbmds_ctx *ctx, const char *what, void *Z, int Z_mem, double *eigvals,
+                       sbmds_solver_report *reports,
+                       const std::function<int(const CmpOp &, void *, CmpResult *)> &solve) {
+    g_err.clear();
+    if (!ctx) return fail(SBMDS_EINVAL, "ctx is NULL");
+    if (Z && Z_mem != SBMDS_MEM_HOST && Z_mem != SBMDS_MEM_DEVICE) return fail(SBMDS_EINVAL, "Z_mem must be 0 or 1");
+    if (ctx->opt.k > kCmpMaxK) return fail(SBMDS_EINVAL, std::string(what) + " returns at most 16 eigenpairs");
+    try {
+        HIPCHK(hipSetDevice(ctx->device));
+        const SolveSet &set = ctx->main;
+        const bool zd = ctx->opt.prec == SBMDS_FP64;
+        const Mode mode = zd ? MODE_FP64 : MODE_FP32;
+        const size_t esz = zd ? 8 : 4;
+        void *zbuf = nullptr;  // device output of one problem
+        size_t zcap = 0;
+        for (const DevProblem &p : set.probs) zcap = std::max(zcap, (size_t)p.n * p.k * esz);
+        if (!ctx->zstage) OKCHK(dalloc(ctx, &ctx->zstage, set.zstage_bytes));
+        zbuf = ctx->zstage;
+        (void)zcap;
+        int worst = SBMDS_OK;
+        size_t zoff = 0;
+        for (size_t i = 0; i < set.probs.size(); ++i) {
+            const DevProblem &p = set.probs[i];
+            CmpOp op;
+            op.n = p.n;
+            op.l = p.l;
+            op.nnz = p.nnz;
+            op.lda = p.lda;
+            op.rp = p.rp;
+            op.ci = p.ci;
+            op.rpT = p.rpT;
+            op.ciT = p.ciT;
+            op.val = p.val[mode];
+            op.valT = p.valT[mode];
+            op.W = p.W[mode];
+            op.c = p.c[mode];
+            op.f64 = zd;
+            if (!op.val || !op.valT || !op.W || !op.c)
+                return fail(SBMDS_EINVAL, std::string(what) + ": the context holds no operator in its top precision");
+            void *dz = Z_mem == SBMDS_MEM_DEVICE && Z ? (void *)((char *)Z + zoff) : (void *)((char *)zbuf + zoff);
+            CmpResult r;
+            const auto t0 = std::chrono::steady_clock::now();
+            const int rc = solve(op, dz, &r);
+            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (rc < 0) return rc;
+            worst = std::max(worst, rc);
+            if (eigvals)
+                for (int j = 0; j < p.k; ++j) eigvals[i * p.k + j] = r.eig[j];
+            if (reports) {
+                sbmds_solver_report &o = reports[i];
+                std::memset(&o, 0, sizeof(o));
+                o.status = rc;
+                o.steps = r.steps;
+                o.basis = r.basis;
+                o.nonpositive = r.nonpositive;
+                o.ms_total = ms;
+                for (int j = 0; j < p.k; ++j) {
+                    o.eig[j] = r.eig[j];
+                    o.err_bound[j] = r.bound[j];
+                    o.resid[j] = r.resid[j];
+                }
+            }
+            zoff += (size_t)p.n * p.k * esz;
+        }
+        if (Z && Z_mem == SBMDS_MEM_HOST) {
+            HIPCHK(hipMemcpyAsync(Z, zbuf, zoff, hipMemcpyDeviceToHost, ctx->stream));
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+        }
+        return worst;
+    } catch (const std::exception &e) {
+        return fail(SBMDS_ENOMEM, std::string("host exception: ") + e.what());
+    }
+}
+
+int sbmds_embed_lanczos(sbmds_ctx *ctx, int block, int max_steps, double *eigvals, void *Z, int Z_mem,
+                        sbmds_solver_report *reports) {
+    if (ctx && (block != 1 && block != 2 && block != 4 && block != 8))
+        return fail(SBMDS_EINVAL, "Lanczos block must be 1, 2, 4 or 8");
+    if (ctx && max_steps < 1) return fail(SBMDS_EINVAL, "max_steps must be >= 1");
+    return run_compare(ctx, "sbmds_embed_lanczos", Z, Z_mem, eigvals, reports,
+                       [&](const CmpOp &op, void *dz, CmpResult *r) {
+                           return lanczos_solve(op, ctx->opt.k, block, max_steps, ctx->opt.tol, ctx->opt.seed, dz,
+                                                ctx->opt.prec == SBMDS_FP64 ? 1 : 0, r, ctx->stream);
+                       });
+}
+
+int sbmds_embed_bmds(sbmds_ctx *ctx, double *eigvals, void *Z, int Z_mem, sbmds_solver_report *reports) {
+    return run_compare(ctx, "sbmds_embed_bmds", Z, Z_mem, eigvals, reports,
+                       [&](const CmpOp &op, void *dz, CmpResult *r) {
+                           return bmds_solve(op, ctx->opt.k, dz, ctx->opt.prec == SBMDS_FP64 ? 1 : 0, r,
+                                             ctx->stream);
+                       });
 }
 
 int sbmds_get_block(sbmds_ctx *ctx, int prob, void *X, int X_mem) {

@@ -161,3 +161,12 @@ def test_stress_argument_checks_without_gpu():
     assert L.sbmds_stress(None, 4, 3, K.ctypes.data, 0, 0, out, None) == -1
     assert L.sbmds_stress(Z.ctypes.data, 4, 3, K.ctypes.data, 0, 2, out, None) == -1
     assert b"mem" in L.sbmds_last_error()
+
+
+def test_comparison_solvers_argument_checks_without_gpu():
+    # a NULL context and a bad Lanczos block are refused before any device call
+    L = sb.lib()
+    assert L.sbmds_embed_lanczos(None, 1, 10, None, None, 0, None) == -1
+    assert b"ctx is NULL" in L.sbmds_last_error()
+    assert L.sbmds_embed_bmds(None, None, None, 0, None) == -1
+    assert b"ctx is NULL" in L.sbmds_last_error()

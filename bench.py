@@ -358,6 +358,44 @@ def largest_workload(sb, torch, steps, warmup, k, block=16, learned=True, only=N
     return prob, forms, chosen, stats, training
 
 
+def eigen_routes(sb, torch, prob, k, block_ms, lam_ref=None, ref_name="stored oracle", max_steps=400):
+    """The paper's other two eigen routes (Section 3.3) on the same problem,
+    timed beside the block subspace iteration (block_ms): single-vector
+    Lanczos on the implicit operator (the paper's sBMDS), block Lanczos of
+    width 4, and BMDS (QR of the dense J P; refused where its n x l doubles
+    do not fit the device).  One call each on a fresh float32 context,
+    tol 1e-6, float64 vectors."""
+    import numpy as np
+    p = sb.Problem.from_arrays(*(torch.from_numpy(prob[x]).cuda() for x in ("rowptr", "col", "val", "W")))
+    out = {}
+    with sb.Context([p], k=k, block=16, prec=sb.FP32) as ctx:
+        Z = torch.empty((prob["n"], k), dtype=torch.float32, device="cuda")
+        runs = [("lanczos_b1", lambda: ctx.embed_lanczos(1, max_steps, Z_out=Z)),
+                ("lanczos_b4", lambda: ctx.embed_lanczos(4, max_steps // 4, Z_out=Z)),
+                ("bmds", lambda: ctx.embed_bmds(Z_out=Z))]
+        for name, fn in runs:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            try:
+                _, eig, reps, rc = fn()
+            except sb.SbmdsError as e:
+                out[name] = {"refused": str(e)}
+                log(f"eigen route {name}: {e}")
+                continue
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0)
+            r = reps[0]
+            d = {"ms": round(ms, 2), "status": rc, "steps": r["steps"], "basis": r["basis"],
+                 "eig": [float(x) for x in eig[0]], "max_err_bound": float(max(r["err_bound"][:k])),
+                 "times_block_method": round(ms / block_ms, 1)}
+            if lam_ref is not None:
+                d["rel_eig_err_vs_" + ref_name.replace(" ", "_")] = float(
+                    np.max(np.abs(eig[0] - np.asarray(lam_ref[:k])) / np.abs(np.asarray(lam_ref[:k]))))
+            out[name] = d
+            log(f"eigen route {name}: {d}")
+    return out
+
+
 def approximation_quality(sb, torch, nsample=128, reps=5):
     """The paper's quality measures as a second workload on the GPU, on a
     192 x 96 bumpy torus (n = 18,432, l = 369 FPS landmarks, the same
@@ -533,6 +571,7 @@ def sphere_workload(sb, torch, configs, args, k, blocks):
     plain fp32, bf16 -> fp32, landmark-MDS and learned starts at each block
     width; its whole working set fits the 256 MB Infinity Cache, so it is
     bound by launch latency, not HBM."""
+    import numpy as np
     prob = configs.sphere7(log=log)
     forms = {}
 
@@ -548,7 +587,7 @@ def sphere_workload(sb, torch, configs, args, k, blocks):
         for name, prec, start, wts in kinds:
             ms, eig, rep, _ = time_form(sb, torch, prob, prec, args.steps, args.warmup, k, block, start=start,
                                         tune_cache=tune_for(block), mlp_weights=wts)
-            forms[f"{name}/b{block}"] = {"ms": ms, "rep": rep, "prec": prec, "start": start, "w": wts,
+            forms[f"{name}/b{block}"] = {"ms": ms, "eig": eig, "rep": rep, "prec": prec, "start": start, "w": wts,
                                          "block": block, "first_ms": time_form.first_ms}
             log(f"sphere7 {name}/b{block} {ms:.3f} ms (first {time_form.first_ms:.2f} ms) iters "
                 f"{rep['iters_bf16']}+{rep['iters_fp32']}+{rep['iters_fp64']}")
@@ -564,6 +603,7 @@ def sphere_workload(sb, torch, configs, args, k, blocks):
         "forms_ms": {f: round(v["ms"], 4) for f, v in forms.items()},
         "first_call_ms": {f: round(v["first_ms"], 3) for f, v in forms.items()},
         "chosen": chosen, "ms": round(ch["ms"], 4), "plain_fp32_ms": round(plain, 4),
+        "eig": [float(x) for x in np.asarray(ch["eig"]).ravel()[:k]],
         "chosen_over_plain": round(plain / ch["ms"], 3),
         "iters": {"bf16": ch["rep"]["iters_bf16"], "fp32": ch["rep"]["iters_fp32"], "fp64": ch["rep"]["iters_fp64"]},
         "kernels": kernel_table(stats, args.steps),
@@ -585,6 +625,7 @@ def main():
     ap.add_argument("--no-torus", action="store_true", help="skip the 1024 x 512 torus, 10,000-landmark workload")
     ap.add_argument("--no-sphere", action="store_true", help="skip the level-7 icosphere workload")
     ap.add_argument("--no-quality", action="store_true", help="skip the approximation-quality workload")
+    ap.add_argument("--no-routes", action="store_true", help="skip the Lanczos / BMDS comparison solvers")
     ap.add_argument("--forms", type=str, default="",
                     help="comma-separated headline forms to time (default: all; plain fp32 always)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -642,6 +683,11 @@ def main():
             if err_stored > 1e-6:
                 raise RuntimeError(f"eigenvalues off the stored oracle by {err_stored:.2e}")
 
+    routes = None
+    if not args.no_routes:
+        log("the paper's other eigen routes on the headline workload")
+        routes = eigen_routes(sb, torch, prob, k, ms_fp32, lam_ref=lam if err_stored is not None else None)
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle, ARPACK route, on the headline workload)")
@@ -656,6 +702,9 @@ def main():
     if not args.no_sphere:
         log("icosphere level 7 (n = 163,842, l = 2,000)")
         sphere = sphere_workload(sb, torch, configs, args, k, blocks)
+        if not args.no_routes:
+            sphere["eigen_routes"] = eigen_routes(sb, torch, configs.sphere7(log=log), k, sphere["plain_fp32_ms"],
+                                                  lam_ref=sphere["eig"], ref_name="block method")
 
     batched = batched_full = None
     if not args.no_batch:
@@ -746,6 +795,7 @@ def main():
         "batched": batched,
         "batched_full_scale": batched_full,
         "spmm_at_scale": at_scale,
+        "eigen_routes": routes,
         "precision_workload": torus,
         "approximation_quality": quality,
     }

@@ -227,6 +227,33 @@ int sbmds_create(const sbmds_problem *probs, int nprob, const sbmds_options *opt
 int sbmds_embed(sbmds_ctx *ctx, double *eigvals, void *Z, int Z_mem, sbmds_report *reports);
 
 /*
+ * Landmarks and the landmark block W on the device (Section 3): farthest-
+ * point sampling, Eq. (FarthestPoint) -- landmarks[0] = first, then each
+ * further landmark is the vertex whose smallest geodesic distance to the
+ * landmarks chosen so far is largest (lowest vertex id on ties) -- and
+ * W = D_ll o D_ll, the squared geodesic distances between the landmarks in
+ * that order, W_ij = (d_ij^2 + d_ji^2) / 2 with d_ij the distance from
+ * landmark i to landmark j, zero diagonal (the input sbmds_create takes).
+ * Geodesic distances are shortest paths over the weighted graph (for a mesh:
+ * its edges weighted by their lengths), in float64, equal bit for bit to a
+ * textbook Dijkstra's.
+ *   rowptr, col, w  CSR of the graph: [n+1] int32, [nnz] int32, [nnz]
+ *             double; every edge stored in both directions, weights finite
+ *             and > 0, no self loops (checked on the device: SBMDS_EINVAL).
+ *   l         landmarks, 1 <= l <= min(n, 65535); first in [0, n).
+ *   landmarks [l] int32 output.
+ *   W         [l*l] row-major double output, or NULL for the landmarks only.
+ *             Entries between disconnected parts are +inf.
+ *   mem       sbmds_mem of every array.
+ *   batch     sources searched at once for W (1..256; 64 is a good default).
+ *   stream    hipStream_t (NULL = the null stream); the call synchronises it.
+ * Device memory: about 32 n bytes, plus 24 n batch + 16 l^2 bytes for W,
+ * allocated and freed by the call.
+ */
+int sbmds_landmarks_geodesic(const int32_t *rowptr, const int32_t *col, const double *w, int64_t n, int64_t l,
+                             int32_t first, int32_t *landmarks, double *W, int mem, int batch, void *stream);
+
+/*
  * The paper's other two routes to the same eigenpairs (Section 3.3), run on
  * the operator a context holds (its top precision: float64 for SBMDS_FP64,
  * float32 otherwise; vectors and products in float64), as comparison

@@ -95,7 +95,7 @@ EXPORTS = [
     "sbmds_default_options", "sbmds_create", "sbmds_embed", "sbmds_get_block",
     "sbmds_kernel_stats", "sbmds_reset_kernel_stats", "sbmds_destroy",
     "sbmds_last_error", "sbmds_version", "sbmds_approx_rows", "sbmds_stress",
-    "sbmds_embed_lanczos", "sbmds_embed_bmds",
+    "sbmds_embed_lanczos", "sbmds_embed_bmds", "sbmds_landmarks_geodesic",
     # learned warm start (include/sbmds_mlp.h)
     "sbmds_mlp_create", "sbmds_mlp_load", "sbmds_mlp_save", "sbmds_mlp_num_params", "sbmds_mlp_get_params",
     "sbmds_mlp_set_params", "sbmds_mlp_set_norm", "sbmds_mlp_features", "sbmds_mlp_forward",
@@ -152,6 +152,7 @@ def lib():
         ("sbmds_stress", [vp, i64, ci, vp, ci, ci, vp, vp], ci),
         ("sbmds_embed_lanczos", [vp, ci, ci, vp, vp, ci, ctypes.POINTER(_SolverReport)], ci),
         ("sbmds_embed_bmds", [vp, vp, vp, ci, ctypes.POINTER(_SolverReport)], ci),
+        ("sbmds_landmarks_geodesic", [vp, vp, vp, i64, i64, ctypes.c_int32, vp, vp, ci, ci, vp], ci),
     ]:
         fn = getattr(L, name)
         fn.argtypes = args
@@ -431,6 +432,30 @@ def approx_rows(rowptr, col, val, L, rows, K_rows=None, want_rows=False):
     if K_rows is None:
         return None, None, out
     return (err[0] / err[1] if err[1] > 0 else float("nan")), (err[0], err[1]), out
+
+
+def landmarks_geodesic(rowptr, col, w, l, first, want_W=True, batch=64):
+    """Farthest-point landmarks and W = D_ll o D_ll on the device
+    (sbmds_landmarks_geodesic) for the weighted graph CSR (rowptr, col, w),
+    NumPy (host) or torch CUDA tensors.  Returns (landmarks [l] int32,
+    W [l, l] float64 or None) in the same place as the inputs."""
+    n = int(rowptr.shape[0]) - 1
+    prp, mem = _ptr_any(rowptr, np.int32)
+    pci, _ = _ptr_any(col, np.int32)
+    pw, _ = _ptr_any(w, np.float64)
+    stream = None
+    if mem == MEM_DEVICE:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+        lm = torch.empty(l, dtype=torch.int32, device=rowptr.device)
+        W = torch.empty((l, l), dtype=torch.float64, device=rowptr.device) if want_W else None
+        plm, pW = lm.data_ptr(), (W.data_ptr() if want_W else None)
+    else:
+        lm = np.empty(l, dtype=np.int32)
+        W = np.empty((l, l), dtype=np.float64) if want_W else None
+        plm, pW = lm.ctypes.data, (W.ctypes.data if want_W else None)
+    _check(lib().sbmds_landmarks_geodesic(prp, pci, pw, n, l, int(first), plm, pW, mem, batch, stream))
+    return lm, W
 
 
 def stress(Z, K):

@@ -1,0 +1,474 @@
+// Landmarks and the landmark block of the geodesic distance matrix on the
+// device (Section 3): farthest-point sampling, Eq. (FarthestPoint) -- the
+// first landmark is given, each further one is the vertex whose smallest
+// distance to the landmarks chosen so far is largest (lowest vertex id on
+// ties) -- and W = D_ll o D_ll, the squared distances between landmarks,
+// averaged with its transpose, zero diagonal.
+//
+// Distances are shortest paths over the weighted graph (mesh edges with
+// their lengths), in float64.  Every search is a frontier relaxation
+// (Bellman-Ford restricted to the vertices whose distance just dropped)
+// with atomicMin on the bit patterns of non-negative doubles, which order
+// like the values.  Its result is the least fixed point of
+// d[v] = min_u fl(d[u] + w_uv), d[src] = 0, which is also what Dijkstra
+// computes (fl(x + w) is monotone in x and never below x), so the distances
+// are those of a textbook Dijkstra bit for bit.
+//
+// Farthest-point step j searches from b_j only where it lowers the running
+// minimum m[v] = min_t d(b_t, v): a relaxation whose candidate is not below
+// m[v] is dropped.  m is 1-Lipschitz along edges (m[v] <= fl(m[u] + w_uv)),
+// so a path through a vertex at or above its minimum never lowers the
+// minimum beyond it, and the kept vertices get their exact distance.  The
+// landmark block then comes from full searches, many sources at once, each
+// keeping its distances at the landmark vertices.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/sbmds.h"
+#include "sbmds_mlp_internal.h"  // api_fail
+
+namespace sbmds {
+namespace {
+
+constexpr unsigned long long kInfBits = 0x7ff0000000000000ull;  // +inf
+constexpr int kRoundGrid = 2048;                                 // blocks of a relaxation round (grid-stride)
+constexpr int kRoundsPerCheck = 4;                               // rounds launched between frontier checks
+
+__device__ inline double as_d(unsigned long long b) { return __longlong_as_double((long long)b); }
+__device__ inline unsigned long long as_b(double d) { return (unsigned long long)__double_as_longlong(d); }
+
+__global__ __launch_bounds__(256) void k_geo_fill_u64(unsigned long long *p, int64_t count, unsigned long long v) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_geo_fill_i32(int32_t *p, int64_t count, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Farthest-point sampling.  State: mind[n] (bits), dist[n] (bits, +inf
+// between steps), inq[n] (round stamp + 1 of the last queueing, 0 between
+// steps), touched list, two frontiers, three frontier counters (round r
+// reads cnt[r % 3], writes cnt[(r + 1) % 3] and clears cnt[(r + 2) % 3]).
+struct FpsState {
+    unsigned long long *mind, *dist;
+    int32_t *inq, *front[2], *touched;
+    int *cnt;       // [3] frontier sizes
+    int *tcount;    // [1] touched vertices
+    int32_t *lm;    // [l] landmarks (device)
+};
+
+// Step j: its source lm[j] enters with distance 0.
+__global__ void k_fps_begin(FpsState s, int j) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int32_t src = s.lm[j];
+    s.dist[src] = 0ull;
+    s.inq[src] = 1;
+    s.front[0][0] = src;
+    s.cnt[0] = 1;
+    s.cnt[1] = 0;
+    s.cnt[2] = 0;
+    s.touched[0] = src;
+    s.tcount[0] = 1;
+}
+
+// One relaxation round over the frontier (grid-stride over its size).
+// prune: drop candidates not below mind (farthest-point steps).
+__global__ __launch_bounds__(256) void k_fps_round(FpsState s, const int32_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ ci, const double *__restrict__ w,
+                                                   int round) {
+    const int in = round % 3, out = (round + 1) % 3, clr = (round + 2) % 3;
+    const int32_t *fin = s.front[round & 1];
+    int32_t *fout = s.front[(round + 1) & 1];
+    const int count = s.cnt[in];
+    if (blockIdx.x == 0 && threadIdx.x == 0) s.cnt[clr] = 0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < count; i += gridDim.x * 256) {
+        const int32_t u = fin[i];
+        const double du = as_d(s.dist[u]);
+        for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+            const int32_t v = ci[e];
+            const double cand = du + w[e];
+            const unsigned long long cb = as_b(cand);
+            if (cb >= s.mind[v] || cb >= s.dist[v]) continue;
+            const unsigned long long old = atomicMin(&s.dist[v], cb);
+            if (cb >= old) continue;
+            if (old == kInfBits) s.touched[atomicAdd(s.tcount, 1)] = v;
+            if (atomicExch(&s.inq[v], round + 2) != round + 2) fout[atomicAdd(&s.cnt[out], 1)] = v;
+        }
+    }
+}
+
+// After the search: mind takes the new distances, dist and inq are reset.
+__global__ __launch_bounds__(256) void k_fps_settle(FpsState s) {
+    const int count = s.tcount[0];
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < count; i += gridDim.x * 256) {
+        const int32_t v = s.touched[i];
+        const unsigned long long d = s.dist[v];
+        if (d < s.mind[v]) s.mind[v] = d;
+        s.dist[v] = kInfBits;
+        s.inq[v] = 0;
+    }
+}
+
+// Argmax of mind, lowest index on ties: per block (value, index), then one
+// block over the block results writes lm[j + 1].
+__global__ __launch_bounds__(256) void k_fps_argmax(const unsigned long long *__restrict__ mind, int64_t n,
+                                                    unsigned long long *__restrict__ bv, int64_t *__restrict__ bi) {
+    __shared__ unsigned long long sv[256];
+    __shared__ int64_t si[256];
+    unsigned long long best = 0ull;
+    int64_t idx = n;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const unsigned long long m = mind[i];
+        if (idx == n || m > best) {  // i increases, so ties keep the first
+            best = m;
+            idx = i;
+        }
+    }
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = idx;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if (threadIdx.x < h) {
+            const unsigned long long ov = sv[threadIdx.x + h];
+            const int64_t oi = si[threadIdx.x + h];
+            if (oi < n && (si[threadIdx.x] == n || ov > sv[threadIdx.x] ||
+                           (ov == sv[threadIdx.x] && oi < si[threadIdx.x]))) {
+                sv[threadIdx.x] = ov;
+                si[threadIdx.x] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        bv[blockIdx.x] = sv[0];
+        bi[blockIdx.x] = si[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fps_argmax_final(const unsigned long long *__restrict__ bv,
+                                                          const int64_t *__restrict__ bi, int nb, int64_t n,
+                                                          int32_t *__restrict__ lm, int j) {
+    __shared__ unsigned long long sv[256];
+    __shared__ int64_t si[256];
+    unsigned long long best = 0ull;
+    int64_t idx = n;
+    for (int b = threadIdx.x; b < nb; b += 256) {
+        const unsigned long long v = bv[b];
+        const int64_t i = bi[b];
+        if (i < n && (idx == n || v > best || (v == best && i < idx))) {
+            best = v;
+            idx = i;
+        }
+    }
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = idx;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if (threadIdx.x < h) {
+            const unsigned long long ov = sv[threadIdx.x + h];
+            const int64_t oi = si[threadIdx.x + h];
+            if (oi < n && (si[threadIdx.x] == n || ov > sv[threadIdx.x] ||
+                           (ov == sv[threadIdx.x] && oi < si[threadIdx.x]))) {
+                sv[threadIdx.x] = ov;
+                si[threadIdx.x] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) lm[j + 1] = (int32_t)si[0];
+}
+
+// ---------------------------------------------------------------------------
+// Full searches from S sources at once (the landmark block).  The frontier
+// holds (source slot, vertex) pairs as slot * n + vertex.
+struct MultiState {
+    unsigned long long *dist;  // [S][n]
+    int32_t *inq;              // [S][n]
+    int64_t *front[2];
+    int *cnt;                  // [3]
+};
+
+__global__ __launch_bounds__(256) void k_ms_begin(MultiState s, const int32_t *__restrict__ lm, int first, int S,
+                                                  int64_t n) {
+    const int q = threadIdx.x;
+    if (blockIdx.x != 0) return;
+    if (q < S) {
+        const int32_t src = lm[first + q];
+        s.dist[(int64_t)q * n + src] = 0ull;
+        s.inq[(int64_t)q * n + src] = 1;
+        s.front[0][q] = (int64_t)q * n + src;
+    }
+    if (q == 0) {
+        s.cnt[0] = S;
+        s.cnt[1] = 0;
+        s.cnt[2] = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ms_round(MultiState s, const int32_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ ci, const double *__restrict__ w,
+                                                  int64_t n, int round) {
+    const int in = round % 3, out = (round + 1) % 3, clr = (round + 2) % 3;
+    const int64_t *fin = s.front[round & 1];
+    int64_t *fout = s.front[(round + 1) & 1];
+    const int count = s.cnt[in];
+    if (blockIdx.x == 0 && threadIdx.x == 0) s.cnt[clr] = 0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < count; i += gridDim.x * 256) {
+        const int64_t key = fin[i];
+        const int64_t q = key / n;
+        const int32_t u = (int32_t)(key - q * n);
+        unsigned long long *dq = s.dist + q * n;
+        const double du = as_d(dq[u]);
+        for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+            const int32_t v = ci[e];
+            const unsigned long long cb = as_b(du + w[e]);
+            if (cb >= dq[v]) continue;
+            const unsigned long long old = atomicMin(&dq[v], cb);
+            if (cb >= old) continue;
+            if (atomicExch(&s.inq[q * n + v], round + 2) != round + 2) fout[atomicAdd(&s.cnt[out], 1)] = q * n + v;
+        }
+    }
+}
+
+// D[(first + q) l + t] = distance from source first + q to landmark t.
+__global__ __launch_bounds__(256) void k_ms_gather(const unsigned long long *__restrict__ dist,
+                                                   const int32_t *__restrict__ lm, int64_t n, int64_t l, int first,
+                                                   int S, double *__restrict__ D) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int q = blockIdx.y;
+    if (t >= l || q >= S) return;
+    D[(int64_t)(first + q) * l + t] = as_d(dist[(int64_t)q * n + lm[t]]);
+}
+
+// W = 1/2 (D o D + (D o D)^T), zero diagonal; each square rounded on its
+// own (no fused multiply-add), as when the squares are formed first and then
+// averaged.
+__global__ __launch_bounds__(256) void k_geo_square_sym(const double *__restrict__ D, int64_t l,
+                                                        double *__restrict__ W) {
+#pragma clang fp contract(off)
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t i = blockIdx.y;
+    if (j >= l || i >= l) return;
+    const double a = D[i * l + j], b = D[j * l + i];
+    const double a2 = a * a, b2 = b * b;
+    W[i * l + j] = i == j ? 0.0 : 0.5 * (a2 + b2);
+}
+
+// Graph checks: rowptr monotone from 0, columns in range and not the row
+// itself, weights finite and positive.  err = smallest failing row (or n).
+__global__ __launch_bounds__(256) void k_geo_check(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                   const double *__restrict__ w, int64_t n, int64_t nnz,
+                                                   unsigned long long *__restrict__ err) {
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (v >= n) return;
+    bool bad = rp[v] > rp[v + 1] || rp[v] < 0 || rp[v + 1] > nnz || (v == 0 && rp[0] != 0) ||
+               (v == n - 1 && rp[n] != nnz);
+    if (!bad)
+        for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+            const double x = w[e];
+            if (ci[e] < 0 || ci[e] >= n || ci[e] == v || !(x > 0.0) || !(x < INFINITY)) {
+                bad = true;
+                break;
+            }
+        }
+    if (bad) atomicMin(err, (unsigned long long)v);
+}
+
+#define GCHK(expr)                                                                                          \
+    do {                                                                                                    \
+        hipError_t _e = (expr);                                                                             \
+        if (_e != hipSuccess) return api_fail(SBMDS_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+struct DevMem {
+    void *p = nullptr;
+    ~DevMem() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+unsigned nblk(int64_t c) { return (unsigned)((c + 255) / 256); }
+
+// Rounds until the frontier is empty, checked every kRoundsPerCheck rounds.
+template <typename Launch>
+int run_rounds(Launch launch, const int *cnt, int *hcnt, hipStream_t s, int64_t max_rounds) {
+    int r = 0;
+    while (true) {
+        for (int q = 0; q < kRoundsPerCheck; ++q, ++r) GCHK(launch(r));
+        GCHK(hipMemcpyAsync(hcnt, cnt + (r % 3), sizeof(int), hipMemcpyDeviceToHost, s));
+        GCHK(hipStreamSynchronize(s));
+        if (*hcnt == 0) return SBMDS_OK;
+        if (r > max_rounds) return api_fail(SBMDS_EHIP, "a shortest-path search did not settle");
+    }
+}
+
+int geodesic_impl(const int32_t *rp_in, const int32_t *ci_in, const double *w_in, int64_t n, int64_t nnz, int64_t l,
+                  int32_t first, int32_t *landmarks, double *W, int mem, int batch, hipStream_t s) {
+    const bool host = mem == SBMDS_MEM_HOST;
+    const int S = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)batch, l, 256}));
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t bn8 = (size_t)n * 8, bn4 = (size_t)n * 4;
+    const size_t bS8 = (size_t)S * n * 8, bS4 = (size_t)S * n * 4;
+    const size_t bL = (size_t)l * l * 8;
+    const int nb_arg = 1024;
+    const bool want_w = W != nullptr;
+    size_t total = 2 * al(bn8) + 4 * al(bn4) + al((size_t)l * 4) + al((size_t)nb_arg * 16) + 4096;
+    if (want_w) total += al(bS8) + al(bS4) + 2 * al(bS8) + 2 * al(bL);
+    if (host) total += al((size_t)(n + 1) * 4) + al((size_t)nnz * 4) + al((size_t)nnz * 8);
+    DevMem mem_;
+    if (hipMalloc(&mem_.p, total) != hipSuccess) {
+        mem_.p = nullptr;
+        return api_fail(SBMDS_ENOMEM, "hipMalloc of " + std::to_string(total) + " bytes failed");
+    }
+    char *q = (char *)mem_.p;
+    auto take = [&](size_t b) {
+        char *r = q;
+        q += al(b);
+        return (void *)r;
+    };
+    FpsState fs;
+    fs.mind = (unsigned long long *)take(bn8);
+    fs.dist = (unsigned long long *)take(bn8);
+    fs.inq = (int32_t *)take(bn4);
+    fs.front[0] = (int32_t *)take(bn4);
+    fs.front[1] = (int32_t *)take(bn4);
+    fs.touched = (int32_t *)take(bn4);
+    fs.lm = (int32_t *)take((size_t)l * 4);
+    MultiState ms{};
+    double *D = nullptr, *Wd = nullptr;
+    if (want_w) {
+        ms.dist = (unsigned long long *)take(bS8);
+        ms.inq = (int32_t *)take(bS4);
+        ms.front[0] = (int64_t *)take(bS8);
+        ms.front[1] = (int64_t *)take(bS8);
+        D = (double *)take(bL);
+        Wd = (double *)take(bL);
+    }
+    unsigned long long *bv = (unsigned long long *)take((size_t)nb_arg * 16);
+    int64_t *bi = (int64_t *)(bv + nb_arg);
+    int *small = (int *)take(4096);
+    fs.cnt = small;
+    fs.tcount = small + 4;
+    ms.cnt = small + 8;
+    unsigned long long *derr = (unsigned long long *)(small + 16);
+    int *hcnt = nullptr;
+    std::vector<int> hc(1);
+    hcnt = hc.data();
+    const int32_t *rp = rp_in, *ci = ci_in;
+    const double *w = w_in;
+    if (host) {
+        int32_t *a = (int32_t *)take((size_t)(n + 1) * 4);
+        int32_t *b = (int32_t *)take((size_t)nnz * 4);
+        double *c = (double *)take((size_t)nnz * 8);
+        GCHK(hipMemcpyAsync(a, rp_in, (size_t)(n + 1) * 4, hipMemcpyHostToDevice, s));
+        if (nnz) GCHK(hipMemcpyAsync(b, ci_in, (size_t)nnz * 4, hipMemcpyHostToDevice, s));
+        if (nnz) GCHK(hipMemcpyAsync(c, w_in, (size_t)nnz * 8, hipMemcpyHostToDevice, s));
+        rp = a;
+        ci = b;
+        w = c;
+    }
+    // the graph is checked before it is used as an index
+    unsigned long long herr = (unsigned long long)n;
+    GCHK(hipMemcpyAsync(derr, &herr, 8, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_geo_check, dim3(nblk(n)), dim3(256), 0, s, rp, ci, w, n, nnz, derr);
+    GCHK(hipGetLastError());
+    GCHK(hipMemcpyAsync(&herr, derr, 8, hipMemcpyDeviceToHost, s));
+    GCHK(hipStreamSynchronize(s));
+    if (herr != (unsigned long long)n)
+        return api_fail(SBMDS_EINVAL, "graph row " + std::to_string(herr) +
+                                          ": bad row pointers, a column out of range or on the diagonal, or a "
+                                          "weight that is not finite and positive");
+
+    hipLaunchKernelGGL(k_geo_fill_u64, dim3(nblk(n)), dim3(256), 0, s, fs.mind, n, kInfBits);
+    hipLaunchKernelGGL(k_geo_fill_u64, dim3(nblk(n)), dim3(256), 0, s, fs.dist, n, kInfBits);
+    hipLaunchKernelGGL(k_geo_fill_i32, dim3(nblk(n)), dim3(256), 0, s, fs.inq, n, 0);
+    GCHK(hipMemcpyAsync(fs.lm, &first, 4, hipMemcpyHostToDevice, s));
+    GCHK(hipGetLastError());
+    const int64_t max_rounds = 4 * n + 64;  // a search settles within n rounds
+    for (int64_t j = 0; j < l; ++j) {
+        hipLaunchKernelGGL(k_fps_begin, dim3(1), dim3(64), 0, s, fs, (int)j);
+        GCHK(hipGetLastError());
+        auto round = [&](int r) {
+            hipLaunchKernelGGL(k_fps_round, dim3(kRoundGrid), dim3(256), 0, s, fs, rp, ci, w, r);
+            return hipGetLastError();
+        };
+        if (int rc = run_rounds(round, fs.cnt, hcnt, s, max_rounds); rc < 0) return rc;
+        hipLaunchKernelGGL(k_fps_settle, dim3(kRoundGrid), dim3(256), 0, s, fs);
+        if (j + 1 < l) {
+            const int nb = (int)std::min<int64_t>(nb_arg, nblk(n));
+            hipLaunchKernelGGL(k_fps_argmax, dim3(nb), dim3(256), 0, s, (const unsigned long long *)fs.mind, n, bv,
+                               bi);
+            hipLaunchKernelGGL(k_fps_argmax_final, dim3(1), dim3(256), 0, s, (const unsigned long long *)bv,
+                               (const int64_t *)bi, nb, n, fs.lm, (int)j);
+        }
+        GCHK(hipGetLastError());
+    }
+    // the landmark block: full searches, S sources at a time
+    if (want_w) {
+        hipLaunchKernelGGL(k_geo_fill_u64, dim3(nblk((int64_t)S * n)), dim3(256), 0, s, ms.dist, (int64_t)S * n,
+                           kInfBits);
+        hipLaunchKernelGGL(k_geo_fill_i32, dim3(nblk((int64_t)S * n)), dim3(256), 0, s, ms.inq, (int64_t)S * n, 0);
+        GCHK(hipGetLastError());
+        for (int64_t f0 = 0; f0 < l; f0 += S) {
+            const int Sb = (int)std::min<int64_t>(S, l - f0);
+            hipLaunchKernelGGL(k_ms_begin, dim3(1), dim3(256), 0, s, ms, (const int32_t *)fs.lm, (int)f0, Sb, n);
+            GCHK(hipGetLastError());
+            auto round = [&](int r) {
+                hipLaunchKernelGGL(k_ms_round, dim3(kRoundGrid), dim3(256), 0, s, ms, rp, ci, w, n, r);
+                return hipGetLastError();
+            };
+            if (int rc = run_rounds(round, ms.cnt, hcnt, s, max_rounds); rc < 0) return rc;
+            hipLaunchKernelGGL(k_ms_gather, dim3(nblk(l), (unsigned)Sb), dim3(256), 0, s,
+                               (const unsigned long long *)ms.dist, (const int32_t *)fs.lm, n, l, (int)f0, Sb, D);
+            hipLaunchKernelGGL(k_geo_fill_u64, dim3(nblk((int64_t)Sb * n)), dim3(256), 0, s, ms.dist,
+                               (int64_t)Sb * n, kInfBits);
+            hipLaunchKernelGGL(k_geo_fill_i32, dim3(nblk((int64_t)Sb * n)), dim3(256), 0, s, ms.inq,
+                               (int64_t)Sb * n, 0);
+            GCHK(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_geo_square_sym, dim3(nblk(l), (unsigned)l), dim3(256), 0, s, (const double *)D, l, Wd);
+        GCHK(hipGetLastError());
+        GCHK(hipMemcpyAsync(W, Wd, bL, host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
+    }
+    GCHK(hipMemcpyAsync(landmarks, fs.lm, (size_t)l * 4, host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
+    GCHK(hipStreamSynchronize(s));
+    return SBMDS_OK;
+}
+
+}  // namespace
+}  // namespace sbmds
+
+extern "C" int sbmds_landmarks_geodesic(const int32_t *rowptr, const int32_t *col, const double *w, int64_t n,
+                                        int64_t l, int32_t first, int32_t *landmarks, double *W, int mem, int batch,
+                                        void *stream) {
+    using namespace sbmds;
+    api_clear_error();
+    if (!rowptr || !landmarks) return api_fail(SBMDS_EINVAL, "rowptr and landmarks must be non-NULL");
+    if (mem != SBMDS_MEM_HOST && mem != SBMDS_MEM_DEVICE) return api_fail(SBMDS_EINVAL, "mem must be 0 or 1");
+    if (n < 1 || n >= ((int64_t)1 << 31)) return api_fail(SBMDS_EINVAL, "need 1 <= n < 2^31");
+    if (l < 1 || l > n || l > 65535) return api_fail(SBMDS_EINVAL, "need 1 <= l <= min(n, 65535)");
+    if (first < 0 || first >= n) return api_fail(SBMDS_EINVAL, "first landmark out of range");
+    if (batch < 1) return api_fail(SBMDS_EINVAL, "batch must be >= 1");
+    int64_t nnz = 0;
+    if (mem == SBMDS_MEM_HOST) {
+        nnz = rowptr[n];
+    } else {
+        int32_t t = 0;
+        if (hipMemcpy(&t, rowptr + n, 4, hipMemcpyDeviceToHost) != hipSuccess)
+            return api_fail(SBMDS_EHIP, "reading rowptr[n] failed");
+        nnz = t;
+    }
+    if (nnz < 0) return api_fail(SBMDS_EINVAL, "rowptr[n] < 0");
+    if (nnz > 0 && (!col || !w)) return api_fail(SBMDS_EINVAL, "col and w must be non-NULL");
+    try {
+        return geodesic_impl(rowptr, col, w, n, nnz, l, first, landmarks, W, mem, batch, (hipStream_t)stream);
+    } catch (const std::exception &e) {
+        return api_fail(SBMDS_ENOMEM, std::string("host exception: ") + e.what());
+    }
+}

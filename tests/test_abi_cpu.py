@@ -170,3 +170,18 @@ def test_comparison_solvers_argument_checks_without_gpu():
     assert b"ctx is NULL" in L.sbmds_last_error()
     assert L.sbmds_embed_bmds(None, None, None, 0, None) == -1
     assert b"ctx is NULL" in L.sbmds_last_error()
+
+
+def test_landmarks_geodesic_argument_checks_without_gpu():
+    L = sb.lib()
+    rp = np.array([0, 1, 2], np.int32)
+    ci = np.array([1, 0], np.int32)
+    w = np.ones(2)
+    lm = np.zeros(2, np.int32)
+    args = [rp.ctypes.data, ci.ctypes.data, w.ctypes.data]
+    assert L.sbmds_landmarks_geodesic(*args, 2, 3, 0, lm.ctypes.data, None, 0, 64, None) == -1
+    assert b"l <= min" in L.sbmds_last_error()
+    assert L.sbmds_landmarks_geodesic(*args, 2, 2, 2, lm.ctypes.data, None, 0, 64, None) == -1
+    assert b"first" in L.sbmds_last_error()
+    assert L.sbmds_landmarks_geodesic(*args, 2, 2, 0, lm.ctypes.data, None, 0, 0, None) == -1
+    assert b"batch" in L.sbmds_last_error()

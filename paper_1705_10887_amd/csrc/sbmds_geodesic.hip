@@ -34,11 +34,25 @@ namespace sbmds {
 namespace {
 
 constexpr unsigned long long kInfBits = 0x7ff0000000000000ull;  // +inf
-constexpr int kRoundGrid = 2048;                                 // blocks of a relaxation round (grid-stride)
+constexpr int kRoundGrid = 2048;                                 // blocks of a many-source round (grid-stride)
 constexpr int kRoundsPerCheck = 4;                               // rounds launched between frontier checks
 
 __device__ inline double as_d(unsigned long long b) { return __longlong_as_double((long long)b); }
 __device__ inline unsigned long long as_b(double d) { return (unsigned long long)__double_as_longlong(d); }
+
+// Appends x for every active lane with pred set: one atomicAdd per wave on
+// the counter, each lane at the base plus its rank among the set lanes.
+template <typename T>
+__device__ inline void wave_append(T *list, int *cnt, bool pred, T x) {
+    const unsigned long long m = __ballot(pred);
+    if (m == 0ull) return;
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(cnt, __popcll(m));
+    base = __shfl(base, leader);
+    if (pred) list[base + __popcll(m & ((1ull << lane) - 1ull))] = x;
+}
 
 __global__ __launch_bounds__(256) void k_geo_fill_u64(unsigned long long *p, int64_t count, unsigned long long v) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -52,146 +66,180 @@ __global__ __launch_bounds__(256) void k_geo_fill_i32(int32_t *p, int64_t count,
 
 // ---------------------------------------------------------------------------
 // Farthest-point sampling.  State: mind[n] (bits), dist[n] (bits, +inf
-// between steps), inq[n] (round stamp + 1 of the last queueing, 0 between
-// steps), touched list, two frontiers, three frontier counters (round r
-// reads cnt[r % 3], writes cnt[(r + 1) % 3] and clears cnt[(r + 2) % 3]).
+// between steps), inq[n] (round stamp of the last queueing, 0 between
+// steps), the touched list and two frontiers (global), the landmarks.
 struct FpsState {
     unsigned long long *mind, *dist;
     int32_t *inq, *front[2], *touched;
-    int *cnt;       // [3] frontier sizes
-    int *tcount;    // [1] touched vertices
     int32_t *lm;    // [l] landmarks (device)
+    int *err;       // [1] set when a search exceeds its round limit
+    // largest mind per chunk of kChunk vertices (value bits, lowest index of
+    // it), a dirty flag per chunk and the list of dirty chunks
+    unsigned long long *cval;
+    int64_t *cidx;
+    int32_t *cflag, *clist;
+    int64_t nchunks;
 };
 
-// Step j: its source lm[j] enters with distance 0.
-__global__ void k_fps_begin(FpsState s, int j) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int32_t src = s.lm[j];
-    s.dist[src] = 0ull;
-    s.inq[src] = 1;
-    s.front[0][0] = src;
-    s.cnt[0] = 1;
-    s.cnt[1] = 0;
-    s.cnt[2] = 0;
-    s.touched[0] = src;
-    s.tcount[0] = 1;
-}
+constexpr int kSearchThreads = 1024;
+constexpr int kSub = 8;  // threads per frontier vertex in a farthest-point search
+constexpr int kChunk = 1024;
 
-// One relaxation round over the frontier (grid-stride over its size).
-// prune: drop candidates not below mind (farthest-point steps).
-__global__ __launch_bounds__(256) void k_fps_round(FpsState s, const int32_t *__restrict__ rp,
-                                                   const int32_t *__restrict__ ci, const double *__restrict__ w,
-                                                   int round) {
-    const int in = round % 3, out = (round + 1) % 3, clr = (round + 2) % 3;
-    const int32_t *fin = s.front[round & 1];
-    int32_t *fout = s.front[(round + 1) & 1];
-    const int count = s.cnt[in];
-    if (blockIdx.x == 0 && threadIdx.x == 0) s.cnt[clr] = 0;
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < count; i += gridDim.x * 256) {
-        const int32_t u = fin[i];
-        const double du = as_d(s.dist[u]);
-        for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
-            const int32_t v = ci[e];
-            const double cand = du + w[e];
-            const unsigned long long cb = as_b(cand);
-            if (cb >= s.mind[v] || cb >= s.dist[v]) continue;
-            const unsigned long long old = atomicMin(&s.dist[v], cb);
-            if (cb >= old) continue;
-            if (old == kInfBits) s.touched[atomicAdd(s.tcount, 1)] = v;
-            if (atomicExch(&s.inq[v], round + 2) != round + 2) fout[atomicAdd(&s.cnt[out], 1)] = v;
-        }
+// (value, index) of the larger value, the lower index on ties (idx < 0: none)
+__device__ inline void better(unsigned long long &bv, int64_t &bi, unsigned long long v, int64_t i) {
+    if (i >= 0 && (bi < 0 || v > bv || (v == bv && i < bi))) {
+        bv = v;
+        bi = i;
     }
 }
 
-// After the search: mind takes the new distances, dist and inq are reset.
-__global__ __launch_bounds__(256) void k_fps_settle(FpsState s) {
-    const int count = s.tcount[0];
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < count; i += gridDim.x * 256) {
-        const int32_t v = s.touched[i];
-        const unsigned long long d = s.dist[v];
+__device__ inline void wave_best(unsigned long long &bv, int64_t &bi) {
+#pragma unroll
+    for (int sh = 32; sh >= 1; sh >>= 1) {
+        const unsigned long long ov = __shfl_xor(bv, sh);
+        const int64_t oi = __shfl_xor(bi, sh);
+        better(bv, bi, ov, oi);
+    }
+}
+
+// Initial chunk maxima: every mind is +inf, so each chunk's first vertex.
+__global__ __launch_bounds__(256) void k_fps_chunks_init(FpsState s, int64_t n) {
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= s.nchunks) return;
+    s.cval[c] = kInfBits;
+    s.cidx[c] = c * kChunk;
+    s.cflag[c] = 0;
+}
+
+template <typename T>
+__device__ inline T ld_l2(const T *p) {  // bypasses the L1 cache
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One farthest-point step in one workgroup, with no host round trip: the
+// pruned search from lm[j] in rounds over frontiers kept in global memory
+// (their sizes in LDS), then mind takes the new distances and the state of
+// the touched vertices is reset.  Data written during the search (frontier
+// entries, distances, the touched list) is read back with L1-bypassing
+// loads.
+__global__ __launch_bounds__(kSearchThreads) void k_fps_search(FpsState s, const int32_t *__restrict__ rp,
+                                                               const int32_t *__restrict__ ci,
+                                                               const double *__restrict__ w, int64_t n, int j,
+                                                               int last, int64_t max_rounds) {
+    __shared__ int cnt[2];
+    __shared__ int tcount;
+    const int tid = threadIdx.x;
+    const int32_t src = s.lm[j];
+    if (tid == 0) {
+        s.dist[src] = 0ull;
+        s.inq[src] = 1;
+        s.front[0][0] = src;
+        s.touched[0] = src;
+        cnt[0] = 1;
+        cnt[1] = 0;
+        tcount = 1;
+    }
+    __syncthreads();
+    for (int64_t round = 0;; ++round) {
+        const int in = (int)(round & 1);
+        const int count = cnt[in];
+        if (count == 0) break;  // the same for every thread (read after a barrier)
+        if (round >= max_rounds) {
+            if (tid == 0) s.err[0] = 1;
+            break;
+        }
+        const int32_t *fin = s.front[in];
+        int32_t *fout = s.front[in ^ 1];
+        const int stamp = (int)round + 2;
+        // kSub threads per frontier vertex, its edges strided over them
+        for (int base = 0; base < count; base += kSearchThreads / kSub) {
+            const int i = base + tid / kSub;
+            if (i >= count) break;
+            const int32_t u = ld_l2(fin + i);
+            const double du = as_d(ld_l2(s.dist + u));
+            for (int32_t e = rp[u] + tid % kSub; e < rp[u + 1]; e += kSub) {
+                const int32_t v = ci[e];
+                const unsigned long long cb = as_b(du + w[e]);
+                bool first = false, queue = false;
+                if (cb < s.mind[v] && cb < s.dist[v]) {
+                    const unsigned long long old = atomicMin(&s.dist[v], cb);
+                    if (cb < old) {
+                        first = old == kInfBits;
+                        queue = atomicExch(&s.inq[v], stamp) != stamp;
+                    }
+                }
+                wave_append(s.touched, &tcount, first, v);
+                wave_append(fout, &cnt[in ^ 1], queue, v);
+            }
+        }
+        __syncthreads();  // every thread has read cnt[in]: it becomes the next output count
+        if (tid == 0) cnt[in] = 0;
+        __syncthreads();
+    }
+    __shared__ int ndirty;
+    if (tid == 0) ndirty = 0;
+    __syncthreads();
+    const int tc = tcount;
+    for (int i = tid; i < tc; i += kSearchThreads) {
+        const int32_t v = ld_l2(s.touched + i);
+        const unsigned long long d = ld_l2(s.dist + v);
         if (d < s.mind[v]) s.mind[v] = d;
         s.dist[v] = kInfBits;
         s.inq[v] = 0;
+        const int32_t c = v / kChunk;
+        const bool fresh = atomicExch(&s.cflag[c], 1) == 0;
+        wave_append(s.clist, &ndirty, fresh, c);
     }
-}
-
-// Argmax of mind, lowest index on ties: per block (value, index), then one
-// block over the block results writes lm[j + 1].
-__global__ __launch_bounds__(256) void k_fps_argmax(const unsigned long long *__restrict__ mind, int64_t n,
-                                                    unsigned long long *__restrict__ bv, int64_t *__restrict__ bi) {
-    __shared__ unsigned long long sv[256];
-    __shared__ int64_t si[256];
-    unsigned long long best = 0ull;
-    int64_t idx = n;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const unsigned long long m = mind[i];
-        if (idx == n || m > best) {  // i increases, so ties keep the first
-            best = m;
-            idx = i;
+    __syncthreads();
+    // the maxima of the chunks whose minima dropped: one wave per chunk
+    const int lane = tid & 63, wave = tid >> 6, nd = ndirty;
+    for (int q = wave; q < nd; q += kSearchThreads / 64) {
+        const int32_t c = ld_l2(s.clist + q);
+        unsigned long long bv = 0ull;
+        int64_t bi = -1;
+        for (int t = lane; t < kChunk; t += 64) {
+            const int64_t v = (int64_t)c * kChunk + t;
+            if (v < n) better(bv, bi, ld_l2(s.mind + v), v);
+        }
+        wave_best(bv, bi);
+        if (lane == 0) {
+            s.cval[c] = bv;
+            s.cidx[c] = bi;
+            s.cflag[c] = 0;
         }
     }
-    sv[threadIdx.x] = best;
-    si[threadIdx.x] = idx;
     __syncthreads();
-    for (int h = 128; h >= 1; h >>= 1) {
-        if (threadIdx.x < h) {
-            const unsigned long long ov = sv[threadIdx.x + h];
-            const int64_t oi = si[threadIdx.x + h];
-            if (oi < n && (si[threadIdx.x] == n || ov > sv[threadIdx.x] ||
-                           (ov == sv[threadIdx.x] && oi < si[threadIdx.x]))) {
-                sv[threadIdx.x] = ov;
-                si[threadIdx.x] = oi;
-            }
+    // the next landmark: the largest chunk maximum
+    if (!last) {
+        __shared__ unsigned long long wv[kSearchThreads / 64];
+        __shared__ int64_t wi[kSearchThreads / 64];
+        unsigned long long bv = 0ull;
+        int64_t bi = -1;
+        for (int64_t c = tid; c < s.nchunks; c += kSearchThreads) better(bv, bi, ld_l2(s.cval + c), ld_l2(s.cidx + c));
+        wave_best(bv, bi);
+        if (lane == 0) {
+            wv[wave] = bv;
+            wi[wave] = bi;
         }
         __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        bv[blockIdx.x] = sv[0];
-        bi[blockIdx.x] = si[0];
-    }
-}
-
-__global__ __launch_bounds__(256) void k_fps_argmax_final(const unsigned long long *__restrict__ bv,
-                                                          const int64_t *__restrict__ bi, int nb, int64_t n,
-                                                          int32_t *__restrict__ lm, int j) {
-    __shared__ unsigned long long sv[256];
-    __shared__ int64_t si[256];
-    unsigned long long best = 0ull;
-    int64_t idx = n;
-    for (int b = threadIdx.x; b < nb; b += 256) {
-        const unsigned long long v = bv[b];
-        const int64_t i = bi[b];
-        if (i < n && (idx == n || v > best || (v == best && i < idx))) {
-            best = v;
-            idx = i;
+        if (tid == 0) {
+            unsigned long long v0 = 0ull;
+            int64_t i0 = -1;
+            for (int q = 0; q < kSearchThreads / 64; ++q) better(v0, i0, wv[q], wi[q]);
+            s.lm[j + 1] = (int32_t)i0;
         }
     }
-    sv[threadIdx.x] = best;
-    si[threadIdx.x] = idx;
-    __syncthreads();
-    for (int h = 128; h >= 1; h >>= 1) {
-        if (threadIdx.x < h) {
-            const unsigned long long ov = sv[threadIdx.x + h];
-            const int64_t oi = si[threadIdx.x + h];
-            if (oi < n && (si[threadIdx.x] == n || ov > sv[threadIdx.x] ||
-                           (ov == sv[threadIdx.x] && oi < si[threadIdx.x]))) {
-                sv[threadIdx.x] = ov;
-                si[threadIdx.x] = oi;
-            }
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) lm[j + 1] = (int32_t)si[0];
 }
 
 // ---------------------------------------------------------------------------
 // Full searches from S sources at once (the landmark block).  The frontier
-// holds (source slot, vertex) pairs as slot * n + vertex.
+// holds (source slot, vertex) pairs as slot << 32 | vertex.
 struct MultiState {
     unsigned long long *dist;  // [S][n]
     int32_t *inq;              // [S][n]
     int64_t *front[2];
     int *cnt;                  // [3]
+    int *last;                 // [1] last round that had a non-empty frontier
 };
 
 __global__ __launch_bounds__(256) void k_ms_begin(MultiState s, const int32_t *__restrict__ lm, int first, int S,
@@ -202,7 +250,7 @@ __global__ __launch_bounds__(256) void k_ms_begin(MultiState s, const int32_t *_
         const int32_t src = lm[first + q];
         s.dist[(int64_t)q * n + src] = 0ull;
         s.inq[(int64_t)q * n + src] = 1;
-        s.front[0][q] = (int64_t)q * n + src;
+        s.front[0][q] = ((int64_t)q << 32) | src;
     }
     if (q == 0) {
         s.cnt[0] = S;
@@ -218,20 +266,25 @@ __global__ __launch_bounds__(256) void k_ms_round(MultiState s, const int32_t *_
     const int64_t *fin = s.front[round & 1];
     int64_t *fout = s.front[(round + 1) & 1];
     const int count = s.cnt[in];
-    if (blockIdx.x == 0 && threadIdx.x == 0) s.cnt[clr] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        s.cnt[clr] = 0;
+        if (count > 0) s.last[0] = round;
+    }
     for (int i = blockIdx.x * 256 + threadIdx.x; i < count; i += gridDim.x * 256) {
         const int64_t key = fin[i];
-        const int64_t q = key / n;
-        const int32_t u = (int32_t)(key - q * n);
+        const int64_t q = key >> 32;
+        const int32_t u = (int32_t)(key & 0xffffffffll);
         unsigned long long *dq = s.dist + q * n;
         const double du = as_d(dq[u]);
         for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
             const int32_t v = ci[e];
             const unsigned long long cb = as_b(du + w[e]);
-            if (cb >= dq[v]) continue;
-            const unsigned long long old = atomicMin(&dq[v], cb);
-            if (cb >= old) continue;
-            if (atomicExch(&s.inq[q * n + v], round + 2) != round + 2) fout[atomicAdd(&s.cnt[out], 1)] = q * n + v;
+            bool queue = false;
+            if (cb < dq[v]) {
+                const unsigned long long old = atomicMin(&dq[v], cb);
+                queue = cb < old && atomicExch(&s.inq[q * n + v], round + 2) != round + 2;
+            }
+            wave_append(fout, &s.cnt[out], queue, (q << 32) | v);
         }
     }
 }
@@ -295,16 +348,25 @@ struct DevMem {
 
 unsigned nblk(int64_t c) { return (unsigned)((c + 255) / 256); }
 
-// Rounds until the frontier is empty, checked every kRoundsPerCheck rounds.
+// Rounds until the frontier is empty: first `first` rounds (one more than
+// the previous search needed, so usually a single check), then
+// kRoundsPerCheck between checks; rounds on an empty frontier do nothing.
+// *used receives the rounds that had work.
 template <typename Launch>
-int run_rounds(Launch launch, const int *cnt, int *hcnt, hipStream_t s, int64_t max_rounds) {
-    int r = 0;
+int run_rounds(Launch launch, const int *cnt, const int *last, int *hcnt, hipStream_t s, int64_t max_rounds,
+               int first, int *used) {
+    int r = 0, batch = std::max(first, kRoundsPerCheck);
     while (true) {
-        for (int q = 0; q < kRoundsPerCheck; ++q, ++r) GCHK(launch(r));
+        for (int q = 0; q < batch; ++q, ++r) GCHK(launch(r));
         GCHK(hipMemcpyAsync(hcnt, cnt + (r % 3), sizeof(int), hipMemcpyDeviceToHost, s));
+        GCHK(hipMemcpyAsync(hcnt + 1, last, sizeof(int), hipMemcpyDeviceToHost, s));
         GCHK(hipStreamSynchronize(s));
-        if (*hcnt == 0) return SBMDS_OK;
+        if (*hcnt == 0) {
+            *used = hcnt[1] + 2;
+            return SBMDS_OK;
+        }
         if (r > max_rounds) return api_fail(SBMDS_EHIP, "a shortest-path search did not settle");
+        batch = kRoundsPerCheck;
     }
 }
 
@@ -316,9 +378,10 @@ int geodesic_impl(const int32_t *rp_in, const int32_t *ci_in, const double *w_in
     const size_t bn8 = (size_t)n * 8, bn4 = (size_t)n * 4;
     const size_t bS8 = (size_t)S * n * 8, bS4 = (size_t)S * n * 4;
     const size_t bL = (size_t)l * l * 8;
-    const int nb_arg = 1024;
     const bool want_w = W != nullptr;
-    size_t total = 2 * al(bn8) + 4 * al(bn4) + al((size_t)l * 4) + al((size_t)nb_arg * 16) + 4096;
+    const int64_t nch = (n + kChunk - 1) / kChunk;
+    size_t total = 2 * al(bn8) + 4 * al(bn4) + al((size_t)l * 4) + 2 * al((size_t)nch * 8) + 2 * al((size_t)nch * 4) +
+                   4096;
     if (want_w) total += al(bS8) + al(bS4) + 2 * al(bS8) + 2 * al(bL);
     if (host) total += al((size_t)(n + 1) * 4) + al((size_t)nnz * 4) + al((size_t)nnz * 8);
     DevMem mem_;
@@ -350,15 +413,18 @@ int geodesic_impl(const int32_t *rp_in, const int32_t *ci_in, const double *w_in
         D = (double *)take(bL);
         Wd = (double *)take(bL);
     }
-    unsigned long long *bv = (unsigned long long *)take((size_t)nb_arg * 16);
-    int64_t *bi = (int64_t *)(bv + nb_arg);
+    fs.nchunks = (n + kChunk - 1) / kChunk;
+    fs.cval = (unsigned long long *)take((size_t)fs.nchunks * 8);
+    fs.cidx = (int64_t *)take((size_t)fs.nchunks * 8);
+    fs.cflag = (int32_t *)take((size_t)fs.nchunks * 4);
+    fs.clist = (int32_t *)take((size_t)fs.nchunks * 4);
     int *small = (int *)take(4096);
-    fs.cnt = small;
-    fs.tcount = small + 4;
+    fs.err = small;
     ms.cnt = small + 8;
+    ms.last = small + 12;
     unsigned long long *derr = (unsigned long long *)(small + 16);
     int *hcnt = nullptr;
-    std::vector<int> hc(1);
+    std::vector<int> hc(2);
     hcnt = hc.data();
     const int32_t *rp = rp_in, *ci = ci_in;
     const double *w = w_in;
@@ -391,24 +457,20 @@ int geodesic_impl(const int32_t *rp_in, const int32_t *ci_in, const double *w_in
     GCHK(hipMemcpyAsync(fs.lm, &first, 4, hipMemcpyHostToDevice, s));
     GCHK(hipGetLastError());
     const int64_t max_rounds = 4 * n + 64;  // a search settles within n rounds
+    int ms_rounds = kRoundsPerCheck;
+    GCHK(hipMemsetAsync(fs.err, 0, sizeof(int), s));
+    // the steps are enqueued back to back: step j + 1 reads the landmark
+    // that step j's argmax wrote on the device
+    hipLaunchKernelGGL(k_fps_chunks_init, dim3(nblk(fs.nchunks)), dim3(256), 0, s, fs, n);
     for (int64_t j = 0; j < l; ++j) {
-        hipLaunchKernelGGL(k_fps_begin, dim3(1), dim3(64), 0, s, fs, (int)j);
-        GCHK(hipGetLastError());
-        auto round = [&](int r) {
-            hipLaunchKernelGGL(k_fps_round, dim3(kRoundGrid), dim3(256), 0, s, fs, rp, ci, w, r);
-            return hipGetLastError();
-        };
-        if (int rc = run_rounds(round, fs.cnt, hcnt, s, max_rounds); rc < 0) return rc;
-        hipLaunchKernelGGL(k_fps_settle, dim3(kRoundGrid), dim3(256), 0, s, fs);
-        if (j + 1 < l) {
-            const int nb = (int)std::min<int64_t>(nb_arg, nblk(n));
-            hipLaunchKernelGGL(k_fps_argmax, dim3(nb), dim3(256), 0, s, (const unsigned long long *)fs.mind, n, bv,
-                               bi);
-            hipLaunchKernelGGL(k_fps_argmax_final, dim3(1), dim3(256), 0, s, (const unsigned long long *)bv,
-                               (const int64_t *)bi, nb, n, fs.lm, (int)j);
-        }
+        hipLaunchKernelGGL(k_fps_search, dim3(1), dim3(kSearchThreads), 0, s, fs, rp, ci, w, n, (int)j,
+                           (int)(j + 1 == l), max_rounds);
         GCHK(hipGetLastError());
     }
+    int herr_fps = 0;
+    GCHK(hipMemcpyAsync(&herr_fps, fs.err, sizeof(int), hipMemcpyDeviceToHost, s));
+    GCHK(hipStreamSynchronize(s));
+    if (herr_fps) return api_fail(SBMDS_EHIP, "a farthest-point search did not settle");
     // the landmark block: full searches, S sources at a time
     if (want_w) {
         hipLaunchKernelGGL(k_geo_fill_u64, dim3(nblk((int64_t)S * n)), dim3(256), 0, s, ms.dist, (int64_t)S * n,
@@ -423,7 +485,7 @@ int geodesic_impl(const int32_t *rp_in, const int32_t *ci_in, const double *w_in
                 hipLaunchKernelGGL(k_ms_round, dim3(kRoundGrid), dim3(256), 0, s, ms, rp, ci, w, n, r);
                 return hipGetLastError();
             };
-            if (int rc = run_rounds(round, ms.cnt, hcnt, s, max_rounds); rc < 0) return rc;
+            if (int rc = run_rounds(round, ms.cnt, ms.last, hcnt, s, max_rounds, ms_rounds, &ms_rounds); rc < 0) return rc;
             hipLaunchKernelGGL(k_ms_gather, dim3(nblk(l), (unsigned)Sb), dim3(256), 0, s,
                                (const unsigned long long *)ms.dist, (const int32_t *)fs.lm, n, l, (int)f0, Sb, D);
             hipLaunchKernelGGL(k_geo_fill_u64, dim3(nblk((int64_t)Sb * n)), dim3(256), 0, s, ms.dist,

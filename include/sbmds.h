@@ -227,6 +227,33 @@ int sbmds_create(const sbmds_problem *probs, int nprob, const sbmds_options *opt
 int sbmds_embed(sbmds_ctx *ctx, double *eigvals, void *Z, int Z_mem, sbmds_report *reports);
 
 /*
+ * The interpolation operator P of Eq. (PDefinition) built on the device from
+ * a triangle mesh (Sections 2.2 and 3.1): cotangent weights and lumped mass
+ * (or, with graph != 0, the generic-graph variant D = I, A = 0/1 edge
+ * adjacency), M = L^T D^-1 L with L = diag(A 1) - A, P_u = -M_uu^-1 M_ub by a
+ * dense Cholesky factorisation, then per column the p entries of largest
+ * magnitude (ties at the cut to the lower vertex id, exact zeros dropped;
+ * p <= 0 keeps every nonzero), and the identity rows of the landmarks.
+ *   V          [n*3] double vertex positions; 2 <= n <= 46340 (the dense
+ *              route holds M_uu: 8 n^2 bytes).
+ *   F          [nf*3] int32 triangles (distinct vertices in [0, n)).
+ *   landmarks  [l] int32 distinct vertex ids, 1 <= l < n; column j of P
+ *              belongs to landmarks[j].
+ *   rowptr, col, val  output CSR of P (n x l): [n+1] int32, [cap] int32,
+ *              [cap] double, columns ascending within a row.
+ *   cap        capacity of col and val; *nnz receives the entry count (also
+ *              when cap is too small, which returns SBMDS_EINVAL).  l + l p
+ *              (l + l (n - l) without thresholding) always suffices.
+ *   mem        sbmds_mem of every array; stream as for the other calls (the
+ *              call synchronises it).
+ * Invalid meshes or landmarks return SBMDS_EINVAL before any use of them as
+ * an index; a matrix M_uu that is not positive definite SBMDS_EBREAKDOWN.
+ */
+int sbmds_interpolation(const double *V, int64_t n, const int32_t *F, int64_t nf, const int32_t *landmarks, int64_t l,
+                        int64_t p, int graph, int32_t *rowptr, int32_t *col, double *val, int64_t cap, int64_t *nnz,
+                        int mem, void *stream);
+
+/*
  * Landmarks and the landmark block W on the device (Section 3): farthest-
  * point sampling, Eq. (FarthestPoint) -- landmarks[0] = first, then each
  * further landmark is the vertex whose smallest geodesic distance to the

@@ -95,7 +95,7 @@ EXPORTS = [
     "sbmds_default_options", "sbmds_create", "sbmds_embed", "sbmds_get_block",
     "sbmds_kernel_stats", "sbmds_reset_kernel_stats", "sbmds_destroy",
     "sbmds_last_error", "sbmds_version", "sbmds_approx_rows", "sbmds_stress",
-    "sbmds_embed_lanczos", "sbmds_embed_bmds", "sbmds_landmarks_geodesic",
+    "sbmds_embed_lanczos", "sbmds_embed_bmds", "sbmds_landmarks_geodesic", "sbmds_interpolation",
     # learned warm start (include/sbmds_mlp.h)
     "sbmds_mlp_create", "sbmds_mlp_load", "sbmds_mlp_save", "sbmds_mlp_num_params", "sbmds_mlp_get_params",
     "sbmds_mlp_set_params", "sbmds_mlp_set_norm", "sbmds_mlp_features", "sbmds_mlp_forward",
@@ -153,6 +153,7 @@ def lib():
         ("sbmds_embed_lanczos", [vp, ci, ci, vp, vp, ci, ctypes.POINTER(_SolverReport)], ci),
         ("sbmds_embed_bmds", [vp, vp, vp, ci, ctypes.POINTER(_SolverReport)], ci),
         ("sbmds_landmarks_geodesic", [vp, vp, vp, i64, i64, ctypes.c_int32, vp, vp, ci, ci, vp], ci),
+        ("sbmds_interpolation", [vp, i64, vp, i64, vp, i64, i64, ci, vp, vp, vp, i64, vp, ci, vp], ci),
     ]:
         fn = getattr(L, name)
         fn.argtypes = args
@@ -432,6 +433,28 @@ def approx_rows(rowptr, col, val, L, rows, K_rows=None, want_rows=False):
     if K_rows is None:
         return None, None, out
     return (err[0] / err[1] if err[1] > 0 else float("nan")), (err[0], err[1]), out
+
+
+def interpolation(V, F, landmarks, p=None, graph=False):
+    """P of Eq. (PDefinition) built on the device (sbmds_interpolation) from
+    the mesh (V [n, 3], F [nf, 3]) and its landmarks, thresholded to p
+    entries per column (None: unthresholded).  Host NumPy inputs and
+    outputs: returns (rowptr, col, val) of the n x l CSR."""
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    F = np.ascontiguousarray(F, dtype=np.int32)
+    lm = np.ascontiguousarray(landmarks, dtype=np.int32)
+    n, l = V.shape[0], lm.shape[0]
+    m = n - l
+    pk = 0 if p is None else int(p)
+    cap = l + l * (m if pk <= 0 or pk >= m else pk)
+    rowptr = np.empty(n + 1, dtype=np.int32)
+    col = np.empty(max(cap, 1), dtype=np.int32)
+    val = np.empty(max(cap, 1), dtype=np.float64)
+    nnz = ctypes.c_int64(0)
+    _check(lib().sbmds_interpolation(V.ctypes.data, n, F.ctypes.data, F.shape[0], lm.ctypes.data, l, pk,
+                                     1 if graph else 0, rowptr.ctypes.data, col.ctypes.data, val.ctypes.data, cap,
+                                     ctypes.byref(nnz), MEM_HOST, None))
+    return rowptr, col[:nnz.value].copy(), val[:nnz.value].copy()
 
 
 def landmarks_geodesic(rowptr, col, w, l, first, want_W=True, batch=64):

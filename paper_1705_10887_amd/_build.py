@@ -14,7 +14,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsbmds.so")
 SOURCES = ["sbmds_runtime.cpp", "sbmds_sparse.hip", "sbmds_dense.hip", "sbmds_dense_sym.hip", "sbmds_small.hip",
            "sbmds_rr.hip", "sbmds_mlp.hip", "sbmds_mlp_api.cpp", "sbmds_prep.hip",
-           "sbmds_quality.hip", "sbmds_compare.hip", "sbmds_geodesic.hip"]
+           "sbmds_quality.hip", "sbmds_compare.hip", "sbmds_geodesic.hip",
+           "sbmds_interp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

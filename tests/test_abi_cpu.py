@@ -185,3 +185,20 @@ def test_landmarks_geodesic_argument_checks_without_gpu():
     assert b"first" in L.sbmds_last_error()
     assert L.sbmds_landmarks_geodesic(*args, 2, 2, 0, lm.ctypes.data, None, 0, 0, None) == -1
     assert b"batch" in L.sbmds_last_error()
+
+
+def test_interpolation_argument_checks_without_gpu():
+    L = sb.lib()
+    V = np.zeros((4, 3))
+    F = np.array([[0, 1, 2], [1, 2, 3]], np.int32)
+    lm = np.array([0], np.int32)
+    rp = np.zeros(5, np.int32)
+    col = np.zeros(8, np.int32)
+    val = np.zeros(8)
+    nnz = ctypes.c_int64(0)
+    args = [V.ctypes.data, 4, F.ctypes.data, 2, lm.ctypes.data]
+    tail = [rp.ctypes.data, col.ctypes.data, val.ctypes.data, 8, ctypes.byref(nnz), 0, None]
+    assert L.sbmds_interpolation(*args, 4, 2, 0, *tail) == -1  # l = n
+    assert b"l < n" in L.sbmds_last_error()
+    assert L.sbmds_interpolation(V.ctypes.data, 50000, F.ctypes.data, 2, lm.ctypes.data, 1, 2, 0, *tail) == -1
+    assert b"46340" in L.sbmds_last_error()

@@ -396,6 +396,125 @@ def eigen_routes(sb, torch, prob, k, block_ms, lam_ref=None, ref_name="stored or
     return out
 
 
+def landmark_workload(sb, torch, big=True):
+    """Farthest-point landmarks and W = D_ll o D_ll on the device
+    (Eq. (FarthestPoint), Section 3), checked bit for bit against the
+    generator's output and timed beside the generator's native host code
+    (sequential pruned Dijkstra for the sampling, Dijkstra from every
+    landmark on all host threads for W): the level-7 sphere (n = 163,842,
+    l = 2,000); then the sampling alone on the 1,800 x 1,000 torus mesh
+    (n = 1.8M) with 50,000 landmarks."""
+    import numpy as np
+
+    from synth import _geodesic, configs, meshes
+    from synth import operator as op
+
+    def dev(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+    def graph(V, F):
+        G = op.edge_graph(V, F).tocsr()
+        G.sort_indices()
+        return G, [dev(G.indptr.astype(np.int32)), dev(G.indices.astype(np.int32)), dev(G.data)]
+
+    out = {}
+    prob = configs.sphere7(log=log)
+    G, arrs = graph(prob["V"], prob["F"])
+    first, l = int(prob["landmarks"][0]), prob["l"]
+    sb.landmarks_geodesic(*arrs, 8, first)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lm, _ = sb.landmarks_geodesic(*arrs, l, first, want_W=False)
+    torch.cuda.synchronize()
+    t_fps = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    lm, W = sb.landmarks_geodesic(*arrs, l, first, batch=256)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t0
+    same_lm = bool(np.array_equal(lm.cpu().numpy(), np.asarray(prob["landmarks"])))
+    same_w = bool(np.array_equal(W.cpu().numpy().astype(np.float32), prob["W"]))
+    threads = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    hlm = _geodesic.fps(G, l, first)
+    h_fps = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _geodesic.sssp_to(G, hlm, hlm, threads)
+    h_w = time.perf_counter() - t0
+    out["sphere7"] = {"n": int(G.shape[0]), "l": l, "gpu_fps_s": round(t_fps, 3), "gpu_fps_and_w_s": round(t_all, 3),
+                      "host_fps_s": round(h_fps, 3), "host_w_s": round(h_w, 3), "host_threads_w": threads,
+                      "landmarks_equal_generator": same_lm, "w_float32_equal_generator": same_w}
+    log(f"landmarks sphere7: {out['sphere7']}")
+    if not (same_lm and same_w):
+        raise RuntimeError("device landmarks / W differ from the generator's")
+    if big:
+        V, F = meshes.torus_grid(1800, 1000, 1.0, 0.4, jitter=0.01, seed=5)
+        G, arrs = graph(V, F)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lm, _ = sb.landmarks_geodesic(*arrs, 50_000, 0, want_W=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        lmh = lm.cpu().numpy()
+        out["torus_1800x1000"] = {"n": int(G.shape[0]), "l": 50_000, "gpu_fps_s": round(t, 3),
+                                  "distinct_landmarks": int(len(np.unique(lmh)))}
+        log(f"landmarks 1.8M torus: {out['torus_1800x1000']}")
+    return out
+
+
+def input_chain(sb, torch):
+    """The whole input chain on the device for the 192 x 96 bumpy torus
+    (n = 18,432, l = 369, p_row = 10): farthest-point landmarks and the
+    geodesic W (sbmds_landmarks_geodesic), then P (sbmds_interpolation:
+    cotangent assembly, dense Cholesky, thresholding), timed beside the host
+    generator (native Dijkstra on all host threads, sparse LU) and compared
+    with its output; then the k = 3 embedding from each."""
+    import numpy as np
+
+    from synth import configs, meshes
+    from synth import operator as op
+
+    V, F = meshes.bumpy_torus(192, 96, 4201)
+    n, l, seed = V.shape[0], 369, 4201
+    first = int(np.random.default_rng(seed).integers(n))
+    p = op.p_from_prow(n, l, 10)
+    G = op.edge_graph(V, F).tocsr()
+    G.sort_indices()
+    arrs = [torch.from_numpy(a).cuda() for a in (G.indptr.astype(np.int32), G.indices.astype(np.int32), G.data)]
+    Vw, Fw = meshes.torus_grid(6, 4)
+    sb.interpolation(Vw, Fw, np.array([0, 5]), p=2)  # loads the solver libraries
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lm, W = sb.landmarks_geodesic(*arrs, l, first, batch=256)
+    torch.cuda.synchronize()
+    t_lw = time.perf_counter() - t0
+    lmh = lm.cpu().numpy()
+    t0 = time.perf_counter()
+    rp, col, val = sb.interpolation(V, F, lmh, p=p)
+    t_p = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    host = configs.build_problem(V, F, l, 10, seed, np.float32)
+    t_host = time.perf_counter() - t0
+    same_lm = bool(np.array_equal(lmh, host["landmarks"]))
+    same_w = bool(np.array_equal(W.cpu().numpy(), host["W64"]))
+    Ph = host["P64"]
+    same_pattern = bool(np.array_equal(rp, Ph.indptr) and np.array_equal(col, Ph.indices))
+    p_err = float(np.max(np.abs(val - Ph.data)) / np.max(np.abs(Ph.data))) if same_pattern else None
+    eig = {}
+    for name, arrays in (("device_chain", (rp, col, val.astype(np.float32), W.cpu().numpy().astype(np.float32))),
+                         ("host_chain", (host["rowptr"], host["col"], host["val"], host["W"]))):
+        _, e, _ = sb.embed(*arrays, k=3, block=16, prec=sb.FP32)
+        eig[name] = [float(x) for x in np.asarray(e).ravel()[:3]]
+    rel = float(np.max(np.abs(np.array(eig["device_chain"]) - np.array(eig["host_chain"])) /
+                       np.abs(np.array(eig["host_chain"]))))
+    out = {"workload": f"bumpy torus 192 x 96 (n={n}), l={l} FPS landmarks, p_row=10 (p={p}), nnz(P)={len(col)}",
+           "gpu_landmarks_and_w_s": round(t_lw, 3), "gpu_p_s": round(t_p, 3),
+           "host_generator_s": round(t_host, 3), "landmarks_equal": same_lm, "w_equal": same_w,
+           "p_pattern_equal": same_pattern, "p_max_rel_diff": p_err, "eigvals": eig,
+           "eig_rel_diff_device_vs_host_chain": rel}
+    log(f"input chain: {out}")
+    return out
+
+
 def approximation_quality(sb, torch, nsample=128, reps=5):
     """The paper's quality measures as a second workload on the GPU, on a
     192 x 96 bumpy torus (n = 18,432, l = 369 FPS landmarks, the same
@@ -626,6 +745,7 @@ def main():
     ap.add_argument("--no-sphere", action="store_true", help="skip the level-7 icosphere workload")
     ap.add_argument("--no-quality", action="store_true", help="skip the approximation-quality workload")
     ap.add_argument("--no-routes", action="store_true", help="skip the Lanczos / BMDS comparison solvers")
+    ap.add_argument("--no-landmarks", action="store_true", help="skip the device landmark / W workload")
     ap.add_argument("--forms", type=str, default="",
                     help="comma-separated headline forms to time (default: all; plain fp32 always)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -730,6 +850,12 @@ def main():
         at_scale = {pat: spmm_at_scale(sb, torch, args.steps, pat) for pat in ("banded", "random")}
         log(f"at scale {at_scale}")
 
+    landmarks = None
+    if not args.no_landmarks:
+        log("landmarks and W on the device (farthest-point sampling, geodesic W)")
+        landmarks = landmark_workload(sb, torch)
+        landmarks["input_chain"] = input_chain(sb, torch)
+
     quality = None
     if not args.no_quality:
         log("approximation quality (Section 4.1): eps on sampled rows, p_row sweep")
@@ -798,6 +924,7 @@ def main():
         "eigen_routes": routes,
         "precision_workload": torus,
         "approximation_quality": quality,
+        "landmarks_geodesic": landmarks,
     }
     print(json.dumps(out), flush=True)
 

@@ -90,42 +90,66 @@ def time_form(sb, torch, prob, prec, steps, warmup, k, block, flags=0, start=Non
     return ms, eig[0], reps[0], stats
 
 
-def time_batch(sb, torch, probs, k, block, steps, warmup, tune_cache, workload=None):
+def time_batch(sb, torch, probs, k, block, steps, warmup, tune_cache, workload=None, details=False):
     """ms per certified solve of all meshes in one context (every launch
-    covers every mesh) and of the same meshes one context each."""
+    covers every mesh) and of the same meshes one context each.  With
+    `details`: the per-kernel table of the batched context (HIP-event
+    timing, algorithmic bytes) and the per-mesh iteration counts."""
     dev = [{x: torch.from_numpy(p[x]).cuda() for x in ("rowptr", "col", "val", "W")} for p in probs]
     ntot = sum(p["n"] for p in probs)
+    info = {}
 
-    def run(groups):
+    def run(groups, flags=0):
         ctxs, outs = [], []
+        t_create = time.perf_counter()
         for g in groups:
             ps = [sb.Problem.from_arrays(dev[i]["rowptr"], dev[i]["col"], dev[i]["val"], dev[i]["W"]) for i in g]
-            ctxs.append(sb.Context(ps, k=k, block=block, prec=sb.FP32, tune_cache=tune_cache))
+            ctxs.append(sb.Context(ps, k=k, block=block, prec=sb.FP32, tune_cache=tune_cache, flags=flags))
             outs.append(torch.empty((sum(probs[i]["n"] for i in g), k), dtype=torch.float32, device="cuda"))
+        torch.cuda.synchronize()
+        info["create_ms"] = round(1e3 * (time.perf_counter() - t_create), 1)
         for _ in range(warmup):
             for c, z in zip(ctxs, outs):
                 c.embed(Z_out=z)
+        for c in ctxs:
+            c.reset_kernel_stats()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        reps = []
         for _ in range(steps):
+            reps = []
             for c, z in zip(ctxs, outs):
-                _, _, reps, rc = c.embed(Z_out=z)
+                _, _, r, rc = c.embed(Z_out=z)
                 if rc != 0:
                     raise RuntimeError("a batched mesh did not certify")
+                reps += r
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / steps
+        info["reps"] = reps
+        info["stats"] = ctxs[0].kernel_stats() if flags else None
         for c in ctxs:
             c.close()
         return ms
 
     ms_batch = run([list(range(len(probs)))])
-    ms_single = run([[i] for i in range(len(probs))])
-    return {"meshes": len(probs), "vertices": ntot, "ms": round(ms_batch, 3),
-            "meshes_per_s": round(len(probs) / (ms_batch * 1e-3), 1),
-            "vertices_per_s": round(ntot / (ms_batch * 1e-3), 1),
-            "ms_one_context_per_mesh": round(ms_single, 3), "dtype": "f32",
-            "workload": workload or "16 meshes, n ~ U[2000, 20000] (bumpy tori and deformed geodesic spheres), "
-                                    "l = n/50, p_row = 10, k = 3, fp32 -> f64 certify"}
+    create_batch = info["create_ms"]
+    out = {"meshes": len(probs), "vertices": ntot, "ms": round(ms_batch, 3),
+           "meshes_per_s": round(len(probs) / (ms_batch * 1e-3), 1),
+           "vertices_per_s": round(ntot / (ms_batch * 1e-3), 1), "create_ms": create_batch,
+           "dtype": "f32", "launch_shapes": "autotuned at create" if tune_cache else "default",
+           "workload": workload or "16 meshes, n ~ U[2000, 20000] (bumpy tori and deformed geodesic spheres), "
+                                   "l = n/50, p_row = 10, k = 3, fp32 -> f64 certify"}
+    if details:
+        its = [r["iters_bf16"] + r["iters_fp32"] + r["iters_fp64"] for r in info["reps"]]
+        hist = {}
+        for v in its:
+            hist[str(v)] = hist.get(str(v), 0) + 1
+        out["iterations_per_mesh"] = {"min": min(its), "max": max(its), "mean": round(sum(its) / len(its), 2),
+                                      "histogram": hist}
+        run([list(range(len(probs)))], flags=sb.FLAG_KERNEL_TIMING)
+        out["kernels"] = kernel_table(info["stats"], steps)
+    out["ms_one_context_per_mesh"] = round(run([[i] for i in range(len(probs))]), 3)
+    return out
 
 
 FORM_NAMES = {
@@ -835,12 +859,14 @@ def main():
         from synth import large
         log("batched workload at full scale: 256 synthetic grid tori")
         probs256 = large.grid_torus_batch()
-        batched_full = time_batch(sb, torch, probs256, k, blocks[0], max(1, min(args.steps, 3)), 1, None,
+        batched_full = time_batch(sb, torch, probs256, k, blocks[0], max(1, min(args.steps, 3)), 1,
+                                  os.path.join(configs.cache_dir(), f"tune_batch256_k{k}_b{blocks[0]}.txt"),
+                                  details=True,
                                   workload="256 synthetic grid-torus meshes, n ~ U[2000, 200000] "
                                            f"({sum(p['n'] for p in probs256)} vertices, "
                                            f"{sum(p['l'] for p in probs256)} landmarks, "
                                            f"{sum(len(p['col']) for p in probs256)} stored entries), l ~ n/50, "
-                                           "10 entries per row, k = 3, fp32 -> f64 certify, default launch shapes")
+                                           "10 entries per row, k = 3, fp32 -> f64 certify")
         del probs256
         log(f"batched full {batched_full}")
 

@@ -87,6 +87,16 @@ typedef enum { SBMDS_MEM_HOST = 0, SBMDS_MEM_DEVICE = 1 } sbmds_mem;
  * matrix). */
 #define SBMDS_FLAG_PACK_W 0x8u        /* pack W whatever its size */
 #define SBMDS_FLAG_FULL_W 0x10u       /* never pack W */
+/* The transposed product P^T Y gathers, for each landmark row, the rows of
+ * Y of its vertices.  With this flag it runs in its push form instead where
+ * that applies (block widths 8, 16 and 32, and vertex blocks that touch few
+ * landmarks: at least 4 entries per block-landmark pair): blocks of 256
+ * vertices read their rows of Y once and write one partial row per landmark
+ * they touch, and a second pass adds those per landmark in block order.  It
+ * costs a second copy of P's values at sbmds_create and moves 2 B words per
+ * block-landmark pair; it is slower than the gathering form on meshes whose
+ * vertex order is not blocked in two dimensions. */
+#define SBMDS_FLAG_PUSH_T 0x20u
 
 /*
  * One problem (mesh).  Arrays live in host or device memory according to

@@ -21,7 +21,7 @@ import numpy as np
 __all__ = [
     "FP64", "FP32", "BF16_FP32",
     "START_RANDOM", "START_LMDS", "START_LEARNED", "START_USER",
-    "FLAG_KERNEL_TIMING", "FLAG_NO_GRAPH", "FLAG_NO_CERTIFY", "FLAG_PACK_W", "FLAG_FULL_W",
+    "FLAG_KERNEL_TIMING", "FLAG_NO_GRAPH", "FLAG_NO_CERTIFY", "FLAG_PACK_W", "FLAG_FULL_W", "FLAG_PUSH_T",
     "SbmdsError", "Problem", "Context", "embed", "approx_rows", "lib", "lib_path", "version",
 ]
 
@@ -29,7 +29,7 @@ FP64, FP32, BF16_FP32 = 0, 1, 2
 START_RANDOM, START_LMDS, START_LEARNED, START_USER = 0, 1, 2, 3
 MEM_HOST, MEM_DEVICE = 0, 1
 FLAG_KERNEL_TIMING, FLAG_NO_GRAPH, FLAG_NO_CERTIFY = 0x1, 0x2, 0x4
-FLAG_PACK_W, FLAG_FULL_W = 0x8, 0x10
+FLAG_PACK_W, FLAG_FULL_W, FLAG_PUSH_T = 0x8, 0x10, 0x20
 MAX_BLOCK = 64
 
 _STATUS = {0: "OK", 1: "ENOCONV", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENODEV", -5: "EBREAKDOWN"}

@@ -104,6 +104,13 @@ struct DevProblem {
     double *red_spmm = nullptr;  // Gram/column-sum partials per block and tree levels
     unsigned *tile_cnt = nullptr, *gemm_cnt = nullptr, *spmm_cnt = nullptr;
     int max_rowtiles = 0, max_ksplit = 0, max_spmm_blocks = 0;
+    // push form of the transposed product (see prep_push_*), or pb == NULL
+    int32_t *pb = nullptr, *pe = nullptr, *qp = nullptr, *ql = nullptr;
+    uint8_t *pvl = nullptr;
+    void *pval[NUM_MODES] = {};  // values in pair order per mode
+    void *ppart = nullptr;       // [npairs][B] partial rows (8-byte elements)
+    int64_t npairs = 0;
+    int nvb = 0;                 // vertex blocks
     SolveState *st = nullptr;
     const void *X0 = nullptr;    // device copy of a user start block
     std::vector<int32_t> lperm;  // internal landmark order: internal j is caller's landmark lperm[j]
@@ -153,6 +160,11 @@ struct ProbView {
     int gemm_ksplit[NUM_MODES];
     int gemm_kchunk[NUM_MODES];
     int sym_c[NUM_MODES];  // region width (tiles) of the packed dense product
+    // push form of the transposed product
+    const int32_t *pb, *pe, *qp, *ql;
+    const uint8_t *pvl;
+    const void *pval[NUM_MODES];
+    void *ppart;
 };
 
 // Block-to-problem tables: for each kind of launch and mode, off[p] is the
@@ -160,7 +172,9 @@ struct ProbView {
 enum BlockKind {
     BK_SPMM = 0, BK_SPMMT = 1, BK_GEMM = 2, BK_ELEM_NB = 3, BK_ELEM_N = 4, BK_ELEM_LB = 5,
     BK_GEMMF = 6,  // 64-row tiles of U (finish launch of the packed dense product)
-    NUM_BK = 7
+    BK_PUSH = 7,   // vertex blocks of the push-form transposed product
+    BK_PUSHR = 8,  // landmark groups of its reduction
+    NUM_BK = 9
 };
 
 // Host handle of a batch: every launch covers all problems of a context.
@@ -172,6 +186,7 @@ struct Batch {
     int gemm_mfma[NUM_MODES] = {};             // dense product on the matrix cores
     int gemm_sym[NUM_MODES] = {};              // dense product from the packed upper triangle of W
     int spmm_wpe8[NUM_MODES] = {};             // row-split SpMM in its two-blocks-per-CU form
+    int spmmt_push[NUM_MODES] = {};            // transposed SpMM in its push form
     ProbView *views = nullptr;   // device [nprob]
     int *offs = nullptr;         // device [NUM_BK][NUM_MODES][nprob + 1]
     int total[NUM_BK][NUM_MODES] = {};
@@ -183,6 +198,10 @@ struct Batch {
 // the launch.  Kernels of an iteration skip problems whose schedule is not
 // in `phase`.
 hipError_t launch_spmm_t(Mode m, const Batch &bt, int phase, hipStream_t stream);
+// The push form applies to widths 8, 16 and 32; landmarks per block of its
+// reduction in mode m.
+bool spmmt_push_width(int B);
+int spmmt_push_rows(Mode m, int B);
 hipError_t launch_gemm(Mode m, const Batch &bt, int phase, hipStream_t stream);
 // rr = 1 (2): the SpMM also runs the iteration's Rayleigh-Ritz step (the
 // start's CholQR) in the block that completes its Gram reduction; only for

@@ -52,4 +52,27 @@ hipError_t prep_operator(const PrepIn &in, const PrepOut &out, void *tmp, size_t
 // Scratch bytes prep_operator needs for nnz entries.
 size_t prep_tmp_bytes(int64_t nnz, bool fp64);
 
+// The push form of the transposed product (T = P^T Y by vertex blocks of
+// kPushVB rows): entries of P grouped by (vertex block, column, vertex);
+// each distinct (block, column) is a "pair" whose partial row one block
+// writes and the reduction sums per column in block order.
+constexpr int kPushVB = 256;
+struct PushOut {
+    int32_t *pb;    // [nvb + 1] first pair of each vertex block
+    int32_t *pe;    // [npairs + 1] first entry of each pair
+    uint8_t *pvl;   // [nnz] vertex within its block, per entry in pair order
+    int32_t *qp;    // [l + 1] first reduction item of each column
+    int32_t *ql;    // [npairs] pairs of each column, in block order
+    void *pv;       // [nnz] values in pair order (element size esz)
+    void *pv16;     // [nnz] bfloat16 values in pair order, or NULL
+};
+// Scratch bytes of the push-form preparation; its first phase sorts the
+// entries and returns the pair count (the stream is synchronised), the
+// second fills PushOut from the same scratch.
+size_t prep_push_tmp_bytes(int64_t nnz);
+hipError_t prep_push_pairs(const int32_t *rp, const int32_t *ci, int64_t n, int64_t l, int64_t nnz, void *tmp,
+                           size_t tmp_bytes, int64_t *npairs, hipStream_t s);
+hipError_t prep_push_fill(int64_t n, int64_t l, int64_t nnz, int64_t npairs, const void *val, int esz,
+                          const void *val16, const PushOut &out, void *tmp, size_t tmp_bytes, hipStream_t s);
+
 }  // namespace sbmds

@@ -6,6 +6,8 @@
 // leave the device; only per-level landmark labels travel to the host.
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
+
 #include "sbmds_common.h"
 #include "sbmds_prep.h"
 
@@ -256,6 +258,192 @@ size_t prep_tmp_bytes(int64_t nnz, bool fp64) {
     }
     (void)fp64;
     return 32 * (size_t)nnz + 256 + sort_bytes + 256;  // three key arrays, two index arrays, the sort
+}
+
+// ---------------------------------------------------------------------------
+// Push form of the transposed product.  Scratch layout: key, sorted key,
+// index, sorted index (nnz each), head / pair id (nnz each), the sort's work
+// area; a second key array for the reduction lists reuses the first two.
+
+namespace {
+
+struct PushTmp {
+    unsigned long long *key, *key2;
+    int32_t *idx, *idx2, *head, *pid;
+    char *sort;
+    size_t sort_bytes;
+};
+
+PushTmp push_tmp(void *tmp, size_t tmp_bytes, int64_t nnz) {
+    PushTmp t{};
+    char *q = (char *)tmp;
+    auto take = [&](size_t b) {
+        char *r = q;
+        q += (b + 255) & ~(size_t)255;
+        return r;
+    };
+    t.key = (unsigned long long *)take(8 * (size_t)nnz);
+    t.key2 = (unsigned long long *)take(8 * (size_t)nnz);
+    t.idx = (int32_t *)take(4 * (size_t)nnz);
+    t.idx2 = (int32_t *)take(4 * (size_t)nnz);
+    t.head = (int32_t *)take(4 * (size_t)nnz);
+    t.pid = (int32_t *)take(4 * (size_t)nnz);
+    t.sort = q;
+    const size_t used = (size_t)(q - (char *)tmp);
+    t.sort_bytes = used <= tmp_bytes ? tmp_bytes - used : 0;
+    return t;
+}
+
+int key_bits(unsigned long long maxkey) {
+    int b = 1;
+    while (b < 64 && (maxkey >> b) != 0) ++b;
+    return b;
+}
+
+// key = (block * l + column) * kPushVB + vertex within block, per entry.
+__global__ __launch_bounds__(256) void k_push_keys(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                   int64_t n, int64_t l, unsigned long long *__restrict__ key,
+                                                   int32_t *__restrict__ idx) {
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (v >= n) return;
+    const unsigned long long blk = (unsigned long long)(v / kPushVB), w = (unsigned long long)(v % kPushVB);
+    for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+        key[e] = (blk * (unsigned long long)l + (unsigned long long)ci[e]) * kPushVB + w;
+        idx[e] = e;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_push_heads(const unsigned long long *__restrict__ key, int64_t nnz,
+                                                    int32_t *__restrict__ head) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nnz) return;
+    head[i] = (i == 0 || key[i] / kPushVB != key[i - 1] / kPushVB) ? 1 : 0;
+}
+
+// Per entry in pair order: vertex within block and value(s); per pair its
+// first entry; the reduction key (column * nvb + block) and pair id.
+template <typename T>
+__global__ __launch_bounds__(256) void k_push_fill(const unsigned long long *__restrict__ key,
+                                                   const int32_t *__restrict__ idx, const int32_t *__restrict__ head,
+                                                   const int32_t *__restrict__ pid, int64_t nnz, int64_t l,
+                                                   int64_t nvb, const T *__restrict__ val,
+                                                   const bf16_t *__restrict__ val16, uint8_t *__restrict__ pvl,
+                                                   T *__restrict__ pv, bf16_t *__restrict__ pv16,
+                                                   int32_t *__restrict__ pe, unsigned long long *__restrict__ rkey,
+                                                   int32_t *__restrict__ rval) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nnz) return;
+    const unsigned long long k = key[i];
+    pvl[i] = (uint8_t)(k % kPushVB);
+    pv[i] = val[idx[i]];
+    if (pv16) pv16[i] = val16[idx[i]];
+    if (head[i]) {
+        const int64_t q = pid[i] - 1;
+        const unsigned long long bc = k / kPushVB;  // block * l + column
+        pe[q] = (int32_t)i;
+        rkey[q] = (bc % (unsigned long long)l) * (unsigned long long)nvb + bc / (unsigned long long)l;
+        rval[q] = (int32_t)q;
+    }
+    if (i == nnz - 1) pe[pid[i]] = (int32_t)nnz;
+}
+
+// Row pointers (nrows + 1) of sorted keys, row = key / div.
+__global__ __launch_bounds__(256) void k_push_rowptr(const unsigned long long *__restrict__ key, int64_t count,
+                                                     unsigned long long div, int64_t nrows, int32_t *__restrict__ rp) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i > count) return;
+    const int64_t r = i < count ? (int64_t)(key[i] / div) : nrows;
+    const int64_t rprev = i > 0 ? (int64_t)(key[i - 1] / div) : -1;
+    for (int64_t q = rprev + 1; q <= r; ++q) rp[q] = (int32_t)i;
+}
+
+// Pair p's vertex block: pb from the pair keys block * l + column.
+__global__ __launch_bounds__(256) void k_push_pair_keys(const unsigned long long *__restrict__ rkey, int64_t npairs,
+                                                        int64_t nvb, unsigned long long *__restrict__ bkey) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= npairs) return;
+    bkey[q] = rkey[q] % (unsigned long long)nvb;  // pairs are already in (block, column) order
+}
+
+}  // namespace
+
+size_t prep_push_tmp_bytes(int64_t nnz) {
+    size_t sort_bytes = 0;
+    if (nnz > 0) {
+        unsigned long long *k = nullptr;
+        int32_t *v = nullptr;
+        (void)hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, k, k, v, v, (int)nnz, 0, 64, (hipStream_t)0);
+    }
+    size_t inclusive = 0;
+    if (nnz > 0) {
+        int32_t *a = nullptr;
+        (void)hipcub::DeviceScan::InclusiveSum(nullptr, inclusive, a, a, (int)nnz, (hipStream_t)0);
+    }
+    return 32 * (size_t)nnz + 6 * 256 + std::max(sort_bytes, inclusive) + 256;
+}
+
+hipError_t prep_push_pairs(const int32_t *rp, const int32_t *ci, int64_t n, int64_t l, int64_t nnz, void *tmp,
+                           size_t tmp_bytes, int64_t *npairs, hipStream_t s) {
+    *npairs = 0;
+    if (nnz <= 0) return hipSuccess;
+    PushTmp t = push_tmp(tmp, tmp_bytes, nnz);
+    const int64_t nvb = (n + kPushVB - 1) / kPushVB;
+    hipLaunchKernelGGL(k_push_keys, dim3(blocks(n)), dim3(256), 0, s, rp, ci, n, l, t.key, t.idx);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int bits = key_bits((unsigned long long)nvb * (unsigned long long)l * kPushVB);
+    size_t sb = t.sort_bytes;
+    e = hipcub::DeviceRadixSort::SortPairs(t.sort, sb, t.key, t.key2, t.idx, t.idx2, (int)nnz, 0, bits, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_push_heads, dim3(blocks(nnz)), dim3(256), 0, s, (const unsigned long long *)t.key2, nnz,
+                       t.head);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    sb = t.sort_bytes;
+    e = hipcub::DeviceScan::InclusiveSum(t.sort, sb, t.head, t.pid, (int)nnz, s);
+    if (e != hipSuccess) return e;
+    int32_t h = 0;
+    if ((e = hipMemcpyAsync(&h, t.pid + nnz - 1, 4, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    *npairs = h;
+    return hipSuccess;
+}
+
+hipError_t prep_push_fill(int64_t n, int64_t l, int64_t nnz, int64_t npairs, const void *val, int esz,
+                          const void *val16, const PushOut &out, void *tmp, size_t tmp_bytes, hipStream_t s) {
+    if (nnz <= 0) return hipSuccess;
+    PushTmp t = push_tmp(tmp, tmp_bytes, nnz);
+    const int64_t nvb = (n + kPushVB - 1) / kPushVB;
+    // the reduction keys and pair ids reuse key / idx (free after the sort)
+    unsigned long long *rkey = t.key;
+    int32_t *rval = t.idx;
+    if (esz == 8)
+        hipLaunchKernelGGL((k_push_fill<double>), dim3(blocks(nnz)), dim3(256), 0, s,
+                           (const unsigned long long *)t.key2, (const int32_t *)t.idx2, (const int32_t *)t.head,
+                           (const int32_t *)t.pid, nnz, l, nvb, (const double *)val, (const bf16_t *)val16, out.pvl,
+                           (double *)out.pv, (bf16_t *)out.pv16, out.pe, rkey, rval);
+    else
+        hipLaunchKernelGGL((k_push_fill<float>), dim3(blocks(nnz)), dim3(256), 0, s,
+                           (const unsigned long long *)t.key2, (const int32_t *)t.idx2, (const int32_t *)t.head,
+                           (const int32_t *)t.pid, nnz, l, nvb, (const float *)val, (const bf16_t *)val16, out.pvl,
+                           (float *)out.pv, (bf16_t *)out.pv16, out.pe, rkey, rval);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // vertex-block ranges of the pairs: the block of pair q is rkey[q] % nvb
+    unsigned long long *bkey = t.key2;  // sorted entry keys are no longer needed
+    hipLaunchKernelGGL(k_push_pair_keys, dim3(blocks(npairs)), dim3(256), 0, s, (const unsigned long long *)rkey,
+                       npairs, nvb, bkey);
+    hipLaunchKernelGGL(k_push_rowptr, dim3(blocks(npairs + 1)), dim3(256), 0, s, (const unsigned long long *)bkey,
+                       npairs, 1ull, nvb, out.pb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // reduction lists: pairs by (column, block)
+    unsigned long long *rkey2 = (unsigned long long *)t.head;  // head + pid: 8 nnz bytes >= 8 npairs
+    const int bits = key_bits((unsigned long long)l * (unsigned long long)nvb);
+    size_t sb = t.sort_bytes;
+    e = hipcub::DeviceRadixSort::SortPairs(t.sort, sb, rkey, rkey2, rval, out.ql, (int)npairs, 0, bits, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_push_rowptr, dim3(blocks(npairs + 1)), dim3(256), 0, s, (const unsigned long long *)rkey2,
+                       npairs, (unsigned long long)nvb, l, out.qp);
+    return hipGetLastError();
 }
 
 template hipError_t prep_validate<float>(const int32_t *, const int32_t *, const void *, const void *, int64_t,

@@ -1005,6 +1005,53 @@ int landmark_order(sbmds_ctx *ctx, const T *dW, int64_t l, std::vector<int32_t> 
 // permuted and padded), the per-precision copies.  Host inputs were
 // validated on the host and are uploaded first; device inputs are validated
 // by kernels and never leave the device.
+// The push form of the transposed product (SBMDS_FLAG_PUSH_T: vertex blocks
+// scatter partial rows per landmark, a reduction adds them in block order)
+// where the blocks touch few landmarks each: at least kPushMinEntries entries
+// per (block, landmark) pair on average, else the row-gather form stays.
+constexpr double kPushMinEntries = 4.0;
+
+int build_push(sbmds_ctx *ctx, DevProblem &p, bool fp64, bool bf) {
+    hipStream_t s = ctx->stream;
+    const int64_t n = p.n, l = p.l, nnz = p.nnz;
+    if (nnz <= 0 || nnz >= ((int64_t)1 << 31)) return SBMDS_OK;
+    DevTmp tmp;
+    const size_t tb = prep_push_tmp_bytes(nnz);
+    OKCHK(tmp.alloc(tb));
+    int64_t npairs = 0;
+    HIPCHK(prep_push_pairs(p.rp, p.ci, n, l, nnz, tmp.p, tb, &npairs, s));
+    if (npairs <= 0 || (double)nnz < kPushMinEntries * (double)npairs) return SBMDS_OK;
+    const int64_t nvb = (n + kPushVB - 1) / kPushVB;
+    PushOut po{};
+    const int esz = fp64 ? 8 : 4;
+    OKCHK(dalloc(ctx, (void **)&po.pb, (nvb + 1) * 4));
+    OKCHK(dalloc(ctx, (void **)&po.pe, (npairs + 1) * 4));
+    OKCHK(dalloc(ctx, (void **)&po.pvl, nnz));
+    OKCHK(dalloc(ctx, (void **)&po.qp, (l + 1) * 4));
+    OKCHK(dalloc(ctx, (void **)&po.ql, npairs * 4));
+    OKCHK(dalloc(ctx, &po.pv, nnz * esz));
+    if (bf) OKCHK(dalloc(ctx, &po.pv16, nnz * 2));
+    OKCHK(dalloc(ctx, &p.ppart, (size_t)npairs * p.B * 8));
+    const void *val = fp64 ? p.val[MODE_FP64] : p.val[MODE_FP32];
+    HIPCHK(prep_push_fill(n, l, nnz, npairs, val, esz, bf ? p.val[MODE_BF16] : nullptr, po, tmp.p, tb, s));
+    HIPCHK(hipStreamSynchronize(s));  // the scratch goes when this returns
+    p.pb = po.pb;
+    p.pe = po.pe;
+    p.pvl = po.pvl;
+    p.qp = po.qp;
+    p.ql = po.ql;
+    p.npairs = npairs;
+    p.nvb = (int)nvb;
+    if (fp64) {
+        p.pval[MODE_FP64] = po.pv;
+    } else {
+        p.pval[MODE_FP32] = po.pv;
+        p.pval[MODE_F64ACC] = po.pv;
+        if (bf) p.pval[MODE_BF16] = po.pv16;
+    }
+    return SBMDS_OK;
+}
+
 template <typename T>
 int prepare_problem(sbmds_ctx *ctx, const sbmds_problem &in, DevProblem &p, bool fp64, int idx) {
     const int64_t n = p.n, l = p.l, nnz = p.nnz;
@@ -1096,9 +1143,15 @@ int prepare_problem(sbmds_ctx *ctx, const sbmds_problem &in, DevProblem &p, bool
             p.c[MODE_BF16] = (double *)c16;
         }
     }
+    if ((ctx->opt.flags & SBMDS_FLAG_PUSH_T) && spmmt_push_width(p.B)) OKCHK(build_push(ctx, p, fp64, bf));
     // the scratch is released when this returns: the stream must be done with it
     HIPCHK(hipStreamSynchronize(s));
     return SBMDS_OK;
+}
+
+// Whether problem p runs the transposed product of mode m in its push form.
+bool push_form(const Batch &bt, const DevProblem &p, int m) {
+    return bt.spmmt_push[m] && p.pb != nullptr && p.pval[m] != nullptr;
 }
 
 // Launch tables of the context: one view per problem and, per kind of
@@ -1119,6 +1172,11 @@ int build_batch(sbmds_ctx *ctx, SolveSet &set) {
         for (const DevProblem &q : set.probs) packed = packed && q.Wp != nullptr;
         bt.gemm_sym[m] = set.tune[m].gemm_sym && packed ? 1 : 0;
         bt.spmm_wpe8[m] = set.tune[m].spmm_wpe == 8 ? 1 : 0;  // read by the widths that have the form
+        // each problem takes its own form of the transposed product, so a
+        // problem solves the same alone or beside others
+        bool push = false;
+        for (const DevProblem &q : set.probs) push = push || (q.pb != nullptr && q.pval[m] != nullptr);
+        bt.spmmt_push[m] = push && spmmt_push_width(bt.B) ? 1 : 0;
     }
 
     std::vector<ProbView> views(np);
@@ -1162,6 +1220,13 @@ int build_batch(sbmds_ctx *ctx, SolveSet &set) {
         v.spmm_cnt = p.spmm_cnt;
         v.st = p.st;
         v.X0 = p.X0;
+        v.pb = p.pb;
+        v.pe = p.pe;
+        v.qp = p.qp;
+        v.ql = p.ql;
+        v.pvl = p.pvl;
+        for (int m = 0; m < NUM_MODES; ++m) v.pval[m] = p.pval[m];
+        v.ppart = p.ppart;
         v.zoff = zoff;
         v.loff = loff;
         v.host_sum = (char *)set.host_sum_dev + (size_t)i * sizeof(Summary);
@@ -1179,7 +1244,9 @@ int build_batch(sbmds_ctx *ctx, SolveSet &set) {
                 int64_t nb = 0;
                 switch (kd) {
                     case BK_SPMM: nb = v.spmm_blocks[m]; break;
-                    case BK_SPMMT: nb = (p.l + 4 / bt.spmmt_wpr[m] - 1) / (4 / bt.spmmt_wpr[m]); break;
+                    case BK_SPMMT:
+                        nb = push_form(bt, p, m) ? 0 : (p.l + 4 / bt.spmmt_wpr[m] - 1) / (4 / bt.spmmt_wpr[m]);
+                        break;
                     case BK_GEMM:
                         nb = bt.gemm_sym[m] ? sym_regions(p.lda / 64, sym_region_rows((Mode)m, bt.B), v.sym_c[m])
                                             : (int64_t)v.gemm_rowtiles[m] * v.gemm_ksplit[m];
@@ -1187,6 +1254,12 @@ int build_batch(sbmds_ctx *ctx, SolveSet &set) {
                     case BK_GEMMF: nb = bt.gemm_sym[m] ? p.lda / 64 : 0; break;
                     case BK_ELEM_NB: nb = (p.n * p.B + 255) / 256; break;
                     case BK_ELEM_LB: nb = (p.l * p.B + 255) / 256; break;
+                    case BK_PUSH: nb = push_form(bt, p, m) ? p.nvb : 0; break;
+                    case BK_PUSHR: {
+                        const int rows = spmmt_push_rows((Mode)m, bt.B);
+                        nb = push_form(bt, p, m) ? (p.l + rows - 1) / rows : 0;
+                        break;
+                    }
                     default: nb = (p.n + 255) / 256; break;
                 }
                 acc += nb;

@@ -20,6 +20,7 @@
 #include <type_traits>
 
 #include "sbmds_common.h"
+#include "sbmds_prep.h"
 #include "sbmds_rr.h"
 
 namespace sbmds {
@@ -737,6 +738,160 @@ __global__ __launch_bounds__(256) void k_spmm_t(const ProbView *__restrict__ vie
 }
 
 // ---------------------------------------------------------------------------
+// Transposed product, push form (see prep_push_*): block vb stages its
+// kPushVB rows of Y in LDS (read once, contiguous), then every (block,
+// landmark) pair q it owns gets the partial row sum_e val_e Y[v_e] over the
+// pair's entries (in vertex order), one group of B / VEC lanes per pair.
+// The reduction adds a landmark's partial rows in block order, applies the
+// inner centering and the basis rotation C, and writes its row of T.
+
+bool spmmt_push_width(int B) { return B == 8 || B == 16 || B == 32; }
+
+constexpr int kPushChunk = 8;
+
+template <typename TA, int B>
+struct PushRed {
+    static constexpr int VA = (16 / (int)sizeof(TA)) < B ? (16 / (int)sizeof(TA)) : B;
+    static constexpr int G = B / VA;       // lanes per landmark
+    static constexpr int ROWS = 256 / G;   // landmarks per block
+};
+
+int spmmt_push_rows(Mode m, int B) {
+    const bool f64 = m == MODE_F64ACC || m == MODE_FP64;
+    const int va = std::min(f64 ? 2 : 4, B);
+    return 256 / (B / va);
+}
+
+template <int M, int B, typename TY>
+__device__ __forceinline__ void spmmt_push_body(const ProbView *__restrict__ views, const int *__restrict__ off,
+                                                int nprob, int phase) {
+    using Tr = Traits<M>;
+    using TA = typename Tr::TA;
+    using TP = typename Tr::TP;
+    constexpr int VEC = VecOf<TY, B>::v;
+    constexpr int G = B / VEC;  // lanes per pair
+    constexpr int GROUPS = 256 / G;
+    __shared__ Pack<TY, VEC> ys[kPushVB * G];
+
+    const int p = find_problem(off, nprob, blockIdx.x);
+    const ProbView &v = views[p];
+    const SolveState *__restrict__ st = v.st;
+    if (st->done || st->phase != phase) return;
+    const int vb = blockIdx.x - off[p];
+    const int64_t v0 = (int64_t)vb * kPushVB;
+    const int nv = (int)((int64_t)v.n - v0 < kPushVB ? (int64_t)v.n - v0 : kPushVB);
+    const TY *__restrict__ Y = (const TY *)(st->ycur ? v.Y1 : v.Y0) + v0 * B;
+    for (int i = threadIdx.x; i < nv * G; i += 256) ys[i] = ldpg<TY, VEC>(Y + (size_t)i * VEC);
+    __syncthreads();
+    const TP *__restrict__ pv = (const TP *)v.pval[M];
+    const uint8_t *__restrict__ pvl = v.pvl;
+    const int32_t *__restrict__ pe = v.pe;
+    TA *__restrict__ part = (TA *)v.ppart;
+    const int grp = threadIdx.x / G, g = threadIdx.x % G;
+    const int q1 = v.pb[vb + 1];
+    constexpr int CH = kPushChunk;  // entries whose loads are in flight together
+    for (int q = v.pb[vb] + grp; q < q1; q += GROUPS) {
+        Pack<TA, VEC> acc;
+#pragma unroll
+        for (int r = 0; r < VEC; ++r) acc.v[r] = (TA)0;
+        const int e1 = pe[q + 1];
+        for (int e0 = pe[q]; e0 < e1; e0 += CH) {
+            TA w[CH];
+            int vl[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const bool ok = e0 + u < e1;  // missing entries read row 0 with weight 0
+                w[u] = ok ? up<TA>(pv[e0 + u]) : (TA)0;
+                vl[u] = ok ? (int)pvl[e0 + u] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const Pack<TY, VEC> y = ys[vl[u] * G + g];
+#pragma unroll
+                for (int r = 0; r < VEC; ++r) acc.v[r] += w[u] * up<TA>(y.v[r]);
+            }
+        }
+        stpg<TA, VEC>(part + (size_t)q * B + g * VEC, acc);
+    }
+}
+
+template <int M, int B>
+__global__ __launch_bounds__(256) void k_spmmt_push(const ProbView *__restrict__ views, const int *__restrict__ off,
+                                                    int nprob, int phase) {
+    const int p = find_problem(off, nprob, blockIdx.x);
+    const int ymode = views[p].st->ymode;  // uniform in the block
+    if (ymode == M || std::is_same<typename PrevY<M>::T, typename Traits<M>::TY>::value)
+        spmmt_push_body<M, B, typename Traits<M>::TY>(views, off, nprob, phase);
+    else
+        spmmt_push_body<M, B, typename PrevY<M>::T>(views, off, nprob, phase);
+}
+
+template <int M, int B>
+__global__ __launch_bounds__(256) void k_spmmt_reduce(const ProbView *__restrict__ views,
+                                                      const int *__restrict__ off, int nprob, int phase) {
+    using Tr = Traits<M>;
+    using TA = typename Tr::TA;
+    using TT = typename Tr::TT;
+    constexpr int VA = PushRed<TA, B>::VA, G = PushRed<TA, B>::G, ROWS = PushRed<TA, B>::ROWS;
+    __shared__ double Cl[B * B];
+    __shared__ double ex[B];
+    __shared__ double rowbuf[ROWS][B];
+
+    const int p = find_problem(off, nprob, blockIdx.x);
+    const ProbView &v = views[p];
+    const SolveState *__restrict__ st = v.st;
+    if (st->done || st->phase != phase) return;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < B * B; i += 256) Cl[i] = st->C[i];
+    if (tid < B) ex[tid] = st->e_x[tid];
+    const int grp = tid / G, g = tid % G;
+    const int64_t j = (int64_t)(blockIdx.x - off[p]) * ROWS + grp;
+    const bool live = j < v.l;
+    Pack<TA, VA> acc;
+#pragma unroll
+    for (int r = 0; r < VA; ++r) acc.v[r] = (TA)0;
+    if (live) {
+        // kPushChunk partial rows in flight together, added in order
+        constexpr int CH = kPushChunk;
+        const TA *__restrict__ part = (const TA *)v.ppart;
+        const int q1 = v.qp[j + 1];
+        for (int q0 = v.qp[j]; q0 < q1; q0 += CH) {
+            int idx[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) idx[u] = q0 + u < q1 ? v.ql[q0 + u] : -1;
+            Pack<TA, VA> x[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u)
+                if (idx[u] >= 0) x[u] = ldpg<TA, VA>(part + (size_t)idx[u] * B + g * VA);
+#pragma unroll
+            for (int u = 0; u < CH; ++u)
+                if (idx[u] >= 0) {
+#pragma unroll
+                    for (int r = 0; r < VA; ++r) acc.v[r] += x[u].v[r];
+                }
+        }
+    }
+    __syncthreads();  // Cl and ex
+    if (live) {
+        const double cj = v.c[M][j] / (double)v.n;
+#pragma unroll
+        for (int r = 0; r < VA; ++r) rowbuf[grp][g * VA + r] = (double)acc.v[r] - cj * ex[g * VA + r];
+    }
+    __syncthreads();
+    if (live) {
+        TT *__restrict__ T = (TT *)v.T;
+#pragma unroll
+        for (int r = 0; r < VA; ++r) {
+            const int col = g * VA + r;
+            double t = 0.0;
+#pragma unroll 8
+            for (int i = 0; i < B; ++i) t += rowbuf[grp][i] * Cl[i * B + col];
+            T[(size_t)j * B + col] = down<TT>((TA)t);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Start blocks, precision changes and outputs.
 // ---------------------------------------------------------------------------
 
@@ -1082,13 +1237,43 @@ hipError_t launch_spmm(Mode m, const Batch &bt, int phase, hipStream_t s, int rr
 template <int MM, int BB, int WPR>
 static hipError_t spmm_t_impl(const Batch &bt, int phase, hipStream_t s) {
     const int grid = bt.total[BK_SPMMT][MM];
-    if (grid <= 0) return hipErrorInvalidValue;
+    if (grid <= 0) return bt.spmmt_push[MM] ? hipSuccess : hipErrorInvalidValue;  // all in the push form
     hipLaunchKernelGGL((k_spmm_t<MM, BB, WPR>), dim3(grid), dim3(256), 0, s, bt.views, bt.off(BK_SPMMT, (Mode)MM),
                        bt.nprob, phase);
     return hipGetLastError();
 }
 
+template <int MM, int BB>
+static hipError_t spmmt_push_impl(const Batch &bt, int phase, hipStream_t s) {
+    const int g1 = bt.total[BK_PUSH][MM], g2 = bt.total[BK_PUSHR][MM];
+    if (g1 <= 0 || g2 <= 0) return hipSuccess;  // no problem of the batch takes the push form
+    hipLaunchKernelGGL((k_spmmt_push<MM, BB>), dim3(g1), dim3(256), 0, s, bt.views, bt.off(BK_PUSH, (Mode)MM),
+                       bt.nprob, phase);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_spmmt_reduce<MM, BB>), dim3(g2), dim3(256), 0, s, bt.views, bt.off(BK_PUSHR, (Mode)MM),
+                       bt.nprob, phase);
+    return hipGetLastError();
+}
+
+static hipError_t launch_spmm_t_push(Mode m, const Batch &bt, int phase, hipStream_t s) {
+    switch (bt.B) {
+        case 8: SBMDS_DISPATCH_M(m, return (spmmt_push_impl<MM, 8>(bt, phase, s))); break;
+        case 16: SBMDS_DISPATCH_M(m, return (spmmt_push_impl<MM, 16>(bt, phase, s))); break;
+        case 32: SBMDS_DISPATCH_M(m, return (spmmt_push_impl<MM, 32>(bt, phase, s))); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipErrorInvalidValue;
+}
+
+// Problems in the push form run its two kernels, the others the row-gather
+// kernel (each launch skips the problems of the other form: they own no
+// blocks of it).
 hipError_t launch_spmm_t(Mode m, const Batch &bt, int phase, hipStream_t s) {
+    if (bt.spmmt_push[m]) {
+        hipError_t e = launch_spmm_t_push(m, bt, phase, s);
+        if (e != hipSuccess || bt.total[BK_SPMMT][m] <= 0) return e;
+    }
     switch (bt.spmmt_wpr[m]) {
         case 1: SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(bt.B, return (spmm_t_impl<MM, BB, 1>(bt, phase, s)))); break;
         case 2: SBMDS_DISPATCH_M(m, SBMDS_DISPATCH_B(bt.B, return (spmm_t_impl<MM, BB, 2>(bt, phase, s)))); break;

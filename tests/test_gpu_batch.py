@@ -160,3 +160,24 @@ def test_batch_256_meshes_full_scale(gpu):
         assert err <= 1e-6, (i, p["n"], eig[i], lam[:3])
         assert ang <= 3.0, (i, p["n"], ang)
     print(f"256 meshes: worst rel eig err {worst_err:.2e}, worst relative subspace angle {worst_ang:.2e}", flush=True)
+
+
+def test_batch_push_form_mixed(gpu):
+    # with SBMDS_FLAG_PUSH_T the chain meshes take the push form and the
+    # random ragged ones (too many block-landmark pairs) keep the gathering
+    # form, in the same launches; every problem still matches the oracle and
+    # solves the same as alone
+    sb = gpu
+    from synth import configs
+    torus = dict(configs.torus64x32())
+    torus["val"] = torus["val"].astype(np.float32)
+    torus["W"] = torus["W"].astype(np.float32)
+    probs = [torus] + problems()[:2]
+    Z, eig, reps, rc, _ = solve(sb, probs, sb.FP32, flags=sb.FLAG_PUSH_T)
+    assert rc == 0
+    for i, (p, Zi) in enumerate(zip(probs, split_rows(Z, probs))):
+        lam, V, _ = H.oracle_for(p, 3)
+        assert H.rel_eig_err(eig[i], lam[:3]) <= 1e-6, i
+        assert H.subspace_angle(Zi, V, lam, 3, tol=1e-6) <= 3.0, i
+    Zs, es, _, _, _ = solve(sb, probs[:1], sb.FP32, flags=sb.FLAG_PUSH_T)
+    np.testing.assert_array_equal(eig[0], es[0])

@@ -375,3 +375,19 @@ def test_device_inputs_validated_on_device(gpu, defect):
             "col_range": "out of range", "rowptr": "P_rowptr"}[defect]
     assert exc.value.code == -1 and want in str(exc.value), str(exc.value)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", ["FP32", "BF16_FP32", "FP64"])
+def test_push_form_transposed_product(gpu, prec):
+    # the push form of P^T Y (SBMDS_FLAG_PUSH_T) on the 64 x 32 torus: the
+    # oracle's eigenpairs, in each arithmetic (bf16 -> fp32 also reads the
+    # previous phase's block in the push kernel)
+    sb = gpu
+    prob = dict(configs.torus64x32())
+    tol = 1e-10 if prec == "FP64" else 1e-6
+    if prec != "FP64":
+        prob["val"] = prob["val"].astype(np.float32)
+        prob["W"] = prob["W"].astype(np.float32)
+    Z, eig, rep, rc, _ = run(sb, prob, 3, 16, getattr(sb, prec), tol=tol, flags=sb.FLAG_PUSH_T)
+    assert rc == 0 and rep["certified"]
+    check(prob, Z, eig, rep, 3, tol)

@@ -753,6 +753,29 @@ def sphere_workload(sb, torch, configs, args, k, blocks):
     }
 
 
+def partial_run(sb, torch, configs, args, k, blocks, want):
+    """Only the named secondary workloads (no headline, so no value): for
+    profiling one of them on its own."""
+    out = {"metric": None, "value": None, "partial": True}
+    if want("sphere") and not args.no_sphere:
+        out["sphere7"] = sphere_workload(sb, torch, configs, args, k, blocks)
+    if want("batch") and not args.no_batch:
+        from synth import large
+        probs256 = large.grid_torus_batch()
+        out["batched_full_scale"] = time_batch(
+            sb, torch, probs256, k, blocks[0], max(1, min(args.steps, 3)), 1,
+            os.path.join(configs.cache_dir(), f"tune_batch256_k{k}_b{blocks[0]}.txt"), workload="256 grid tori",
+            details=True)
+    if want("scale") and not args.no_scale:
+        out["spmm_at_scale"] = {pat: spmm_at_scale(sb, torch, args.steps, pat) for pat in ("banded", "random")}
+    if want("landmarks") and not args.no_landmarks:
+        out["landmarks_geodesic"] = landmark_workload(sb, torch)
+        out["landmarks_geodesic"]["input_chain"] = input_chain(sb, torch)
+    if want("quality") and not args.no_quality:
+        out["approximation_quality"] = approximation_quality(sb, torch)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -770,6 +793,10 @@ def main():
     ap.add_argument("--no-quality", action="store_true", help="skip the approximation-quality workload")
     ap.add_argument("--no-routes", action="store_true", help="skip the Lanczos / BMDS comparison solvers")
     ap.add_argument("--no-landmarks", action="store_true", help="skip the device landmark / W workload")
+    ap.add_argument("--workloads", type=str, default="",
+                    help="comma list of workloads to run (headline, routes, cpu, sphere, batch, scale, landmarks, "
+                         "quality, torus); default all.  Without the headline the line carries no value (for "
+                         "profiling one workload)")
     ap.add_argument("--forms", type=str, default="",
                     help="comma-separated headline forms to time (default: all; plain fp32 always)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -800,6 +827,15 @@ def main():
     torch.cuda.set_device(0)
     k = args.k
     blocks = [int(x) for x in args.blocks.split(",") if x]
+
+    chosen_set = set(x for x in args.workloads.split(",") if x)
+
+    def want(name):
+        return not chosen_set or name in chosen_set
+
+    if not want("headline"):
+        args.no_routes = args.no_routes or not want("routes")
+        return partial_run(sb, torch, configs, args, k, blocks, want)
 
     # ---- headline: the 1.8M-vertex, 50,000-landmark shape
     log("headline workload: n = 1.8M, 50,000 landmarks")

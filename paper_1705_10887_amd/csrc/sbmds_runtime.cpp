@@ -266,6 +266,7 @@ std::vector<PhaseRule> schedule(const sbmds_options &o) {
 }
 
 constexpr int kMaxGemmSplit = 64;   // K splits of the dense product (bounds its scratch)
+constexpr size_t kFusedRrMaxProblems = 16;  // batches above this size run the Rayleigh-Ritz step on its own
 constexpr double kPackMinBytes = 256e6;  // float32 W of a batch above which its upper triangle is packed
 constexpr int kMaxSpmmBlocks = 1024;
 
@@ -314,7 +315,7 @@ Tune default_tune(Mode m, const std::vector<DevProblem> &probs) {
     // bandwidth, not the latency of the separate Rayleigh-Ritz launch, counts
     double sp_bytes = 0;
     for (const DevProblem &p : probs) sp_bytes += spmm_bytes(m, p);
-    t.spmm_wpe = sp_bytes > 48e6 ? 8 : 4;
+    t.spmm_wpe = (sp_bytes > 48e6 || probs.size() > kFusedRrMaxProblems) ? 8 : 4;
     const double per_row = nnz / l;  // mean entries per landmark column of P
     // (351 entries per landmark row at 50,000 landmarks: one wave per row
     // measured fastest, 108 against 183 us with four)
@@ -836,8 +837,14 @@ int autotune(sbmds_ctx *ctx, SolveSet &set) {
         {
             // both forms of the row-split SpMM where the width has them; the
             // two-block form leaves the Rayleigh-Ritz step to a launch of
-            // its own, which its time is charged with
-            std::vector<int> wpes{4};
+            // its own, which its time is charged with.  The fused form runs
+            // each problem's Rayleigh-Ritz step in that problem's last block,
+            // which the timing here (no step) does not see; with many
+            // problems those steps pile up at the end of the launch (256
+            // meshes: 4.4 against 1.6 ms), so large batches take the
+            // two-block form.
+            std::vector<int> wpes;
+            if (!spmm_has_two_block_form(set.probs[0].B) || set.probs.size() <= kFusedRrMaxProblems) wpes.push_back(4);
             if (spmm_has_two_block_form(set.probs[0].B)) wpes.push_back(8);
             double best = 1e30;
             Tune keep = set.tune[m];

@@ -239,16 +239,26 @@ int sbmds_embed(sbmds_ctx *ctx, double *eigvals, void *Z, int Z_mem, sbmds_repor
 /*
  * The interpolation operator P of Eq. (PDefinition) built on the device from
  * a triangle mesh (Sections 2.2 and 3.1): cotangent weights and lumped mass
- * (or, with graph != 0, the generic-graph variant D = I, A = 0/1 edge
- * adjacency), M = L^T D^-1 L with L = diag(A 1) - A, P_u = -M_uu^-1 M_ub by a
- * dense Cholesky factorisation, then per column the p entries of largest
- * magnitude (ties at the cut to the lower vertex id, exact zeros dropped;
- * p <= 0 keeps every nonzero), and the identity rows of the landmarks.
- *   V          [n*3] double vertex positions; 2 <= n <= 46340 (the dense
- *              route holds M_uu: 8 n^2 bytes).
+ * (or, with SBMDS_INTERP_GRAPH, the generic-graph variant D = I, A = 0/1
+ * edge adjacency), M = L^T D^-1 L with L = diag(A 1) - A, P_u = -M_uu^-1 M_ub
+ * by a Cholesky factorisation of M_uu (Section 3.2 names a sparse Cholesky
+ * decomposition), then per column the p entries of largest magnitude (ties
+ * at the cut to the lower vertex id, exact zeros dropped; p <= 0 keeps
+ * every nonzero), and the identity rows of the landmarks.  Two routes:
+ *   dense    M_uu as a dense matrix: 8 n^2 bytes, O(n^3); n <= 46340.
+ *   blocked  the mesh's breadth-first levels order the non-landmarks so
+ *            that M_uu is block tridiagonal with blocks of two levels; its
+ *            factor keeps that shape and is applied to batches of the
+ *            right-hand sides.  About 16 n w bytes and O(n w (w + l))
+ *            flops for blocks of w vertices; n < 2^30.
+ *   V          [n*3] double vertex positions.
  *   F          [nf*3] int32 triangles (distinct vertices in [0, n)).
  *   landmarks  [l] int32 distinct vertex ids, 1 <= l < n; column j of P
  *              belongs to landmarks[j].
+ *   flags      SBMDS_INTERP_* bits: GRAPH for the generic-graph variant;
+ *              DENSE or BLOCKED picks the route (neither: dense up to 4096
+ *              vertices, blocked above).  Both routes compute the same
+ *              sums for M; their solutions differ by rounding.
  *   rowptr, col, val  output CSR of P (n x l): [n+1] int32, [cap] int32,
  *              [cap] double, columns ascending within a row.
  *   cap        capacity of col and val; *nnz receives the entry count (also
@@ -256,11 +266,16 @@ int sbmds_embed(sbmds_ctx *ctx, double *eigvals, void *Z, int Z_mem, sbmds_repor
  *              (l + l (n - l) without thresholding) always suffices.
  *   mem        sbmds_mem of every array; stream as for the other calls (the
  *              call synchronises it).
- * Invalid meshes or landmarks return SBMDS_EINVAL before any use of them as
- * an index; a matrix M_uu that is not positive definite SBMDS_EBREAKDOWN.
+ * Invalid meshes, landmarks or flags return SBMDS_EINVAL before any use of
+ * them as an index; a matrix M_uu that is not positive definite (a
+ * component of the mesh without a landmark) SBMDS_EBREAKDOWN; a route that
+ * does not fit the free device memory SBMDS_ENOMEM.
  */
+#define SBMDS_INTERP_GRAPH 0x1   /* generic-graph variant: D = I, A = edge adjacency */
+#define SBMDS_INTERP_DENSE 0x2   /* dense route */
+#define SBMDS_INTERP_BLOCKED 0x4 /* level-blocked route */
 int sbmds_interpolation(const double *V, int64_t n, const int32_t *F, int64_t nf, const int32_t *landmarks, int64_t l,
-                        int64_t p, int graph, int32_t *rowptr, int32_t *col, double *val, int64_t cap, int64_t *nnz,
+                        int64_t p, int flags, int32_t *rowptr, int32_t *col, double *val, int64_t cap, int64_t *nnz,
                         int mem, void *stream);
 
 /*

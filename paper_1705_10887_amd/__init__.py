@@ -22,6 +22,7 @@ __all__ = [
     "FP64", "FP32", "BF16_FP32",
     "START_RANDOM", "START_LMDS", "START_LEARNED", "START_USER",
     "FLAG_KERNEL_TIMING", "FLAG_NO_GRAPH", "FLAG_NO_CERTIFY", "FLAG_PACK_W", "FLAG_FULL_W", "FLAG_PUSH_T",
+    "INTERP_GRAPH", "INTERP_DENSE", "INTERP_BLOCKED",
     "SbmdsError", "Problem", "Context", "embed", "approx_rows", "lib", "lib_path", "version",
 ]
 
@@ -30,6 +31,7 @@ START_RANDOM, START_LMDS, START_LEARNED, START_USER = 0, 1, 2, 3
 MEM_HOST, MEM_DEVICE = 0, 1
 FLAG_KERNEL_TIMING, FLAG_NO_GRAPH, FLAG_NO_CERTIFY = 0x1, 0x2, 0x4
 FLAG_PACK_W, FLAG_FULL_W, FLAG_PUSH_T = 0x8, 0x10, 0x20
+INTERP_GRAPH, INTERP_DENSE, INTERP_BLOCKED = 0x1, 0x2, 0x4  # sbmds_interpolation flags
 MAX_BLOCK = 64
 
 _STATUS = {0: "OK", 1: "ENOCONV", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENODEV", -5: "EBREAKDOWN"}
@@ -435,10 +437,11 @@ def approx_rows(rowptr, col, val, L, rows, K_rows=None, want_rows=False):
     return (err[0] / err[1] if err[1] > 0 else float("nan")), (err[0], err[1]), out
 
 
-def interpolation(V, F, landmarks, p=None, graph=False):
+def interpolation(V, F, landmarks, p=None, graph=False, route=None):
     """P of Eq. (PDefinition) built on the device (sbmds_interpolation) from
     the mesh (V [n, 3], F [nf, 3]) and its landmarks, thresholded to p
-    entries per column (None: unthresholded).  Host NumPy inputs and
+    entries per column (None: unthresholded).  ``route`` is "dense",
+    "blocked" or None (the library's choice by size).  Host NumPy inputs and
     outputs: returns (rowptr, col, val) of the n x l CSR."""
     V = np.ascontiguousarray(V, dtype=np.float64)
     F = np.ascontiguousarray(F, dtype=np.int32)
@@ -446,14 +449,17 @@ def interpolation(V, F, landmarks, p=None, graph=False):
     n, l = V.shape[0], lm.shape[0]
     m = n - l
     pk = 0 if p is None else int(p)
+    flags = INTERP_GRAPH if graph else 0
+    if route is not None:
+        flags |= {"dense": INTERP_DENSE, "blocked": INTERP_BLOCKED}[route]
     cap = l + l * (m if pk <= 0 or pk >= m else pk)
     rowptr = np.empty(n + 1, dtype=np.int32)
     col = np.empty(max(cap, 1), dtype=np.int32)
     val = np.empty(max(cap, 1), dtype=np.float64)
     nnz = ctypes.c_int64(0)
-    _check(lib().sbmds_interpolation(V.ctypes.data, n, F.ctypes.data, F.shape[0], lm.ctypes.data, l, pk,
-                                     1 if graph else 0, rowptr.ctypes.data, col.ctypes.data, val.ctypes.data, cap,
-                                     ctypes.byref(nnz), MEM_HOST, None))
+    _check(lib().sbmds_interpolation(V.ctypes.data, n, F.ctypes.data, F.shape[0], lm.ctypes.data, l, pk, flags,
+                                     rowptr.ctypes.data, col.ctypes.data, val.ctypes.data, cap, ctypes.byref(nnz),
+                                     MEM_HOST, None))
     return rowptr, col[:nnz.value].copy(), val[:nnz.value].copy()
 
 

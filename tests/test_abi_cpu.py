@@ -200,5 +200,14 @@ def test_interpolation_argument_checks_without_gpu():
     tail = [rp.ctypes.data, col.ctypes.data, val.ctypes.data, 8, ctypes.byref(nnz), 0, None]
     assert L.sbmds_interpolation(*args, 4, 2, 0, *tail) == -1  # l = n
     assert b"l < n" in L.sbmds_last_error()
-    assert L.sbmds_interpolation(V.ctypes.data, 50000, F.ctypes.data, 2, lm.ctypes.data, 1, 2, 0, *tail) == -1
+    # the dense route holds M densely: n <= 46340
+    assert L.sbmds_interpolation(V.ctypes.data, 50000, F.ctypes.data, 2, lm.ctypes.data, 1, 2, sb.INTERP_DENSE,
+                                 *tail) == -1
     assert b"46340" in L.sbmds_last_error()
+    assert L.sbmds_interpolation(*args, 1, 2, sb.INTERP_DENSE | sb.INTERP_BLOCKED, *tail) == -1
+    assert b"exclude" in L.sbmds_last_error()
+    assert L.sbmds_interpolation(*args, 1, 2, 0x8, *tail) == -1
+    assert b"unknown" in L.sbmds_last_error()
+    assert L.sbmds_interpolation(V.ctypes.data, 1 << 30, F.ctypes.data, 2, lm.ctypes.data, 1, 2,
+                                 sb.INTERP_BLOCKED, *tail) == -1
+    assert b"2^30" in L.sbmds_last_error()

@@ -1,9 +1,11 @@
 """The interpolation operator P of Eq. (PDefinition) built on the GPU
-(cotangent assembly, M = L^T D^-1 L, dense Cholesky solve, per-column
-thresholding of Section 3.1) through the C ABI, against the oracle's dense
-brute-force chain (oracle.refchain) on small meshes and the generator's P
-on the 64 x 32 torus: the kept index sets equal, values within 1e-10 of
-the largest entry (needs a gfx950 GPU)."""
+(cotangent assembly, M = L^T D^-1 L, Cholesky solve of M_uu by the dense or
+the level-blocked route, per-column thresholding of Section 3.1) through the
+C ABI, against the oracle's dense brute-force chain (oracle.refchain) on
+small meshes and the generator's sparse-LU P on the 64 x 32 torus (kept
+index sets equal, values within 1e-10 of the largest entry), and, for the
+blocked route, against the generator's P of the level-7 sphere and the
+1024 x 512 bumpy torus (needs a gfx950 GPU)."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -23,13 +25,17 @@ def compare(P, Pref, rtol=1e-10):
     assert np.max(np.abs(P - Pref)) <= rtol * np.max(np.abs(Pref))
 
 
+ROUTES = ["dense", "blocked"]
+
+
+@pytest.mark.parametrize("route", ROUTES)
 @pytest.mark.parametrize("p", [None, 6, 20])
-def test_cotan_chain_matches_oracle(gpu, p):
+def test_cotan_chain_matches_oracle(gpu, p, route):
     # jittered 12 x 8 torus (n = 96), 9 landmarks: the dense oracle chain
     sb = gpu
     V, F = meshes.torus_grid(12, 8, 1.0, 0.4, jitter=0.05, seed=7)
     lm = np.array([0, 13, 27, 40, 52, 61, 75, 83, 90])
-    rp, col, val = sb.interpolation(V, F, lm, p=p)
+    rp, col, val = sb.interpolation(V, F, lm, p=p, route=route)
     Mref, _, _ = ref.biharmonic_dense(V, F)
     Pref = ref.interp_dense(Mref, lm, p)
     P = dense(rp, col, val, V.shape[0], len(lm))
@@ -38,22 +44,25 @@ def test_cotan_chain_matches_oracle(gpu, p):
     assert np.all(np.diff(rp) >= 0) and rp[-1] == len(col)
 
 
-def test_graph_variant_matches_oracle(gpu):
+@pytest.mark.parametrize("route", ROUTES)
+def test_graph_variant_matches_oracle(gpu, route):
     sb = gpu
     V, F = meshes.deformed_icosphere(2, 3)
     lm = np.arange(0, V.shape[0], 9)
-    rp, col, val = sb.interpolation(V, F, lm, p=12, graph=True)
+    rp, col, val = sb.interpolation(V, F, lm, p=12, graph=True, route=route)
     Mref = ref.graph_biharmonic_dense(V.shape[0], F)
     compare(dense(rp, col, val, V.shape[0], len(lm)), ref.interp_dense(Mref, lm, 12))
 
 
-def test_torus64x32_matches_generator(gpu):
+@pytest.mark.parametrize("route", ROUTES)
+def test_torus64x32_matches_generator(gpu, route):
     # the 64 x 32 torus of the small configuration (n = 2048, 64 FPS
-    # landmarks, p = 310): the generator's sparse-LU P (pinned to the oracle
-    # chain at small sizes) is reproduced
+    # landmarks, p = 310; the blocked route splits M_uu into 15 blocks): the
+    # generator's sparse-LU P (pinned to the oracle chain at small sizes) is
+    # reproduced
     sb = gpu
     prob = configs.torus64x32()
-    rp, col, val = sb.interpolation(prob["V"], prob["F"], prob["landmarks"], p=prob["p"])
+    rp, col, val = sb.interpolation(prob["V"], prob["F"], prob["landmarks"], p=prob["p"], route=route)
     np.testing.assert_array_equal(rp, prob["rowptr"])
     np.testing.assert_array_equal(col, prob["col"])
     ref_val = np.asarray(prob["val"], dtype=np.float64)
@@ -71,3 +80,80 @@ def test_bad_inputs(gpu):
     with pytest.raises(sb.SbmdsError) as exc:
         sb.interpolation(V, bad, np.array([1, 5]), p=4)
     assert "face" in str(exc.value)
+
+
+def test_blocked_route_two_components(gpu):
+    # two disjoint tori: the breadth-first levels restart in the second
+    # component; each component holds landmarks, so M_uu stays definite
+    sb = gpu
+    V1, F1 = meshes.torus_grid(12, 8, 1.0, 0.4, jitter=0.05, seed=7)
+    V2, F2 = meshes.torus_grid(10, 6, 1.0, 0.4, jitter=0.05, seed=8)
+    V = np.vstack([V1, V2 + 3.0])
+    F = np.vstack([F1, F2 + V1.shape[0]])
+    lm = np.array([130, 3, 50, 100, 141])
+    Mref, _, _ = ref.biharmonic_dense(V, F)
+    for p in (None, 7):
+        rp, col, val = sb.interpolation(V, F, lm, p=p, route="blocked")
+        compare(dense(rp, col, val, V.shape[0], len(lm)), ref.interp_dense(Mref, lm, p))
+
+
+def test_blocked_route_many_blocks_matches_dense_route(gpu):
+    # a long thin torus (320 x 6): 27 blocks in the level order; both
+    # routes give the same pattern, values within 1e-10 of the largest
+    sb = gpu
+    V, F = meshes.torus_grid(320, 6, 1.0, 0.3, jitter=0.05, seed=11)
+    lm = np.arange(0, V.shape[0], 23)
+    a = sb.interpolation(V, F, lm, p=40, route="blocked")
+    b = sb.interpolation(V, F, lm, p=40, route="dense")
+    n, l = V.shape[0], len(lm)
+    compare(dense(*a, n, l), dense(*b, n, l))
+
+
+def compare_with_cut(n, l, got, want, rel_val):
+    """Per column: the kept sets agree except at ties of the cut (an entry
+    kept by one side only lies within 1e-7 of the column's largest entry
+    above the other side's cut); kept values agree to rel_val relative plus
+    1e-9 of the column's largest entry.  Returns the number of entries kept
+    by one side only."""
+    G = sp.csr_matrix((got[2], got[1], got[0]), shape=(n, l)).tocsc()
+    R = sp.csr_matrix((np.asarray(want[2], np.float64), want[1], want[0]), shape=(n, l)).tocsc()
+    assert np.array_equal(np.diff(G.indptr), np.diff(R.indptr)), "kept counts differ"
+    odd = 0
+    for c in range(l):
+        gi, gv = G.indices[G.indptr[c]:G.indptr[c + 1]], G.data[G.indptr[c]:G.indptr[c + 1]]
+        ri, rv = R.indices[R.indptr[c]:R.indptr[c + 1]], R.data[R.indptr[c]:R.indptr[c + 1]]
+        big = np.max(np.abs(rv))
+        common, ig, ir = np.intersect1d(gi, ri, return_indices=True)
+        assert np.all(np.abs(gv[ig] - rv[ir]) <= rel_val * np.abs(rv[ir]) + 1e-9 * big), c
+        if common.size != gi.size:
+            odd += gi.size - common.size
+            only_g = np.setdiff1d(np.arange(gi.size), ig)
+            only_r = np.setdiff1d(np.arange(ri.size), ir)
+            cut_r, cut_g = np.min(np.abs(rv)), np.min(np.abs(gv))
+            assert np.all(np.abs(gv[only_g]) <= cut_r + 1e-7 * big), c
+            assert np.all(np.abs(rv[only_r]) <= cut_g + 1e-7 * big), c
+    return odd
+
+
+def test_blocked_route_sphere7_matches_generator(gpu):
+    # the level-7 sphere (n = 163,842, l = 2,000, p = 809): the generator's
+    # P (sparse LU on the host, rounded to float32) against the blocked
+    # route's float64 P
+    sb = gpu
+    prob = configs.sphere7()
+    got = sb.interpolation(prob["V"], prob["F"], prob["landmarks"], p=prob["p"], route="blocked")
+    odd = compare_with_cut(prob["n"], prob["l"], got, (prob["rowptr"], prob["col"], prob["val"]), 2.0 ** -24)
+    print("sphere7: entries kept by one side only", odd)
+    assert odd <= 4
+
+
+def test_blocked_route_bumpy_torus1024x512_matches_generator(gpu):
+    # the precision workload's operator (n = 524,288, l = 10,000, p = 514)
+    sb = gpu
+    prob = configs.bumpy_torus(1024, 512, l=10000, generate=False)
+    if prob is None:
+        pytest.skip("the 1024 x 512 torus input is not generated (about an hour of host time)")
+    got = sb.interpolation(prob["V"], prob["F"], prob["landmarks"], p=prob["p"], route="blocked")
+    odd = compare_with_cut(prob["n"], prob["l"], got, (prob["rowptr"], prob["col"], prob["val"]), 2.0 ** -24)
+    print("bumpy torus 1024 x 512: entries kept by one side only", odd)
+    assert odd <= 20

@@ -539,6 +539,77 @@ def input_chain(sb, torch):
     return out
 
 
+def _p_agreement(n, l, got, want):
+    """Entries of P kept by one side only, and the largest difference of a
+    common entry relative to its column's largest entry (``want`` holds
+    float32 values: the generator's P as stored)."""
+    import numpy as np
+    import scipy.sparse as sp
+
+    G = sp.csr_matrix((got[2], got[1], got[0]), shape=(n, l)).tocsc()
+    R = sp.csr_matrix((np.asarray(want[2], np.float64), want[1], want[0]), shape=(n, l)).tocsc()
+    odd, worst = 0, 0.0
+    for c in range(l):
+        gi, gv = G.indices[G.indptr[c]:G.indptr[c + 1]], G.data[G.indptr[c]:G.indptr[c + 1]]
+        ri, rv = R.indices[R.indptr[c]:R.indptr[c + 1]], R.data[R.indptr[c]:R.indptr[c + 1]]
+        common, ig, ir = np.intersect1d(gi, ri, return_indices=True)
+        odd += gi.size - common.size
+        if common.size:
+            worst = max(worst, float(np.max(np.abs(gv[ig].astype(np.float32) - rv[ir])) / np.max(np.abs(rv))))
+    return odd, worst
+
+
+def interpolation_at_scale(sb, torch, big=False):
+    """P built on the device by the level-blocked route (sbmds_interpolation)
+    at the level-7 sphere (n = 163,842, l = 2,000, p = 809) and the
+    1024 x 512 bumpy torus (n = 524,288, l = 10,000, p = 514; when its input
+    is cached), against the generator's P (host sparse LU, stored in
+    float32): entries kept by one side only, and the largest difference of
+    the device P rounded to float32.  With ``big`` also the 1,800 x 1,000
+    torus mesh (n = 1.8M) with 50,000 device farthest-point landmarks
+    (p = 350), the size of the paper's largest run."""
+    import numpy as np
+
+    from synth import configs, meshes
+    from synth import operator as op
+
+    out = {}
+    Vw, Fw = meshes.torus_grid(12, 8)
+    sb.interpolation(Vw, Fw, np.array([0, 5]), p=2, route="blocked")  # loads the solver libraries
+    for name, prob in (("sphere7", configs.sphere7()),
+                       ("bumpy_torus_1024x512", configs.bumpy_torus(1024, 512, l=10000, generate=False))):
+        if prob is None:
+            out[name] = "input not cached"
+            continue
+        t0 = time.perf_counter()
+        got = sb.interpolation(prob["V"], prob["F"], prob["landmarks"], p=prob["p"], route="blocked")
+        t = time.perf_counter() - t0
+        odd, worst = _p_agreement(prob["n"], prob["l"], got, (prob["rowptr"], prob["col"], prob["val"]))
+        out[name] = {"n": int(prob["n"]), "l": int(prob["l"]), "p": int(prob["p"]), "nnz": int(len(got[1])),
+                     "gpu_p_s": round(t, 3), "entries_kept_by_one_side_only": int(odd),
+                     "max_rel_diff_float32": worst}
+        log(f"P at scale {name}: {out[name]}")
+        del prob, got
+    if big:
+        V, F = meshes.torus_grid(1800, 1000, 1.0, 0.4, jitter=0.01, seed=5)
+        G = op.edge_graph(V, F).tocsr()
+        G.sort_indices()
+        arrs = [torch.from_numpy(a).cuda() for a in (G.indptr.astype(np.int32), G.indices.astype(np.int32), G.data)]
+        n, l = V.shape[0], 50_000
+        lm, _ = sb.landmarks_geodesic(*arrs, l, 0, want_W=False)
+        lmh = lm.cpu().numpy()
+        del arrs
+        p = op.p_from_prow(n, l, 10)
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        rp, col, val = sb.interpolation(V, F, lmh, p=p, route="blocked")
+        t = time.perf_counter() - t0
+        out["torus_1800x1000"] = {"n": int(n), "l": l, "p": int(p), "nnz": int(len(col)), "gpu_p_s": round(t, 3),
+                                  "kept_per_column_min": int(np.bincount(col, minlength=l).min())}
+        log(f"P at scale 1.8M torus: {out['torus_1800x1000']}")
+    return out
+
+
 def approximation_quality(sb, torch, nsample=128, reps=5):
     """The paper's quality measures as a second workload on the GPU, on a
     192 x 96 bumpy torus (n = 18,432, l = 369 FPS landmarks, the same
@@ -771,6 +842,8 @@ def partial_run(sb, torch, configs, args, k, blocks, want):
     if want("landmarks") and not args.no_landmarks:
         out["landmarks_geodesic"] = landmark_workload(sb, torch)
         out["landmarks_geodesic"]["input_chain"] = input_chain(sb, torch)
+    if want("interp") or want("interp_big"):
+        out["interpolation_at_scale"] = interpolation_at_scale(sb, torch, big=want("interp_big"))
     if want("quality") and not args.no_quality:
         out["approximation_quality"] = approximation_quality(sb, torch)
     print(json.dumps(out), flush=True)
@@ -795,7 +868,7 @@ def main():
     ap.add_argument("--no-landmarks", action="store_true", help="skip the device landmark / W workload")
     ap.add_argument("--workloads", type=str, default="",
                     help="comma list of workloads to run (headline, routes, cpu, sphere, batch, scale, landmarks, "
-                         "quality, torus); default all.  Without the headline the line carries no value (for "
+                         "quality, torus, interp, interp_big); default all but interp_big.  Without the headline the line carries no value (for "
                          "profiling one workload)")
     ap.add_argument("--forms", type=str, default="",
                     help="comma-separated headline forms to time (default: all; plain fp32 always)")
@@ -917,6 +990,8 @@ def main():
         log("landmarks and W on the device (farthest-point sampling, geodesic W)")
         landmarks = landmark_workload(sb, torch)
         landmarks["input_chain"] = input_chain(sb, torch)
+        log("P on the device at full size (level-blocked route)")
+        landmarks["interpolation_at_scale"] = interpolation_at_scale(sb, torch)
 
     quality = None
     if not args.no_quality:

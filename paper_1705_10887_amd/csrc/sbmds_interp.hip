@@ -371,9 +371,24 @@ __global__ __launch_bounds__(256) void k_block_pos(const int32_t *__restrict__ o
     if (i < m) bpos[order[i]] = (int32_t)i;
 }
 
-__global__ __launch_bounds__(256) void k_lm_index(const int32_t *__restrict__ lm, int64_t l, int32_t *__restrict__ lmidx) {
+// Landmarks in the order of their level groups' blocks (key = block * l +
+// landmark): a batch of consecutive landmarks in this order has right-hand
+// sides that vanish above its first block, where the forward solve starts.
+__global__ __launch_bounds__(256) void k_lm_keys(const int32_t *__restrict__ lm, const int32_t *__restrict__ lev,
+                                                 const int32_t *__restrict__ gblk, int64_t l, int64_t nblk,
+                                                 int64_t *__restrict__ key, int32_t *__restrict__ ids) {
     const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c < l) lmidx[lm[c]] = (int32_t)c;
+    if (c >= l) return;
+    const int64_t b = std::min<int64_t>(gblk[lev[lm[c]] >> 1], nblk - 1);
+    key[c] = b * l + c;
+    ids[c] = (int32_t)c;
+}
+
+// lmidx[v] = rank of landmark vertex v in the processing order (-1 else).
+__global__ __launch_bounds__(256) void k_lm_index(const int32_t *__restrict__ lm, const int32_t *__restrict__ lmorder,
+                                                  int64_t l, int32_t *__restrict__ lmidx) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q < l) lmidx[lm[lmorder[q]]] = (int32_t)q;
 }
 
 // Layout of the blocked M_uu: block b holds positions [boff[b], boff[b+1]);
@@ -436,8 +451,9 @@ __global__ __launch_bounds__(256) void k_block_m(const int32_t *__restrict__ rp,
     });
 }
 
-// Right-hand sides -M_ub for the landmarks [c0, c0 + r), column-major
-// (m x r) in position order; the same sums as the dense route, negated.
+// Right-hand sides -M_ub for the landmarks of ranks [c0, c0 + r) in the
+// processing order, column-major (m x r) in position order; the same sums
+// as the dense route, negated.
 __global__ __launch_bounds__(256) void k_block_rhs(const int32_t *__restrict__ rp, const int64_t *__restrict__ dkey,
                                                    const double *__restrict__ dval, const double *__restrict__ d,
                                                    BlockMap bm, int64_t n, int64_t m, int64_t c0, int64_t r,
@@ -478,23 +494,23 @@ __device__ inline int64_t wg_sum(int64_t v, int64_t *sh) {
     return sh[0] + sh[1] + sh[2] + sh[3];
 }
 
-// Thresholding of Section 3.1 for one column per workgroup (column c0 + c
-// of P, m values in ascending vertex order): the pk entries of largest
+// Thresholding of Section 3.1 for one column per workgroup (column
+// lmorder[c0 + c] of P, m values in ascending vertex order): the pk entries of largest
 // magnitude, ties at the cut to the lower vertex, zeros never kept.  The
 // cut is found by a radix selection over the magnitude bits (8 passes of 8
-// bits); kept entries go to slots [(c0 + c) pk, (c0 + c + 1) pk) in any
-// order, with key = vertex * l + column, and cnt[c0 + c] their number.
+// bits); kept entries of column j go to slots [j pk, (j + 1) pk) in any
+// order, with key = vertex * l + j, and cnt[j] their number.
 __global__ __launch_bounds__(256) void k_topp(const double *__restrict__ Xv, int64_t m, int64_t pk, int64_t c0,
                                               int64_t l, const int32_t *__restrict__ uvert,
-                                              int64_t *__restrict__ okey, double *__restrict__ oval,
-                                              int32_t *__restrict__ ocnt) {
+                                              const int32_t *__restrict__ lmorder, int64_t *__restrict__ okey,
+                                              double *__restrict__ oval, int32_t *__restrict__ ocnt) {
     __shared__ uint32_t hist[256];
     __shared__ int64_t sh[4];
     __shared__ uint64_t sh_prefix;
     __shared__ int64_t sh_need, sh_eq;
     __shared__ uint32_t slot;
     __shared__ uint32_t wtot[4];
-    const int64_t c = blockIdx.x, col = c0 + c;
+    const int64_t c = blockIdx.x, col = lmorder[c0 + c];
     const double *x = Xv + c * m;
     const int tid = threadIdx.x;
     int64_t nzl = 0;
@@ -820,9 +836,19 @@ int blocked_entries(Pool &pool, const EdgeData &ed, int64_t n, int64_t l, int64_
     ICHK(hipGetLastError());
     if ((rc = sort_pairs(pool, key, key2, ids, order, n, bits_for((nblk + 1) * n), s)) < 0) return rc;
     hipLaunchKernelGGL(k_block_pos, dim3(nb(m)), dim3(256), 0, s, (const int32_t *)order, m, bpos);
-    hipLaunchKernelGGL(k_fill_i, dim3(nb(n)), dim3(256), 0, s, lmidx, n, -1);
-    hipLaunchKernelGGL(k_lm_index, dim3(nb(l)), dim3(256), 0, s, lm, l, lmidx);
+    // landmarks in block order (ranks in lmidx, first block of each batch)
+    int64_t *lkey = pool.get<int64_t>(l, &rc), *lkey2 = pool.get<int64_t>(l, &rc);
+    int32_t *lids = pool.get<int32_t>(l, &rc), *lmorder = pool.get<int32_t>(l, &rc);
+    if (rc < 0) return rc;
+    hipLaunchKernelGGL(k_lm_keys, dim3(nb(l)), dim3(256), 0, s, lm, (const int32_t *)lev, (const int32_t *)gblk_d, l,
+                       nblk, lkey, lids);
     ICHK(hipGetLastError());
+    if ((rc = sort_pairs(pool, lkey, lkey2, lids, lmorder, l, bits_for(nblk * l), s)) < 0) return rc;
+    hipLaunchKernelGGL(k_fill_i, dim3(nb(n)), dim3(256), 0, s, lmidx, n, -1);
+    hipLaunchKernelGGL(k_lm_index, dim3(nb(l)), dim3(256), 0, s, lm, (const int32_t *)lmorder, l, lmidx);
+    ICHK(hipGetLastError());
+    std::vector<int64_t> hlkey(l);
+    ICHK(hipMemcpyAsync(hlkey.data(), lkey2, l * 8, hipMemcpyDeviceToHost, s));
     const BlockMap bm{blk, bpos, uflag, lmidx, boff_d, doff_d, eoff_d};
 
     // M_uu in blocks
@@ -878,9 +904,12 @@ int blocked_entries(Pool &pool, const EdgeData &ed, int64_t n, int64_t l, int64_
         hipLaunchKernelGGL(k_block_rhs, dim3(nb(n)), dim3(256), 0, s, ed.rp, ed.dkey, ed.dval, ed.d, bm, n, m, c0, rr,
                            X);
         ICHK(hipGetLastError());
-        for (int64_t b = 0; b < nblk; ++b) {  // L y = rhs
+        // L y = rhs: the right-hand sides vanish on the blocks before the one
+        // above the batch's first landmark block, and so does y there
+        const int64_t bfirst = std::max<int64_t>(0, hlkey[c0] / l - 1);
+        for (int64_t b = bfirst; b < nblk; ++b) {
             double *Xb = X + boff[b];
-            if (b > 0)
+            if (b > bfirst)
                 IRB(rocblas_dgemm(hd.h, rocblas_operation_none, rocblas_operation_none, (int)bs[b], ri,
                                   (int)bs[b - 1], &mone, Mb + eoff[b - 1], (int)bs[b], X + boff[b - 1], mi, &one, Xb,
                                   mi));
@@ -899,7 +928,7 @@ int blocked_entries(Pool &pool, const EdgeData &ed, int64_t n, int64_t l, int64_
         hipLaunchKernelGGL(k_unpermute, dim3(nb(m), (unsigned)rr), dim3(256), 0, s, (const double *)X, uvert,
                            (const int32_t *)bpos, m, Xv);
         hipLaunchKernelGGL(k_topp, dim3((unsigned)rr), dim3(256), 0, s, (const double *)Xv, m, pk, c0, l, uvert,
-                           okey, oval, ocnt);
+                           (const int32_t *)lmorder, okey, oval, ocnt);
         ICHK(hipGetLastError());
     }
     hipLaunchKernelGGL(k_identity_rows, dim3(nb(l)), dim3(256), 0, s, lm, l, l * pk, okey, oval);

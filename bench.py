@@ -610,6 +610,55 @@ def interpolation_at_scale(sb, torch, big=False):
     return out
 
 
+def chain_batch(sb, torch, k, block, steps, count=256, nmin=2000, nmax=200_000, seed0=4004):
+    """The batched workload with every input built from the biharmonic chain
+    on the device: `count` bumpy tori and deformed geodesic spheres with
+    n ~ U[nmin, nmax] (synth.configs.batch_meshes), l = n/50, p_row = 10;
+    per mesh farthest-point landmarks and the geodesic W
+    (sbmds_landmarks_geodesic), then P (sbmds_interpolation); then the
+    certified k = 3 solve of all meshes in one context (autotuned launch
+    shapes) against one context per mesh (time_batch)."""
+    import numpy as np
+
+    from synth import configs
+    from synth import operator as op
+
+    t0 = time.perf_counter()
+    ms = configs.batch_meshes(count, nmin, nmax, seed0)
+    t_mesh = time.perf_counter() - t0
+    probs, t_graph, t_lw, t_p = [], 0.0, 0.0, 0.0
+    for i, m in enumerate(ms):
+        t0 = time.perf_counter()
+        G = op.edge_graph(m["V"], m["F"]).tocsr()
+        G.sort_indices()
+        arrs = [torch.from_numpy(a).cuda() for a in (G.indptr.astype(np.int32), G.indices.astype(np.int32), G.data)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lm, W = sb.landmarks_geodesic(*arrs, m["l"], m["first"], batch=256)
+        Wf = W.float().cpu().numpy()
+        t2 = time.perf_counter()
+        rp, col, val = sb.interpolation(m["V"], m["F"], lm.cpu().numpy(), p=m["p"])
+        t3 = time.perf_counter()
+        t_graph, t_lw, t_p = t_graph + (t1 - t0), t_lw + (t2 - t1), t_p + (t3 - t2)
+        probs.append({"n": m["n"], "l": m["l"], "rowptr": rp, "col": col, "val": val.astype(np.float32), "W": Wf})
+        del arrs, lm, W
+        if i % 16 == 15 or i == count - 1:
+            log(f"chain batch: {i + 1}/{count} meshes on the device (landmarks + W {t_lw:.1f} s, P {t_p:.1f} s)")
+    nnz = sum(len(p["col"]) for p in probs)
+    out = time_batch(sb, torch, probs, k, block, steps, 1,
+                     os.path.join(configs.cache_dir(), f"tune_chain{count}_k{k}_b{block}.txt"),
+                     workload=f"{count} bumpy tori and deformed geodesic spheres, n ~ U[{nmin}, {nmax}] "
+                              f"({sum(p['n'] for p in probs)} vertices), l = n/50 "
+                              f"({sum(p['l'] for p in probs)} landmarks), p_row = 10 ({nnz} stored entries); "
+                              f"landmarks, geodesic W and P built on the device; k = {k}, fp32 -> f64 certify",
+                     details=True)
+    out["inputs"] = {"host_meshes_s": round(t_mesh, 2), "host_edge_graphs_s": round(t_graph, 2),
+                     "gpu_landmarks_and_w_s": round(t_lw, 2), "gpu_p_s": round(t_p, 2),
+                     "w_bytes_float32": int(sum(4 * p["l"] ** 2 for p in probs))}
+    log(f"chain batch: {json.dumps({x: out[x] for x in ('ms', 'ms_one_context_per_mesh', 'inputs')})}")
+    return out
+
+
 def approximation_quality(sb, torch, nsample=128, reps=5):
     """The paper's quality measures as a second workload on the GPU, on a
     192 x 96 bumpy torus (n = 18,432, l = 369 FPS landmarks, the same
@@ -842,6 +891,8 @@ def partial_run(sb, torch, configs, args, k, blocks, want):
     if want("landmarks") and not args.no_landmarks:
         out["landmarks_geodesic"] = landmark_workload(sb, torch)
         out["landmarks_geodesic"]["input_chain"] = input_chain(sb, torch)
+    if want("batch_chain"):
+        out["batched_chain"] = chain_batch(sb, torch, k, blocks[0], max(1, min(args.steps, 3)))
     if want("interp") or want("interp_big"):
         out["interpolation_at_scale"] = interpolation_at_scale(sb, torch, big=want("interp_big"))
     if want("quality") and not args.no_quality:
@@ -868,7 +919,7 @@ def main():
     ap.add_argument("--no-landmarks", action="store_true", help="skip the device landmark / W workload")
     ap.add_argument("--workloads", type=str, default="",
                     help="comma list of workloads to run (headline, routes, cpu, sphere, batch, scale, landmarks, "
-                         "quality, torus, interp, interp_big); default all but interp_big.  Without the headline the line carries no value (for "
+                         "quality, torus, interp, interp_big, batch_chain); default all but interp_big and batch_chain.  Without the headline the line carries no value (for "
                          "profiling one workload)")
     ap.add_argument("--forms", type=str, default="",
                     help="comma-separated headline forms to time (default: all; plain fp32 always)")

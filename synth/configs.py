@@ -170,13 +170,15 @@ def bumpy_torus(nu, nv, l=None, p_row=10, seed=3003, use_cache=True, log=None, g
     return _cached(f"bumpy_torus{nu}x{nv}", params, make, use_cache, log, generate)
 
 
-def mesh_batch(count=16, nmin=2000, nmax=20000, seed0=4004, p_row=10, use_cache=True, log=None):
-    """Many meshes of uneven size (the batched workload's recipe at reduced
-    scale): n_i ~ U[nmin, nmax] from default_rng(seed0); even i is a bumpy
-    torus with n_v = round(sqrt(n_i / 2)), n_u = round(n_i / n_v); odd i is a
+def batch_meshes(count=16, nmin=2000, nmax=20000, seed0=4004, p_row=10):
+    """The meshes of the batched workload's recipe, without their inputs:
+    n_i ~ U[nmin, nmax] from default_rng(seed0); even i is a bumpy torus
+    with n_v = round(sqrt(n_i / 2)), n_u = round(n_i / n_v); odd i is a
     class-I geodesic sphere of frequency round(sqrt((n_i - 2) / 10)) with the
     radial spherical-harmonic deformation of sphere7; l_i = round(n_i / 50),
-    seed seed0 + i for the mesh and its landmarks."""
+    seed seed0 + i for the mesh and its landmarks (the first landmark is
+    default_rng(seed).integers(n), as in the input chain).  Returns dicts
+    with V, F, n, l, p, seed, first, kind and the mesh's parameters."""
     rng = np.random.default_rng(seed0)
     sizes = rng.integers(nmin, nmax + 1, size=count)
     out = []
@@ -185,20 +187,36 @@ def mesh_batch(count=16, nmin=2000, nmax=20000, seed0=4004, p_row=10, use_cache=
         if i % 2 == 0:
             nv = max(3, int(round(np.sqrt(ni / 2))))
             nu = max(3, int(round(ni / nv)))
-            prob = bumpy_torus(nu, nv, l=max(2, int(round(nu * nv / 50))), p_row=p_row, seed=seed,
-                               use_cache=use_cache, log=log)
+            V, F = meshes.bumpy_torus(nu, nv, seed)
+            d = {"kind": "torus", "nu": nu, "nv": nv}
         else:
             freq = max(1, int(round(np.sqrt((ni - 2) / 10))))
-            n = 10 * freq * freq + 2
-            l = max(2, int(round(n / 50)))
-            params = dict(freq=freq, l=l, p_row=p_row, seed=seed, v=1)
+            V, F = meshes.geodesic_sphere(freq)
+            V = meshes._radial_deform(V, seed, 0.05, 8, 6)
+            d = {"kind": "geosphere", "freq": freq}
+        n = V.shape[0]
+        l = max(2, int(round(n / 50)))
+        d.update(V=V, F=F, n=n, l=l, p=op.p_from_prow(n, l, p_row), p_row=p_row, seed=seed,
+                 first=int(np.random.default_rng(seed).integers(n)))
+        out.append(d)
+    return out
 
-            def make(freq=freq, l=l, seed=seed):
-                V, F = meshes.geodesic_sphere(freq)
-                V = meshes._radial_deform(V, seed, 0.05, 8, 6)
-                return build_problem(V, F, l, p_row, seed, np.float32, log=log)
 
-            prob = _cached(f"geosphere{freq}", params, make, use_cache, log)
+def mesh_batch(count=16, nmin=2000, nmax=20000, seed0=4004, p_row=10, use_cache=True, log=None):
+    """The batched workload's recipe (batch_meshes) at reduced scale with
+    every mesh's input chain run on the host (cached)."""
+    out = []
+    for m in batch_meshes(count, nmin, nmax, seed0, p_row):
+        seed, l = m["seed"], m["l"]
+        if m["kind"] == "torus":
+            prob = bumpy_torus(m["nu"], m["nv"], l=l, p_row=p_row, seed=seed, use_cache=use_cache, log=log)
+        else:
+            params = dict(freq=m["freq"], l=l, p_row=p_row, seed=seed, v=1)
+
+            def make(m=m):
+                return build_problem(m["V"], m["F"], m["l"], p_row, m["seed"], np.float32, log=log)
+
+            prob = _cached(f"geosphere{m['freq']}", params, make, use_cache, log)
         out.append(prob)
     return out
 

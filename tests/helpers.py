@@ -98,3 +98,20 @@ def random_problem(n, l, row_len_max, seed, dtype=np.float32, empty_rows=0.0, lo
 def as_csr(prob):
     return sp.csr_matrix((prob["val"].astype(np.float64), prob["col"], prob["rowptr"]),
                          shape=(prob["n"], prob["l"]))
+
+
+def device_chain(sb, torch, m):
+    """The input chain of one mesh on the device: farthest-point landmarks
+    from m["first"] and W (sbmds_landmarks_geodesic on the edge graph), then
+    P (sbmds_interpolation); W and P's values rounded to float32 as the
+    host generator stores them."""
+    from synth import operator as op
+
+    G = op.edge_graph(m["V"], m["F"]).tocsr()
+    G.sort_indices()
+    arrs = [torch.from_numpy(a).cuda() for a in (G.indptr.astype(np.int32), G.indices.astype(np.int32), G.data)]
+    lm, W = sb.landmarks_geodesic(*arrs, m["l"], m["first"], batch=256)
+    lmh = lm.cpu().numpy()
+    rp, col, val = sb.interpolation(m["V"], m["F"], lmh, p=m["p"])
+    return {"n": m["n"], "l": m["l"], "p": m["p"], "landmarks": lmh, "rowptr": rp, "col": col,
+            "val": val.astype(np.float32), "val64": val, "W": W.float().cpu().numpy()}

@@ -124,6 +124,36 @@ def test_mesh_batch_matches_oracle(gpu, prec):
     print(f"{prec}: 16 meshes, worst rel eig err {worst:.2e}", flush=True)
 
 
+def test_device_chain_batch_matches_host_chain(gpu):
+    # the same 16 meshes with their inputs built on the device (landmarks,
+    # geodesic W, P by the blocked route for n > 4096): landmarks and W equal
+    # the host chain's bit for bit, P's pattern equal and its float32 values
+    # within one rounding; the batched solve on the device inputs matches
+    # the oracle on them
+    import torch
+
+    from synth import configs
+    sb = gpu
+    host = configs.mesh_batch()
+    dev = [H.device_chain(sb, torch, m) for m in configs.batch_meshes()]
+    for i, (d, h) in enumerate(zip(dev, host)):
+        assert np.array_equal(d["landmarks"], h["landmarks"]), i
+        assert np.array_equal(d["W"], h["W"]), i
+        assert np.array_equal(d["rowptr"], h["rowptr"]) and np.array_equal(d["col"], h["col"]), i
+        hv = h["val"].astype(np.float64)
+        assert np.all(np.abs(d["val"] - hv) <= 2.0 ** -23 * np.abs(hv) + 1e-12), i
+    Z, eig, reps, rc, _ = solve(sb, dev, sb.FP32)
+    assert rc == 0
+    worst = 0.0
+    for i, (p, Zi) in enumerate(zip(dev, split_rows(Z, dev))):
+        lam, V, _ = H.oracle_for(p, 3)
+        err = H.rel_eig_err(eig[i], lam[:3])
+        worst = max(worst, err)
+        assert reps[i]["certified"] and err <= 1e-6, (i, p["n"], eig[i], lam[:3])
+        assert H.subspace_angle(Zi, V, lam, 3, tol=1e-6) <= 3.0, i
+    print(f"device chain: 16 meshes, worst rel eig err {worst:.2e}", flush=True)
+
+
 GOLDEN_256 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "grid_torus_batch256.npz")
 
 

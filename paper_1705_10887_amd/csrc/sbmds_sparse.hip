@@ -896,8 +896,8 @@ __global__ __launch_bounds__(256) void k_spmmt_reduce(const ProbView *__restrict
 // ---------------------------------------------------------------------------
 
 // Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
-// easy as 1, 2, 3", SC 2011): counter = (row, column, row >> 32, problem),
-// key = seed.
+// easy as 1, 2, 3", SC 2011): four 32-bit words of counter (each use below
+// states its layout), key = seed.
 __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
     const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
     const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
@@ -926,30 +926,54 @@ __device__ __forceinline__ float gauss_from(uint32_t a, uint32_t b) {
     return sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
 }
 
+// Two standard normals from two uniforms (Box-Muller: the radius from the
+// first, the angle from the second, both its cosine and its sine).
+__device__ __forceinline__ void gauss_pair(uint32_t a, uint32_t b, float &z0, float &z1) {
+    const float u1 = ((float)(a >> 8) + 1.0f) * (1.0f / 16777216.0f);
+    const float u2 = (float)(b >> 8) * (1.0f / 16777216.0f);
+    const float r = sqrtf(-2.0f * logf(u1));
+    float sn, cs;
+    sincospif(2.0f * u2, &sn, &cs);
+    z0 = r * cs;
+    z1 = r * sn;
+}
+
 // Start block into buffer 0 (random, or the caller's block); columns >= b
-// are zero.
+// are zero.  One thread per four consecutive columns of a row: a random
+// block takes the four outputs of one Philox call (counter = row, column
+// quad, row >> 32, problem) as two Box-Muller pairs, so the integer
+// multiplies of the generator, which bound this kernel, are a quarter of
+// one call per element.  The launch has one thread per element; the last
+// three quarters of a problem's blocks have no work.
 template <int M, int B, int USER, typename TS>
 __global__ __launch_bounds__(256) void k_start_block(const ProbView *__restrict__ views, const int *__restrict__ off,
                                                      int nprob, int b, uint64_t seed) {
     using TY = typename Traits<M>::TY;
     using TA = typename Traits<M>::TA;
+    static_assert(B % 4 == 0, "whole column quads");
     const int p = find_problem(off, nprob, blockIdx.x);
     const ProbView &v = views[p];
-    const int64_t idx = (int64_t)(blockIdx.x - off[p]) * 256 + threadIdx.x;
-    if (idx >= (int64_t)v.n * B) return;
-    const int64_t row = idx / B;
-    const int col = (int)(idx % B);
-    TA z = (TA)0;
-    if (col < b) {
-        if (USER) {
-            z = (TA)((const TS *)v.X0)[row * b + col];
-        } else {
-            uint32_t ctr[4] = {(uint32_t)row, (uint32_t)col, (uint32_t)(row >> 32), (uint32_t)p};
-            philox4x32_10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32));
-            z = (TA)gauss_from(ctr[0], ctr[1]);
-        }
+    const int64_t q = (int64_t)(blockIdx.x - off[p]) * 256 + threadIdx.x;
+    if (q >= (int64_t)v.n * (B / 4)) return;
+    const int64_t row = q / (B / 4);
+    const int c0 = (int)(q % (B / 4)) * 4;
+    float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    TA zu[4] = {(TA)0, (TA)0, (TA)0, (TA)0};
+    if (USER) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (c0 + t < b) zu[t] = (TA)((const TS *)v.X0)[row * b + c0 + t];
+    } else if (c0 < b) {
+        uint32_t ctr[4] = {(uint32_t)row, (uint32_t)(c0 >> 2), (uint32_t)(row >> 32), (uint32_t)p};
+        philox4x32_10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32));
+        gauss_pair(ctr[0], ctr[1], z[0], z[1]);
+        gauss_pair(ctr[2], ctr[3], z[2], z[3]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) zu[t] = c0 + t < b ? (TA)z[t] : (TA)0;
     }
-    ((TY *)v.Y0)[idx] = down<TY>(z);
+    TY *dst = (TY *)v.Y0 + row * B + c0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) dst[t] = down<TY>(zu[t]);
 }
 
 // Precision change at the start of phase `phase`: the current block is

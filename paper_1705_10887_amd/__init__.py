@@ -451,7 +451,9 @@ def interpolation(V, F, landmarks, p=None, graph=False, route=None):
     pk = 0 if p is None else int(p)
     flags = INTERP_GRAPH if graph else 0
     if route is not None:
-        flags |= {"dense": INTERP_DENSE, "blocked": INTERP_BLOCKED}[route]
+        if route not in ("dense", "blocked"):
+            raise ValueError(f"route must be 'dense', 'blocked' or None, not {route!r}")
+        flags |= INTERP_DENSE if route == "dense" else INTERP_BLOCKED
     cap = l + l * (m if pk <= 0 or pk >= m else pk)
     rowptr = np.empty(n + 1, dtype=np.int32)
     col = np.empty(max(cap, 1), dtype=np.int32)

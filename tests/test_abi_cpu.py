@@ -211,3 +211,5 @@ def test_interpolation_argument_checks_without_gpu():
     assert L.sbmds_interpolation(V.ctypes.data, 1 << 30, F.ctypes.data, 2, lm.ctypes.data, 1, 2,
                                  sb.INTERP_BLOCKED, *tail) == -1
     assert b"2^30" in L.sbmds_last_error()
+    with pytest.raises(ValueError):
+        sb.interpolation(V, F, lm, p=2, route="sparse")

@@ -861,24 +861,60 @@ int blocked_entries(Pool &pool, const EdgeData &ed, int64_t n, int64_t l, int64_
     ICHK(hipStreamSynchronize(s));
     if (herr) return api_fail(SBMDS_EHIP, "blocked route: M_uu is not block tridiagonal in the level order");
 
-    // block Cholesky: D_b -= E_{b-1} E_{b-1}^T; D_b = L_bb L_bb^T; E_b = E_b L_bb^-T
+    // Block Cholesky from both ends ("twisted"): the blocks above the
+    // meeting block k are eliminated downwards and the blocks below it
+    // upwards; block k takes the Schur complements of both and is
+    // eliminated last.
+    //   top, b < k:     D_b -= E_{b-1} E_{b-1}^T, D_b = L_bb L_bb^T,
+    //                   E_b <- E_b L_bb^-T
+    //   bottom, b > k:  D_b -= H_b^T H_b, D_b = L_bb L_bb^T,
+    //                   E_{b-1} <- H_{b-1} = L_bb^-1 E_{b-1}
+    //   k:              D_k -= E_{k-1} E_{k-1}^T + H_k^T H_k, D_k = L_kk L_kk^T
+    // (E_b, rows of block b+1 by columns of block b, holds its top or bottom
+    // form in place.)  k splits sum s_b^2 in halves.  Eliminating from both
+    // ends lets a batch's forward solve cover only the blocks between its
+    // first and last landmark: the right-hand sides, and so the forward
+    // solution, vanish on both chain ends outside them.  The two chains are
+    // independent; they run one after the other on the caller's stream.
+    int64_t kmid = 0;
+    {
+        double tot = 0.0, run = 0.0;
+        for (int64_t b = 0; b < nblk; ++b) tot += (double)bs[b] * (double)bs[b];
+        while (kmid + 1 < nblk && run + (double)bs[kmid] * (double)bs[kmid] < 0.5 * tot)
+            run += (double)bs[kmid] * (double)bs[kmid], ++kmid;
+    }
     Handle hd;
     IRB(rocblas_create_handle(&hd.h));
     IRB(rocblas_set_stream(hd.h, s));
     const double one = 1.0, mone = -1.0;
+    auto sz = [&](int64_t b) { return (int)bs[b]; };
+    auto Dp = [&](int64_t b) { return Mb + doff[b]; };
+    auto Ep = [&](int64_t b) { return Mb + eoff[b]; };
+    // D -= A^T A for A (k x n, lda k): the lower triangle of D is what the
+    // factorisation reads
+    auto sub_ata = [&](rocblas_handle h, double *D, int nn, const double *A, int kk) {
+        return rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_transpose, nn, kk, &mone, A, kk, &one, D, nn);
+    };
     ICHK(hipMemsetAsync(info, 0, nblk * 4, s));
-    for (int64_t b = 0; b < nblk; ++b) {
-        const int sb = (int)bs[b];
-        double *D = Mb + doff[b];
+    for (int64_t b = 0; b < kmid; ++b) {
         if (b > 0)
-            IRB(rocblas_dsyrk(hd.h, rocblas_fill_lower, rocblas_operation_none, sb, (int)bs[b - 1], &mone,
-                              Mb + eoff[b - 1], sb, &one, D, sb));
-        IRB(rocsolver_dpotrf(hd.h, rocblas_fill_lower, sb, D, sb, info + b));
-        if (b + 1 < nblk)
-            IRB(rocblas_dtrsm(hd.h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
-                              rocblas_diagonal_non_unit, (int)bs[b + 1], sb, &one, D, sb, Mb + eoff[b],
-                              (int)bs[b + 1]));
+            IRB(rocblas_dsyrk(hd.h, rocblas_fill_lower, rocblas_operation_none, sz(b), sz(b - 1), &mone, Ep(b - 1),
+                              sz(b), &one, Dp(b), sz(b)));
+        IRB(rocsolver_dpotrf(hd.h, rocblas_fill_lower, sz(b), Dp(b), sz(b), info + b));
+        IRB(rocblas_dtrsm(hd.h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                          rocblas_diagonal_non_unit, sz(b + 1), sz(b), &one, Dp(b), sz(b), Ep(b), sz(b + 1)));
     }
+    for (int64_t b = nblk - 1; b > kmid; --b) {
+        if (b + 1 < nblk) IRB(sub_ata(hd.h, Dp(b), sz(b), Ep(b), sz(b + 1)));
+        IRB(rocsolver_dpotrf(hd.h, rocblas_fill_lower, sz(b), Dp(b), sz(b), info + b));
+        IRB(rocblas_dtrsm(hd.h, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
+                          rocblas_diagonal_non_unit, sz(b), sz(b - 1), &one, Dp(b), sz(b), Ep(b - 1), sz(b)));
+    }
+    if (kmid > 0)
+        IRB(rocblas_dsyrk(hd.h, rocblas_fill_lower, rocblas_operation_none, sz(kmid), sz(kmid - 1), &mone,
+                          Ep(kmid - 1), sz(kmid), &one, Dp(kmid), sz(kmid)));
+    if (kmid + 1 < nblk) IRB(sub_ata(hd.h, Dp(kmid), sz(kmid), Ep(kmid), sz(kmid + 1)));
+    IRB(rocsolver_dpotrf(hd.h, rocblas_fill_lower, sz(kmid), Dp(kmid), sz(kmid), info + kmid));
     {
         std::vector<int> hi(nblk);
         ICHK(hipMemcpyAsync(hi.data(), info, nblk * 4, hipMemcpyDeviceToHost, s));
@@ -904,26 +940,40 @@ int blocked_entries(Pool &pool, const EdgeData &ed, int64_t n, int64_t l, int64_
         hipLaunchKernelGGL(k_block_rhs, dim3(nb(n)), dim3(256), 0, s, ed.rp, ed.dkey, ed.dval, ed.d, bm, n, m, c0, rr,
                            X);
         ICHK(hipGetLastError());
-        // L y = rhs: the right-hand sides vanish on the blocks before the one
-        // above the batch's first landmark block, and so does y there
+        auto Xp = [&](int64_t b) { return X + boff[b]; };
+        auto gemm = [&](rocblas_handle h, rocblas_operation ta, int64_t b, const double *A, int lda, int64_t bsrc) {
+            return rocblas_dgemm(h, ta, rocblas_operation_none, sz(b), ri, sz(bsrc), &mone, A, lda, Xp(bsrc), mi,
+                                 &one, Xp(b), mi);
+        };
+        auto trsm = [&](rocblas_handle h, rocblas_operation ta, int64_t b) {
+            return rocblas_dtrsm(h, rocblas_side_left, rocblas_fill_lower, ta, rocblas_diagonal_non_unit, sz(b), ri,
+                                 &one, Dp(b), sz(b), Xp(b), mi);
+        };
+        // L y = rhs.  The batch's landmarks lie in blocks [first, last] of
+        // the level order, so its right-hand sides vanish outside
+        // [first - 1, last + 1], and so does y on the chain ends before them.
         const int64_t bfirst = std::max<int64_t>(0, hlkey[c0] / l - 1);
-        for (int64_t b = bfirst; b < nblk; ++b) {
-            double *Xb = X + boff[b];
-            if (b > bfirst)
-                IRB(rocblas_dgemm(hd.h, rocblas_operation_none, rocblas_operation_none, (int)bs[b], ri,
-                                  (int)bs[b - 1], &mone, Mb + eoff[b - 1], (int)bs[b], X + boff[b - 1], mi, &one, Xb,
-                                  mi));
-            IRB(rocblas_dtrsm(hd.h, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
-                              rocblas_diagonal_non_unit, (int)bs[b], ri, &one, Mb + doff[b], (int)bs[b], Xb, mi));
+        const int64_t blast = std::min<int64_t>(nblk - 1, hlkey[c0 + rr - 1] / l + 1);
+        for (int64_t b = bfirst; b < kmid; ++b) {
+            if (b > bfirst) IRB(gemm(hd.h, rocblas_operation_none, b, Ep(b - 1), sz(b), b - 1));
+            IRB(trsm(hd.h, rocblas_operation_none, b));
         }
-        for (int64_t b = nblk - 1; b >= 0; --b) {  // L^T x = y
-            double *Xb = X + boff[b];
-            if (b + 1 < nblk)
-                IRB(rocblas_dgemm(hd.h, rocblas_operation_transpose, rocblas_operation_none, (int)bs[b], ri,
-                                  (int)bs[b + 1], &mone, Mb + eoff[b], (int)bs[b + 1], X + boff[b + 1], mi, &one, Xb,
-                                  mi));
-            IRB(rocblas_dtrsm(hd.h, rocblas_side_left, rocblas_fill_lower, rocblas_operation_transpose,
-                              rocblas_diagonal_non_unit, (int)bs[b], ri, &one, Mb + doff[b], (int)bs[b], Xb, mi));
+        for (int64_t b = blast; b > kmid; --b) {
+            if (b < blast) IRB(gemm(hd.h, rocblas_operation_transpose, b, Ep(b), sz(b + 1), b + 1));
+            IRB(trsm(hd.h, rocblas_operation_none, b));
+        }
+        if (kmid > 0) IRB(gemm(hd.h, rocblas_operation_none, kmid, Ep(kmid - 1), sz(kmid), kmid - 1));
+        if (kmid + 1 < nblk) IRB(gemm(hd.h, rocblas_operation_transpose, kmid, Ep(kmid), sz(kmid + 1), kmid + 1));
+        IRB(trsm(hd.h, rocblas_operation_none, kmid));
+        // L^T x = y: block k, then both chains outwards
+        IRB(trsm(hd.h, rocblas_operation_transpose, kmid));
+        for (int64_t b = kmid - 1; b >= 0; --b) {
+            IRB(gemm(hd.h, rocblas_operation_transpose, b, Ep(b), sz(b + 1), b + 1));
+            IRB(trsm(hd.h, rocblas_operation_transpose, b));
+        }
+        for (int64_t b = kmid + 1; b < nblk; ++b) {
+            IRB(gemm(hd.h, rocblas_operation_none, b, Ep(b - 1), sz(b), b - 1));
+            IRB(trsm(hd.h, rocblas_operation_transpose, b));
         }
         hipLaunchKernelGGL(k_unpermute, dim3(nb(m), (unsigned)rr), dim3(256), 0, s, (const double *)X, uvert,
                            (const int32_t *)bpos, m, Xv);

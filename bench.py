@@ -610,6 +610,53 @@ def interpolation_at_scale(sb, torch, big=False):
     return out
 
 
+def chain_torus(sb, torch):
+    """The whole input chain of the 1024 x 512 bumpy torus (n = 524,288,
+    l = 10,000, p = 514) on the device -- farthest-point landmarks, the
+    geodesic W, then P by the level-blocked route -- against the generator's
+    output for the same mesh and first landmark (stored; about an hour of
+    host time): landmarks and float32 W bit for bit, P's kept entries."""
+    import numpy as np
+
+    from synth import configs
+    from synth import operator as op
+
+    prob = configs.bumpy_torus(1024, 512, l=10000, generate=False)
+    if prob is None:
+        return "input not cached"
+    V, F, l, p = prob["V"], prob["F"], prob["l"], prob["p"]
+    G = op.edge_graph(V, F).tocsr()
+    G.sort_indices()
+    arrs = [torch.from_numpy(a).cuda() for a in (G.indptr.astype(np.int32), G.indices.astype(np.int32), G.data)]
+    first = int(prob["landmarks"][0])
+    sb.landmarks_geodesic(*arrs, 8, first)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lm, _ = sb.landmarks_geodesic(*arrs, l, first, want_W=False)
+    torch.cuda.synchronize()
+    t_fps = time.perf_counter() - t0
+    log(f"chain torus: {l} landmarks in {t_fps:.2f} s")
+    t0 = time.perf_counter()
+    lm, W = sb.landmarks_geodesic(*arrs, l, first, batch=256)
+    torch.cuda.synchronize()
+    t_lw = time.perf_counter() - t0
+    lmh = lm.cpu().numpy()
+    same_lm = bool(np.array_equal(lmh, prob["landmarks"]))
+    same_w = bool(np.array_equal(W.float().cpu().numpy(), prob["W"]))
+    del W, arrs
+    log(f"chain torus: landmarks + W in {t_lw:.1f} s (landmarks equal {same_lm}, W equal {same_w})")
+    t0 = time.perf_counter()
+    got = sb.interpolation(V, F, lmh, p=p)
+    t_p = time.perf_counter() - t0
+    odd, worst = _p_agreement(prob["n"], l, got, (prob["rowptr"], prob["col"], prob["val"]))
+    out = {"n": int(prob["n"]), "l": l, "p": int(p), "gpu_landmarks_s": round(t_fps, 2),
+           "gpu_landmarks_and_w_s": round(t_lw, 2), "gpu_p_s": round(t_p, 2), "landmarks_equal_generator": same_lm,
+           "w_float32_equal_generator": same_w, "p_entries_kept_by_one_side_only": int(odd),
+           "p_max_rel_diff_float32": worst}
+    log(f"chain torus: {out}")
+    return out
+
+
 def chain_batch(sb, torch, k, block, steps, count=256, nmin=2000, nmax=200_000, seed0=4004):
     """The batched workload with every input built from the biharmonic chain
     on the device: `count` bumpy tori and deformed geodesic spheres with
@@ -907,6 +954,8 @@ def partial_run(sb, torch, configs, args, k, blocks, want):
     if want("landmarks") and not args.no_landmarks:
         out["landmarks_geodesic"] = landmark_workload(sb, torch)
         out["landmarks_geodesic"]["input_chain"] = input_chain(sb, torch)
+    if want("chain_torus"):
+        out["chain_torus_1024x512"] = chain_torus(sb, torch)
     if want("batch_chain"):
         out["batched_chain"] = chain_batch(sb, torch, k, blocks[0], max(1, min(args.steps, 3)))
     if want("interp") or want("interp_big"):
@@ -935,7 +984,7 @@ def main():
     ap.add_argument("--no-landmarks", action="store_true", help="skip the device landmark / W workload")
     ap.add_argument("--workloads", type=str, default="",
                     help="comma list of workloads to run (headline, routes, cpu, sphere, batch, scale, landmarks, "
-                         "quality, torus, interp, interp_big, batch_chain); default all but interp_big and batch_chain.  Without the headline the line carries no value (for "
+                         "quality, torus, interp, interp_big, batch_chain, chain_torus); default all but the last three.  Without the headline the line carries no value (for "
                          "profiling one workload)")
     ap.add_argument("--forms", type=str, default="",
                     help="comma-separated headline forms to time (default: all; plain fp32 always)")

@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -233,13 +234,24 @@ __global__ __launch_bounds__(kSearchThreads) void k_fps_search(FpsState s, const
 
 // ---------------------------------------------------------------------------
 // Full searches from S sources at once (the landmark block).  The frontier
-// holds (source slot, vertex) pairs as slot << 32 | vertex.
+// holds (source slot, vertex) pairs as slot << 32 | vertex.  Relaxations go
+// in distance buckets (near-far): a pair whose new distance is below the
+// current threshold joins the next round's frontier, one at or above it
+// waits (once) on a far list; when the frontier runs empty the threshold
+// moves past the smallest waiting distance and the far pairs below it
+// return.  Rounds in hop order alone relax a vertex again each time a path
+// with more hops but a smaller length reaches it (six to nine times per
+// vertex on the meshes here); buckets a few edges wide keep that near one.
 struct MultiState {
     unsigned long long *dist;  // [S][n]
-    int32_t *inq;              // [S][n]
+    int32_t *inq;              // [S][n] round stamp of the last queueing
+    int32_t *farf;             // [S][n] 1 while the pair waits on a far list
     int64_t *front[2];
+    int64_t *far[2];           // far lists: one gets this bucket's pairs, the other the pairs kept at a refill
     int *cnt;                  // [3]
+    int *fcnt;                 // [2]
     int *last;                 // [1] last round that had a non-empty frontier
+    unsigned long long *fmin;  // [1] smallest distance on a far list (bits)
 };
 
 __global__ __launch_bounds__(256) void k_ms_begin(MultiState s, const int32_t *__restrict__ lm, int first, int S,
@@ -256,12 +268,14 @@ __global__ __launch_bounds__(256) void k_ms_begin(MultiState s, const int32_t *_
         s.cnt[0] = S;
         s.cnt[1] = 0;
         s.cnt[2] = 0;
+        s.fcnt[0] = 0;
+        s.fcnt[1] = 0;
     }
 }
 
 __global__ __launch_bounds__(256) void k_ms_round(MultiState s, const int32_t *__restrict__ rp,
                                                   const int32_t *__restrict__ ci, const double *__restrict__ w,
-                                                  int64_t n, int round) {
+                                                  int64_t n, int round, double thr, int fsel) {
     const int in = round % 3, out = (round + 1) % 3, clr = (round + 2) % 3;
     const int64_t *fin = s.front[round & 1];
     int64_t *fout = s.front[(round + 1) & 1];
@@ -278,15 +292,58 @@ __global__ __launch_bounds__(256) void k_ms_round(MultiState s, const int32_t *_
         const double du = as_d(dq[u]);
         for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
             const int32_t v = ci[e];
-            const unsigned long long cb = as_b(du + w[e]);
-            bool queue = false;
+            const double cd = du + w[e];
+            const unsigned long long cb = as_b(cd);
+            bool queue = false, defer = false;
             if (cb < dq[v]) {
                 const unsigned long long old = atomicMin(&dq[v], cb);
-                queue = cb < old && atomicExch(&s.inq[q * n + v], round + 2) != round + 2;
+                if (cb < old) {
+                    if (cd < thr) queue = atomicExch(&s.inq[q * n + v], round + 2) != round + 2;
+                    else defer = atomicExch(&s.farf[q * n + v], 1) == 0;
+                }
             }
             wave_append(fout, &s.cnt[out], queue, (q << 32) | v);
+            wave_append(s.far[fsel], &s.fcnt[fsel], defer, (q << 32) | v);
         }
     }
+}
+
+// Smallest distance among the pairs on far list fsel.
+__global__ __launch_bounds__(256) void k_ms_farmin(MultiState s, int fsel, int64_t n) {
+    const int count = s.fcnt[fsel];
+    const int64_t *lst = s.far[fsel];
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < count; i += gridDim.x * 256) {
+        const int64_t key = lst[i];
+        atomicMin(s.fmin, s.dist[(key >> 32) * n + (key & 0xffffffffll)]);
+    }
+}
+
+// Next bucket: the pairs of far list fsel below thr join the frontier of
+// round `round` (stamped as queued for it), the others move to the other far
+// list.  (A pair lowered below an earlier threshold after it was deferred
+// was processed then; processing it again changes nothing.)
+__global__ __launch_bounds__(256) void k_ms_refill(MultiState s, int fsel, double thr, int round, int64_t n) {
+    const int count = s.fcnt[fsel];
+    const int64_t *lst = s.far[fsel];
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < count; i += gridDim.x * 256) {
+        const int64_t key = lst[i];
+        const int64_t at = (key >> 32) * n + (key & 0xffffffffll);
+        const bool below = as_d(s.dist[at]) < thr;
+        bool to_near = false;
+        if (below) {
+            s.farf[at] = 0;
+            to_near = atomicExch(&s.inq[at], round + 1) != round + 1;
+        }
+        wave_append(s.front[round & 1], &s.cnt[round % 3], to_near, key);
+        wave_append(s.far[fsel ^ 1], &s.fcnt[fsel ^ 1], !below, key);
+    }
+}
+
+// Largest edge weight (bits of a positive double), for the bucket width.
+__global__ __launch_bounds__(256) void k_geo_wmax(const double *__restrict__ w, int64_t nnz,
+                                                  unsigned long long *__restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < nnz) atomicMax(out, as_b(w[e]));
 }
 
 // D[(first + q) l + t] = distance from source first + q to landmark t.
@@ -348,28 +405,6 @@ struct DevMem {
 
 unsigned nblk(int64_t c) { return (unsigned)((c + 255) / 256); }
 
-// Rounds until the frontier is empty: first `first` rounds (one more than
-// the previous search needed, so usually a single check), then
-// kRoundsPerCheck between checks; rounds on an empty frontier do nothing.
-// *used receives the rounds that had work.
-template <typename Launch>
-int run_rounds(Launch launch, const int *cnt, const int *last, int *hcnt, hipStream_t s, int64_t max_rounds,
-               int first, int *used) {
-    int r = 0, batch = std::max(first, kRoundsPerCheck);
-    while (true) {
-        for (int q = 0; q < batch; ++q, ++r) GCHK(launch(r));
-        GCHK(hipMemcpyAsync(hcnt, cnt + (r % 3), sizeof(int), hipMemcpyDeviceToHost, s));
-        GCHK(hipMemcpyAsync(hcnt + 1, last, sizeof(int), hipMemcpyDeviceToHost, s));
-        GCHK(hipStreamSynchronize(s));
-        if (*hcnt == 0) {
-            *used = hcnt[1] + 2;
-            return SBMDS_OK;
-        }
-        if (r > max_rounds) return api_fail(SBMDS_EHIP, "a shortest-path search did not settle");
-        batch = kRoundsPerCheck;
-    }
-}
-
 int geodesic_impl(const int32_t *rp_in, const int32_t *ci_in, const double *w_in, int64_t n, int64_t nnz, int64_t l,
                   int32_t first, int32_t *landmarks, double *W, int mem, int batch, hipStream_t s) {
     const bool host = mem == SBMDS_MEM_HOST;
@@ -382,7 +417,7 @@ int geodesic_impl(const int32_t *rp_in, const int32_t *ci_in, const double *w_in
     const int64_t nch = (n + kChunk - 1) / kChunk;
     size_t total = 2 * al(bn8) + 4 * al(bn4) + al((size_t)l * 4) + 2 * al((size_t)nch * 8) + 2 * al((size_t)nch * 4) +
                    4096;
-    if (want_w) total += al(bS8) + al(bS4) + 2 * al(bS8) + 2 * al(bL);
+    if (want_w) total += al(bS8) + 2 * al(bS4) + 4 * al(bS8) + 2 * al(bL);
     if (host) total += al((size_t)(n + 1) * 4) + al((size_t)nnz * 4) + al((size_t)nnz * 8);
     DevMem mem_;
     if (hipMalloc(&mem_.p, total) != hipSuccess) {
@@ -408,8 +443,11 @@ int geodesic_impl(const int32_t *rp_in, const int32_t *ci_in, const double *w_in
     if (want_w) {
         ms.dist = (unsigned long long *)take(bS8);
         ms.inq = (int32_t *)take(bS4);
+        ms.farf = (int32_t *)take(bS4);
         ms.front[0] = (int64_t *)take(bS8);
         ms.front[1] = (int64_t *)take(bS8);
+        ms.far[0] = (int64_t *)take(bS8);
+        ms.far[1] = (int64_t *)take(bS8);
         D = (double *)take(bL);
         Wd = (double *)take(bL);
     }
@@ -422,10 +460,10 @@ int geodesic_impl(const int32_t *rp_in, const int32_t *ci_in, const double *w_in
     fs.err = small;
     ms.cnt = small + 8;
     ms.last = small + 12;
+    ms.fcnt = small + 20;
+    ms.fmin = (unsigned long long *)(small + 24);
+    unsigned long long *dwmax = (unsigned long long *)(small + 26);
     unsigned long long *derr = (unsigned long long *)(small + 16);
-    int *hcnt = nullptr;
-    std::vector<int> hc(2);
-    hcnt = hc.data();
     const int32_t *rp = rp_in, *ci = ci_in;
     const double *w = w_in;
     if (host) {
@@ -457,7 +495,6 @@ int geodesic_impl(const int32_t *rp_in, const int32_t *ci_in, const double *w_in
     GCHK(hipMemcpyAsync(fs.lm, &first, 4, hipMemcpyHostToDevice, s));
     GCHK(hipGetLastError());
     const int64_t max_rounds = 4 * n + 64;  // a search settles within n rounds
-    int ms_rounds = kRoundsPerCheck;
     GCHK(hipMemsetAsync(fs.err, 0, sizeof(int), s));
     // the steps are enqueued back to back: step j + 1 reads the landmark
     // that step j's argmax wrote on the device
@@ -471,26 +508,66 @@ int geodesic_impl(const int32_t *rp_in, const int32_t *ci_in, const double *w_in
     GCHK(hipMemcpyAsync(&herr_fps, fs.err, sizeof(int), hipMemcpyDeviceToHost, s));
     GCHK(hipStreamSynchronize(s));
     if (herr_fps) return api_fail(SBMDS_EHIP, "a farthest-point search did not settle");
-    // the landmark block: full searches, S sources at a time
+    // the landmark block: full searches, S sources at a time, in distance
+    // buckets twice the largest edge weight wide
     if (want_w) {
         hipLaunchKernelGGL(k_geo_fill_u64, dim3(nblk((int64_t)S * n)), dim3(256), 0, s, ms.dist, (int64_t)S * n,
                            kInfBits);
         hipLaunchKernelGGL(k_geo_fill_i32, dim3(nblk((int64_t)S * n)), dim3(256), 0, s, ms.inq, (int64_t)S * n, 0);
+        hipLaunchKernelGGL(k_geo_fill_i32, dim3(nblk((int64_t)S * n)), dim3(256), 0, s, ms.farf, (int64_t)S * n, 0);
+        GCHK(hipMemsetAsync(dwmax, 0, 8, s));
+        if (nnz > 0) hipLaunchKernelGGL(k_geo_wmax, dim3(nblk(nnz)), dim3(256), 0, s, w, nnz, dwmax);
         GCHK(hipGetLastError());
+        unsigned long long hwmax = 0;
+        GCHK(hipMemcpyAsync(&hwmax, dwmax, 8, hipMemcpyDeviceToHost, s));
+        GCHK(hipStreamSynchronize(s));
+        double wmax = 0.0;
+        std::memcpy(&wmax, &hwmax, 8);
+        const double delta = wmax > 0.0 ? 2.0 * wmax : 1.0;
         for (int64_t f0 = 0; f0 < l; f0 += S) {
             const int Sb = (int)std::min<int64_t>(S, l - f0);
             hipLaunchKernelGGL(k_ms_begin, dim3(1), dim3(256), 0, s, ms, (const int32_t *)fs.lm, (int)f0, Sb, n);
             GCHK(hipGetLastError());
-            auto round = [&](int r) {
-                hipLaunchKernelGGL(k_ms_round, dim3(kRoundGrid), dim3(256), 0, s, ms, rp, ci, w, n, r);
-                return hipGetLastError();
-            };
-            if (int rc = run_rounds(round, ms.cnt, ms.last, hcnt, s, max_rounds, ms_rounds, &ms_rounds); rc < 0) return rc;
+            int r = 0, fsel = 0;
+            double thr = delta;
+            for (;;) {
+                // rounds until the frontier runs empty
+                int hc[2] = {0, 0};
+                for (;;) {
+                    for (int q = 0; q < kRoundsPerCheck; ++q, ++r)
+                        hipLaunchKernelGGL(k_ms_round, dim3(kRoundGrid), dim3(256), 0, s, ms, rp, ci, w, n, r, thr,
+                                           fsel);
+                    GCHK(hipGetLastError());
+                    GCHK(hipMemcpyAsync(&hc[0], ms.cnt + (r % 3), sizeof(int), hipMemcpyDeviceToHost, s));
+                    GCHK(hipMemcpyAsync(&hc[1], ms.fcnt + fsel, sizeof(int), hipMemcpyDeviceToHost, s));
+                    GCHK(hipStreamSynchronize(s));
+                    if (hc[0] == 0) break;
+                    if (r > max_rounds) return api_fail(SBMDS_EHIP, "a shortest-path search did not settle");
+                }
+                if (hc[1] == 0) break;  // nothing waits: the search has settled
+                // the next bucket starts at the smallest waiting distance
+                unsigned long long hmin = kInfBits;
+                GCHK(hipMemcpyAsync(ms.fmin, &hmin, 8, hipMemcpyHostToDevice, s));
+                hipLaunchKernelGGL(k_ms_farmin, dim3(kRoundGrid), dim3(256), 0, s, ms, fsel, n);
+                GCHK(hipGetLastError());
+                GCHK(hipMemcpyAsync(&hmin, ms.fmin, 8, hipMemcpyDeviceToHost, s));
+                GCHK(hipStreamSynchronize(s));
+                double dmin = 0.0;
+                std::memcpy(&dmin, &hmin, 8);
+                thr = std::max(thr, dmin) + delta;
+                GCHK(hipMemsetAsync(ms.fcnt + (fsel ^ 1), 0, sizeof(int), s));
+                hipLaunchKernelGGL(k_ms_refill, dim3(kRoundGrid), dim3(256), 0, s, ms, fsel, thr, r, n);
+                GCHK(hipGetLastError());
+                fsel ^= 1;
+                if (r > max_rounds) return api_fail(SBMDS_EHIP, "a shortest-path search did not settle");
+            }
             hipLaunchKernelGGL(k_ms_gather, dim3(nblk(l), (unsigned)Sb), dim3(256), 0, s,
                                (const unsigned long long *)ms.dist, (const int32_t *)fs.lm, n, l, (int)f0, Sb, D);
             hipLaunchKernelGGL(k_geo_fill_u64, dim3(nblk((int64_t)Sb * n)), dim3(256), 0, s, ms.dist,
                                (int64_t)Sb * n, kInfBits);
             hipLaunchKernelGGL(k_geo_fill_i32, dim3(nblk((int64_t)Sb * n)), dim3(256), 0, s, ms.inq,
+                               (int64_t)Sb * n, 0);
+            hipLaunchKernelGGL(k_geo_fill_i32, dim3(nblk((int64_t)Sb * n)), dim3(256), 0, s, ms.farf,
                                (int64_t)Sb * n, 0);
             GCHK(hipGetLastError());
         }

@@ -610,6 +610,90 @@ def interpolation_at_scale(sb, torch, big=False):
     return out
 
 
+def real_large(sb, torch, k=3, block=16, steps=3):
+    """The paper's largest configuration with its own operator, every input
+    built on the device: a bumpy torus of 1,800 x 1,000 vertices (n = 1.8M),
+    50,000 farthest-point landmarks from default_rng(3005)'s vertex, the
+    geodesic W (float32, 10 GB) and the biharmonic P thresholded to
+    p_row = 10 (p = 350); then the certified k = 3 embedding (plain fp32 and
+    bf16 -> fp32, random start, block 16) on it, and the float64 oracle's
+    ARPACK solve of the same operator on the host as this workload's CPU
+    baseline."""
+    import numpy as np
+
+    from synth import meshes
+    from synth import operator as op
+
+    t0 = time.perf_counter()
+    seed = 3005
+    V, F = meshes.bumpy_torus(1800, 1000, seed)
+    n, l = V.shape[0], 50_000
+    G = op.edge_graph(V, F).tocsr()
+    G.sort_indices()
+    arrs = [torch.from_numpy(a).cuda() for a in (G.indptr.astype(np.int32), G.indices.astype(np.int32), G.data)]
+    first = int(np.random.default_rng(seed).integers(n))
+    out = {"workload": f"bumpy torus 1800 x 1000 (n={n}), l={l} FPS landmarks, geodesic W = D^2_ll float32, "
+                       f"biharmonic P with p_row = 10, k = {k}, block {block}; every input built on the device",
+           "host_mesh_and_graph_s": round(time.perf_counter() - t0, 1)}
+    log(f"real large: mesh and edge graph on the host in {out['host_mesh_and_graph_s']} s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lm, _ = sb.landmarks_geodesic(*arrs, l, first, want_W=False)
+    torch.cuda.synchronize()
+    out["gpu_landmarks_s"] = round(time.perf_counter() - t0, 2)
+    log(f"real large: {l} landmarks in {out['gpu_landmarks_s']} s")
+    t0 = time.perf_counter()
+    lm, W = sb.landmarks_geodesic(*arrs, l, first, batch=256)
+    torch.cuda.synchronize()
+    out["gpu_landmarks_and_w_s"] = round(time.perf_counter() - t0, 1)
+    Wf = W.float()
+    del W, arrs
+    torch.cuda.empty_cache()
+    log(f"real large: landmarks + W in {out['gpu_landmarks_and_w_s']} s")
+    lmh = lm.cpu().numpy()
+    p = op.p_from_prow(n, l, 10)
+    t0 = time.perf_counter()
+    rp, col, val = sb.interpolation(V, F, lmh, p=p)
+    out["gpu_p_s"] = round(time.perf_counter() - t0, 1)
+    out["nnz"] = int(len(col))
+    log(f"real large: P ({len(col)} entries) in {out['gpu_p_s']} s")
+    val32 = val.astype(np.float32)
+    dv = [torch.from_numpy(a).cuda() for a in (rp, col, val32)]
+    forms = {}
+    for name, prec in (("fp32", sb.FP32), ("bf16_fp32", sb.BF16_FP32)):
+        ctx = sb.Context([sb.Problem.from_arrays(dv[0], dv[1], dv[2], Wf)], k=k, block=block, prec=prec)
+        Z = torch.empty((n, k), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.embed(Z_out=Z)
+        torch.cuda.synchronize()
+        first_ms = 1e3 * (time.perf_counter() - t1)
+        ts, eig, rep, rc = [], None, None, None
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, eig, reps, rc = ctx.embed(Z_out=Z)
+            torch.cuda.synchronize()
+            ts.append(1e3 * (time.perf_counter() - t1))
+            rep = reps[0]
+        ctx.close()
+        forms[name] = {"ms": round(sorted(ts)[len(ts) // 2], 3), "first_call_ms": round(first_ms, 3), "status": rc,
+                       "certified": bool(rep["certified"]), "eig": [float(x) for x in np.asarray(eig).ravel()[:k]],
+                       "iters": {"bf16": rep["iters_bf16"], "fp32": rep["iters_fp32"], "fp64": rep["iters_fp64"]}}
+        log(f"real large: {name} {forms[name]}")
+    out["forms"] = forms
+    del dv
+    prob = {"n": n, "l": l, "rowptr": rp, "col": col, "val": val32, "W": Wf.cpu().numpy()}
+    del Wf
+    torch.cuda.empty_cache()
+    cpu, lam = cpu_baseline(prob, k, route="arpack")
+    cpu["gpu_vs_oracle_rel_eig_err"] = float(np.max(np.abs(np.asarray(forms["fp32"]["eig"]) - lam[:k]) /
+                                                    np.abs(lam[:k])))
+    out["cpu_baseline"] = cpu
+    log(f"real large: cpu baseline {cpu}")
+    return out
+
+
 def chain_torus(sb, torch):
     """The whole input chain of the 1024 x 512 bumpy torus (n = 524,288,
     l = 10,000, p = 514) on the device -- farthest-point landmarks, the
@@ -954,6 +1038,8 @@ def partial_run(sb, torch, configs, args, k, blocks, want):
     if want("landmarks") and not args.no_landmarks:
         out["landmarks_geodesic"] = landmark_workload(sb, torch)
         out["landmarks_geodesic"]["input_chain"] = input_chain(sb, torch)
+    if want("real_large"):
+        out["real_large"] = real_large(sb, torch, k, blocks[0], max(1, min(args.steps, 3)))
     if want("chain_torus"):
         out["chain_torus_1024x512"] = chain_torus(sb, torch)
     if want("batch_chain"):
@@ -984,7 +1070,7 @@ def main():
     ap.add_argument("--no-landmarks", action="store_true", help="skip the device landmark / W workload")
     ap.add_argument("--workloads", type=str, default="",
                     help="comma list of workloads to run (headline, routes, cpu, sphere, batch, scale, landmarks, "
-                         "quality, torus, interp, interp_big, batch_chain, chain_torus); default all but the last three.  Without the headline the line carries no value (for "
+                         "quality, torus, interp, interp_big, batch_chain, chain_torus, real_large); default all but the last four.  Without the headline the line carries no value (for "
                          "profiling one workload)")
     ap.add_argument("--forms", type=str, default="",
                     help="comma-separated headline forms to time (default: all; plain fp32 always)")

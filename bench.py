@@ -615,14 +615,51 @@ def real_large(sb, torch, k=3, block=16, steps=3):
     built on the device: a bumpy torus of 1,800 x 1,000 vertices (n = 1.8M),
     50,000 farthest-point landmarks from default_rng(3005)'s vertex, the
     geodesic W (float32, 10 GB) and the biharmonic P thresholded to
-    p_row = 10 (p = 350); then the certified k = 3 embedding (plain fp32 and
-    bf16 -> fp32, random start, block 16) on it, and the float64 oracle's
+    p_row = 10 (p = 350); then the certified k = 3 embedding (fp32 and
+    bf16 -> fp32, random and learned starts, block 16) on it, and the float64 oracle's
     ARPACK solve of the same operator on the host as this workload's CPU
-    baseline."""
+    baseline.  The learned start's network is trained first on 24 smaller
+    bumpy tori of the same aspect ratio and landmark density (n ~ U[8000,
+    60000], l = n/36, seeds 3101-3124), their inputs built on the device the
+    same way, targets from the library's own fp32 solves."""
     import numpy as np
 
-    from synth import meshes
+    from paper_1705_10887_amd import mlp
+    from synth import configs, meshes
     from synth import operator as op
+
+    def device_chain(V, F, l, first):
+        G = op.edge_graph(V, F).tocsr()
+        G.sort_indices()
+        ga = [torch.from_numpy(a).cuda() for a in (G.indptr.astype(np.int32), G.indices.astype(np.int32), G.data)]
+        lm, W = sb.landmarks_geodesic(*ga, l, first, batch=256)
+        lmh = lm.cpu().numpy()
+        rp, col, val = sb.interpolation(V, F, lmh, p=op.p_from_prow(V.shape[0], l, 10))
+        return {"n": V.shape[0], "l": l, "rowptr": rp, "col": col, "val": val.astype(np.float32),
+                "W": W.float().cpu().numpy(), "landmarks": lmh, "xyz": V.astype(np.float32)}
+
+    t0 = time.perf_counter()
+    rng = np.random.default_rng(3100)
+    fam = []
+    for i, ni in enumerate(rng.integers(8000, 60001, size=24)):
+        nu = int(round(np.sqrt(1.8 * ni)))
+        nv = int(round(ni / nu))
+        Vt, Ft = meshes.bumpy_torus(nu, nv, 3101 + i)
+        fam.append(device_chain(Vt, Ft, max(2, int(round(nu * nv / 36))),
+                                int(np.random.default_rng(3101 + i).integers(nu * nv))))
+    t_fam = time.perf_counter() - t0
+    targets = mlp.solve_targets(fam, k=k, block=block)
+    feats = [mlp.features(m["xyz"], m["landmarks"], m["W"]) for m in fam]
+    net, losses = mlp.train(feats, targets, k=k, steps=800, lr=3e-3, seed=0)
+    weights = os.path.join(configs.cache_dir(), f"mlp_realtorus_k{k}.bin")
+    net.save(weights)
+    net.close()
+    torch.cuda.synchronize()
+    start_net = {"meshes": len(fam), "n_range": [int(min(m["n"] for m in fam)), int(max(m["n"] for m in fam))],
+                 "device_inputs_s": round(t_fam, 1), "train_s": round(time.perf_counter() - t0 - t_fam, 1),
+                 "loss_first": losses[0], "loss_last": losses[-1], "adam_steps": 800}
+    log(f"real large: start network {start_net}")
+    del fam, targets, feats
 
     t0 = time.perf_counter()
     seed = 3005
@@ -634,7 +671,7 @@ def real_large(sb, torch, k=3, block=16, steps=3):
     first = int(np.random.default_rng(seed).integers(n))
     out = {"workload": f"bumpy torus 1800 x 1000 (n={n}), l={l} FPS landmarks, geodesic W = D^2_ll float32, "
                        f"biharmonic P with p_row = 10, k = {k}, block {block}; every input built on the device",
-           "host_mesh_and_graph_s": round(time.perf_counter() - t0, 1)}
+           "host_mesh_and_graph_s": round(time.perf_counter() - t0, 1), "start_network": start_net}
     log(f"real large: mesh and edge graph on the host in {out['host_mesh_and_graph_s']} s")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -660,8 +697,14 @@ def real_large(sb, torch, k=3, block=16, steps=3):
     val32 = val.astype(np.float32)
     dv = [torch.from_numpy(a).cuda() for a in (rp, col, val32)]
     forms = {}
-    for name, prec in (("fp32", sb.FP32), ("bf16_fp32", sb.BF16_FP32)):
-        ctx = sb.Context([sb.Problem.from_arrays(dv[0], dv[1], dv[2], Wf)], k=k, block=block, prec=prec)
+    geo = {"xyz": torch.from_numpy(V.astype(np.float32)).cuda(),
+           "landmark_vertex": torch.from_numpy(lmh.astype(np.int32)).cuda()}
+    for name, prec, start in (("fp32", sb.FP32, None), ("bf16_fp32", sb.BF16_FP32, None),
+                              ("fp32_learned", sb.FP32, sb.START_LEARNED),
+                              ("bf16_fp32_learned", sb.BF16_FP32, sb.START_LEARNED)):
+        kw = {"start": start, "mlp_weights": weights} if start is not None else {}
+        pr = sb.Problem.from_arrays(dv[0], dv[1], dv[2], Wf, **(geo if start is not None else {}))
+        ctx = sb.Context([pr], k=k, block=block, prec=prec, **kw)
         Z = torch.empty((n, k), dtype=torch.float32, device="cuda")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -682,7 +725,7 @@ def real_large(sb, torch, k=3, block=16, steps=3):
                        "iters": {"bf16": rep["iters_bf16"], "fp32": rep["iters_fp32"], "fp64": rep["iters_fp64"]}}
         log(f"real large: {name} {forms[name]}")
     out["forms"] = forms
-    del dv
+    del dv, geo
     prob = {"n": n, "l": l, "rowptr": rp, "col": col, "val": val32, "W": Wf.cpu().numpy()}
     del Wf
     torch.cuda.empty_cache()

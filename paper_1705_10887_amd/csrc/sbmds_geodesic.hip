@@ -252,10 +252,11 @@ struct MultiState {
     int *fcnt;                 // [2]
     int *last;                 // [1] last round that had a non-empty frontier
     unsigned long long *fmin;  // [1] smallest distance on a far list (bits)
+    double *thr;               // [1] the current bucket's threshold
 };
 
 __global__ __launch_bounds__(256) void k_ms_begin(MultiState s, const int32_t *__restrict__ lm, int first, int S,
-                                                  int64_t n) {
+                                                  int64_t n, double delta) {
     const int q = threadIdx.x;
     if (blockIdx.x != 0) return;
     if (q < S) {
@@ -270,12 +271,15 @@ __global__ __launch_bounds__(256) void k_ms_begin(MultiState s, const int32_t *_
         s.cnt[2] = 0;
         s.fcnt[0] = 0;
         s.fcnt[1] = 0;
+        s.thr[0] = delta;
+        s.fmin[0] = kInfBits;
     }
 }
 
 __global__ __launch_bounds__(256) void k_ms_round(MultiState s, const int32_t *__restrict__ rp,
                                                   const int32_t *__restrict__ ci, const double *__restrict__ w,
-                                                  int64_t n, int round, double thr, int fsel) {
+                                                  int64_t n, int round, int fsel) {
+    const double thr = s.thr[0];
     const int in = round % 3, out = (round + 1) % 3, clr = (round + 2) % 3;
     const int64_t *fin = s.front[round & 1];
     int64_t *fout = s.front[(round + 1) & 1];
@@ -318,11 +322,20 @@ __global__ __launch_bounds__(256) void k_ms_farmin(MultiState s, int fsel, int64
     }
 }
 
+// The next bucket's threshold: past the smallest waiting distance (k_ms_farmin
+// wrote it), by delta; the minimum is reset for the next bucket.
+__global__ void k_ms_next_thr(MultiState s, double delta) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    s.thr[0] = fmax(s.thr[0], as_d(s.fmin[0])) + delta;
+    s.fmin[0] = kInfBits;
+}
+
 // Next bucket: the pairs of far list fsel below thr join the frontier of
 // round `round` (stamped as queued for it), the others move to the other far
 // list.  (A pair lowered below an earlier threshold after it was deferred
 // was processed then; processing it again changes nothing.)
-__global__ __launch_bounds__(256) void k_ms_refill(MultiState s, int fsel, double thr, int round, int64_t n) {
+__global__ __launch_bounds__(256) void k_ms_refill(MultiState s, int fsel, int round, int64_t n) {
+    const double thr = s.thr[0];
     const int count = s.fcnt[fsel];
     const int64_t *lst = s.far[fsel];
     for (int i = blockIdx.x * 256 + threadIdx.x; i < count; i += gridDim.x * 256) {
@@ -463,6 +476,7 @@ int geodesic_impl(const int32_t *rp_in, const int32_t *ci_in, const double *w_in
     ms.fcnt = small + 20;
     ms.fmin = (unsigned long long *)(small + 24);
     unsigned long long *dwmax = (unsigned long long *)(small + 26);
+    ms.thr = (double *)(small + 28);
     unsigned long long *derr = (unsigned long long *)(small + 16);
     const int32_t *rp = rp_in, *ci = ci_in;
     const double *w = w_in;
@@ -526,40 +540,30 @@ int geodesic_impl(const int32_t *rp_in, const int32_t *ci_in, const double *w_in
         const double delta = wmax > 0.0 ? 2.0 * wmax : 1.0;
         for (int64_t f0 = 0; f0 < l; f0 += S) {
             const int Sb = (int)std::min<int64_t>(S, l - f0);
-            hipLaunchKernelGGL(k_ms_begin, dim3(1), dim3(256), 0, s, ms, (const int32_t *)fs.lm, (int)f0, Sb, n);
+            hipLaunchKernelGGL(k_ms_begin, dim3(1), dim3(256), 0, s, ms, (const int32_t *)fs.lm, (int)f0, Sb, n,
+                               delta);
             GCHK(hipGetLastError());
             int r = 0, fsel = 0;
-            double thr = delta;
             for (;;) {
-                // rounds until the frontier runs empty
-                int hc[2] = {0, 0};
-                for (;;) {
-                    for (int q = 0; q < kRoundsPerCheck; ++q, ++r)
-                        hipLaunchKernelGGL(k_ms_round, dim3(kRoundGrid), dim3(256), 0, s, ms, rp, ci, w, n, r, thr,
-                                           fsel);
-                    GCHK(hipGetLastError());
-                    GCHK(hipMemcpyAsync(&hc[0], ms.cnt + (r % 3), sizeof(int), hipMemcpyDeviceToHost, s));
-                    GCHK(hipMemcpyAsync(&hc[1], ms.fcnt + fsel, sizeof(int), hipMemcpyDeviceToHost, s));
-                    GCHK(hipStreamSynchronize(s));
-                    if (hc[0] == 0) break;
-                    if (r > max_rounds) return api_fail(SBMDS_EHIP, "a shortest-path search did not settle");
-                }
-                if (hc[1] == 0) break;  // nothing waits: the search has settled
-                // the next bucket starts at the smallest waiting distance
-                unsigned long long hmin = kInfBits;
-                GCHK(hipMemcpyAsync(ms.fmin, &hmin, 8, hipMemcpyHostToDevice, s));
-                hipLaunchKernelGGL(k_ms_farmin, dim3(kRoundGrid), dim3(256), 0, s, ms, fsel, n);
+                // rounds until the frontier runs empty; one host check per
+                // kRoundsPerCheck rounds, the threshold stays on the device
+                for (int q = 0; q < kRoundsPerCheck; ++q, ++r)
+                    hipLaunchKernelGGL(k_ms_round, dim3(kRoundGrid), dim3(256), 0, s, ms, rp, ci, w, n, r, fsel);
                 GCHK(hipGetLastError());
-                GCHK(hipMemcpyAsync(&hmin, ms.fmin, 8, hipMemcpyDeviceToHost, s));
+                int hc[2] = {0, 0};
+                GCHK(hipMemcpyAsync(&hc[0], ms.cnt + (r % 3), sizeof(int), hipMemcpyDeviceToHost, s));
+                GCHK(hipMemcpyAsync(&hc[1], ms.fcnt + fsel, sizeof(int), hipMemcpyDeviceToHost, s));
                 GCHK(hipStreamSynchronize(s));
-                double dmin = 0.0;
-                std::memcpy(&dmin, &hmin, 8);
-                thr = std::max(thr, dmin) + delta;
+                if (r > max_rounds) return api_fail(SBMDS_EHIP, "a shortest-path search did not settle");
+                if (hc[0] != 0) continue;
+                if (hc[1] == 0) break;  // nothing waits: the search has settled
+                // next bucket: past the smallest waiting distance
+                hipLaunchKernelGGL(k_ms_farmin, dim3(kRoundGrid), dim3(256), 0, s, ms, fsel, n);
+                hipLaunchKernelGGL(k_ms_next_thr, dim3(1), dim3(64), 0, s, ms, delta);
                 GCHK(hipMemsetAsync(ms.fcnt + (fsel ^ 1), 0, sizeof(int), s));
-                hipLaunchKernelGGL(k_ms_refill, dim3(kRoundGrid), dim3(256), 0, s, ms, fsel, thr, r, n);
+                hipLaunchKernelGGL(k_ms_refill, dim3(kRoundGrid), dim3(256), 0, s, ms, fsel, r, n);
                 GCHK(hipGetLastError());
                 fsel ^= 1;
-                if (r > max_rounds) return api_fail(SBMDS_EHIP, "a shortest-path search did not settle");
             }
             hipLaunchKernelGGL(k_ms_gather, dim3(nblk(l), (unsigned)Sb), dim3(256), 0, s,
                                (const unsigned long long *)ms.dist, (const int32_t *)fs.lm, n, l, (int)f0, Sb, D);
